@@ -1,0 +1,102 @@
+"""Pins of the oracle's rate formulas against forms computed from H itself
+(projection, whitened interference, Sylvester determinant) and the bounds of
+Appendix A."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import channel as ch
+from oracle import rates as R
+
+
+def _drop(n=24, k=5, seed=1, amp=W.AMP_FREESPACE):
+    rng = np.random.default_rng(seed)
+    arr = W.ula(n, W.LAMBDA_28GHZ, amp)
+    r = rng.uniform(1.0, 6.0, k)
+    th = rng.uniform(-1.0, 1.0, k)
+    u = np.stack([r * np.cos(th), r * np.sin(th), np.zeros(k)], axis=-1)
+    h = ch.channel_matrix(arr, u)
+    g = h.conj().T @ h
+    rho = rng.uniform(0.5, 2.0, k) * 10.0 / np.real(np.diag(g)).mean()
+    return h, g, rho
+
+
+def test_single_user_reduces_to_awgn():
+    h, g, rho = _drop(k=1)
+    want = math.log2(1 + rho[0] * np.linalg.norm(h) ** 2)
+    out = R.rates(g, rho, R.SCHEME_ZF | R.SCHEME_MMSE | R.SCHEME_MRC | R.SCHEME_CAP)
+    for v in out.values():
+        assert v == pytest.approx(want, rel=1e-13)
+
+
+def test_zf_equals_projection_form():
+    # ZF SINR_k = rho_k || P_perp(H_{-k}) h_k ||^2, P_perp the projector orthogonal to the other users
+    h, g, rho = _drop()
+    s = R.sinr_zf(g, rho)
+    for k in range(h.shape[1]):
+        others = np.delete(h, k, axis=1)
+        coef, *_ = np.linalg.lstsq(others, h[:, k], rcond=None)
+        resid = h[:, k] - others @ coef
+        assert s[k] == pytest.approx(rho[k] * np.linalg.norm(resid) ** 2, rel=1e-8)
+
+
+def test_mmse_equals_whitened_form():
+    # MMSE SINR_k = rho_k h_k^H (I + sum_{j != k} rho_j h_j h_j^H)^{-1} h_k   (sigma^2 = 1)
+    h, g, rho = _drop()
+    s = R.sinr_mmse(g, rho)
+    n = h.shape[0]
+    for k in range(h.shape[1]):
+        c = np.eye(n, dtype=complex)
+        for j in range(h.shape[1]):
+            if j != k:
+                c += rho[j] * np.outer(h[:, j], h[:, j].conj())
+        want = rho[k] * np.real(h[:, k].conj() @ np.linalg.solve(c, h[:, k]))
+        assert s[k] == pytest.approx(want, rel=1e-9)
+
+
+def test_mrc_and_capacity_from_h():
+    h, g, rho = _drop()
+    s = R.sinr_mrc(g, rho)
+    for k in range(h.shape[1]):
+        w = h[:, k]
+        sig = rho[k] * abs(w.conj() @ h[:, k]) ** 2
+        interf = sum(rho[j] * abs(w.conj() @ h[:, j]) ** 2 for j in range(h.shape[1]) if j != k)
+        assert s[k] == pytest.approx(sig / (interf + np.linalg.norm(w) ** 2), rel=1e-12)
+    # eq. (9) via Sylvester: det(I_K + D^1/2 G D^1/2) = det(I_N + H D H^H)
+    _, ld = np.linalg.slogdet(np.eye(h.shape[0]) + (h * rho) @ h.conj().T)
+    assert R.capacity(g, rho) == pytest.approx(ld / math.log(2), rel=1e-12)
+
+
+def test_mismatched_from_filter():
+    h, g, rho = _drop(seed=4)
+    rng = np.random.default_rng(5)
+    e = rng.normal(size=g.shape) + 1j * rng.normal(size=g.shape)
+    gt = g + 0.01 * np.abs(g).max() * (e + e.conj().T)   # a Hermitian filter Gram
+    s = R.sinr_mismatched(g, gt, rho)
+    w = np.linalg.inv(gt) @ h.conj().T                    # W = G~^{-1} H^H
+    b = w @ h
+    for k in range(h.shape[1]):
+        sig = rho[k] * abs(b[k, k]) ** 2
+        interf = sum(rho[j] * abs(b[k, j]) ** 2 for j in range(h.shape[1]) if j != k)
+        assert s[k] == pytest.approx(sig / (interf + np.linalg.norm(w[k]) ** 2), rel=1e-9)
+    # with the true Gram as the filter it is ZF
+    assert np.allclose(R.sinr_mismatched(g, g, rho), R.sinr_zf(g, rho), rtol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_orderings_and_appendix_a_bounds(seed):
+    h, g, rho = _drop(seed=seed, amp=W.AMP_PNUSW)
+    zf, mm = R.sinr_zf(g, rho), R.sinr_mmse(g, rho)
+    assert np.all(zf <= mm * (1 + 1e-12))
+    cap = R.capacity(g, rho)
+    assert R.sum_rate(mm) <= cap + 1e-12
+    assert cap <= R.hadamard_bound(g, rho) + 1e-12
+    assert cap >= R.schur_horn_bound(g, rho) - 1e-12
+
+
+def test_mmse_tends_to_zf_at_high_snr():
+    h, g, rho = _drop()
+    big = rho * 1e10
+    assert np.allclose(R.sinr_mmse(g, big), R.sinr_zf(g, big), rtol=1e-6)
