@@ -1,0 +1,189 @@
+/*
+ * xlmimo.h - C ABI of the MI355X (gfx950) library for near-field XL-MIMO
+ * multiuser Gram matrices, linear-receiver sum-rates and capacity saturation.
+ *
+ * Method: Cui, Park, Alouini, "Channel Capacity Saturation Point and
+ * Beamforming Acceleration for Near-Field XL-MIMO Multiuser Communications".
+ *
+ * Conventions shared by every entry point
+ *   - Units are SI (metres); SNRs are linear, never dB.
+ *   - Complex numbers are interleaved (re, im) pairs of double.
+ *   - Pointers documented as DEVICE must point to memory of the context's
+ *     device (hipMalloc'd or a torch tensor's data_ptr()); HOST pointers are
+ *     ordinary process memory read before the call returns.  The caller owns
+ *     all of them; the library allocates only its own workspace, held by the
+ *     context.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     is asynchronous: outputs are valid once the stream has synchronised.
+ *   - Return codes: XLMIMO_OK, or a negative whole-call error.  Whole-call
+ *     errors are detected on the host before anything is enqueued
+ *     (XLMIMO_EINVAL) or come from the HIP runtime (XLMIMO_EDEVICE, text in
+ *     xlmimo_last_error).  Per-drop numerical conditions never fail a call:
+ *     they are reported in per-drop status words (XLMIMO_ST_* bits).
+ *   - Calls on one context are serialised by an internal mutex, and they
+ *     share the context's workspace: work enqueued by two calls of one
+ *     context on different streams must not overlap in time (use one context
+ *     per stream for concurrent work).
+ *   - The first call with a new batch shape builds and uploads a launch plan
+ *     synchronously; later calls with the same shape enqueue kernels only, so
+ *     a warmed-up call sequence can be captured into a hipGraph.
+ */
+#ifndef XLMIMO_H
+#define XLMIMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XLMIMO_OK        0
+#define XLMIMO_EINVAL   (-1)   /* invalid argument (message in xlmimo_last_error) */
+#define XLMIMO_EDEVICE  (-2)   /* HIP runtime error */
+#define XLMIMO_ENOMEM   (-3)   /* workspace allocation failed */
+#define XLMIMO_ENOTIMPL (-4)   /* combination not implemented */
+
+/* Array geometry (Sec. II-A: the ULA lies on the y axis, centred at the
+ * origin; the UPA is the same construction in the y-z plane).
+ * ULA element n = 0..N-1 sits at (0, (n - (N-1)/2) d, 0); UPA element
+ * (a, b) sits at (0, (a - (n_y-1)/2) d, (b - (n_z-1)/2) d). */
+#define XLMIMO_ULA 0
+#define XLMIMO_UPA 1
+
+/* Channel amplitude model.
+ * FREESPACE: h = lambda / (4 pi r) e^{-j 2 pi r / lambda}.
+ * PNUSW (eq. (3)): h = sqrt(beta0) e^{-j 2 pi r / lambda} / r * sqrt(x_perp / r),
+ *   x_perp = distance of the user from the array line (ULA) or plane (UPA). */
+#define XLMIMO_AMP_FREESPACE 0
+#define XLMIMO_AMP_PNUSW     1
+
+/* Exact-Gram precision.
+ * FP64 : distance, phase, sin/cos, amplitude and accumulation in FP64.
+ * FP32C: distance and phase reduction (2 pi r / lambda modulo 2 pi) in FP64,
+ *        sin/cos and amplitude in FP32, products summed in FP32 over blocks
+ *        of at most 256 elements whose partial sums are carried in FP64. */
+#define XLMIMO_FP64  0
+#define XLMIMO_FP32C 1
+
+/* Closed-form variants (eqs. (4), (6), (22), (23); see xlmimo_gram_closedform). */
+#define XLMIMO_CF_PAPER 0      /* formulas as printed, for every pair */
+#define XLMIMO_CF_GATED 1      /* off-diagonal set to 0 when the stationary point is off the aperture */
+
+/* Rate schemes (bitmask).  rates_out holds one value per set bit, in
+ * increasing bit order. */
+#define XLMIMO_ZF         1    /* sum log2(1 + rho_k / [G^-1]_kk) */
+#define XLMIMO_MMSE       2    /* sum log2(1 / [(I + D^1/2 G D^1/2)^-1]_kk) */
+#define XLMIMO_MRC        4    /* sum log2(1 + rho_k G_kk^2 / (sum_{j!=k} rho_j |G_kj|^2 + G_kk)) */
+#define XLMIMO_CAP        8    /* log2 det(I + D^1/2 G D^1/2), eq. (9) */
+#define XLMIMO_MZF       16    /* ZF formula evaluated on the filter Gram (nominal modified ZF) */
+#define XLMIMO_MZF_MISM  32    /* modified-ZF filter G~^-1 H^H applied to the true channel */
+
+/* Per-drop status bits. */
+#define XLMIMO_ST_G_NOT_PD      1   /* Cholesky of the ZF Gram failed: ZF-type rates are NaN */
+#define XLMIMO_ST_MMSE_NOT_PD   2   /* Cholesky of I + A failed: MMSE/CAP are NaN */
+#define XLMIMO_ST_FILTER_NOT_PD 4   /* Cholesky of the filter Gram failed: MZF rates are NaN */
+#define XLMIMO_ST_BAD_INPUT     8   /* non-finite position or a user on the array line/plane */
+#define XLMIMO_ST_CF_DEGENERATE 16  /* closed form hit |x_i| == |x_j| or coincident users (entry set to 0) */
+
+/* Capacity-sweep Gram forms. */
+#define XLMIMO_FORM_EXACT_FP64  0
+#define XLMIMO_FORM_EXACT_FP32C 1
+#define XLMIMO_FORM_CF_PAPER    2
+#define XLMIMO_FORM_CF_GATED    3
+
+#define XLMIMO_MAX_USERS 64
+
+typedef struct xlmimo_ctx xlmimo_ctx;
+
+/* Receive array and channel model. */
+typedef struct {
+  int32_t geometry;      /* XLMIMO_ULA or XLMIMO_UPA */
+  int32_t amp_model;     /* XLMIMO_AMP_FREESPACE or XLMIMO_AMP_PNUSW */
+  int64_t n_y, n_z;      /* ULA: n_y = default N, n_z = 1. UPA: panel size */
+  double  spacing_m;     /* element spacing d > 0 (the paper uses lambda / 2) */
+  double  wavelength_m;  /* lambda > 0 */
+  double  beta0;         /* PNUSW gain constant (the paper sets 1); ignored for FREESPACE */
+} xlmimo_array;
+
+/* A batch of Monte-Carlo drops, possibly uneven in N and K. */
+typedef struct {
+  int64_t        n_drops;  /* >= 0; 0 makes every call a no-op */
+  const int64_t* n_elems;  /* HOST [n_drops]: ULA antennas per drop; NULL = array n_y. Ignored for UPA */
+  const int32_t* n_users;  /* HOST [n_drops]: users per drop, 1..XLMIMO_MAX_USERS */
+  const double*  user_pos; /* DEVICE [total_users][3]: x, y, z of each user, drops back to back */
+} xlmimo_batch;
+
+/* Output layout of every Gram: drop d's K_d x K_d complex matrix, row-major,
+ * full Hermitian, starts at complex element sum_{d' < d} K_{d'}^2. */
+
+int         xlmimo_ctx_create(xlmimo_ctx** out, int device);
+int         xlmimo_ctx_destroy(xlmimo_ctx* ctx);
+const char* xlmimo_last_error(const xlmimo_ctx* ctx);
+const char* xlmimo_version(void);
+
+/* Exact Gram G = H^H H (Sec. III: G_ii = P_i / P, rho_ij = G_ij / sqrt(G_ii G_jj);
+ * Sec. V-B: the inner products the paper accelerates).  H is generated on the
+ * fly from the geometry and user positions and never stored.
+ *   precision  XLMIMO_FP64 or XLMIMO_FP32C
+ *   gram_out   DEVICE complex128, layout above
+ * Drops with a non-finite position or a user at distance 0 from an element
+ * get NaN entries (no status array here; xlmimo_zf_mmse_sumrate flags them). */
+int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                      int32_t precision, double* gram_out, void* stream);
+
+/* Closed-form Gram of the paper's modified ZF (eqs. (22)-(23)):
+ *   G~_ii = eq. (4) / P (PNUSW ULA, general spacing d: beta0/(d x_i) S_i with
+ *           half-aperture L = N d / 2); the free-space ULA analogue
+ *           (lambda/4pi)^2 /(d x_i) [atan((L-y_i)/x_i) + atan((L+y_i)/x_i)];
+ *           the UPA panel integral of |h|^2 / d^2.
+ *   G~_ij = rho_ij sqrt(G~_ii G~_jj) with rho_ij of eq. (6) (sgn of eq. (7)),
+ *           or the corresponding stationary-phase term for the free-space
+ *           ULA and the UPA (phase offset -pi/2 on the panel).
+ *   variant     XLMIMO_CF_PAPER or XLMIMO_CF_GATED
+ *   gram_out    DEVICE complex128, layout above
+ *   status_out  DEVICE int32 [n_drops] or NULL: XLMIMO_ST_BAD_INPUT,
+ *               XLMIMO_ST_CF_DEGENERATE bits (overwritten, not or-ed). */
+int xlmimo_gram_closedform(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                           int32_t variant, double* gram_out, int32_t* status_out, void* stream);
+
+/* ZF / MMSE / MRC / capacity / modified-ZF sum-rates of every drop (eq. (9),
+ * eq. (21) and the textbook linear-receiver SINRs), from batched FP64
+ * Cholesky factorisations of K x K Grams.
+ *   gram_true    DEVICE complex128 Grams (layout above)
+ *   gram_filter  DEVICE complex128 Grams used by XLMIMO_MZF / XLMIMO_MZF_MISM; may be NULL otherwise
+ *   n_snr        number of SNR points (>= 1)
+ *   rho          DEVICE double [n_snr][total_users]: rho_k = P_k / sigma^2 (linear)
+ *   schemes      bitmask of XLMIMO_ZF ... XLMIMO_MZF_MISM (non-zero)
+ *   rates_out    DEVICE double [n_drops][n_snr][popcount(schemes)] bit/s/Hz (NaN when not PD)
+ *   status_out   DEVICE int32 [n_drops] or NULL: OR of XLMIMO_ST_* over the SNR points */
+int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
+                           const double* gram_true, const double* gram_filter,
+                           int32_t n_snr, const double* rho, int32_t schemes,
+                           double* rates_out, int32_t* status_out, void* stream);
+
+/* Capacity-vs-N sweep of a ULA (Sec. IV-C): for every N in N_list the same
+ * drops are re-evaluated with the chosen Gram form, rates are averaged over
+ * drops (ergodic mean over drops whose rate is finite), and the saturation
+ * point is located two ways:
+ *   analytic  eqs. (15)-(16) per drop with threshold t_sat, averaged:
+ *             sat_out[0] = E[y_up], sat_out[1] = E[y_down],
+ *             sat_out[2] = (E[y_up] - E[y_down]) / spacing  (antennas);
+ *   empirical sat_out[3 + s * n_sch + c] = first N, log-interpolated, with
+ *             ergodic(N) / ergodic(N_max) >= 1 - eps_sat, for SNR s, scheme c.
+ * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32C
+ * Gram as the true channel; every other scheme uses the chosen form's Gram.
+ *   N_list       HOST int64 [n_N], ascending, each >= 1
+ *   rho          DEVICE double [n_snr][total_users]
+ *   ergodic_out  DEVICE double [n_N][n_snr][n_sch]
+ *   sat_out      DEVICE double [3 + n_snr * n_sch]
+ *   status_out   DEVICE int32 [n_N][n_drops] or NULL
+ * The batch's n_elems is ignored. */
+int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N, const int64_t* N_list,
+                          const xlmimo_batch* batch, int32_t form, int32_t n_snr, const double* rho,
+                          int32_t schemes, double t_sat, double eps_sat,
+                          double* ergodic_out, double* sat_out, int32_t* status_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XLMIMO_H */

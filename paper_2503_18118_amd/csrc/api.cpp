@@ -1,0 +1,479 @@
+// C ABI of libxlmimo: argument validation, per-context workspace, launch
+// plans (work lists) cached per batch shape, and stream-ordered launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "xlmimo.h"
+
+using namespace xl;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct Plan {
+  int n_drops = 0;
+  int n_items = 0;
+  int nb_max = 1;
+  int k_max = 1;
+  int64_t total_users = 0;
+  int64_t gram_elems = 0;    // complex elements of the whole Gram output
+  int64_t partial_doubles = 0;
+  int grid_fp32 = 0, grid_fp64 = 0;
+  DropK* d_drops = nullptr;
+  ItemK* d_items = nullptr;
+};
+
+}  // namespace
+
+struct xlmimo_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::string err;
+  int* d_counter = nullptr;
+  double* d_gl = nullptr;
+  int n_gl = 0;
+  DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist;
+  std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
+  std::unordered_map<uint64_t, Plan> plans;
+};
+
+namespace {
+
+int set_err(xlmimo_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                               \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) return set_err((ctx), XLMIMO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure(xlmimo_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
+  if (b.n >= bytes) return XLMIMO_OK;
+  if (b.p) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, XLMIMO_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+  }
+  b.n = bytes;
+  return XLMIMO_OK;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n from the
+// Chebyshev initial guess), used by the UPA free-space closed-form diagonal.
+void gauss_legendre(int n, std::vector<double>& out) {
+  out.assign(2 * n, 0.0);
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    out[2 * i] = x;
+    out[2 * i + 1] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_array(xlmimo_ctx* c, const xlmimo_array* a) {
+  if (!a) return set_err(c, XLMIMO_EINVAL, "array is NULL");
+  if (a->geometry != XLMIMO_ULA && a->geometry != XLMIMO_UPA) return set_err(c, XLMIMO_EINVAL, "bad geometry %d", a->geometry);
+  if (a->amp_model != XLMIMO_AMP_FREESPACE && a->amp_model != XLMIMO_AMP_PNUSW)
+    return set_err(c, XLMIMO_EINVAL, "bad amplitude model %d", a->amp_model);
+  if (!finite_pos(a->spacing_m)) return set_err(c, XLMIMO_EINVAL, "spacing must be finite and > 0");
+  if (!finite_pos(a->wavelength_m)) return set_err(c, XLMIMO_EINVAL, "wavelength must be finite and > 0");
+  if (a->amp_model == XLMIMO_AMP_PNUSW && !finite_pos(a->beta0)) return set_err(c, XLMIMO_EINVAL, "beta0 must be finite and > 0");
+  if (a->n_y < 1 || a->n_z < 1) return set_err(c, XLMIMO_EINVAL, "array sizes must be >= 1");
+  if (a->geometry == XLMIMO_ULA && a->n_z != 1) return set_err(c, XLMIMO_EINVAL, "a ULA has n_z == 1");
+  if (a->n_y * a->n_z > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "at most 2^31-1 elements");
+  return XLMIMO_OK;
+}
+
+int check_batch(xlmimo_ctx* c, const xlmimo_batch* b, bool need_pos) {
+  if (!b) return set_err(c, XLMIMO_EINVAL, "batch is NULL");
+  if (b->n_drops < 0 || b->n_drops > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "bad n_drops");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!b->n_users) return set_err(c, XLMIMO_EINVAL, "n_users is NULL");
+  for (int64_t d = 0; d < b->n_drops; ++d) {
+    if (b->n_users[d] < 1 || b->n_users[d] > XLMIMO_MAX_USERS)
+      return set_err(c, XLMIMO_EINVAL, "drop %lld: K = %d outside 1..%d", (long long)d, b->n_users[d], XLMIMO_MAX_USERS);
+    if (b->n_elems && (b->n_elems[d] < 1 || b->n_elems[d] > 2147483647LL))
+      return set_err(c, XLMIMO_EINVAL, "drop %lld: N = %lld outside 1..2^31-1", (long long)d, (long long)b->n_elems[d]);
+  }
+  if (need_pos && !b->user_pos) return set_err(c, XLMIMO_EINVAL, "user_pos is NULL");
+  return XLMIMO_OK;
+}
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+
+// Work-item length: long enough to amortise the per-item reduction, short
+// enough to give the persistent grid several items per workgroup.
+int64_t chunk_length(int64_t total_elems, int grid) {
+  int64_t target = total_elems / (8LL * std::max(grid, 1));
+  target = std::max<int64_t>(target, 2048);
+  target = std::min<int64_t>(target, 65536);
+  return (target + 15) / 16 * 16;
+}
+
+// Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
+// descriptors synchronously; warm the cache before capturing a graph.
+int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override, Plan** out) {
+  uint64_t h = 1469598103934665603ULL;
+  h = fnv(h, &a->geometry, sizeof(a->geometry));
+  h = fnv(h, &a->n_y, sizeof(a->n_y));
+  h = fnv(h, &a->n_z, sizeof(a->n_z));
+  h = fnv(h, &b->n_drops, sizeof(b->n_drops));
+  const int64_t flag = n_override ? *n_override : (b->n_elems ? -1 : -2);
+  h = fnv(h, &flag, sizeof(flag));
+  if (b->n_elems && !n_override) h = fnv(h, b->n_elems, sizeof(int64_t) * b->n_drops);
+  h = fnv(h, b->n_users, sizeof(int32_t) * b->n_drops);
+  auto it = c->plans.find(h);
+  if (it != c->plans.end()) {
+    *out = &it->second;
+    return XLMIMO_OK;
+  }
+  if (c->plans.size() >= 64) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    for (auto& kv : c->plans) {
+      (void)hipFree(kv.second.d_drops);
+      (void)hipFree(kv.second.d_items);
+    }
+    c->plans.clear();
+  }
+  const int n = (int)b->n_drops;
+  Plan p;
+  p.n_drops = n;
+  std::vector<DropK> drops(n);
+  int64_t uoff = 0, goff = 0, total_elems = 0;
+  for (int d = 0; d < n; ++d) {
+    DropK& dk = drops[d];
+    int64_t ne;
+    if (a->geometry == XLMIMO_UPA) ne = a->n_y * a->n_z;
+    else ne = n_override ? *n_override : (b->n_elems ? b->n_elems[d] : a->n_y);
+    dk.n_elems = (int32_t)ne;
+    dk.k = b->n_users[d];
+    dk.nb = (dk.k + 15) / 16;
+    dk.user_off = uoff;
+    dk.gram_off = goff;
+    uoff += dk.k;
+    goff += (int64_t)dk.k * dk.k;
+    total_elems += ne;
+    p.nb_max = std::max(p.nb_max, dk.nb);
+    p.k_max = std::max(p.k_max, dk.k);
+  }
+  p.total_users = uoff;
+  p.gram_elems = goff;
+  p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, 1 << 30);
+  p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, 1 << 30);
+  const int64_t ch = chunk_length(total_elems, std::min(p.grid_fp32, p.grid_fp64));
+  std::vector<ItemK> items;
+  std::vector<int64_t> cost;
+  int64_t poff = 0;
+  for (int d = 0; d < n; ++d) {
+    DropK& dk = drops[d];
+    const int64_t ni = (dk.n_elems + ch - 1) / ch;
+    dk.n_items = (int32_t)ni;
+    dk.part_off = poff;
+    poff += ni * (int64_t)partial_values(dk.nb) * 64;
+    for (int64_t i = 0; i < ni; ++i) {
+      ItemK itm;
+      itm.drop = d;
+      itm.chunk = (int32_t)i;
+      itm.e_begin = (int32_t)(i * ch);
+      itm.e_end = (int32_t)std::min<int64_t>((i + 1) * ch, dk.n_elems);
+      items.push_back(itm);
+      const int nb = dk.nb;
+      cost.push_back((int64_t)(itm.e_end - itm.e_begin) * (nb * 8 + 3 * (nb * (nb + 1) / 2 + nb * nb)));
+    }
+  }
+  // longest-first order for the persistent queue (stable for equal costs)
+  std::vector<int> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<ItemK> sorted(items.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+  p.n_items = (int)sorted.size();
+  p.partial_doubles = poff;
+  HIP_TRY(c, hipMalloc(&p.d_drops, sizeof(DropK) * std::max(n, 1)));
+  HIP_TRY(c, hipMalloc(&p.d_items, sizeof(ItemK) * std::max<size_t>(sorted.size(), 1)));
+  HIP_TRY(c, hipMemcpy(p.d_drops, drops.data(), sizeof(DropK) * n, hipMemcpyHostToDevice));
+  if (!sorted.empty()) HIP_TRY(c, hipMemcpy(p.d_items, sorted.data(), sizeof(ItemK) * sorted.size(), hipMemcpyHostToDevice));
+  auto ins = c->plans.emplace(h, p);
+  *out = &ins.first->second;
+  return XLMIMO_OK;
+}
+
+ArrayK to_kernel(const xlmimo_array* a) {
+  ArrayK k;
+  k.geom = a->geometry;
+  k.amp = a->amp_model;
+  k.n_y = (int32_t)a->n_y;
+  k.n_z = (int32_t)a->n_z;
+  k.spacing = a->spacing_m;
+  k.lambda = a->wavelength_m;
+  k.inv_lambda = 1.0 / a->wavelength_m;
+  k.beta0 = a->beta0;
+  return k;
+}
+
+int set_device(xlmimo_ctx* c) {
+  HIP_TRY(c, hipSetDevice(c->device));
+  return XLMIMO_OK;
+}
+
+int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
+                    int32_t precision, double* gram_out, hipStream_t s) {
+  Plan* p = nullptr;
+  int rc = get_plan(c, a, b, n_override, &p);
+  if (rc) return rc;
+  rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s);
+  if (rc) return rc;
+  const int grid = std::min(precision == XLMIMO_FP64 ? p->grid_fp64 : p->grid_fp32, std::max(p->n_items, 1));
+  HIP_TRY(c, launch_gram_exact(precision, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
+                               p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s));
+  return XLMIMO_OK;
+}
+
+int closedform_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
+                    int32_t variant, double* gram_out, int32_t* status, hipStream_t s) {
+  Plan* p = nullptr;
+  int rc = get_plan(c, a, b, n_override, &p);
+  if (rc) return rc;
+  HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
+                               gram_out, status, p->k_max, s));
+  return XLMIMO_OK;
+}
+
+int rates_k_max(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+}  // namespace
+
+extern "C" {
+
+const char* xlmimo_version(void) { return "xlmimo 0.1 (gfx950)"; }
+
+int xlmimo_ctx_create(xlmimo_ctx** out, int device) {
+  if (!out) return XLMIMO_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return XLMIMO_EDEVICE;
+  }
+  xlmimo_ctx* c = new xlmimo_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess) {
+    delete c;
+    return XLMIMO_EDEVICE;
+  }
+  std::vector<double> gl;
+  c->n_gl = 64;
+  gauss_legendre(c->n_gl, gl);
+  if (hipMalloc(&c->d_gl, sizeof(double) * gl.size()) != hipSuccess ||
+      hipMemcpy(c->d_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c->d_counter);
+    delete c;
+    return XLMIMO_EDEVICE;
+  }
+  *out = c;
+  return XLMIMO_OK;
+}
+
+int xlmimo_ctx_destroy(xlmimo_ctx* c) {
+  if (!c) return XLMIMO_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->plans) {
+    (void)hipFree(kv.second.d_drops);
+    (void)hipFree(kv.second.d_items);
+  }
+  DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds, &c->scratch_nlist};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  (void)hipFree(c->d_counter);
+  (void)hipFree(c->d_gl);
+  delete c;
+  return XLMIMO_OK;
+}
+
+const char* xlmimo_last_error(const xlmimo_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,
+                      double* gram_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true);
+  if (rc) return rc;
+  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C) return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
+  if ((rc = set_device(c))) return rc;
+  return gram_exact_impl(c, a, b, nullptr, precision, gram_out, (hipStream_t)stream);
+}
+
+int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t variant,
+                           double* gram_out, int32_t* status_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true);
+  if (rc) return rc;
+  if (variant != XLMIMO_CF_PAPER && variant != XLMIMO_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
+  if ((rc = set_device(c))) return rc;
+  return closedform_impl(c, a, b, nullptr, variant, gram_out, status_out, (hipStream_t)stream);
+}
+
+static int check_rates_args(xlmimo_ctx* c, const xlmimo_batch* b, const double* gram_true, const double* gram_filter,
+                            int32_t n_snr, const double* rho, int32_t schemes) {
+  int rc = check_batch(c, b, false);
+  if (rc) return rc;
+  if (schemes <= 0 || schemes > 63) return set_err(c, XLMIMO_EINVAL, "bad scheme mask %d", schemes);
+  if (n_snr < 1) return set_err(c, XLMIMO_EINVAL, "n_snr must be >= 1");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_true || !rho) return set_err(c, XLMIMO_EINVAL, "gram_true and rho are required");
+  if ((schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM)) && !gram_filter)
+    return set_err(c, XLMIMO_EINVAL, "modified-ZF schemes need gram_filter");
+  return XLMIMO_OK;
+}
+
+int xlmimo_zf_mmse_sumrate(xlmimo_ctx* c, const xlmimo_batch* b, const double* gram_true, const double* gram_filter,
+                           int32_t n_snr, const double* rho, int32_t schemes, double* rates_out, int32_t* status_out,
+                           void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_rates_args(c, b, gram_true, gram_filter, n_snr, rho, schemes);
+  if (rc) return rc;
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!rates_out) return set_err(c, XLMIMO_EINVAL, "rates_out is NULL");
+  if ((rc = set_device(c))) return rc;
+  xlmimo_array dummy = {XLMIMO_ULA, XLMIMO_AMP_FREESPACE, 1, 1, 1.0, 1.0, 1.0};
+  xlmimo_batch bb = *b;
+  bb.n_elems = nullptr;
+  Plan* p = nullptr;
+  if ((rc = get_plan(c, &dummy, &bb, nullptr, &p))) return rc;
+  HIP_TRY(c, launch_rates(p->d_drops, p->n_drops, rates_k_max(p->k_max), gram_true, gram_filter, n_snr, rho,
+                          p->total_users, schemes, rates_out, status_out, (hipStream_t)stream));
+  return XLMIMO_OK;
+}
+
+int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, const int64_t* N_list,
+                          const xlmimo_batch* b, int32_t form, int32_t n_snr, const double* rho, int32_t schemes,
+                          double t_sat, double eps_sat, double* ergodic_out, double* sat_out, int32_t* status_out,
+                          void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_array(c, a);
+  if (rc) return rc;
+  if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the capacity sweep varies a ULA's N");
+  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
+  if (n_N < 1 || !N_list) return set_err(c, XLMIMO_EINVAL, "N_list is empty");
+  for (int i = 0; i < n_N; ++i) {
+    if (N_list[i] < 1 || N_list[i] > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "N_list[%d] out of range", i);
+    if (i && N_list[i] <= N_list[i - 1]) return set_err(c, XLMIMO_EINVAL, "N_list must be strictly ascending");
+  }
+  if (!(t_sat > 0.0 && t_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "t_sat must lie in (0, 1)");
+  if (!(eps_sat >= 0.0 && eps_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "eps_sat must lie in [0, 1)");
+  const bool cf = form >= XLMIMO_FORM_CF_PAPER;
+  if (!cf && (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM)))
+    return set_err(c, XLMIMO_EINVAL, "modified-ZF schemes need a closed-form sweep");
+  if ((rc = check_rates_args(c, b, (const double*)1, (const double*)1, n_snr, rho, schemes))) return rc;
+  if (!b->user_pos && b->n_drops) return set_err(c, XLMIMO_EINVAL, "user_pos is NULL");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!ergodic_out || !sat_out) return set_err(c, XLMIMO_EINVAL, "ergodic_out and sat_out are required");
+  if ((rc = set_device(c))) return rc;
+
+  const int n_sch = __builtin_popcount(schemes);
+  const int n_vals = n_snr * n_sch;
+  const int nd = (int)b->n_drops;
+  Plan* p = nullptr;
+  int64_t n0 = N_list[0];
+  if ((rc = get_plan(c, a, b, &n0, &p))) return rc;
+  const int64_t gbytes = sizeof(double) * 2 * p->gram_elems;
+  if ((rc = ensure(c, c->scratch_gram, gbytes, s))) return rc;
+  const bool need_exact_true = cf && (schemes & XLMIMO_MZF_MISM);
+  if (need_exact_true && (rc = ensure(c, c->scratch_gram2, gbytes, s))) return rc;
+  if ((rc = ensure(c, c->scratch_rates, sizeof(double) * (size_t)nd * n_vals, s))) return rc;
+  if ((rc = ensure(c, c->scratch_bounds, sizeof(double) * 2 * (size_t)nd, s))) return rc;
+  if (c->scratch_nlist.n < sizeof(double) * n_N) c->nlist_host.clear();
+  if ((rc = ensure(c, c->scratch_nlist, sizeof(double) * n_N, s))) return rc;
+  std::vector<double> nl(N_list, N_list + n_N);
+  if (nl != c->nlist_host) {
+    // synchronous upload, skipped when the list is unchanged (so a warmed-up sweep can be graph-captured)
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(c->scratch_nlist.p, nl.data(), sizeof(double) * n_N, hipMemcpyHostToDevice));
+    c->nlist_host = nl;
+  }
+
+  double* g = (double*)c->scratch_gram.p;
+  double* g2 = (double*)c->scratch_gram2.p;
+  for (int i = 0; i < n_N; ++i) {
+    const int64_t nn = N_list[i];
+    int32_t* st = status_out ? status_out + (int64_t)i * nd : nullptr;
+    if (!cf) {
+      if ((rc = gram_exact_impl(c, a, b, &nn, form == XLMIMO_FORM_EXACT_FP64 ? XLMIMO_FP64 : XLMIMO_FP32C, g, s))) return rc;
+    } else {
+      const int variant = form == XLMIMO_FORM_CF_PAPER ? XLMIMO_CF_PAPER : XLMIMO_CF_GATED;
+      if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) return rc;
+      if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP32C, g2, s))) return rc;
+    }
+    if ((rc = get_plan(c, a, b, &nn, &p))) return rc;
+    const double* gtrue = need_exact_true ? g2 : g;
+    HIP_TRY(c, launch_rates(p->d_drops, nd, rates_k_max(p->k_max), gtrue, g, n_snr, rho, p->total_users, schemes,
+                            (double*)c->scratch_rates.p, st, s));
+    HIP_TRY(c, launch_ergodic((double*)c->scratch_rates.p, nd, n_vals, ergodic_out + (int64_t)i * n_vals, s));
+  }
+  HIP_TRY(c, launch_y_bounds(b->user_pos, p->d_drops, nd, a->geometry, t_sat, (double*)c->scratch_bounds.p, s));
+  HIP_TRY(c, launch_saturation((double*)c->scratch_bounds.p, nd, ergodic_out, (double*)c->scratch_nlist.p, n_N, n_vals,
+                               a->spacing_m, eps_sat, sat_out, s));
+  return XLMIMO_OK;
+}
+
+}  // extern "C"

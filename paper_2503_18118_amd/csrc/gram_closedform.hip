@@ -1,0 +1,177 @@
+// Closed-form Gram of the paper's modified ZF (eqs. (22)-(23)): O(K^2) per drop,
+// no loop over antennas.
+//
+// Diagonal G~_ii (P_i / P):
+//   ULA PNUSW      eq. (4) with half-aperture L = N d / 2:  beta0 / (d x) S,
+//                  S = (L - y)/sqrt(x^2 + (L - y)^2) + (L + y)/sqrt(x^2 + (L + y)^2)
+//   ULA FREESPACE  (lambda/4pi)^2 / (d x) [atan((L - y)/x) + atan((L + y)/x)]
+//   UPA PNUSW      beta0 / d^2 * solid angle of the panel seen from the user
+//   UPA FREESPACE  (lambda/4pi)^2 / d^2 * int int du dv / (x^2 + u^2 + v^2) over the
+//                  panel: inner integral in closed form (atan), outer by
+//                  Gauss-Legendre on each side of the user's foot point.
+// Off-diagonal (stationary phase; the stationary point is where the line through
+// both users meets the array):
+//   ULA PNUSW      rho_ij of eq. (6) (sgn of eq. (7)) times sqrt(G~_ii G~_jj), eq. (23)
+//   ULA FREESPACE  (lambda/4pi)^2 sqrt(lambda) / (d sqrt(x_i x_j d_ij)) e^{j s (k d_ij - pi/4)}
+//   UPA PNUSW      beta0 lambda / (d^2 d_ij) e^{j s (k d_ij - pi/2)}
+//   UPA FREESPACE  (lambda/4pi)^2 lambda / (d^2 |x_i - x_j|) e^{j s (k d_ij - pi/2)}
+//   with s = sgn(|x_i| - |x_j|).  Variant GATED zeroes the entry when the
+//   stationary point is off the aperture; |x_i| == |x_j| or d_ij == 0 gives 0.
+// All arithmetic is FP64; the phase d_ij / lambda is reduced in revolutions.
+#include "device_math.h"
+#include "internal.h"
+#include "xlmimo.h"
+
+namespace xl {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+__device__ double upa_freespace_integral(double x, double u1, double u2, double v1, double v2,
+                                         const double* __restrict__ gl, int n_gl) {
+  // int_{u1}^{u2} (atan(v2/a) - atan(v1/a)) / a du,  a = sqrt(x^2 + u^2);  split at u = 0
+  double total = 0.0;
+  double seg[3] = {u1, u2, u2};
+  int nseg = 1;
+  if (u1 < 0.0 && u2 > 0.0) {
+    seg[1] = 0.0;
+    seg[2] = u2;
+    nseg = 2;
+  }
+  for (int s = 0; s < nseg; ++s) {
+    const double lo = seg[s], hi = seg[s + 1];
+    const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+    double acc = 0.0;
+    for (int i = 0; i < n_gl; ++i) {
+      const double u = fma(half, gl[2 * i], mid);
+      const double a = sqrt(fma(u, u, x * x));
+      acc = fma(gl[2 * i + 1], (atan(v2 / a) - atan(v1 / a)) / a, acc);
+    }
+    total = fma(half, acc, total);
+  }
+  return total;
+}
+
+__device__ double solid_angle_rect(double x, double u1, double u2, double v1, double v2) {
+  auto f = [x](double u, double v) { return atan(u * v / (x * sqrt(x * x + u * u + v * v))); };
+  return f(u2, v2) - f(u1, v2) - f(u2, v1) + f(u1, v1);
+}
+
+__global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __restrict__ drops, int variant,
+                                                     const double* __restrict__ pos,
+                                                     const double* __restrict__ gl, int n_gl,
+                                                     double* __restrict__ gram, int32_t* __restrict__ status) {
+  __shared__ double s_x[XLMIMO_MAX_USERS], s_y[XLMIMO_MAX_USERS], s_z[XLMIMO_MAX_USERS];
+  __shared__ double s_diag[XLMIMO_MAX_USERS], s_sfac[XLMIMO_MAX_USERS];
+  __shared__ int s_status;
+  const DropK dp = drops[blockIdx.x];
+  const int K = dp.k;
+  const double d = arr.spacing, lam = arr.lambda;
+  const double c_fs = (lam / (4.0 * kPi)) * (lam / (4.0 * kPi));
+  const bool ula = arr.geom == XLMIMO_ULA;
+  const double Ly = 0.5 * (double)(ula ? dp.n_elems : arr.n_y) * d;
+  const double Lz = 0.5 * (double)arr.n_z * d;
+  if (threadIdx.x == 0) s_status = 0;
+  __syncthreads();
+
+  for (int i = threadIdx.x; i < K; i += blockDim.x) {
+    const double* p = pos + (dp.user_off + i) * 3;
+    const double px = p[0], py = p[1], pz = p[2];
+    const double x = ula ? sqrt(fma(px, px, pz * pz)) : fabs(px);
+    s_x[i] = x;
+    s_y[i] = py;
+    s_z[i] = pz;
+    double g = 0.0, sf = 0.0;
+    const bool ok = x > 0.0 && isfinite(x) && isfinite(py) && isfinite(pz);
+    if (!ok) {
+      atomicOr(&s_status, XLMIMO_ST_BAD_INPUT);
+      g = __builtin_nan("");
+    } else if (ula) {
+      if (arr.amp == XLMIMO_AMP_PNUSW) {
+        const double a = Ly - py, b = Ly + py;
+        sf = a / sqrt(fma(a, a, x * x)) + b / sqrt(fma(b, b, x * x));
+        g = arr.beta0 / (d * x) * sf;
+      } else {
+        g = c_fs / (d * x) * (atan((Ly - py) / x) + atan((Ly + py) / x));
+      }
+    } else {
+      if (arr.amp == XLMIMO_AMP_PNUSW) {
+        g = arr.beta0 / (d * d) * solid_angle_rect(x, -Ly - py, Ly - py, -Lz - pz, Lz - pz);
+      } else {
+        g = c_fs / (d * d) * upa_freespace_integral(x, -Ly - py, Ly - py, -Lz - pz, Lz - pz, gl, n_gl);
+      }
+    }
+    s_diag[i] = g;
+    s_sfac[i] = sf;
+  }
+  __syncthreads();
+
+  double* out = gram + 2 * dp.gram_off;
+  for (int idx = threadIdx.x; idx < K * K; idx += blockDim.x) {
+    const int i = idx / K, j = idx - (idx / K) * K;
+    double re = 0.0, im = 0.0;
+    if (i == j) {
+      re = s_diag[i];
+    } else {
+      const int p = i < j ? i : j, q = i < j ? j : i;  // compute (p, q), conjugate for i > j
+      const double xp = s_x[p], xq = s_x[q];
+      const double dx = xp - xq, dy = s_y[p] - s_y[q], dz = ula ? 0.0 : s_z[p] - s_z[q];
+      const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+      if (!(isfinite(s_diag[p]) && isfinite(s_diag[q]))) {
+        re = im = __builtin_nan("");
+      } else if (dx == 0.0 || dist == 0.0) {
+        if (i < j) atomicOr(&s_status, XLMIMO_ST_CF_DEGENERATE);
+      } else {
+        bool inside = true;
+        if (variant == XLMIMO_CF_GATED) {
+          const double ys = (s_y[p] * xq - xp * s_y[q]) / (xq - xp);
+          inside = fabs(ys) <= Ly;
+          if (!ula) {
+            const double zs = (s_z[p] * xq - xp * s_z[q]) / (xq - xp);
+            inside = inside && fabs(zs) <= Lz;
+          }
+        }
+        if (inside) {
+          const double sg = dx > 0.0 ? 1.0 : -1.0;
+          double mag, off;
+          if (ula) {
+            off = 0.125;  // pi/4 in revolutions
+            if (arr.amp == XLMIMO_AMP_PNUSW) {
+              const double rho = sqrt(lam) * fabs(dx) / (dist * sqrt(dist)) / sqrt(s_sfac[p] * s_sfac[q]);
+              mag = rho * sqrt(s_diag[p] * s_diag[q]);
+            } else {
+              mag = c_fs * sqrt(lam) / (d * sqrt(xp * xq * dist));
+            }
+          } else {
+            off = 0.25;  // pi/2 in revolutions
+            mag = (arr.amp == XLMIMO_AMP_PNUSW) ? arr.beta0 * lam / (d * d * dist) : c_fs * lam / (d * d * fabs(dx));
+          }
+          double t;
+          int qd;
+          reduce_quarter(dist * arr.inv_lambda - off, t, qd);
+          double s, c, cre, cim;
+          sincos_rev(t, s, c);
+          rotate_conj(1.0, s, c, qd, cre, cim);  // (cos phi, -sin phi), phi = 2 pi (d/lambda - off)
+          re = mag * cre;
+          im = -sg * mag * cim;                  // e^{j s phi}
+        }
+      }
+      if (i > j) im = -im;
+    }
+    out[2 * idx] = re;
+    out[2 * idx + 1] = im;
+  }
+  __syncthreads();
+  if (status != nullptr && threadIdx.x == 0) status[blockIdx.x] = s_status;
+}
+
+hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
+                             const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,
+                             int k_max, hipStream_t s) {
+  (void)d_diag;
+  (void)k_max;
+  if (n_drops == 0) return hipSuccess;
+  k_closedform<<<n_drops, 256, 0, s>>>(arr, d_drops, variant, d_pos, d_gl, n_gl, d_gram, d_status);
+  return hipGetLastError();
+}
+
+}  // namespace xl

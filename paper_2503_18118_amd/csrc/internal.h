@@ -1,0 +1,70 @@
+// Internal declarations shared by the C-ABI layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xl {
+
+// Array description as the kernels see it.
+struct ArrayK {
+  int32_t geom;       // XLMIMO_ULA / XLMIMO_UPA
+  int32_t amp;        // XLMIMO_AMP_*
+  int32_t n_y, n_z;   // UPA panel (ULA: per-drop N in DropK)
+  double spacing;
+  double lambda;
+  double inv_lambda;
+  double beta0;
+};
+
+// One drop of a batch, device resident.
+struct DropK {
+  int64_t user_off;   // first user in the position array
+  int64_t gram_off;   // first complex element of the drop's K x K output
+  int64_t part_off;   // first double of the drop's partials (exact Gram)
+  int32_t n_elems;    // antennas (ULA: N, UPA: n_y * n_z)
+  int32_t k;          // users
+  int32_t nb;         // ceil(k / 16) user blocks
+  int32_t n_items;    // work items (element chunks) of this drop
+};
+
+// One work item of the exact Gram: a contiguous element range of one drop.
+struct ItemK {
+  int32_t drop;
+  int32_t chunk;      // partial = drops[drop].part_off + chunk * partial_values(nb) * 64
+  int32_t e_begin;
+  int32_t e_end;
+};
+
+// Values of one partial: per lane, NB(NB+1)/2 symmetric Re blocks and NB^2
+// cross blocks, 4 accumulator registers each.
+__host__ __device__ constexpr int partial_values(int nb) { return (nb * (nb + 1) / 2 + nb * nb) * 4; }
+__host__ __device__ constexpr int tri_index(int bi, int bj, int nb) {
+  // index of block (bi <= bj) in row-major upper-triangular order
+  return bi * nb - bi * (bi - 1) / 2 + (bj - bi);
+}
+
+constexpr int kGramThreads = 256;     // 4 waves per work item
+constexpr int kFlushRounds = 64;      // FP32 MFMA partial sums are carried to FP64 every 64 rounds (256 elements per wave)
+
+// Launchers (stream-ordered, no host synchronisation).
+hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
+                             const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
+                             double* d_partials, double* d_gram, int grid, hipStream_t s);
+int gram_exact_grid(int precision, int nb_max, int n_items);
+
+hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
+                             const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,
+                             int k_max, hipStream_t s);
+
+hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
+                        int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
+                        int32_t* d_status, hipStream_t s);
+
+hipError_t launch_ergodic(const double* d_rates, int n_drops, int n_vals, double* d_out, hipStream_t s);
+hipError_t launch_y_bounds(const double* d_pos, const DropK* d_drops, int n_drops, int geom, double t_sat,
+                           double* d_bounds, hipStream_t s);
+hipError_t launch_saturation(const double* d_bounds, int n_drops, const double* d_ergodic, const double* d_nlist,
+                             int n_N, int n_vals, double spacing, double eps, double* d_sat, hipStream_t s);
+
+}  // namespace xl

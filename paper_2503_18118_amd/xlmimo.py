@@ -1,0 +1,232 @@
+"""ctypes binding of libxlmimo (include/xlmimo.h): argument marshalling only.
+
+Device buffers are torch CUDA tensors; every computation runs in the HIP
+library.  Importing this module loads ``libxlmimo.so`` from the package
+directory and raises if it has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxlmimo.so")
+
+OK, EINVAL, EDEVICE, ENOMEM, ENOTIMPL = 0, -1, -2, -3, -4
+ULA, UPA = 0, 1
+AMP_FREESPACE, AMP_PNUSW = 0, 1
+FP64, FP32C = 0, 1
+CF_PAPER, CF_GATED = 0, 1
+ZF, MMSE, MRC, CAP, MZF, MZF_MISM = 1, 2, 4, 8, 16, 32
+ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE = 1, 2, 4, 8, 16
+FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED = 0, 1, 2, 3
+MAX_USERS = 64
+
+EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlmimo_version",
+            "xlmimo_gram_exact", "xlmimo_gram_closedform", "xlmimo_zf_mmse_sumrate",
+            "xlmimo_capacity_sweep")
+
+
+class XlArray(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("amp_model", C.c_int32), ("n_y", C.c_int64), ("n_z", C.c_int64),
+                ("spacing_m", C.c_double), ("wavelength_m", C.c_double), ("beta0", C.c_double)]
+
+
+class XlBatch(C.Structure):
+    _fields_ = [("n_drops", C.c_int64), ("n_elems", C.POINTER(C.c_int64)), ("n_users", C.POINTER(C.c_int32)),
+                ("user_pos", C.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(the HIP library is required; there is no CPU fallback)")
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.xlmimo_ctx_create.argtypes = [C.POINTER(vp), C.c_int]
+    lib.xlmimo_ctx_destroy.argtypes = [vp]
+    lib.xlmimo_last_error.argtypes = [vp]
+    lib.xlmimo_last_error.restype = C.c_char_p
+    lib.xlmimo_version.restype = C.c_char_p
+    lib.xlmimo_gram_exact.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp]
+    lib.xlmimo_gram_closedform.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp, vp]
+    lib.xlmimo_zf_mmse_sumrate.argtypes = [vp, C.POINTER(XlBatch), vp, vp, i32, vp, i32, vp, vp, vp]
+    lib.xlmimo_capacity_sweep.argtypes = [vp, C.POINTER(XlArray), i32, C.POINTER(C.c_int64), C.POINTER(XlBatch),
+                                          i32, i32, vp, i32, C.c_double, C.c_double, vp, vp, vp, vp]
+    return lib
+
+
+_lib = load_library()
+
+
+class XlmimoError(RuntimeError):
+    pass
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device buffers must be CUDA tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_array(arr) -> XlArray:
+    """workloads.ArraySpec -> struct xlmimo_array."""
+    return XlArray(int(arr.geometry), int(arr.amp_model), int(arr.n_y), int(arr.n_z),
+                   float(arr.spacing), float(arr.wavelength), float(arr.beta0))
+
+
+class Batch:
+    """Host descriptors + device positions of a workloads.Drops batch (kept alive together)."""
+
+    def __init__(self, drops, pos: Optional[torch.Tensor] = None, device: int = 0, use_n_elems: bool = True):
+        self.n_drops = drops.n_drops
+        self.n_elems = np.ascontiguousarray(drops.n_elems, np.int64)
+        self.n_users = np.ascontiguousarray(drops.n_users, np.int32)
+        self.total_users = int(drops.user_off[-1])
+        self.k = self.n_users.astype(np.int64)
+        self.gram_off = np.concatenate([[0], np.cumsum(self.k * self.k)]).astype(np.int64)
+        self.user_off = np.asarray(drops.user_off, np.int64)
+        if pos is None:
+            pos = torch.as_tensor(np.ascontiguousarray(drops.pos, np.float64), device=f"cuda:{device}")
+        self.pos = pos.contiguous()
+        self.struct = XlBatch(self.n_drops,
+                              self.n_elems.ctypes.data_as(C.POINTER(C.c_int64)) if use_n_elems else None,
+                              self.n_users.ctypes.data_as(C.POINTER(C.c_int32)),
+                              C.c_void_p(self.pos.data_ptr()) if self.total_users else None)
+
+    @property
+    def gram_elems(self) -> int:
+        return int(self.gram_off[-1])
+
+    def split(self, flat: torch.Tensor) -> list:
+        """Split a flat complex128 Gram buffer into per-drop K x K numpy arrays."""
+        g = flat.detach().cpu().numpy().view(np.complex128)
+        return [g[self.gram_off[d]:self.gram_off[d + 1]].reshape(self.k[d], self.k[d]) for d in range(self.n_drops)]
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        rc = _lib.xlmimo_ctx_create(C.byref(h), device)
+        if rc != OK:
+            raise XlmimoError(f"xlmimo_ctx_create failed ({rc})")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.xlmimo_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            msg = _lib.xlmimo_last_error(self.h)
+            raise XlmimoError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    # -- entry points ------------------------------------------------------
+    def gram_exact(self, arr, batch: Batch, precision: int = FP32C, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(2 * batch.gram_elems, dtype=torch.float64, device=batch.pos.device)
+        a = make_array(arr)
+        self._check(_lib.xlmimo_gram_exact(self.h, C.byref(a), C.byref(batch.struct), precision, _ptr(out),
+                                           _stream(stream)), "xlmimo_gram_exact")
+        return out
+
+    def gram_closedform(self, arr, batch: Batch, variant: int = CF_PAPER, out: Optional[torch.Tensor] = None,
+                        status: Optional[torch.Tensor] = None, stream=None):
+        if out is None:
+            out = torch.empty(2 * batch.gram_elems, dtype=torch.float64, device=batch.pos.device)
+        if status is None:
+            status = torch.empty(batch.n_drops, dtype=torch.int32, device=batch.pos.device)
+        a = make_array(arr)
+        self._check(_lib.xlmimo_gram_closedform(self.h, C.byref(a), C.byref(batch.struct), variant, _ptr(out),
+                                                _ptr(status), _stream(stream)), "xlmimo_gram_closedform")
+        return out, status
+
+    def sumrate(self, batch: Batch, gram_true: torch.Tensor, rho: torch.Tensor, schemes: int = ZF | MMSE,
+                gram_filter: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                status: Optional[torch.Tensor] = None, stream=None):
+        """rho: CUDA float64 [n_snr, total_users].  Returns (rates [n_drops, n_snr, n_sch], status)."""
+        n_snr = int(rho.shape[0])
+        n_sch = bin(schemes).count("1")
+        if out is None:
+            out = torch.empty((batch.n_drops, n_snr, n_sch), dtype=torch.float64, device=gram_true.device)
+        if status is None:
+            status = torch.empty(batch.n_drops, dtype=torch.int32, device=gram_true.device)
+        self._check(_lib.xlmimo_zf_mmse_sumrate(self.h, C.byref(batch.struct), _ptr(gram_true), _ptr(gram_filter),
+                                                n_snr, _ptr(rho.contiguous()), schemes, _ptr(out), _ptr(status),
+                                                _stream(stream)), "xlmimo_zf_mmse_sumrate")
+        return out, status
+
+    def capacity_sweep(self, arr, n_list: Sequence[int], batch: Batch, form: int, rho: torch.Tensor,
+                       schemes: int = ZF | MMSE, t_sat: float = 0.9, eps_sat: float = 0.05,
+                       ergodic: Optional[torch.Tensor] = None, sat: Optional[torch.Tensor] = None,
+                       status: Optional[torch.Tensor] = None, stream=None):
+        n_snr = int(rho.shape[0])
+        n_sch = bin(schemes).count("1")
+        dev = batch.pos.device
+        nl = np.ascontiguousarray(n_list, np.int64)
+        if ergodic is None:
+            ergodic = torch.empty((len(nl), n_snr, n_sch), dtype=torch.float64, device=dev)
+        if sat is None:
+            sat = torch.empty(3 + n_snr * n_sch, dtype=torch.float64, device=dev)
+        if status is None:
+            status = torch.empty((len(nl), batch.n_drops), dtype=torch.int32, device=dev)
+        a = make_array(arr)
+        self._check(_lib.xlmimo_capacity_sweep(self.h, C.byref(a), len(nl), nl.ctypes.data_as(C.POINTER(C.c_int64)),
+                                               C.byref(batch.struct), form, n_snr, _ptr(rho.contiguous()), schemes,
+                                               float(t_sat), float(eps_sat), _ptr(ergodic), _ptr(sat), _ptr(status),
+                                               _stream(stream)), "xlmimo_capacity_sweep")
+        return ergodic, sat, status
+
+
+def version() -> str:
+    return _lib.xlmimo_version().decode()
+
+
+# -- harness helper: SNR calibration -----------------------------------------
+
+def reference_gain(arr, ref_distance: float) -> float:
+    """Array gain of a broadside reference user at ``ref_distance``.
+
+    ULA: the N -> infinity limit of the diagonal (free space: lambda / (8 pi x)
+    at half-wavelength spacing, i.e. (lambda/4pi)^2 pi / (d x); PNUSW: eq. (5),
+    2 beta0 / (d x)).  UPA (no finite limit): the panel's own diagonal, taken
+    as the far-field value N (lambda / (4 pi x))^2 (free space) or N beta0 / x^2.
+    """
+    lam, d, x = arr.wavelength, arr.spacing, float(ref_distance)
+    if arr.geometry == ULA:
+        if arr.amp_model == AMP_FREESPACE:
+            return (lam / (4 * np.pi)) ** 2 * np.pi / (d * x)
+        return 2.0 * arr.beta0 / (d * x)
+    n = arr.n_y * arr.n_z
+    if arr.amp_model == AMP_FREESPACE:
+        return n * (lam / (4 * np.pi * x)) ** 2
+    return n * arr.beta0 / (x * x)
+
+
+def rho_for_snr(arr, snr_db: Sequence[float], ref_distance: float, total_users: int, device=0) -> torch.Tensor:
+    """Per-user P/sigma^2 so that the reference user's gain gives the stated SNR (common power)."""
+    g = reference_gain(arr, ref_distance)
+    vals = [10.0 ** (s / 10.0) / g for s in snr_db]
+    return torch.tensor(vals, dtype=torch.float64, device=f"cuda:{device}")[:, None].expand(
+        len(vals), max(total_users, 1)).contiguous()

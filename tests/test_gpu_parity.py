@@ -1,0 +1,285 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (normwise |dG_ij| / sqrt(G_ii G_jj) for Grams):
+  exact FP64    1e-9   the oracle rounds its phase 2 pi r / lambda (<= 7e5 rad) to
+                       ~1e-10 rad; both sides are otherwise FP64
+  exact FP32C   1e-5   the accuracy target of the FP32-compensated form
+  closed form   1e-10 relative per entry (same formulas, FP64 on both sides)
+  rates         1e-9 relative (FP64 Cholesky vs LAPACK inverse)
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import channel as och
+from oracle import closedform as ocf
+from oracle import rates as orates
+from oracle import saturation as osat
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+TOL_FP32C = 1e-5
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2503_18118_amd import xlmimo
+    return xlmimo
+
+
+@pytest.fixture(scope="module")
+def ctx(X):
+    c = X.Context(0)
+    yield c
+    c.close()
+
+
+def _exact_ref(arr, drops, d):
+    a = arr.with_n(int(drops.n_elems[d])) if arr.geometry == W.GEOM_ULA else arr
+    return och.gram_exact(a, drops.users_of(d))
+
+
+def _custom_drops(ns, ks, seed, r=(2.0, 40.0), th=(-70.0, 70.0), z=False):
+    rng = np.random.default_rng(seed)
+    pos = []
+    for k in ks:
+        rr = rng.uniform(*r, k)
+        t = np.deg2rad(rng.uniform(*th, k))
+        zz = rng.uniform(-0.5, 0.5, k) if z else np.zeros(k)
+        pos.append(np.stack([rr * np.cos(t), rr * np.sin(t), zz], axis=-1))
+    return W._pack(ns, ks, np.concatenate(pos))
+
+
+@pytest.mark.parametrize("precision,tol", [("FP64", TOL_FP64), ("FP32C", TOL_FP32C)])
+def test_exact_ragged_ula(X, ctx, precision, tol):
+    # N spans one partial tile up to many tiles with ragged tails; K crosses the
+    # 16-user block boundaries (1, 15, 16, 17, 32, 33, 64).
+    ns = [1, 2, 3, 17, 255, 1000, 4097, 70001, 300, 5000, 4096, 12345]
+    ks = [1, 2, 15, 16, 17, 32, 33, 64, 4, 5, 16, 7]
+    drops = _custom_drops(ns, ks, seed=5)
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    out = ctx.gram_exact(arr, b, getattr(X, precision))
+    torch.cuda.synchronize()
+    g = b.split(out)
+    for d in range(drops.n_drops):
+        ref = _exact_ref(arr, drops, d)
+        err = och.normwise_error(g[d], ref)
+        assert err < tol, (precision, d, ns[d], ks[d], err)
+        # exactly Hermitian with a real diagonal
+        assert np.array_equal(g[d], g[d].conj().T)
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+def test_exact_pnusw_and_3d_users(X, ctx, amp):
+    drops = _custom_drops([700, 2048, 33], [3, 20, 9], seed=6, r=(0.5, 8.0), z=True)
+    arr = W.ula(1, W.LAMBDA_100GHZ, amp)
+    b = X.Batch(drops)
+    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C)):
+        g = b.split(ctx.gram_exact(arr, b, prec))
+        for d in range(drops.n_drops):
+            assert och.normwise_error(g[d], _exact_ref(arr, drops, d)) < tol
+
+
+@pytest.mark.parametrize("ny,nz,k", [(32, 24, 5), (7, 50, 40), (64, 1, 17), (1, 64, 3)])
+def test_exact_upa(X, ctx, ny, nz, k):
+    lam = W.LAMBDA_100GHZ_UPA
+    arr = W.ArraySpec(W.GEOM_UPA, ny, nz, lam / 2, lam)
+    drops = W.cone_drops(np.random.default_rng(ny * 100 + nz), 3, k, ny * nz, (0.3, 5.0), (-60, 60), (-60, 60))
+    b = X.Batch(drops)
+    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C)):
+        g = b.split(ctx.gram_exact(arr, b, prec))
+        for d in range(drops.n_drops):
+            assert och.normwise_error(g[d], och.gram_exact(arr, drops.users_of(d))) < tol
+
+
+def test_exact_deterministic_and_empty(X, ctx):
+    arr, drops, _ = W.plain_fp64(64)
+    b = X.Batch(drops)
+    a1 = ctx.gram_exact(arr, b, X.FP32C).clone()
+    a2 = ctx.gram_exact(arr, b, X.FP32C)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2)
+    empty = X.Batch(drops.subset([]))
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ctx.gram_exact(arr, empty, X.FP32C, out=out)
+    assert torch.count_nonzero(out) == 0
+
+
+def test_invalid_arguments_rejected(X, ctx):
+    arr, drops, _ = W.plain_fp64(2)
+    b = X.Batch(drops)
+    bad = W.ArraySpec(W.GEOM_ULA, 256, 1, -1.0, W.LAMBDA_28GHZ)
+    with pytest.raises(X.XlmimoError, match="spacing"):
+        ctx.gram_exact(bad, b, X.FP32C)
+    bad = W.ArraySpec(W.GEOM_ULA, 256, 1, 0.005, float("nan"))
+    with pytest.raises(X.XlmimoError, match="wavelength"):
+        ctx.gram_exact(bad, b, X.FP64)
+    with pytest.raises(X.XlmimoError, match="precision"):
+        ctx.gram_exact(arr, b, 7)
+    big = W._pack([10], [65], np.ones((65, 3)))
+    with pytest.raises(X.XlmimoError, match="K = 65"):
+        ctx.gram_exact(arr, X.Batch(big), X.FP64)
+    zero_n = W._pack([0], [2], np.ones((2, 3)))
+    with pytest.raises(X.XlmimoError, match="N = 0"):
+        ctx.gram_exact(arr, X.Batch(zero_n), X.FP64)
+
+
+@pytest.mark.parametrize("geom,amp", [(W.GEOM_ULA, W.AMP_FREESPACE), (W.GEOM_ULA, W.AMP_PNUSW),
+                                      (W.GEOM_UPA, W.AMP_FREESPACE), (W.GEOM_UPA, W.AMP_PNUSW)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_closedform(X, ctx, geom, amp, variant):
+    if geom == W.GEOM_ULA:
+        arr = W.ula(1, W.LAMBDA_100GHZ, amp)
+        drops = _custom_drops([256, 4096, 65536, 262144, 1000], [4, 16, 33, 64, 2], seed=7, r=(0.8, 20.0))
+    else:
+        lam = W.LAMBDA_100GHZ_UPA
+        arr = W.ArraySpec(W.GEOM_UPA, 512, 384, lam / 2, lam, amp)
+        drops = W.cone_drops(np.random.default_rng(8), 3, 12, 512 * 384, (0.5, 10.0), (-60, 60), (-60, 60))
+    b = X.Batch(drops)
+    out, status = ctx.gram_closedform(arr, b, variant)
+    torch.cuda.synchronize()
+    g = b.split(out)
+    for d in range(drops.n_drops):
+        n = int(drops.n_elems[d]) if geom == W.GEOM_ULA else None
+        ref = ocf.gram_closedform(arr, drops.users_of(d), n, variant)
+        scale = np.sqrt(np.outer(np.abs(np.diag(ref)), np.abs(np.diag(ref))))
+        assert np.all(np.abs(g[d] - ref) <= 1e-10 * np.maximum(np.abs(ref), 1e-6 * scale)), d
+    assert torch.all(status == 0)
+
+
+def test_closedform_bad_and_degenerate_inputs(X, ctx):
+    arr = W.ula(1024, W.LAMBDA_28GHZ)
+    pos = np.array([[0.0, 1.0, 0.0], [3.0, 1.0, 0.0],      # user on the array line
+                    [3.0, 0.5, 0.0], [3.0, -0.5, 0.0]])    # equal x: degenerate pair
+    drops = W._pack([1024, 1024], [2, 2], pos)
+    b = X.Batch(drops)
+    out, status = ctx.gram_closedform(arr, b, X.CF_PAPER)
+    st = status.cpu().numpy()
+    assert st[0] & X.ST_BAD_INPUT
+    assert st[1] & X.ST_CF_DEGENERATE and not st[1] & X.ST_BAD_INPUT
+    g = b.split(out)
+    assert g[1][0, 1] == 0 and g[1][0, 0] > 0
+
+
+def _rho_host(X, rho):
+    return rho.cpu().numpy()
+
+
+@pytest.mark.parametrize("kset", [[1, 2, 4], [16, 16, 3], [33, 64, 20]])
+def test_rates_all_schemes(X, ctx, kset):
+    rng = np.random.default_rng(sum(kset))
+    ns = [max(4 * k, 300) for k in kset]
+    drops = _custom_drops(ns, kset, seed=int(sum(kset)), r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    # a Hermitian positive-definite filter Gram: the true one, perturbed
+    gh = b.split(g)
+    filt = []
+    for d, m in enumerate(gh):
+        e = rng.normal(size=m.shape) + 1j * rng.normal(size=m.shape)
+        filt.append(m + 0.02 * np.abs(m).max() / len(m) * (e + e.conj().T))
+    gf = torch.as_tensor(np.concatenate([f.ravel() for f in filt]).view(np.float64), device="cuda")
+    rho = torch.as_tensor(rng.uniform(0.5, 2.0, (2, b.total_users)) * 1e4 / np.mean([np.real(np.diag(m)).mean() for m in gh]),
+                          device="cuda")
+    schemes = X.ZF | X.MMSE | X.MRC | X.CAP | X.MZF | X.MZF_MISM
+    rates, status = ctx.sumrate(b, g, rho, schemes, gram_filter=gf)
+    torch.cuda.synchronize()
+    rates = rates.cpu().numpy()
+    rh = rho.cpu().numpy()
+    assert torch.all(status == 0)
+    order = [orates.SCHEME_ZF, orates.SCHEME_MMSE, orates.SCHEME_MRC, orates.SCHEME_CAP, orates.SCHEME_MZF,
+             orates.SCHEME_MZF_MISMATCH]
+    for d in range(drops.n_drops):
+        for s in range(2):
+            rk = rh[s, drops.user_off[d]:drops.user_off[d + 1]]
+            ref = orates.rates(gh[d], rk, sum(order), g_filter=filt[d])
+            for c, key in enumerate(order):
+                assert rates[d, s, c] == pytest.approx(ref[key], rel=1e-9), (d, s, key)
+
+
+def test_rates_not_pd_flagged(X, ctx):
+    k = 3
+    m = np.ones((k, k), np.complex128)   # rank one: not positive definite
+    drops = W._pack([10], [k], np.ones((k, 3)))
+    b = X.Batch(drops)
+    g = torch.as_tensor(m.ravel().view(np.float64), device="cuda")
+    rho = torch.ones((1, k), dtype=torch.float64, device="cuda")
+    rates, status = ctx.sumrate(b, g, rho, X.ZF | X.MMSE)
+    r = rates.cpu().numpy()
+    assert status.item() & X.ST_G_NOT_PD and not status.item() & X.ST_MMSE_NOT_PD
+    assert math.isnan(r[0, 0, 0]) and np.isfinite(r[0, 0, 1])
+
+
+def test_capacity_sweep_small(X, ctx):
+    arr = W.ula(4096, W.LAMBDA_28GHZ)
+    drops = W.polar_drops(W.rng_for(1), 40, 8, 4096, (5.0, 50.0), (-60.0, 60.0))
+    b = X.Batch(drops)
+    n_list = [64, 256, 1024, 4096]
+    rho = X.rho_for_snr(arr, (0.0, 20.0), 27.5, b.total_users)
+    schemes = X.ZF | X.MMSE
+    for form in (X.FORM_EXACT_FP64, X.FORM_EXACT_FP32C):
+        erg, sat, status = ctx.capacity_sweep(arr, n_list, b, form, rho, schemes, t_sat=0.9, eps_sat=0.05)
+        torch.cuda.synchronize()
+        erg = erg.cpu().numpy()
+        sat = sat.cpu().numpy()
+        rh = rho.cpu().numpy()
+        ref = np.zeros((len(n_list), 2, 2))
+        for i, n in enumerate(n_list):
+            a = arr.with_n(n)
+            for d in range(drops.n_drops):
+                gg = och.gram_exact(a, drops.users_of(d))
+                for s in range(2):
+                    rr = orates.rates(gg, rh[s, drops.user_off[d]:drops.user_off[d + 1]])
+                    ref[i, s, 0] += rr[orates.SCHEME_ZF] / drops.n_drops
+                    ref[i, s, 1] += rr[orates.SCHEME_MMSE] / drops.n_drops
+        tol = 1e-9 if form == X.FORM_EXACT_FP64 else 1e-4
+        assert np.allclose(erg, ref, rtol=tol), (form, np.max(np.abs(erg / ref - 1)))
+        up, dn = zip(*[osat.y_bounds_eq15_16(np.hypot(u[:, 0], u[:, 2]), u[:, 1], 0.9)
+                       for u in (drops.users_of(d) for d in range(drops.n_drops))])
+        assert sat[0] == pytest.approx(np.mean(up), rel=1e-12)
+        assert sat[1] == pytest.approx(np.mean(dn), rel=1e-12)
+        assert sat[2] == pytest.approx(osat.saturation_m(np.mean(up), np.mean(dn), arr.spacing), rel=1e-12)
+        for s in range(2):
+            for c in range(2):
+                want = osat.empirical_saturation(n_list, ref[:, s, c], 0.05)
+                assert sat[3 + s * 2 + c] == pytest.approx(want, rel=1e-3)
+
+
+@pytest.mark.slow
+def test_full_size_sweep_samples(X, ctx):
+    # The sweep workload at N = 262144, K = 16, all 10^4 drops in one launch;
+    # the oracle checks a sample of drops one by one.
+    arr, drops, meta = W.sweep()
+    b = X.Batch(drops, use_n_elems=True)
+    g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    for d in (0, 4999, 9999):
+        ref = och.gram_exact(arr, drops.users_of(d))
+        assert och.normwise_error(g[d], ref) < TOL_FP32C
+
+
+@pytest.mark.slow
+def test_full_size_upa_samples(X, ctx):
+    arr, drops, meta = W.upa(n_drops=64)
+    b = X.Batch(drops)
+    g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    for d in (0, 63):
+        ref = och.gram_exact(arr, drops.users_of(d), chunk=1 << 15)
+        assert och.normwise_error(g[d], ref) < TOL_FP32C
+
+
+@pytest.mark.slow
+def test_uneven_batch_samples(X, ctx):
+    arr, drops, meta = W.uneven()
+    b = X.Batch(drops)
+    g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    for d in (0, 1, 2047, 4095):
+        ref = _exact_ref(arr, drops, d)
+        assert och.normwise_error(g[d], ref) < TOL_FP32C
