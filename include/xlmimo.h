@@ -121,6 +121,16 @@ int         xlmimo_ctx_destroy(xlmimo_ctx* ctx);
 const char* xlmimo_last_error(const xlmimo_ctx* ctx);
 const char* xlmimo_version(void);
 
+/* Benchmark timing of the exact-Gram main kernel (not part of the method).
+ * While enabled, every exact-Gram launch of this context (also those made by
+ * xlmimo_capacity_sweep) is bracketed by a pair of hipEvents recorded on its
+ * launch stream.  xlmimo_timing_read waits for the recorded events, returns
+ * the summed kernel time in ms and the number of launches, and clears the
+ * record.  Events are created on demand and reused; enabling or disabling
+ * clears the record. */
+int xlmimo_timing_enable(xlmimo_ctx* ctx, int on);
+int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
+
 /* Exact Gram G = H^H H (Sec. III: G_ii = P_i / P, rho_ij = G_ij / sqrt(G_ii G_jj);
  * Sec. V-B: the inner products the paper accelerates).  H is generated on the
  * fly from the geometry and user positions and never stored.

@@ -16,7 +16,9 @@ SOURCES = ["api.cpp", "gram_exact.hip", "gram_closedform.hip", "rates.hip", "swe
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          # no packed FP32 (v_pk_*_f32) instructions in any kernel
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in VGPRs (no AGPR copies around loop-carried sums)
+         "-mllvm", "--amdgpu-mfma-vgpr-form"]
 
 
 def _hipcc():

@@ -49,6 +49,10 @@ struct xlmimo_ctx {
   DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist;
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
   std::unordered_map<uint64_t, Plan> plans;
+  // kernel timing (xlmimo_timing_enable / xlmimo_timing_read)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -164,6 +168,7 @@ int64_t chunk_length(int64_t total_elems, int grid) {
 int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override, Plan** out) {
   uint64_t h = 1469598103934665603ULL;
   h = fnv(h, &a->geometry, sizeof(a->geometry));
+  h = fnv(h, &a->amp_model, sizeof(a->amp_model));
   h = fnv(h, &a->n_y, sizeof(a->n_y));
   h = fnv(h, &a->n_z, sizeof(a->n_z));
   h = fnv(h, &b->n_drops, sizeof(b->n_drops));
@@ -207,8 +212,8 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   }
   p.total_users = uoff;
   p.gram_elems = goff;
-  p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, 1 << 30);
-  p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, 1 << 30);
+  p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
+  p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
   const int64_t ch = chunk_length(total_elems, std::min(p.grid_fp32, p.grid_fp64));
   std::vector<ItemK> items;
   std::vector<int64_t> cost;
@@ -273,8 +278,19 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s);
   if (rc) return rc;
   const int grid = std::min(precision == XLMIMO_FP64 ? p->grid_fp64 : p->grid_fp32, std::max(p->n_items, 1));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->timing) {
+    while (c->ev_pool.size() < c->ev_used + 2) {
+      hipEvent_t e;
+      HIP_TRY(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+    ev0 = c->ev_pool[c->ev_used];
+    ev1 = c->ev_pool[c->ev_used + 1];
+    c->ev_used += 2;
+  }
   HIP_TRY(c, launch_gram_exact(precision, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
-                               p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s));
+                               p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, ev0, ev1));
   return XLMIMO_OK;
 }
 
@@ -336,11 +352,36 @@ int xlmimo_ctx_destroy(xlmimo_ctx* c) {
     if (b->p) (void)hipFree(b->p);
   (void)hipFree(c->d_counter);
   (void)hipFree(c->d_gl);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return XLMIMO_OK;
 }
 
 const char* xlmimo_last_error(const xlmimo_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int xlmimo_timing_enable(xlmimo_ctx* c, int on) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->timing = on != 0;
+  c->ev_used = 0;
+  return XLMIMO_OK;
+}
+
+int xlmimo_timing_read(xlmimo_ctx* c, double* total_ms, int64_t* n_launches) {
+  if (!c || !total_ms || !n_launches) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    HIP_TRY(c, hipEventSynchronize(c->ev_pool[i + 1]));
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *n_launches = (int64_t)(c->ev_used / 2);
+  c->ev_used = 0;
+  return XLMIMO_OK;
+}
 
 int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,
                       double* gram_out, void* stream) {

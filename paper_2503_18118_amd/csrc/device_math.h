@@ -14,6 +14,11 @@
 //    (coefficients (2 pi)^n / n! evaluated at compile time).  Truncation
 //    error: FP32 (sin to t^9, cos to t^10) < 2e-9; FP64 (sin to t^17, cos to
 //    t^18) < 1e-19.
+//  * sincos_quarter: sin(pi t / 2), cos(pi t / 2) for |t| <= 1/2 (the same
+//    angles, with t in quarter turns), coefficients (pi/2)^n / n!.
+//  * sincos_half: sin(pi t), cos(pi t) for |t| <= 1/2 (t in half turns),
+//    coefficients pi^n / n!.  Truncation error: FP32 (sin to t^13, cos to t^12)
+//    < 7e-9; FP64 (sin to t^21, cos to t^22) < 1e-17.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,13 +31,18 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kTwoPi = 6.28318530717958647692528676655900577;
 
-constexpr double taylor_coef(int n) {
-  // (2 pi)^n / n! with the alternating sign of sin (odd n) / cos (even n) series
+constexpr double kHalfPi = 1.57079632679489661923132169163975144;
+
+constexpr double taylor_coef_w(int n, double w) {
+  // w^n / n! with the alternating sign of the sin (odd n) / cos (even n) series
   double v = 1.0;
-  for (int i = 1; i <= n; ++i) v *= kTwoPi / i;
+  for (int i = 1; i <= n; ++i) v *= w / i;
   const int k = n / 2;
   return (k % 2) ? -v : v;
 }
+constexpr double taylor_coef(int n) { return taylor_coef_w(n, kTwoPi); }
+constexpr double quarter_coef(int n) { return taylor_coef_w(n, kHalfPi); }
+constexpr double half_coef(int n) { return taylor_coef_w(n, 2.0 * kHalfPi); }
 
 __device__ __forceinline__ double rsqrt_nr1(double r2) {
   double y = (double)__builtin_amdgcn_rsqf((float)r2);
@@ -78,6 +88,59 @@ __device__ __forceinline__ void sincos_rev(double t, double& s, double& c) {
   double pc = taylor_coef(18);
 #pragma unroll
   for (int n = 16; n >= 2; n -= 2) pc = fma(pc, t2, taylor_coef(n));
+  c = fma(pc, t2, 1.0);
+}
+
+__device__ __forceinline__ void sincos_quarter(float t, float& s, float& c) {
+  const float t2 = t * t;
+  float ps = (float)quarter_coef(9);
+  ps = fmaf(ps, t2, (float)quarter_coef(7));
+  ps = fmaf(ps, t2, (float)quarter_coef(5));
+  ps = fmaf(ps, t2, (float)quarter_coef(3));
+  ps = fmaf(ps, t2, (float)quarter_coef(1));
+  s = ps * t;
+  float pc = (float)quarter_coef(10);
+  pc = fmaf(pc, t2, (float)quarter_coef(8));
+  pc = fmaf(pc, t2, (float)quarter_coef(6));
+  pc = fmaf(pc, t2, (float)quarter_coef(4));
+  pc = fmaf(pc, t2, (float)quarter_coef(2));
+  c = fmaf(pc, t2, 1.0f);
+}
+
+__device__ __forceinline__ void sincos_quarter(double t, double& s, double& c) {
+  const double t2 = t * t;
+  double ps = quarter_coef(17);
+#pragma unroll
+  for (int n = 15; n >= 1; n -= 2) ps = fma(ps, t2, quarter_coef(n));
+  s = ps * t;
+  double pc = quarter_coef(18);
+#pragma unroll
+  for (int n = 16; n >= 2; n -= 2) pc = fma(pc, t2, quarter_coef(n));
+  c = fma(pc, t2, 1.0);
+}
+
+// sin(pi t), cos(pi t), |t| <= 1/2; `neg_sin` returns -sin(pi t) (sign folded into the coefficients).
+__device__ __forceinline__ void sincos_half(float t, float& ns, float& c) {
+  const float t2 = t * t;
+  float ps = (float)-half_coef(13);
+#pragma unroll
+  for (int n = 11; n >= 1; n -= 2) ps = fmaf(ps, t2, (float)-half_coef(n));
+  ns = ps * t;
+  float pc = (float)half_coef(12);
+#pragma unroll
+  for (int n = 10; n >= 2; n -= 2) pc = fmaf(pc, t2, (float)half_coef(n));
+  c = fmaf(pc, t2, 1.0f);
+}
+
+__device__ __forceinline__ void sincos_half(double t, double& ns, double& c) {
+  const double t2 = t * t;
+  double ps = -half_coef(21);
+#pragma unroll
+  for (int n = 19; n >= 1; n -= 2) ps = fma(ps, t2, -half_coef(n));
+  ns = ps * t;
+  double pc = half_coef(22);
+#pragma unroll
+  for (int n = 20; n >= 2; n -= 2) pc = fma(pc, t2, half_coef(n));
   c = fma(pc, t2, 1.0);
 }
 

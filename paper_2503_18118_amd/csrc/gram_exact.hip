@@ -19,13 +19,21 @@
 //   Im G_ij = X_ij - X_ji                          (applied in the finalize pass)
 //   i.e. 3 MFMA per 4 elements for K <= 16.
 //
+// Channel entry (one lane, one user, one element), coordinates in units of
+// lambda / 2 so that the distance r is the phase in half turns:
+//   r^2 = (y_u - y_e)^2 (+ (z_u - z_e)^2) + x_u^2                 FP64
+//   y0 = rsq(r^2) in FP32 (~1 ulp); r = r^2 y0 refined by one Newton step in
+//   FP64 (relative error ~1e-14; the FP64 form refines 1/r to FP64 first)
+//   q = nearest integer to r, t = r - q in [-1/2, 1/2]:  phase = pi (q + t)
+//   sin, cos of pi t by Taylor series (device_math.h); odd q flips the sign;
+//   amplitude 1/r (FREESPACE) or r^{-3/2} (PNUSW) from y0; the remaining
+//   constants are applied in FP64 in the finalize pass.
+//
 // Precision
-//   FP32C: distance and phase reduction in FP64 (device_math.h), sin/cos and
-//   amplitude in FP32, FP32 MFMA partial sums flushed to FP64 every
-//   kFlushRounds rounds (256 elements per wave), FP64 across waves and items.
+//   FP32C: distance and phase reduction in FP64, sin/cos and amplitude in FP32,
+//   FP32 MFMA partial sums flushed to FP64 every kFlushRounds rounds (256
+//   elements per wave), FP64 across waves and items.
 //   FP64: every step in FP64, FP64 MFMA accumulation.
-//   Amplitude constants are applied in FP64 at the end: FREESPACE lanes carry
-//   1/r (scale (lambda/4pi)^2), PNUSW lanes carry r^{-3/2} (scale beta0 sqrt(x_i x_j)).
 //
 // Determinism: every sum has a fixed order (waves in order through LDS, items
 // of a drop in chunk order in the finalize pass), so results are bitwise
@@ -37,9 +45,8 @@
 namespace xl {
 
 struct UserLane {
-  double xp2;   // squared distance from the array line (ULA) or plane (UPA)
+  double xp2;   // squared distance from the array line (ULA) or plane (UPA), (lambda/2) units
   double uy, uz;
-  bool active;
 };
 
 template <typename T>
@@ -59,56 +66,78 @@ struct Mfma<double> {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ void channel_entry(const ArrayK& arr, double ey, double ez, const UserLane& u, bool valid,
-                                              T& re, T& im) {
+// Distances are in units of lambda / 2, so r counts half turns of phase:
+// h = a e^{-j pi r} = a (-1)^q (cos(pi t) - j sin(pi t)),  q = rint(r), t = r - q.
+// Lanes with nothing to contribute (users beyond K, elements past the end)
+// carry a coordinate of 1e30: rsq(inf) = 0 makes their entry exactly zero.
+template <int GEOM, int AMP>
+__device__ __forceinline__ void channel_entry(double ey, double ez, const UserLane& u, float& re, float& im) {
   const double dy = u.uy - ey;
   double r2 = fma(dy, dy, u.xp2);
-  if (arr.geom == XLMIMO_UPA) {
+  if constexpr (GEOM == XLMIMO_UPA) {
     const double dz = u.uz - ez;
     r2 = fma(dz, dz, r2);
   }
-  const double y = (sizeof(T) == 4) ? rsqrt_nr1(r2) : rsqrt_nr2(r2);  // 1 / r
-  double t;
-  int q;
-  reduce_quarter((r2 * y) * arr.inv_lambda, t, q);
-  T s, c;
-  sincos_rev((T)t, s, c);
-  T a = (T)y;
-  if (arr.amp == XLMIMO_AMP_PNUSW) {
-    if constexpr (sizeof(T) == 4) a = a * __builtin_amdgcn_sqrtf(a);
-    else a = a * sqrt(a);
-  }
-  rotate_conj(a, s, c, q, re, im);
-  if (!(valid && u.active)) {
-    re = (T)0;
-    im = (T)0;
-  }
+  const float yf = __builtin_amdgcn_rsqf((float)r2);
+  const double y0 = (double)yf;
+  const double r0 = r2 * y0;
+  const double r = fma(0.5 * y0, fma(-r0, r0, r2), r0);
+  const double qd = __builtin_rint(r);
+  float ns, c;
+  sincos_half((float)(r - qd), ns, c);
+  float a = yf;
+  if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * __builtin_amdgcn_sqrtf(a);
+  a = __int_as_float(__float_as_int(a) ^ ((int)qd << 31));
+  re = a * c;
+  im = a * ns;
 }
 
-template <int NB, typename T>
+template <int GEOM, int AMP>
+__device__ __forceinline__ void channel_entry(double ey, double ez, const UserLane& u, double& re, double& im) {
+  const double dy = u.uy - ey;
+  double r2 = fma(dy, dy, u.xp2);
+  if constexpr (GEOM == XLMIMO_UPA) {
+    const double dz = u.uz - ez;
+    r2 = fma(dz, dz, r2);
+  }
+  const double y = rsqrt_nr2(r2);  // 1 / r to FP64 rounding
+  double r = r2 * y;
+  r = fma(0.5 * y, fma(-r, r, r2), r);
+  const double qd = __builtin_rint(r);
+  double ns, c;
+  sincos_half(r - qd, ns, c);
+  double a = y;
+  if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * sqrt(a);
+  if (((int)qd) & 1) a = -a;
+  re = a * c;
+  im = a * ns;
+}
+
+template <int NB, typename T, int GEOM, int AMP>
 __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it, const double* __restrict__ pos,
                              double* __restrict__ part_out, double* s_red) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NRE = NB * (NB + 1) / 2;
   constexpr int NX = NB * NB;
   constexpr int NV = (NRE + NX) * 4;
+  constexpr bool F32 = sizeof(T) == 4;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const double sc = 2.0 * arr.inv_lambda;  // metres -> half wavelengths
+  constexpr double kFar = 1e30;            // coordinate of a lane that must contribute zero
 
   UserLane u[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int k = 16 * b + (lane & 15);
-    u[b].active = k < dp.k;
-    double x = 1.0, y = 0.0, z = 0.0;
-    if (u[b].active) {
+    double x = kFar, y = 0.0, z = 0.0;
+    if (k < dp.k) {
       const double* p = pos + (dp.user_off + k) * 3;
-      x = p[0];
-      y = p[1];
-      z = p[2];
+      x = p[0] * sc;
+      y = p[1] * sc;
+      z = p[2] * sc;
     }
-    u[b].xp2 = (arr.geom == XLMIMO_ULA) ? fma(x, x, z * z) : x * x;
+    u[b].xp2 = (GEOM == XLMIMO_ULA) ? fma(x, x, z * z) : x * x;
     u[b].uy = y;
     u[b].uz = z;
   }
@@ -118,33 +147,23 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   for (int i = 0; i < NRE; ++i) are[i] = acc_t{0, 0, 0, 0};
 #pragma unroll
   for (int i = 0; i < NX; ++i) ax[i] = acc_t{0, 0, 0, 0};
-  double carry[sizeof(T) == 4 ? NV : 1];
+  double carry[F32 ? NV : 1];
 #pragma unroll
-  for (int i = 0; i < (sizeof(T) == 4 ? NV : 1); ++i) carry[i] = 0.0;
+  for (int i = 0; i < (F32 ? NV : 1); ++i) carry[i] = 0.0;
 
-  const int n_rounds = (it.e_end - it.e_begin + 15) >> 4;
-  int e = it.e_begin + 4 * wave + (lane >> 4);
-  const int ny = (arr.geom == XLMIMO_ULA) ? dp.n_elems : arr.n_y;
-  const double cy = 0.5 * (double)(ny - 1) * arr.spacing;
-  const double cz = 0.5 * (double)(arr.n_z - 1) * arr.spacing;
-  int ea = 0, eb = 0;
-  if (arr.geom == XLMIMO_UPA) {
-    ea = e / arr.n_z;
-    eb = e - ea * arr.n_z;
-  }
+  const int len = it.e_end - it.e_begin;
+  const int n_full = len >> 4;                 // rounds with all 16 elements in range
+  const int n_rounds = (len + 15) >> 4;
+  const int e0 = it.e_begin + 4 * wave + (lane >> 4);
+  const int ny = (GEOM == XLMIMO_ULA) ? dp.n_elems : arr.n_y;
+  const double ds = arr.spacing * sc;
+  const double cy = 0.5 * (double)(ny - 1) * ds;
+  const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
 
-  for (int r = 0; r < n_rounds; ++r) {
-    const bool valid = e < it.e_end;
-    double ey, ez = 0.0;
-    if (arr.geom == XLMIMO_ULA) {
-      ey = fma((double)e, arr.spacing, -cy);
-    } else {
-      ey = fma((double)ea, arr.spacing, -cy);
-      ez = fma((double)eb, arr.spacing, -cz);
-    }
+  auto round = [&](double ey, double ez) {
     T hre[NB], him[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) channel_entry<T>(arr, ey, ez, u[b], valid, hre[b], him[b]);
+    for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP>(ey, ez, u[b], hre[b], him[b]);
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
@@ -159,43 +178,79 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
 #pragma unroll
       for (int bj = 0; bj < NB; ++bj) ax[bi * NB + bj] = Mfma<T>::run(hre[bi], him[bj], ax[bi * NB + bj]);
     }
-    e += 16;
-    if (arr.geom == XLMIMO_UPA) {
-      eb += 16;
-      while (eb >= arr.n_z) {
-        eb -= arr.n_z;
-        ++ea;
+  };
+  auto flush = [&]() {
+    if constexpr (F32) {
+#pragma unroll
+      for (int i = 0; i < NRE; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) carry[i * 4 + c] += (double)are[i][c];
+        are[i] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) carry[(NRE + i) * 4 + c] += (double)ax[i][c];
+        ax[i] = acc_t{0, 0, 0, 0};
       }
     }
-    if constexpr (sizeof(T) == 4) {
-      if (((r + 1) % kFlushRounds) == 0) {
-#pragma unroll
-        for (int i = 0; i < NRE; ++i) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) carry[i * 4 + c] += (double)are[i][c];
-          are[i] = acc_t{0, 0, 0, 0};
+  };
+
+  // Blocks of kFlushRounds rounds: the element coordinate is recomputed exactly
+  // at each block start and advanced by 16 elements per round inside it.
+  for (int r0 = 0; r0 < n_rounds; r0 += kFlushRounds) {
+    const int r1 = min(r0 + kFlushRounds, n_full);
+    const int e = e0 + 16 * r0;
+    if constexpr (GEOM == XLMIMO_ULA) {
+      if constexpr (F32) {
+        // FP32C: advancing ey by 16 d for <= 64 rounds adds < 1e-9 half turns of error
+        double ey = fma((double)e, ds, -cy);
+        const double step = 16.0 * ds;
+        for (int r = r0; r < r1; ++r) {
+          round(ey, 0.0);
+          ey += step;
         }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) carry[(NRE + i) * 4 + c] += (double)ax[i][c];
-          ax[i] = acc_t{0, 0, 0, 0};
+      } else {
+        for (int r = r0; r < r1; ++r) round(fma((double)(e + 16 * (r - r0)), ds, -cy), 0.0);
+      }
+    } else {
+      int ea = e / arr.n_z, eb = e - (e / arr.n_z) * arr.n_z;
+      for (int r = r0; r < r1; ++r) {
+        round(fma((double)ea, ds, -cy), fma((double)eb, ds, -cz));
+        eb += 16;
+        while (eb >= arr.n_z) {
+          eb -= arr.n_z;
+          ++ea;
         }
       }
     }
+    if (r0 + kFlushRounds >= n_rounds && n_rounds > n_full) {
+      // ragged last round: elements past the end take the far coordinate
+      const int et = e0 + 16 * n_full;
+      const bool valid = et < it.e_end;
+      double ey, ez = 0.0;
+      if constexpr (GEOM == XLMIMO_ULA) {
+        ey = fma((double)et, ds, -cy);
+      } else {
+        const int ea = et / arr.n_z;
+        ey = fma((double)ea, ds, -cy);
+        ez = fma((double)(et - ea * arr.n_z), ds, -cz);
+      }
+      round(valid ? ey : kFar, ez);
+    }
+    flush();
   }
 
   double fin[NV];
 #pragma unroll
   for (int i = 0; i < NRE; ++i) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) fin[i * 4 + c] = (double)are[i][c] + (sizeof(T) == 4 ? carry[i * 4 + c] : 0.0);
+    for (int c = 0; c < 4; ++c) fin[i * 4 + c] = F32 ? carry[i * 4 + c] : (double)are[i][c];
   }
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      fin[(NRE + i) * 4 + c] = (double)ax[i][c] + (sizeof(T) == 4 ? carry[(NRE + i) * 4 + c] : 0.0);
+    for (int c = 0; c < 4; ++c) fin[(NRE + i) * 4 + c] = F32 ? carry[(NRE + i) * 4 + c] : (double)ax[i][c];
   }
 
   // Fixed-order reduction over the 4 waves through LDS.
@@ -210,7 +265,7 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   __syncthreads();
 }
 
-template <int NBMAX, typename T>
+template <int NBMAX, typename T, int GEOM, int AMP>
 __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
                                                                const double* __restrict__ pos,
                                                                const ItemK* __restrict__ items, int n_items,
@@ -228,10 +283,10 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
     const DropK dp = drops[it.drop];
     double* out = partials + dp.part_off + it.chunk * (int64_t)(partial_values(dp.nb) * 64);
     switch (dp.nb) {
-      case 1: process_item<1, T>(arr, dp, it, pos, out, s_red); break;
-      case 2: if constexpr (NBMAX >= 2) process_item<2, T>(arr, dp, it, pos, out, s_red); break;
-      case 3: if constexpr (NBMAX >= 3) process_item<3, T>(arr, dp, it, pos, out, s_red); break;
-      case 4: if constexpr (NBMAX >= 4) process_item<4, T>(arr, dp, it, pos, out, s_red); break;
+      case 1: process_item<1, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+      case 2: if constexpr (NBMAX >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+      case 3: if constexpr (NBMAX >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+      case 4: if constexpr (NBMAX >= 4) process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
       default: break;
     }
   }
@@ -263,6 +318,7 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
   const int NRE = NB * (NB + 1) / 2;
   const int64_t PV = partial_values(NB) * 64;
   const double* base = partials + dp.part_off;
+  constexpr double kPi = 3.14159265358979323846264338327950288;
   for (int idx = threadIdx.x; idx < K * K; idx += blockDim.x) {
     const int i = idx / K, j = idx - (idx / K) * K;
     const int p = i < j ? i : j, q = i < j ? j : i;  // canonical p <= q
@@ -278,16 +334,17 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
       xqp += pc[s_xqp];
     }
     double im = (p == q) ? 0.0 : xpq - xqp;
+    // Lanes carried 1/r' (or r'^{-3/2}) with r' = 2 r / lambda.
     double scale;
     if (arr.amp == XLMIMO_AMP_FREESPACE) {
-      const double c0 = arr.lambda / (4.0 * 3.14159265358979323846264338327950288);
-      scale = c0 * c0;
+      scale = 0.25 / (kPi * kPi);  // (lambda / 4 pi)^2 (2 / lambda)^2
     } else {
       const double* up = pos + (dp.user_off + p) * 3;
       const double* uq = pos + (dp.user_off + q) * 3;
       const double xp = (arr.geom == XLMIMO_ULA) ? sqrt(fma(up[0], up[0], up[2] * up[2])) : fabs(up[0]);
       const double xq = (arr.geom == XLMIMO_ULA) ? sqrt(fma(uq[0], uq[0], uq[2] * uq[2])) : fabs(uq[0]);
-      scale = arr.beta0 * sqrt(xp * xq);
+      const double s2 = 2.0 * arr.inv_lambda;
+      scale = arr.beta0 * sqrt(xp * xq) * s2 * s2 * s2;
     }
     if (i > j) im = -im;  // G_ji = conj(G_ij)
     gram[(dp.gram_off + idx) * 2] = re * scale;
@@ -295,41 +352,83 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
   }
 }
 
-template <int NBMAX, typename T>
-static int grid_for() {
+template <int NBMAX, typename T, int GEOM, int AMP>
+static int occupancy_grid() {
   static int cached = 0;
   if (!cached) {
     int dev = 0, n_cu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gram_exact<NBMAX, T>, kGramThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gram_exact<NBMAX, T, GEOM, AMP>, kGramThreads, 0);
     cached = (n_cu > 0 ? n_cu : 256) * (per_cu > 0 ? per_cu : 1);
   }
   return cached;
 }
 
-int gram_exact_grid(int precision, int nb_max, int n_items) {
-  int g;
-  if (precision == XLMIMO_FP64) g = nb_max <= 2 ? grid_for<2, double>() : grid_for<4, double>();
-  else g = nb_max <= 2 ? grid_for<2, float>() : grid_for<4, float>();
-  return n_items < g ? n_items : g;
+template <typename T, int GEOM, int AMP>
+static int grid_nb(int nb_max) {
+  return nb_max <= 1 ? occupancy_grid<1, T, GEOM, AMP>()
+                     : (nb_max <= 2 ? occupancy_grid<2, T, GEOM, AMP>() : occupancy_grid<4, T, GEOM, AMP>());
+}
+
+template <typename T>
+static int grid_t(int nb_max, int geom, int amp) {
+  if (geom == XLMIMO_ULA)
+    return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE>(nb_max)
+                                       : grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW>(nb_max);
+  return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE>(nb_max)
+                                     : grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW>(nb_max);
+}
+
+int gram_exact_grid(int precision, int nb_max, int geom, int amp) {
+  return precision == XLMIMO_FP64 ? grid_t<double>(nb_max, geom, amp) : grid_t<float>(nb_max, geom, amp);
+}
+
+struct MainArgs {
+  ArrayK arr;
+  const DropK* drops;
+  const double* pos;
+  const ItemK* items;
+  int n_items;
+  int* counter;
+  double* partials;
+};
+
+template <typename T, int GEOM, int AMP>
+static void launch_main(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
+  if (nb_max <= 1)
+    k_gram_exact<1, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+  else if (nb_max <= 2)
+    k_gram_exact<2, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+  else
+    k_gram_exact<4, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+}
+
+template <typename T>
+static void launch_t(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
+  if (a.arr.geom == XLMIMO_ULA) {
+    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE>(nb_max, grid, s, a);
+    else launch_main<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW>(nb_max, grid, s, a);
+  } else {
+    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE>(nb_max, grid, s, a);
+    else launch_main<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW>(nb_max, grid, s, a);
+  }
 }
 
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
-                             double* d_partials, double* d_gram, int grid, hipStream_t s) {
+                             double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
   if (n_drops == 0) return hipSuccess;
   k_reset_counter<<<1, 64, 0, s>>>(d_counter);
   if (grid < 1) grid = 1;
-  if (precision == XLMIMO_FP64) {
-    if (nb_max <= 2) k_gram_exact<2, double><<<grid, kGramThreads, 0, s>>>(arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials);
-    else k_gram_exact<4, double><<<grid, kGramThreads, 0, s>>>(arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials);
-    k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
-  } else {
-    if (nb_max <= 2) k_gram_exact<2, float><<<grid, kGramThreads, 0, s>>>(arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials);
-    else k_gram_exact<4, float><<<grid, kGramThreads, 0, s>>>(arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials);
-    k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
-  }
+  const MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials};
+  if (ev0) (void)hipEventRecord(ev0, s);
+  if (precision == XLMIMO_FP64) launch_t<double>(nb_max, grid, s, a);
+  else launch_t<float>(nb_max, grid, s, a);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  if (precision == XLMIMO_FP64) k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
+  else k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
   return hipGetLastError();
 }
 

@@ -50,8 +50,9 @@ constexpr int kFlushRounds = 64;      // FP32 MFMA partial sums are carried to F
 // Launchers (stream-ordered, no host synchronisation).
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
-                             double* d_partials, double* d_gram, int grid, hipStream_t s);
-int gram_exact_grid(int precision, int nb_max, int n_items);
+                             double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+int gram_exact_grid(int precision, int nb_max, int geom, int amp);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
                              const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,

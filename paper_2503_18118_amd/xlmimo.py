@@ -28,7 +28,7 @@ MAX_USERS = 64
 
 EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlmimo_version",
             "xlmimo_gram_exact", "xlmimo_gram_closedform", "xlmimo_zf_mmse_sumrate",
-            "xlmimo_capacity_sweep")
+            "xlmimo_capacity_sweep", "xlmimo_timing_enable", "xlmimo_timing_read")
 
 
 class XlArray(C.Structure):
@@ -57,6 +57,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_zf_mmse_sumrate.argtypes = [vp, C.POINTER(XlBatch), vp, vp, i32, vp, i32, vp, vp, vp]
     lib.xlmimo_capacity_sweep.argtypes = [vp, C.POINTER(XlArray), i32, C.POINTER(C.c_int64), C.POINTER(XlBatch),
                                           i32, i32, vp, i32, C.c_double, C.c_double, vp, vp, vp, vp]
+    lib.xlmimo_timing_enable.argtypes = [vp, C.c_int]
+    lib.xlmimo_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     return lib
 
 
@@ -140,6 +142,15 @@ class Context:
         if rc != OK:
             msg = _lib.xlmimo_last_error(self.h)
             raise XlmimoError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    # -- benchmark timing of the exact-Gram kernel ----------------------------
+    def timing_enable(self, on: bool = True):
+        self._check(_lib.xlmimo_timing_enable(self.h, 1 if on else 0), "xlmimo_timing_enable")
+
+    def timing_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(_lib.xlmimo_timing_read(self.h, C.byref(ms), C.byref(n)), "xlmimo_timing_read")
+        return ms.value, n.value
 
     # -- entry points ------------------------------------------------------
     def gram_exact(self, arr, batch: Batch, precision: int = FP32C, out: Optional[torch.Tensor] = None,
