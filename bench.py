@@ -36,6 +36,20 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
 #   per unique user pair and element: conj(h_i) h_j complex multiply-add      = 8
 FLOP_PER_ENTRY_EVAL = 11
 FLOP_PER_PAIR_MAC = 8
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gram_exact_fp32c_sweep_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_18118_amd", "csrc", f) for f in ("gram_exact.hip", "device_math.h")]
+
+
+def traffic_per_launch():
+    """HBM bytes per exact-Gram launch from the committed counter record, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    return rec["bytes_per_launch"] if rec.get("kernel_source_sha256") == h else None
 
 
 def parse():
@@ -46,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
 
 
@@ -143,7 +159,7 @@ def main():
     flops_per_step = FLOP_PER_ENTRY_EVAL * evals + FLOP_PER_PAIR_MAC * pair_macs
     achieved = flops_per_step * args.steps / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic_per_launch(),
                 "kernel": "k_gram_exact<1,float> (exact Gram, FP32C)",
                 "launches": n_launch, "avg_launch_ms": kern_ms / max(n_launch, 1),
                 "entry_evals_per_s": evals * args.steps / (kern_ms * 1e-3),
@@ -161,6 +177,12 @@ def main():
                                           "ms": t_cf / args.steps}},
            "roofline": roofline}
 
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 256 << 20
     if not args.no_accuracy:
         out["accuracy"] = accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, out["forms"])
     if not args.no_cpu_baseline:

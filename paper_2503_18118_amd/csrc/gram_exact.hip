@@ -19,13 +19,13 @@
 //   Im G_ij = X_ij - X_ji                          (applied in the finalize pass)
 //   i.e. 3 MFMA per 4 elements for K <= 16.
 //
-// Channel entry (one lane, one user, one element), coordinates in units of
-// lambda / 2 so that the distance r is the phase in half turns:
+// Channel entry (one lane, one user, one element), coordinates scaled so that
+// the distance r is the phase in turns (FP32C) or half turns (FP64):
 //   r^2 = (y_u - y_e)^2 (+ (z_u - z_e)^2) + x_u^2                 FP64
 //   y0 = rsq(r^2) in FP32 (~1 ulp); r = r^2 y0 refined by one Newton step in
 //   FP64 (relative error ~1e-14; the FP64 form refines 1/r to FP64 first)
-//   q = nearest integer to r, t = r - q in [-1/2, 1/2]:  phase = pi (q + t)
-//   sin, cos of pi t by Taylor series (device_math.h); odd q flips the sign;
+//   FP32C: r in wavelengths, phase = 2 pi fract(r), hardware sin/cos of turns;
+//   FP64:  r in half wavelengths, phase = pi (q + t), q = rint(r), Taylor sin/cos
 //   amplitude 1/r (FREESPACE) or r^{-3/2} (PNUSW) from y0; the remaining
 //   constants are applied in FP64 in the finalize pass.
 //
@@ -66,40 +66,33 @@ struct Mfma<double> {
   }
 };
 
-// Distances are in units of lambda / 2, so r counts half turns of phase:
-// h = a e^{-j pi r} = a (-1)^q (cos(pi t) - j sin(pi t)),  q = rint(r), t = r - q.
-// Lanes with nothing to contribute (users beyond K, elements past the end)
-// carry a coordinate of 1e30: rsq(inf) = 0 makes their entry exactly zero.
+// FP32C: distances are in units of lambda, so r counts whole turns of phase:
+// h = a e^{-j 2 pi r} = a (cos(2 pi t) - j sin(2 pi t)),  t = fract(r) (v_fract_f64, exact),
+// with the hardware v_sin_f32 / v_cos_f32, which take revolutions (measured on
+// gfx950: |error| <= 1.3e-7 over a full turn).  Lanes with nothing to contribute
+// (users beyond K, elements past the end) carry a coordinate of 1e30:
+// rsq(inf) = 0 makes their entry exactly zero.
 template <int GEOM, int AMP>
-__device__ __forceinline__ void channel_entry(double ey, double ez, const UserLane& u, float& re, float& im) {
-  const double dy = u.uy - ey;
-  double r2 = fma(dy, dy, u.xp2);
-  if constexpr (GEOM == XLMIMO_UPA) {
-    const double dz = u.uz - ez;
-    r2 = fma(dz, dz, r2);
-  }
+__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im) {
+  double r2 = fma(dy, dy, xp2);
+  if constexpr (GEOM == XLMIMO_UPA) r2 = fma(dz, dz, r2);
   const float yf = __builtin_amdgcn_rsqf((float)r2);
   const double y0 = (double)yf;
   const double r0 = r2 * y0;
   const double r = fma(0.5 * y0, fma(-r0, r0, r2), r0);
-  const double qd = __builtin_rint(r);
-  float ns, c;
-  sincos_half((float)(r - qd), ns, c);
+  const float t = (float)__builtin_amdgcn_fract(r);
   float a = yf;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * __builtin_amdgcn_sqrtf(a);
-  a = __int_as_float(__float_as_int(a) ^ ((int)qd << 31));
-  re = a * c;
-  im = a * ns;
+  re = a * __builtin_amdgcn_cosf(t);
+  im = -a * __builtin_amdgcn_sinf(t);
 }
 
+// FP64: distances in units of lambda / 2 (r counts half turns),
+// h = a (-1)^q (cos(pi t) - j sin(pi t)), q = rint(r), t = r - q, Taylor sin/cos.
 template <int GEOM, int AMP>
-__device__ __forceinline__ void channel_entry(double ey, double ez, const UserLane& u, double& re, double& im) {
-  const double dy = u.uy - ey;
-  double r2 = fma(dy, dy, u.xp2);
-  if constexpr (GEOM == XLMIMO_UPA) {
-    const double dz = u.uz - ez;
-    r2 = fma(dz, dz, r2);
-  }
+__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, double& re, double& im) {
+  double r2 = fma(dy, dy, xp2);
+  if constexpr (GEOM == XLMIMO_UPA) r2 = fma(dz, dz, r2);
   const double y = rsqrt_nr2(r2);  // 1 / r to FP64 rounding
   double r = r2 * y;
   r = fma(0.5 * y, fma(-r, r, r2), r);
@@ -123,7 +116,8 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   constexpr bool F32 = sizeof(T) == 4;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const double sc = 2.0 * arr.inv_lambda;  // metres -> half wavelengths
+  // metres -> wavelengths (FP32C, phase in turns) or half wavelengths (FP64, half turns)
+  const double sc = (F32 ? 1.0 : 2.0) * arr.inv_lambda;
   constexpr double kFar = 1e30;            // coordinate of a lane that must contribute zero
 
   UserLane u[NB];
@@ -160,10 +154,10 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   const double cy = 0.5 * (double)(ny - 1) * ds;
   const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
 
-  auto round = [&](double ey, double ez) {
+  auto round = [&](const double* dy, double ez) {
     T hre[NB], him[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP>(ey, ez, u[b], hre[b], him[b]);
+    for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP>(dy[b], u[b].uz - ez, u[b].xp2, hre[b], him[b]);
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
@@ -197,26 +191,38 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   };
 
   // Blocks of kFlushRounds rounds: the element coordinate is recomputed exactly
-  // at each block start and advanced by 16 elements per round inside it.
+  // at each block start.  FP32C advances y_user - y_element by 16 d per round
+  // inside a block (<= 64 additions: < 1e-9 turns of error).
   for (int r0 = 0; r0 < n_rounds; r0 += kFlushRounds) {
     const int r1 = min(r0 + kFlushRounds, n_full);
     const int e = e0 + 16 * r0;
+    double dy[NB];
     if constexpr (GEOM == XLMIMO_ULA) {
+      const double ey = fma((double)e, ds, -cy);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) dy[b] = u[b].uy - ey;
       if constexpr (F32) {
-        // FP32C: advancing ey by 16 d for <= 64 rounds adds < 1e-9 half turns of error
-        double ey = fma((double)e, ds, -cy);
         const double step = 16.0 * ds;
         for (int r = r0; r < r1; ++r) {
-          round(ey, 0.0);
-          ey += step;
+          round(dy, 0.0);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) dy[b] -= step;
         }
       } else {
-        for (int r = r0; r < r1; ++r) round(fma((double)(e + 16 * (r - r0)), ds, -cy), 0.0);
+        for (int r = r0; r < r1; ++r) {
+          const double eyr = fma((double)(e + 16 * (r - r0)), ds, -cy);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) dy[b] = u[b].uy - eyr;
+          round(dy, 0.0);
+        }
       }
     } else {
       int ea = e / arr.n_z, eb = e - (e / arr.n_z) * arr.n_z;
       for (int r = r0; r < r1; ++r) {
-        round(fma((double)ea, ds, -cy), fma((double)eb, ds, -cz));
+        const double eyr = fma((double)ea, ds, -cy);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) dy[b] = u[b].uy - eyr;
+        round(dy, fma((double)eb, ds, -cz));
         eb += 16;
         while (eb >= arr.n_z) {
           eb -= arr.n_z;
@@ -236,7 +242,10 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
         ey = fma((double)ea, ds, -cy);
         ez = fma((double)(et - ea * arr.n_z), ds, -cz);
       }
-      round(valid ? ey : kFar, ez);
+      ey = valid ? ey : kFar;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) dy[b] = u[b].uy - ey;
+      round(dy, ez);
     }
     flush();
   }
@@ -334,17 +343,18 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
       xqp += pc[s_xqp];
     }
     double im = (p == q) ? 0.0 : xpq - xqp;
-    // Lanes carried 1/r' (or r'^{-3/2}) with r' = 2 r / lambda.
+    // Lanes carried 1/r' (or r'^{-3/2}) with r' = su r, su = 1/lambda (FP32C) or 2/lambda (FP64).
+    const double su = (sizeof(T) == 4 ? 1.0 : 2.0) * arr.inv_lambda;
     double scale;
     if (arr.amp == XLMIMO_AMP_FREESPACE) {
-      scale = 0.25 / (kPi * kPi);  // (lambda / 4 pi)^2 (2 / lambda)^2
+      const double c = arr.lambda * su / (4.0 * kPi);  // (lambda / 4 pi)^2 su^2
+      scale = c * c;
     } else {
       const double* up = pos + (dp.user_off + p) * 3;
       const double* uq = pos + (dp.user_off + q) * 3;
       const double xp = (arr.geom == XLMIMO_ULA) ? sqrt(fma(up[0], up[0], up[2] * up[2])) : fabs(up[0]);
       const double xq = (arr.geom == XLMIMO_ULA) ? sqrt(fma(uq[0], uq[0], uq[2] * uq[2])) : fabs(uq[0]);
-      const double s2 = 2.0 * arr.inv_lambda;
-      scale = arr.beta0 * sqrt(xp * xq) * s2 * s2 * s2;
+      scale = arr.beta0 * sqrt(xp * xq) * su * su * su;
     }
     if (i > j) im = -im;  // G_ji = conj(G_ij)
     gram[(dp.gram_off + idx) * 2] = re * scale;
