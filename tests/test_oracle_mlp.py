@@ -1,0 +1,95 @@
+"""Pins of the FP64 MLP reference: finite-difference gradients, GELU's erf form,
+Adam on a quadratic, and the phasor basis against the exact channel phases."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import channel as och
+from oracle import closedform as ocf
+from oracle import mlp as M
+
+
+def _batch(rng, n):
+    x = rng.normal(size=(n, M.N_IN))
+    ph = np.exp(1j * rng.uniform(-math.pi, math.pi, size=(n, 3)))
+    t = 0.05 * (rng.normal(size=n) + 1j * rng.normal(size=n))
+    return x, ph, t
+
+
+def test_gelu_matches_closed_form_values():
+    # GELU(z) = z Phi(z): Phi(1) = 0.841344746..., Phi(-1) = 0.158655253...
+    assert M.gelu(np.array([1.0]))[0] == pytest.approx(0.8413447460685429, rel=1e-14)
+    assert M.gelu(np.array([-1.0]))[0] == pytest.approx(-0.15865525393145707, rel=1e-14)
+    z = np.linspace(-4, 4, 41)
+    h = 1e-6
+    assert np.allclose(M.gelu_grad(z), (M.gelu(z + h) - M.gelu(z - h)) / (2 * h), rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("width,depth", [(8, 2), (16, 4)])
+def test_gradient_matches_finite_differences(width, depth):
+    rng = np.random.default_rng(1)
+    p = M.init_params(rng, width, depth)
+    p[-M.N_OUT:] = rng.normal(size=M.N_OUT) * 0.1   # non-trivial output bias
+    x, ph, t = _batch(rng, 37)
+    loss, g = M.loss_grad(p, x, ph, t, width, depth)
+    idx = rng.choice(p.size, 40, replace=False)
+    for i in idx:
+        e = np.zeros_like(p)
+        h = 1e-6 * max(1.0, abs(p[i]))
+        e[i] = h
+        fd = (M.loss_grad(p + e, x, ph, t, width, depth)[0] - M.loss_grad(p - e, x, ph, t, width, depth)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-9), i
+
+
+def test_adam_converges_on_quadratic():
+    rng = np.random.default_rng(2)
+    target = rng.normal(size=10)
+    w = np.zeros(10)
+    opt = M.Adam(10, lr=0.05)
+    for _ in range(3000):
+        w = opt.step(w, w - target)
+    assert np.allclose(w, target, atol=1e-4)
+    # first step of Adam moves every coordinate by lr (bias-corrected m/sqrt(v) = sign(g))
+    opt = M.Adam(3, lr=0.1)
+    assert np.allclose(opt.step(np.zeros(3), np.array([2.0, -5.0, 0.3])), [-0.1, 0.1, -0.1], atol=1e-6)
+
+
+def test_param_layout():
+    assert M.param_count(256, 4) == 6 * 256 + 256 + 3 * (256 * 256 + 256) + 256 * 7 + 7
+    p = np.arange(M.param_count(4, 2), dtype=float)
+    (w0, b0), (w1, b1), (w2, b2) = M.unpack(p, 4, 2)
+    assert w0.shape == (4, 6) and b0[0] == 24 and w2.shape == (7, 4)
+
+
+def test_phasors_are_exact_end_element_phases():
+    # e^{j phi(y_end)} equals the phase of conj(h_i) h_j at the end elements (channel oracle)
+    lam = W.LAMBDA_28GHZ
+    n = 1000
+    arr = W.ula(n, lam)
+    u = np.array([[7.0, 1.5, 0.0], [12.0, -3.0, 0.0]])
+    h = och.channel_matrix(arr, u)
+    f, ph = M.pair_inputs(7.0, 1.5, 12.0, -3.0, n, arr.spacing, lam)
+    top = h[-1, 0].conj() * h[-1, 1]
+    bot = h[0, 0].conj() * h[0, 1]
+    assert abs(ph[0] - top / abs(top)) < 1e-9
+    assert abs(ph[1] - bot / abs(bot)) < 1e-9
+    # the stationary-point phasor carries the eq. (6) phase before the -pi/4 offset
+    rho = ocf.rho_eq6(7.0, 1.5, 12.0, -3.0, n, lam)
+    assert abs(ph[2] * np.exp(-1j * math.copysign(1, 7.0 - 12.0) * math.pi / 4) - rho / abs(rho)) < 1e-9
+    assert f[4] == pytest.approx(math.log(1000) / math.log(4) - 6)
+
+
+def test_loss_is_minimised_by_the_target():
+    rng = np.random.default_rng(3)
+    x, ph, t = _batch(rng, 50)
+    out = np.zeros((50, 7))
+    # choose c_top so that p = t exactly, and s = log mean |e|^2 -> e = 0 gives loss = s
+    out[:, 0] = (t * ph[:, 0].conj()).real
+    out[:, 1] = (t * ph[:, 0].conj()).imag
+    p, s = M.predict(out, ph)
+    assert np.allclose(p, t)
+    loss, dout = M.loss_and_dout(out, ph, t)
+    assert loss == pytest.approx(0.0)
+    assert np.allclose(dout[:, :6], 0.0)
