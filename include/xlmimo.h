@@ -84,16 +84,25 @@ extern "C" {
 #define XLMIMO_ST_FILTER_NOT_PD 4   /* Cholesky of the filter Gram failed: MZF rates are NaN */
 #define XLMIMO_ST_BAD_INPUT     8   /* non-finite position or a user on the array line/plane */
 #define XLMIMO_ST_CF_DEGENERATE 16  /* closed form hit |x_i| == |x_j| or coincident users (entry set to 0) */
+#define XLMIMO_ST_FELL_BACK     32  /* learned correction was uncertain: the drop's Gram was computed exactly */
 
 /* Capacity-sweep Gram forms. */
 #define XLMIMO_FORM_EXACT_FP64  0
 #define XLMIMO_FORM_EXACT_FP32C 1
 #define XLMIMO_FORM_CF_PAPER    2
 #define XLMIMO_FORM_CF_GATED    3
+#define XLMIMO_FORM_CF_GATED_MLP 4  /* gated closed form + learned residual + exact fallback */
 
 #define XLMIMO_MAX_USERS 64
 
+/* Learned correction: network inputs and outputs per user pair. */
+#define XLMIMO_MLP_IN  6
+#define XLMIMO_MLP_OUT 7
+#define XLMIMO_PAIR_FEAT_PITCH 8   /* bf16 features per pair (6 used) */
+#define XLMIMO_PAIR_AUX_PITCH  8   /* floats per pair: 3 complex phasors, sqrt(G~_ii G~_jj), pad */
+
 typedef struct xlmimo_ctx xlmimo_ctx;
+typedef struct xlmimo_mlp xlmimo_mlp;
 
 /* Receive array and channel model. */
 typedef struct {
@@ -182,16 +191,68 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
  *             ergodic(N) / ergodic(N_max) >= 1 - eps_sat, for SNR s, scheme c.
  * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32C
  * Gram as the true channel; every other scheme uses the chosen form's Gram.
- *   N_list       HOST int64 [n_N], ascending, each >= 1
+ *   form         XLMIMO_FORM_*; XLMIMO_FORM_CF_GATED_MLP needs mlp and log_var_max
+ *                (see xlmimo_gram_closedform_mlp), otherwise mlp may be NULL
+ *   N_list       HOST int64 [n_N], strictly ascending, each >= 1
  *   rho          DEVICE double [n_snr][total_users]
  *   ergodic_out  DEVICE double [n_N][n_snr][n_sch]
  *   sat_out      DEVICE double [3 + n_snr * n_sch]
  *   status_out   DEVICE int32 [n_N][n_drops] or NULL
  * The batch's n_elems is ignored. */
 int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N, const int64_t* N_list,
-                          const xlmimo_batch* batch, int32_t form, int32_t n_snr, const double* rho,
-                          int32_t schemes, double t_sat, double eps_sat,
+                          const xlmimo_batch* batch, int32_t form, xlmimo_mlp* mlp, double log_var_max,
+                          int32_t n_snr, const double* rho, int32_t schemes, double t_sat, double eps_sat,
                           double* ergodic_out, double* sat_out, int32_t* status_out, void* stream);
+
+/* ---- Learned residual correction of the closed form (not in the paper) ----
+ * Per user pair i < j of a ULA drop the network sees
+ *   (r_i/50, theta_i/(pi/3), r_j/50, theta_j/(pi/3), log4 N - 6, d/lambda - 1/2)
+ * (r, theta: polar coordinates of the user about the array centre, theta from
+ * broadside, with x the distance from the array line) and predicts
+ *   delta_rho = sum_m c_m e^{j phi_m},  phi(y) = (2 pi / lambda)(r_i(y) - r_j(y)),
+ * at y = the two end elements and the stationary point (phasors computed in
+ * FP64), plus s = log sigma^2.  Network: XLMIMO_MLP_IN -> [Linear(width) +
+ * GELU] x depth -> Linear(XLMIMO_MLP_OUT); BF16 weights and activations on the
+ * matrix cores, FP32 accumulation; FP32 master weights and Adam state.
+ * Parameters, flat FP32: per layer W (out x in, row-major) then b (out). */
+int     xlmimo_mlp_create(xlmimo_ctx* ctx, int32_t width, int32_t depth, xlmimo_mlp** out);
+int     xlmimo_mlp_destroy(xlmimo_mlp* mlp);
+int64_t xlmimo_mlp_param_count(const xlmimo_mlp* mlp);
+/* HOST float [param_count]; set also resets the Adam state.  Both synchronise the device. */
+int     xlmimo_mlp_set_params(xlmimo_mlp* mlp, const float* host_params);
+int     xlmimo_mlp_get_params(xlmimo_mlp* mlp, float* host_params);
+/* Number of pairs i < j over the batch (host arithmetic, -1 on bad input). */
+int64_t xlmimo_pair_count(const xlmimo_batch* batch);
+
+/* Pair inputs of every drop, pairs drop-major and (i, j) row-major:
+ *   gram_cf     DEVICE closed-form Gram (layout above)
+ *   gram_exact  DEVICE exact Gram, or NULL when no targets are wanted
+ *   features    DEVICE bf16 [n_pairs][XLMIMO_PAIR_FEAT_PITCH]
+ *   aux         DEVICE float [n_pairs][XLMIMO_PAIR_AUX_PITCH]
+ *   target      DEVICE float [n_pairs][2] = rho_exact - rho~ (complex), or NULL
+ *   pair_map    DEVICE int32 [n_pairs][2] = (drop, 64 i + j) */
+int xlmimo_mlp_pair_inputs(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                           const double* gram_cf, const double* gram_exact, void* features, float* aux,
+                           float* target, int32_t* pair_map, void* stream);
+
+/* Mean Gaussian negative log-likelihood over n pairs and its gradient (DEVICE
+ * float [param_count], or NULL to keep it internal); loss_out DEVICE double. */
+int xlmimo_mlp_loss_grad(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
+                         const float* target, float* grad_out, double* loss_out, void* stream);
+/* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the loss above. */
+int xlmimo_mlp_train_step(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
+                          const float* target, float lr, double* loss_out, void* stream);
+/* Network outputs, DEVICE float [n][XLMIMO_MLP_OUT]. */
+int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, float* out,
+                       void* stream);
+
+/* Closed form (variant as in xlmimo_gram_closedform) + learned residual:
+ * G_ij = G~_ij + delta_rho sqrt(G~_ii G~_jj) for every pair.  A drop with any
+ * pair whose predicted log-variance exceeds log_var_max is recomputed with the
+ * exact FP32C Gram and gets XLMIMO_ST_FELL_BACK in status_out (ULA only). */
+int xlmimo_gram_closedform_mlp(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                               int32_t variant, xlmimo_mlp* mlp, double log_var_max, double* gram_out,
+                               int32_t* status_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,7 @@ struct Plan {
   int k_max = 1;
   int64_t total_users = 0;
   int64_t gram_elems = 0;    // complex elements of the whole Gram output
+  int64_t n_pairs = 0;       // user pairs i < j over all drops
   int64_t partial_doubles = 0;
   int grid_fp32 = 0, grid_fp64 = 0;
   DropK* d_drops = nullptr;
@@ -46,7 +47,7 @@ struct xlmimo_ctx {
   int* d_counter = nullptr;
   double* d_gl = nullptr;
   int n_gl = 0;
-  DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist;
+  DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist, scratch_pairs;
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
   std::unordered_map<uint64_t, Plan> plans;
   // kernel timing (xlmimo_timing_enable / xlmimo_timing_read)
@@ -193,7 +194,7 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   Plan p;
   p.n_drops = n;
   std::vector<DropK> drops(n);
-  int64_t uoff = 0, goff = 0, total_elems = 0;
+  int64_t uoff = 0, goff = 0, total_elems = 0, pairs = 0;
   for (int d = 0; d < n; ++d) {
     DropK& dk = drops[d];
     int64_t ne;
@@ -204,6 +205,8 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
     dk.nb = (dk.k + 15) / 16;
     dk.user_off = uoff;
     dk.gram_off = goff;
+    dk.pair_off = pairs;
+    pairs += (int64_t)dk.k * (dk.k - 1) / 2;
     uoff += dk.k;
     goff += (int64_t)dk.k * dk.k;
     total_elems += ne;
@@ -212,6 +215,7 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   }
   p.total_users = uoff;
   p.gram_elems = goff;
+  p.n_pairs = pairs;
   p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
   const int64_t ch = chunk_length(total_elems, std::min(p.grid_fp32, p.grid_fp64));
@@ -308,6 +312,391 @@ int rates_k_max(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 
 }  // namespace
 
+struct xlmimo_mlp {
+  xlmimo_ctx* ctx = nullptr;
+  int width = 0, depth = 0, n_layers = 0;
+  std::vector<int> in_dim, out_dim;
+  std::vector<int64_t> w_off, b_off;
+  int64_t n_params = 0;
+  float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  __bf16* wbf = nullptr;
+  int64_t t = 0;
+  DevBuf act, partial;
+};
+
+namespace {
+
+constexpr int kFeatPitch = 8;   // features per pair (6 used)
+constexpr int kAuxPitch = 8;    // phasors (6), closed-form scale, pad
+constexpr int kOut = 7;
+
+// Activation layout for a batch of n pairs: per hidden layer, the GELU output
+// (bf16, next layer's input) and the pre-activation (fp32); the network output;
+// two bf16 gradient buffers and the output gradient.
+struct Acts {
+  std::vector<__bf16*> x;   // x[l] = input of layer l for l >= 1
+  std::vector<float*> z;    // z[l] = pre-activation of hidden layer l
+  float* out = nullptr;
+  __bf16 *da = nullptr, *db = nullptr, *dout = nullptr;
+};
+
+int mlp_acts(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, bool train, Acts& a, hipStream_t s) {
+  const int H = M->width, L = M->n_layers;
+  size_t bytes = 0;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t xb = al(sizeof(__bf16) * n * H), zb = al(sizeof(float) * n * H);
+  const size_t ob = al(sizeof(float) * n * kOut), dob = al(sizeof(__bf16) * n * kOut);
+  bytes = (train ? (L - 1) * (xb + zb) + 2 * xb + dob : 2 * xb) + ob;
+  int rc = ensure(c, M->act, bytes, s);
+  if (rc) return rc;
+  char* p = (char*)M->act.p;
+  a.x.assign(L, nullptr);
+  a.z.assign(L, nullptr);
+  if (train) {
+    for (int l = 1; l < L; ++l) { a.x[l] = (__bf16*)p; p += xb; }
+    for (int l = 0; l < L - 1; ++l) { a.z[l] = (float*)p; p += zb; }
+    a.da = (__bf16*)p; p += xb;
+    a.db = (__bf16*)p; p += xb;
+    a.dout = (__bf16*)p; p += dob;
+  } else {
+    // inference ping-pongs two activation buffers
+    __bf16* x0 = (__bf16*)p; p += xb;
+    __bf16* x1 = (__bf16*)p; p += xb;
+    for (int l = 1; l < L; ++l) a.x[l] = (l & 1) ? x0 : x1;
+  }
+  a.out = (float*)p;
+  return XLMIMO_OK;
+}
+
+int mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, bool keep_z,
+                hipStream_t s) {
+  for (int l = 0; l < M->n_layers; ++l) {
+    GemmArgs g{};
+    g.M = (int)n;
+    g.N = M->out_dim[l];
+    g.K = M->in_dim[l];
+    g.A = l == 0 ? feat : a.x[l];
+    g.a_m = l == 0 ? kFeatPitch : M->width;
+    g.a_k = 1;
+    g.B = M->wbf + M->w_off[l];
+    g.b_k = 1;
+    g.b_n = M->in_dim[l];
+    g.bias = M->master + M->b_off[l];
+    if (l < M->n_layers - 1) {
+      g.Z = keep_z ? a.z[l] : nullptr;
+      g.out_bf = a.x[l + 1];
+      g.ldo = M->width;
+      HIP_TRY(c, launch_gemm(EPI_FWD_HIDDEN, g, s));
+    } else {
+      g.out_f = a.out;
+      g.ldo = kOut;
+      HIP_TRY(c, launch_gemm(EPI_FWD_OUT, g, s));
+    }
+  }
+  return XLMIMO_OK;
+}
+
+int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, hipStream_t s) {
+  const __bf16* dz = a.dout;
+  int64_t ldz = kOut;
+  __bf16* bufs[2] = {a.da, a.db};
+  int flip = 0;
+  for (int l = M->n_layers - 1; l >= 0; --l) {
+    const int in = M->in_dim[l], o = M->out_dim[l];
+    const __bf16* x = l == 0 ? feat : a.x[l];
+    const int64_t ldx = l == 0 ? kFeatPitch : M->width;
+    GemmArgs gw{};
+    gw.M = o;
+    gw.N = in;
+    gw.K = (int)n;
+    gw.A = dz;
+    gw.a_m = 1;
+    gw.a_k = ldz;
+    gw.B = x;
+    gw.b_k = ldx;
+    gw.b_n = 1;
+    gw.out_f = M->grad + M->w_off[l];
+    gw.ldo = in;
+    HIP_TRY(c, launch_gemm(EPI_STORE_F32, gw, s));
+    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], s));
+    if (l > 0) {
+      GemmArgs gx{};
+      gx.M = (int)n;
+      gx.N = in;
+      gx.K = o;
+      gx.A = dz;
+      gx.a_m = ldz;
+      gx.a_k = 1;
+      gx.B = M->wbf + M->w_off[l];
+      gx.b_k = in;
+      gx.b_n = 1;
+      gx.Z = a.z[l - 1];
+      gx.out_bf = bufs[flip];
+      gx.ldo = in;
+      HIP_TRY(c, launch_gemm(EPI_BWD_DX, gx, s));
+      dz = bufs[flip];
+      ldz = in;
+      flip ^= 1;
+    }
+  }
+  return XLMIMO_OK;
+}
+
+int mlp_loss_grad_impl(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const float* aux,
+                       const float* target, double* loss_out, hipStream_t s) {
+  Acts a;
+  int rc = mlp_acts(c, M, n, true, a, s);
+  if (rc) return rc;
+  if ((rc = ensure(c, M->partial, sizeof(double) * kMlpHeadBlocks, s))) return rc;
+  if ((rc = mlp_forward(c, M, n, feat, a, true, s))) return rc;
+  HIP_TRY(c, launch_mlp_head(n, a.out, aux, target, a.dout, (double*)M->partial.p, loss_out, s));
+  return mlp_backward(c, M, n, feat, a, s);
+}
+
+int check_mlp_args(xlmimo_ctx* c, const xlmimo_mlp* M, int64_t n, const void* feat, const void* aux) {
+  if (!M || M->ctx != c) return set_err(c, XLMIMO_EINVAL, "mlp is NULL or belongs to another context");
+  if (n < 0 || n > (1LL << 31) - 1) return set_err(c, XLMIMO_EINVAL, "bad pair count");
+  if (n > 0 && (!feat || !aux)) return set_err(c, XLMIMO_EINVAL, "features and aux are required");
+  return XLMIMO_OK;
+}
+
+int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
+                        int32_t variant, xlmimo_mlp* M, double log_var_max, double* gram_out, int32_t* status,
+                        hipStream_t s, int32_t** flags_out = nullptr);
+
+
+}  // namespace
+
+
+namespace {
+
+// Closed form, then the learned residual for every pair; drops whose predicted
+// log-variance exceeds log_var_max anywhere are recomputed with the exact FP32C
+// Gram (same launch plan, drop mask) and flagged XLMIMO_ST_FELL_BACK.
+int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
+                        int32_t variant, xlmimo_mlp* M, double log_var_max, double* gram_out, int32_t* status,
+                        hipStream_t s, int32_t** flags_out) {
+  Plan* p = nullptr;
+  int rc = get_plan(c, a, b, n_override, &p);
+  if (rc) return rc;
+  HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
+                               gram_out, status, p->k_max, s));
+  const int64_t np = p->n_pairs;
+  const size_t fb = (sizeof(__bf16) * kFeatPitch * np + 255) / 256 * 256;
+  const size_t ab = (sizeof(float) * kAuxPitch * np + 255) / 256 * 256;
+  const size_t pb = (sizeof(int32_t) * 2 * np + 255) / 256 * 256;
+  const size_t flb = (sizeof(int32_t) * p->n_drops + 255) / 256 * 256;
+  if ((rc = ensure(c, c->scratch_pairs, fb + ab + pb + flb, s))) return rc;
+  char* base = (char*)c->scratch_pairs.p;
+  __bf16* feat = (__bf16*)base;
+  float* aux = (float*)(base + fb);
+  int32_t* pmap = (int32_t*)(base + fb + ab);
+  int32_t* flags = (int32_t*)(base + fb + ab + pb);
+  HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 0, s));
+  HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_out, nullptr, feat, aux,
+                                nullptr, pmap, s));
+  const int64_t chunk = 1 << 20;
+  for (int64_t off = 0; off < np; off += chunk) {
+    const int64_t n = std::min(chunk, np - off);
+    Acts acts;
+    if ((rc = mlp_acts(c, M, n, false, acts, s))) return rc;
+    if ((rc = mlp_forward(c, M, n, feat + off * kFeatPitch, acts, false, s))) return rc;
+    HIP_TRY(c, launch_mlp_apply(n, acts.out, aux + off * kAuxPitch, pmap + 2 * off, p->d_drops, gram_out, flags,
+                                (float)log_var_max, s));
+  }
+  if ((rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s))) return rc;
+  const int grid = std::min(p->grid_fp32, std::max(p->n_items, 1));
+  HIP_TRY(c, launch_gram_exact(XLMIMO_FP32C, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
+                               p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, nullptr, nullptr,
+                               flags));
+  if (status) HIP_TRY(c, launch_or_flags(status, flags, p->n_drops, XLMIMO_ST_FELL_BACK, s));
+  if (flags_out) *flags_out = flags;
+  return XLMIMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xlmimo_mlp_create(xlmimo_ctx* c, int32_t width, int32_t depth, xlmimo_mlp** out) {
+  if (!c || !out) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  *out = nullptr;
+  if (width < 16 || width > 4096 || width % 16) return set_err(c, XLMIMO_EINVAL, "width must be a multiple of 16 in 16..4096");
+  if (depth < 1 || depth > 16) return set_err(c, XLMIMO_EINVAL, "depth must lie in 1..16");
+  int rc = set_device(c);
+  if (rc) return rc;
+  xlmimo_mlp* M = new xlmimo_mlp();
+  M->ctx = c;
+  M->width = width;
+  M->depth = depth;
+  M->n_layers = depth + 1;
+  int64_t off = 0;
+  for (int l = 0; l < M->n_layers; ++l) {
+    const int in = l == 0 ? XLMIMO_MLP_IN : width, o = l == depth ? XLMIMO_MLP_OUT : width;
+    M->in_dim.push_back(in);
+    M->out_dim.push_back(o);
+    M->w_off.push_back(off);
+    off += (int64_t)in * o;
+    M->b_off.push_back(off);
+    off += o;
+  }
+  M->n_params = off;
+  const size_t fb = sizeof(float) * off;
+  if (hipMalloc(&M->master, fb) || hipMalloc(&M->m, fb) || hipMalloc(&M->v, fb) || hipMalloc(&M->grad, fb) ||
+      hipMalloc(&M->wbf, sizeof(__bf16) * off) || hipMemset(M->master, 0, fb) || hipMemset(M->m, 0, fb) ||
+      hipMemset(M->v, 0, fb) || hipMemset(M->grad, 0, fb) || hipMemset(M->wbf, 0, sizeof(__bf16) * off)) {
+    (void)hipGetLastError();
+    (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
+    delete M;
+    return set_err(c, XLMIMO_ENOMEM, "MLP parameter allocation failed");
+  }
+  *out = M;
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_destroy(xlmimo_mlp* M) {
+  if (!M) return XLMIMO_OK;
+  xlmimo_ctx* c = M->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
+  if (M->act.p) (void)hipFree(M->act.p);
+  if (M->partial.p) (void)hipFree(M->partial.p);
+  delete M;
+  return XLMIMO_OK;
+}
+
+int64_t xlmimo_mlp_param_count(const xlmimo_mlp* M) { return M ? M->n_params : -1; }
+
+int xlmimo_mlp_set_params(xlmimo_mlp* M, const float* host) {
+  if (!M || !host) return XLMIMO_EINVAL;
+  xlmimo_ctx* c = M->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = set_device(c);
+  if (rc) return rc;
+  const size_t fb = sizeof(float) * M->n_params;
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipMemcpy(M->master, host, fb, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemset(M->m, 0, fb));
+  HIP_TRY(c, hipMemset(M->v, 0, fb));
+  HIP_TRY(c, launch_to_bf16(M->n_params, M->master, M->wbf, nullptr));
+  HIP_TRY(c, hipDeviceSynchronize());
+  M->t = 0;
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_get_params(xlmimo_mlp* M, float* host) {
+  if (!M || !host) return XLMIMO_EINVAL;
+  xlmimo_ctx* c = M->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipMemcpy(host, M->master, sizeof(float) * M->n_params, hipMemcpyDeviceToHost));
+  return XLMIMO_OK;
+}
+
+int64_t xlmimo_pair_count(const xlmimo_batch* b) {
+  if (!b || b->n_drops < 0 || (b->n_drops > 0 && !b->n_users)) return -1;
+  int64_t n = 0;
+  for (int64_t d = 0; d < b->n_drops; ++d) n += (int64_t)b->n_users[d] * (b->n_users[d] - 1) / 2;
+  return n;
+}
+
+int xlmimo_mlp_pair_inputs(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const double* gram_cf,
+                           const double* gram_exact, void* features, float* aux, float* target, int32_t* pair_map,
+                           void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true);
+  if (rc) return rc;
+  if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the learned correction is defined for a ULA");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_cf || !features || !aux || !pair_map) return set_err(c, XLMIMO_EINVAL, "gram_cf, features, aux and pair_map are required");
+  if (target && !gram_exact) return set_err(c, XLMIMO_EINVAL, "targets need gram_exact");
+  if ((rc = set_device(c))) return rc;
+  Plan* p = nullptr;
+  if ((rc = get_plan(c, a, b, nullptr, &p))) return rc;
+  HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_cf, gram_exact,
+                                (__bf16*)features, aux, target, pair_map, (hipStream_t)stream));
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_loss_grad(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, const float* aux,
+                         const float* target, float* grad_out, double* loss_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_mlp_args(c, M, n, features, aux);
+  if (rc) return rc;
+  if (n < 1 || !target || !loss_out) return set_err(c, XLMIMO_EINVAL, "need n >= 1, targets and loss_out");
+  if ((rc = set_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = mlp_loss_grad_impl(c, M, n, (const __bf16*)features, aux, target, loss_out, s))) return rc;
+  if (grad_out) HIP_TRY(c, hipMemcpyAsync(grad_out, M->grad, sizeof(float) * M->n_params, hipMemcpyDeviceToDevice, s));
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_train_step(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, const float* aux,
+                          const float* target, float lr, double* loss_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_mlp_args(c, M, n, features, aux);
+  if (rc) return rc;
+  if (n < 1 || !target || !loss_out) return set_err(c, XLMIMO_EINVAL, "need n >= 1, targets and loss_out");
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return set_err(c, XLMIMO_EINVAL, "bad learning rate");
+  if ((rc = set_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = mlp_loss_grad_impl(c, M, n, (const __bf16*)features, aux, target, loss_out, s))) return rc;
+  M->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
+  HIP_TRY(c, launch_adam(M->n_params, M->master, M->m, M->v, M->grad, lr, b1, b2, 1e-8f, bc1, bc2, M->wbf, s));
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, float* out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_mlp_args(c, M, n, features, (const void*)1);
+  if (rc) return rc;
+  if (n == 0) return XLMIMO_OK;
+  if (!out) return set_err(c, XLMIMO_EINVAL, "out is NULL");
+  if ((rc = set_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t chunk = 1 << 20;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    Acts acts;
+    if ((rc = mlp_acts(c, M, m, false, acts, s))) return rc;
+    if ((rc = mlp_forward(c, M, m, (const __bf16*)features + off * kFeatPitch, acts, false, s))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(out + off * kOut, acts.out, sizeof(float) * m * kOut, hipMemcpyDeviceToDevice, s));
+  }
+  return XLMIMO_OK;
+}
+
+int xlmimo_gram_closedform_mlp(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t variant,
+                               xlmimo_mlp* M, double log_var_max, double* gram_out, int32_t* status_out,
+                               void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true);
+  if (rc) return rc;
+  if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the learned correction is defined for a ULA");
+  if (variant != XLMIMO_CF_PAPER && variant != XLMIMO_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (!M || M->ctx != c) return set_err(c, XLMIMO_EINVAL, "mlp is NULL or belongs to another context");
+  if (std::isnan(log_var_max)) return set_err(c, XLMIMO_EINVAL, "log_var_max is NaN");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
+  if ((rc = set_device(c))) return rc;
+  return closedform_mlp_impl(c, a, b, nullptr, variant, M, log_var_max, gram_out, status_out, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
 extern "C" {
 
 const char* xlmimo_version(void) { return "xlmimo 0.1 (gfx950)"; }
@@ -347,7 +736,8 @@ int xlmimo_ctx_destroy(xlmimo_ctx* c) {
     (void)hipFree(kv.second.d_drops);
     (void)hipFree(kv.second.d_items);
   }
-  DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds, &c->scratch_nlist};
+  DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds,
+                    &c->scratch_nlist, &c->scratch_pairs};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipFree(c->d_counter);
@@ -445,16 +835,17 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* c, const xlmimo_batch* b, const double* g
 }
 
 int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, const int64_t* N_list,
-                          const xlmimo_batch* b, int32_t form, int32_t n_snr, const double* rho, int32_t schemes,
-                          double t_sat, double eps_sat, double* ergodic_out, double* sat_out, int32_t* status_out,
-                          void* stream) {
+                          const xlmimo_batch* b, int32_t form, xlmimo_mlp* mlp, double log_var_max, int32_t n_snr,
+                          const double* rho, int32_t schemes, double t_sat, double eps_sat, double* ergodic_out,
+                          double* sat_out, int32_t* status_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   hipStream_t s = (hipStream_t)stream;
   int rc = check_array(c, a);
   if (rc) return rc;
   if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the capacity sweep varies a ULA's N");
-  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
+  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_CF_GATED_MLP) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
+  if (form == XLMIMO_FORM_CF_GATED_MLP && (!mlp || mlp->ctx != c)) return set_err(c, XLMIMO_EINVAL, "the MLP form needs an mlp of this context");
   if (n_N < 1 || !N_list) return set_err(c, XLMIMO_EINVAL, "N_list is empty");
   for (int i = 0; i < n_N; ++i) {
     if (N_list[i] < 1 || N_list[i] > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "N_list[%d] out of range", i);
@@ -496,19 +887,25 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   double* g = (double*)c->scratch_gram.p;
   double* g2 = (double*)c->scratch_gram2.p;
   for (int i = 0; i < n_N; ++i) {
+    int32_t* fb_flags = nullptr;
     const int64_t nn = N_list[i];
     int32_t* st = status_out ? status_out + (int64_t)i * nd : nullptr;
     if (!cf) {
       if ((rc = gram_exact_impl(c, a, b, &nn, form == XLMIMO_FORM_EXACT_FP64 ? XLMIMO_FP64 : XLMIMO_FP32C, g, s))) return rc;
     } else {
       const int variant = form == XLMIMO_FORM_CF_PAPER ? XLMIMO_CF_PAPER : XLMIMO_CF_GATED;
-      if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) return rc;
+      if (form == XLMIMO_FORM_CF_GATED_MLP) {
+        if ((rc = closedform_mlp_impl(c, a, b, &nn, variant, mlp, log_var_max, g, nullptr, s, &fb_flags))) return rc;
+      } else if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) {
+        return rc;
+      }
       if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP32C, g2, s))) return rc;
     }
     if ((rc = get_plan(c, a, b, &nn, &p))) return rc;
     const double* gtrue = need_exact_true ? g2 : g;
     HIP_TRY(c, launch_rates(p->d_drops, nd, rates_k_max(p->k_max), gtrue, g, n_snr, rho, p->total_users, schemes,
                             (double*)c->scratch_rates.p, st, s));
+    if (st && fb_flags) HIP_TRY(c, launch_or_flags(st, fb_flags, nd, XLMIMO_ST_FELL_BACK, s));
     HIP_TRY(c, launch_ergodic((double*)c->scratch_rates.p, nd, n_vals, ergodic_out + (int64_t)i * n_vals, s));
   }
   HIP_TRY(c, launch_y_bounds(b->user_pos, p->d_drops, nd, a->geometry, t_sat, (double*)c->scratch_bounds.p, s));

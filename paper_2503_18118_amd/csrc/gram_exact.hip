@@ -279,7 +279,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
                                                                const double* __restrict__ pos,
                                                                const ItemK* __restrict__ items, int n_items,
                                                                int* __restrict__ counter,
-                                                               double* __restrict__ partials) {
+                                                               double* __restrict__ partials,
+                                                               const int32_t* __restrict__ mask) {
   __shared__ double s_red[partial_values(NBMAX) * 64];
   __shared__ int s_item;
   for (;;) {
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
     __syncthreads();
     if (idx >= n_items) break;  // uniform over the workgroup: every wave leaves together
     const ItemK it = items[idx];
+    if (mask != nullptr && mask[it.drop] == 0) continue;  // drop not selected: skip its items
     const DropK dp = drops[it.drop];
     double* out = partials + dp.part_off + it.chunk * (int64_t)(partial_values(dp.nb) * 64);
     switch (dp.nb) {
@@ -321,7 +323,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* __restrict__ drops,
                                                        const double* __restrict__ pos,
                                                        const double* __restrict__ partials,
-                                                       double* __restrict__ gram) {
+                                                       double* __restrict__ gram,
+                                                       const int32_t* __restrict__ mask) {
+  if (mask != nullptr && mask[blockIdx.x] == 0) return;
   const DropK dp = drops[blockIdx.x];
   const int K = dp.k, NB = dp.nb;
   const int NRE = NB * (NB + 1) / 2;
@@ -402,16 +406,17 @@ struct MainArgs {
   int n_items;
   int* counter;
   double* partials;
+  const int32_t* mask;
 };
 
 template <typename T, int GEOM, int AMP>
 static void launch_main(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
   if (nb_max <= 1)
-    k_gram_exact<1, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+    k_gram_exact<1, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
   else if (nb_max <= 2)
-    k_gram_exact<2, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+    k_gram_exact<2, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
   else
-    k_gram_exact<4, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials);
+    k_gram_exact<4, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
 }
 
 template <typename T>
@@ -428,17 +433,17 @@ static void launch_t(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
                              double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0,
-                             hipEvent_t ev1) {
+                             hipEvent_t ev1, const int32_t* d_mask) {
   if (n_drops == 0) return hipSuccess;
   k_reset_counter<<<1, 64, 0, s>>>(d_counter);
   if (grid < 1) grid = 1;
-  const MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials};
+  const MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials, d_mask};
   if (ev0) (void)hipEventRecord(ev0, s);
   if (precision == XLMIMO_FP64) launch_t<double>(nb_max, grid, s, a);
   else launch_t<float>(nb_max, grid, s, a);
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (precision == XLMIMO_FP64) k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
-  else k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram);
+  if (precision == XLMIMO_FP64) k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask);
+  else k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct DropK {
   int64_t user_off;   // first user in the position array
   int64_t gram_off;   // first complex element of the drop's K x K output
   int64_t part_off;   // first double of the drop's partials (exact Gram)
+  int64_t pair_off;   // first user pair (i < j) of the drop in pair-indexed buffers
   int32_t n_elems;    // antennas (ULA: N, UPA: n_y * n_z)
   int32_t k;          // users
   int32_t nb;         // ceil(k / 16) user blocks
@@ -47,11 +48,27 @@ __host__ __device__ constexpr int tri_index(int bi, int bj, int nb) {
 constexpr int kGramThreads = 256;     // 4 waves per work item
 constexpr int kFlushRounds = 64;      // FP32 MFMA partial sums are carried to FP64 every 64 rounds (256 elements per wave)
 
+// BF16 GEMM for the learned correction (mlp.hip): C[M x N] = sum_k A(m,k) B(k,n),
+// A(m,k) = A[m a_m + k a_k], B(k,n) = B[k b_k + n b_n], outputs row-major with pitch ldo.
+enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_BWD_DX = 2, EPI_STORE_F32 = 3 };
+struct GemmArgs {
+  int M, N, K;
+  const __bf16* A;
+  int64_t a_m, a_k;
+  const __bf16* B;
+  int64_t b_k, b_n;
+  const float* bias;  // [N]: FWD_HIDDEN, FWD_OUT
+  float* Z;           // FWD_HIDDEN: pre-activations out (may be null); BWD_DX: pre-activations in
+  __bf16* out_bf;     // FWD_HIDDEN: GELU(z); BWD_DX: dZ of the previous layer
+  float* out_f;       // FWD_OUT, STORE_F32
+  int64_t ldo;
+};
+
 // Launchers (stream-ordered, no host synchronisation).
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
                              double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
-                             hipEvent_t ev1 = nullptr);
+                             hipEvent_t ev1 = nullptr, const int32_t* d_mask = nullptr);
 int gram_exact_grid(int precision, int nb_max, int geom, int amp);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
@@ -67,5 +84,21 @@ hipError_t launch_y_bounds(const double* d_pos, const DropK* d_drops, int n_drop
                            double* d_bounds, hipStream_t s);
 hipError_t launch_saturation(const double* d_bounds, int n_drops, const double* d_ergodic, const double* d_nlist,
                              int n_N, int n_vals, double spacing, double eps, double* d_sat, hipStream_t s);
+
+hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s);
+hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_drops, const double* d_pos,
+                              const double* d_cf, const double* d_exact, __bf16* feat, float* aux, float* target,
+                              int32_t* pmap, hipStream_t s);
+hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
+                           double* partial, double* loss, hipStream_t s);
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, hipStream_t s);
+hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s);
+hipError_t launch_to_bf16(int64_t n, const float* w, __bf16* wbf, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit, hipStream_t s);
+hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const int32_t* pmap, const DropK* d_drops,
+                            double* gram, int32_t* flags, float log_var_max, hipStream_t s);
+constexpr int kMlpHeadBlocks = 256;
 
 }  // namespace xl

@@ -1,0 +1,362 @@
+// Learned residual correction of the closed-form correlation (an MLP in BF16 on
+// the matrix cores, FP32 accumulation), with training kernels.
+//
+// Not in the paper: the correction targets the regime where the paper notes the
+// modified ZF is worse (before saturation, Sec. V-C).  Per user pair (i < j):
+//   features  (r_i/50, theta_i/(pi/3), r_j/50, theta_j/(pi/3), log4 N - 6, d/lambda - 1/2)
+//   phasors   e^{j phi(y)} at the two end elements and at the stationary point,
+//             phi(y) = (2 pi/lambda)(r_i(y) - r_j(y))
+//   network   6 -> [Linear(w) + GELU] x depth -> Linear(7)
+//   output    coefficients c_m (3 complex) and s = log sigma^2;
+//             delta_rho = sum_m c_m e^{j phi_m};  G_ij += delta_rho sqrt(G~_ii G~_jj)
+//   loss      mean |target - delta_rho|^2 e^{-s} + s   (Gaussian negative log-likelihood)
+//   optimiser Adam on FP32 master weights, BF16 copies for the matrix cores.
+//
+// GEMM: C[M x N] = sum_k A(m,k) B(k,n) on v_mfma_f32_16x16x32_bf16, 64 x 64 tiles
+// per 256-thread workgroup (each wave 32 x 32 = 2 x 2 MFMA blocks), K in steps
+// of 32 staged through LDS with k contiguous, operands with arbitrary strides
+// (so the same kernel serves X W^T, dZ W and dZ^T X).  Epilogues fuse
+// bias + GELU (forward), the last-layer bias, and GELU' (backward).
+#include <hip/hip_bf16.h>
+
+#include "device_math.h"
+#include "internal.h"
+#include "xlmimo.h"
+
+namespace xl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64, TN = 64, TK = 32;
+constexpr int LDS_K = TK + 8;  // row pitch in bf16 (80 bytes: 16-byte aligned operand reads)
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 sA[TM * LDS_K];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[TN * LDS_K];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8 k-values
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    {
+      const int m = m0 + lr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + lk + q;
+        sA[lr * LDS_K + lk + q] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.a_m + (int64_t)k * g.a_k] : (__bf16)0.0f;
+      }
+      const int n = n0 + lr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + lk + q;
+        sB[lr * LDS_K + lk + q] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (__bf16)0.0f;
+      }
+    }
+    __syncthreads();
+    const int kk = 8 * (lane >> 4);
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDS_K + kk]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDS_K + kk]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // C layout of 16x16 blocks: lane l, register r -> row 4 (l / 16) + r, column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (row >= g.M || col >= g.N) continue;
+        const int64_t o = (int64_t)row * g.ldo + col;
+        const float v = acc[i][j][r];
+        if constexpr (EPI == EPI_FWD_HIDDEN) {
+          const float z = v + g.bias[col];
+          if (g.Z) g.Z[o] = z;
+          g.out_bf[o] = (__bf16)gelu(z);
+        } else if constexpr (EPI == EPI_FWD_OUT) {
+          g.out_f[o] = v + g.bias[col];
+        } else if constexpr (EPI == EPI_BWD_DX) {
+          g.out_bf[o] = (__bf16)(v * gelu_grad(g.Z[o]));
+        } else {
+          g.out_f[o] = v;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s) {
+  dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+  switch (epi) {
+    case EPI_FWD_HIDDEN: k_gemm_bf16<EPI_FWD_HIDDEN><<<grid, 256, 0, s>>>(g); break;
+    case EPI_FWD_OUT: k_gemm_bf16<EPI_FWD_OUT><<<grid, 256, 0, s>>>(g); break;
+    case EPI_BWD_DX: k_gemm_bf16<EPI_BWD_DX><<<grid, 256, 0, s>>>(g); break;
+    default: k_gemm_bf16<EPI_STORE_F32><<<grid, 256, 0, s>>>(g); break;
+  }
+  return hipGetLastError();
+}
+
+// e^{j 2 pi u} for a phase u in turns (FP64 reduction, FP64 Taylor sin/cos).
+__device__ __forceinline__ void phasor_turns(double u, float& re, float& im) {
+  const double v = 2.0 * u;  // half turns
+  const double q = __builtin_rint(v);
+  double ns, c;
+  sincos_half(v - q, ns, c);
+  const double sg = (((long long)q) & 1) ? -1.0 : 1.0;
+  re = (float)(sg * c);
+  im = (float)(-sg * ns);
+}
+
+__global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __restrict__ drops,
+                                                      const double* __restrict__ pos,
+                                                      const double* __restrict__ gram_cf,
+                                                      const double* __restrict__ gram_exact,
+                                                      __bf16* __restrict__ feat, float* __restrict__ aux,
+                                                      float* __restrict__ target, int32_t* __restrict__ pmap) {
+  const DropK dp = drops[blockIdx.x];
+  const int K = dp.k;
+  const int np = K * (K - 1) / 2;
+  const double lam = arr.lambda;
+  for (int t = threadIdx.x; t < np; t += blockDim.x) {
+    int i = 0, rem = t;
+    while (rem >= K - 1 - i) {
+      rem -= K - 1 - i;
+      ++i;
+    }
+    const int j = i + 1 + rem;
+    const int64_t p = dp.pair_off + t;
+    const double* ui = pos + (dp.user_off + i) * 3;
+    const double* uj = pos + (dp.user_off + j) * 3;
+    const double xi = sqrt(fma(ui[0], ui[0], ui[2] * ui[2])), yi = ui[1];
+    const double xj = sqrt(fma(uj[0], uj[0], uj[2] * uj[2])), yj = uj[1];
+    const double f[8] = {sqrt(xi * xi + yi * yi) / 50.0, atan2(yi, xi) / (kPiD / 3.0),
+                         sqrt(xj * xj + yj * yj) / 50.0, atan2(yj, xj) / (kPiD / 3.0),
+                         log((double)dp.n_elems) / log(4.0) - 6.0, arr.spacing / lam - 0.5, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) feat[p * 8 + q] = (__bf16)(float)f[q];
+    auto dphase = [&](double y) {  // (r_i(y) - r_j(y)) / lambda in turns
+      const double di = y - yi, dj = y - yj;
+      return (sqrt(fma(di, di, xi * xi)) - sqrt(fma(dj, dj, xj * xj))) * arr.inv_lambda;
+    };
+    const double ytop = 0.5 * (double)(dp.n_elems - 1) * arr.spacing;
+    float pr, pi;
+    phasor_turns(dphase(ytop), pr, pi);
+    aux[p * 8 + 0] = pr;
+    aux[p * 8 + 1] = pi;
+    phasor_turns(dphase(-ytop), pr, pi);
+    aux[p * 8 + 2] = pr;
+    aux[p * 8 + 3] = pi;
+    if (xi != xj) {
+      phasor_turns(dphase((yi * xj - xi * yj) / (xj - xi)), pr, pi);
+    } else {
+      pr = 1.0f;
+      pi = 0.0f;
+    }
+    aux[p * 8 + 4] = pr;
+    aux[p * 8 + 5] = pi;
+    const double* gc = gram_cf + 2 * dp.gram_off;
+    const double cii = gc[2 * (i * K + i)], cjj = gc[2 * (j * K + j)];
+    const double scale = sqrt(cii * cjj);
+    aux[p * 8 + 6] = (float)scale;
+    aux[p * 8 + 7] = 0.0f;
+    if (target != nullptr) {
+      const double* ge = gram_exact + 2 * dp.gram_off;
+      const double eii = ge[2 * (i * K + i)], ejj = ge[2 * (j * K + j)];
+      const double se = sqrt(eii * ejj);
+      target[p * 2 + 0] = (float)(ge[2 * (i * K + j)] / se - gc[2 * (i * K + j)] / scale);
+      target[p * 2 + 1] = (float)(ge[2 * (i * K + j) + 1] / se - gc[2 * (i * K + j) + 1] / scale);
+    }
+    pmap[p * 2 + 0] = (int32_t)blockIdx.x;
+    pmap[p * 2 + 1] = i * XLMIMO_MAX_USERS + j;
+  }
+}
+
+hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_drops, const double* d_pos,
+                              const double* d_cf, const double* d_exact, __bf16* feat, float* aux, float* target,
+                              int32_t* pmap, hipStream_t s) {
+  if (n_drops == 0) return hipSuccess;
+  k_pair_inputs<<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_cf, d_exact, feat, aux, target, pmap);
+  return hipGetLastError();
+}
+
+// Loss head: per-sample NLL and its gradient with respect to the 7 outputs
+// (scaled by 1/n); per-block partial loss sums in fixed order.
+__global__ __launch_bounds__(256) void k_mlp_head(int64_t n, const float* __restrict__ out,
+                                                  const float* __restrict__ aux, const float* __restrict__ target,
+                                                  __bf16* __restrict__ dout, double* __restrict__ partial) {
+  __shared__ double s_sum[256];
+  double acc = 0.0;
+  const float inv_n = 1.0f / (float)n;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const float* o = out + p * 7;
+    const float* a = aux + p * 8;
+    float prr = 0.f, pii = 0.f;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      prr += o[2 * m] * a[2 * m] - o[2 * m + 1] * a[2 * m + 1];
+      pii += o[2 * m] * a[2 * m + 1] + o[2 * m + 1] * a[2 * m];
+    }
+    const float s = o[6];
+    const float er = target[2 * p] - prr, ei = target[2 * p + 1] - pii;
+    const float w = expf(-s);
+    const float e2 = er * er + ei * ei;
+    acc += (double)(e2 * w + s);
+    const float gpr = -2.0f * er * w * inv_n, gpi = -2.0f * ei * w * inv_n;
+    __bf16* d = dout + p * 7;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      d[2 * m] = (__bf16)(gpr * a[2 * m] + gpi * a[2 * m + 1]);
+      d[2 * m + 1] = (__bf16)(-gpr * a[2 * m + 1] + gpi * a[2 * m]);
+    }
+    d[6] = (__bf16)((1.0f - e2 * w) * inv_n);
+  }
+  s_sum[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s_sum[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n_part, int64_t n,
+                                                      double* __restrict__ loss) {
+  __shared__ double s_sum[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n_part; i += 256) acc += partial[i];
+  s_sum[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = s_sum[0] / (double)n;
+}
+
+hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
+                           double* partial, double* loss, hipStream_t s) {
+  k_mlp_head<<<kMlpHeadBlocks, 256, 0, s>>>(n, out, aux, target, dout, partial);
+  k_sum_partials<<<1, 256, 0, s>>>(partial, kMlpHeadBlocks, n, loss);
+  return hipGetLastError();
+}
+
+// db[c] = sum over rows of dZ[row][c] (fixed row order).
+__global__ void k_colsum(const __bf16* __restrict__ dz, int64_t rows, int cols, float* __restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float acc = 0.0f;
+  for (int64_t r = 0; r < rows; ++r) acc += (float)dz[r * cols + c];
+  db[c] = acc;
+}
+
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, hipStream_t s) {
+  k_colsum<<<(cols + 255) / 256, 256, 0, s>>>(dz, rows, cols, db);
+  return hipGetLastError();
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                       __bf16* __restrict__ wbf) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  w[i] = wi;
+  wbf[i] = (__bf16)wi;
+}
+
+hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s) {
+  k_adam<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, w, m, v, g, lr, b1, b2, eps, bc1, bc2, wbf);
+  return hipGetLastError();
+}
+
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ w, __bf16* __restrict__ wbf) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) wbf[i] = (__bf16)w[i];
+}
+
+hipError_t launch_to_bf16(int64_t n, const float* w, __bf16* wbf, hipStream_t s) {
+  k_to_bf16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, w, wbf);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n > 0) k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && flags[i]) status[i] |= bit;
+}
+
+hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit, hipStream_t s) {
+  if (n > 0) k_or_flags<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(status, flags, n, bit);
+  return hipGetLastError();
+}
+
+// Apply the predicted residual to the closed-form Gram and flag drops whose
+// predicted log-variance exceeds the threshold (they are recomputed exactly).
+__global__ void k_mlp_apply(int64_t n, const float* __restrict__ out, const float* __restrict__ aux,
+                            const int32_t* __restrict__ pmap, const DropK* __restrict__ drops,
+                            double* __restrict__ gram, int32_t* __restrict__ flags, float log_var_max) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float* o = out + p * 7;
+  const float* a = aux + p * 8;
+  double pr = 0.0, pi = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    pr += (double)o[2 * m] * a[2 * m] - (double)o[2 * m + 1] * a[2 * m + 1];
+    pi += (double)o[2 * m] * a[2 * m + 1] + (double)o[2 * m + 1] * a[2 * m];
+  }
+  const int d = pmap[2 * p];
+  const int i = pmap[2 * p + 1] / XLMIMO_MAX_USERS, j = pmap[2 * p + 1] % XLMIMO_MAX_USERS;
+  const DropK dp = drops[d];
+  const double sc = (double)a[6];
+  double* gij = gram + 2 * (dp.gram_off + (int64_t)i * dp.k + j);
+  double* gji = gram + 2 * (dp.gram_off + (int64_t)j * dp.k + i);
+  gij[0] += pr * sc;
+  gij[1] += pi * sc;
+  gji[0] += pr * sc;
+  gji[1] -= pi * sc;
+  if (!(o[6] <= log_var_max)) atomicOr(&flags[d], 1);
+}
+
+hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const int32_t* pmap, const DropK* d_drops,
+                            double* gram, int32_t* flags, float log_var_max, hipStream_t s) {
+  if (n > 0) k_mlp_apply<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, out, aux, pmap, d_drops, gram, flags, log_var_max);
+  return hipGetLastError();
+}
+
+}  // namespace xl

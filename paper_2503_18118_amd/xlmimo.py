@@ -22,13 +22,17 @@ AMP_FREESPACE, AMP_PNUSW = 0, 1
 FP64, FP32C = 0, 1
 CF_PAPER, CF_GATED = 0, 1
 ZF, MMSE, MRC, CAP, MZF, MZF_MISM = 1, 2, 4, 8, 16, 32
-ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE = 1, 2, 4, 8, 16
-FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED = 0, 1, 2, 3
+ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE, ST_FELL_BACK = 1, 2, 4, 8, 16, 32
+FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED, FORM_CF_GATED_MLP = 0, 1, 2, 3, 4
 MAX_USERS = 64
+MLP_IN, MLP_OUT, PAIR_FEAT_PITCH, PAIR_AUX_PITCH = 6, 7, 8, 8
 
 EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlmimo_version",
             "xlmimo_gram_exact", "xlmimo_gram_closedform", "xlmimo_zf_mmse_sumrate",
-            "xlmimo_capacity_sweep", "xlmimo_timing_enable", "xlmimo_timing_read")
+            "xlmimo_capacity_sweep", "xlmimo_timing_enable", "xlmimo_timing_read",
+            "xlmimo_mlp_create", "xlmimo_mlp_destroy", "xlmimo_mlp_param_count", "xlmimo_mlp_set_params",
+            "xlmimo_mlp_get_params", "xlmimo_pair_count", "xlmimo_mlp_pair_inputs", "xlmimo_mlp_loss_grad",
+            "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp")
 
 
 class XlArray(C.Structure):
@@ -56,7 +60,21 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_gram_closedform.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp, vp]
     lib.xlmimo_zf_mmse_sumrate.argtypes = [vp, C.POINTER(XlBatch), vp, vp, i32, vp, i32, vp, vp, vp]
     lib.xlmimo_capacity_sweep.argtypes = [vp, C.POINTER(XlArray), i32, C.POINTER(C.c_int64), C.POINTER(XlBatch),
-                                          i32, i32, vp, i32, C.c_double, C.c_double, vp, vp, vp, vp]
+                                          i32, vp, C.c_double, i32, vp, i32, C.c_double, C.c_double, vp, vp, vp, vp]
+    lib.xlmimo_mlp_create.argtypes = [vp, i32, i32, C.POINTER(vp)]
+    lib.xlmimo_mlp_destroy.argtypes = [vp]
+    lib.xlmimo_mlp_param_count.argtypes = [vp]
+    lib.xlmimo_mlp_param_count.restype = i64
+    lib.xlmimo_mlp_set_params.argtypes = [vp, vp]
+    lib.xlmimo_mlp_get_params.argtypes = [vp, vp]
+    lib.xlmimo_pair_count.argtypes = [C.POINTER(XlBatch)]
+    lib.xlmimo_pair_count.restype = i64
+    lib.xlmimo_mlp_pair_inputs.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), vp, vp, vp, vp, vp, vp, vp]
+    lib.xlmimo_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.xlmimo_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp]
+    lib.xlmimo_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.xlmimo_gram_closedform_mlp.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, C.c_double, vp,
+                                               vp, vp]
     lib.xlmimo_timing_enable.argtypes = [vp, C.c_int]
     lib.xlmimo_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     return lib
@@ -191,7 +209,7 @@ class Context:
     def capacity_sweep(self, arr, n_list: Sequence[int], batch: Batch, form: int, rho: torch.Tensor,
                        schemes: int = ZF | MMSE, t_sat: float = 0.9, eps_sat: float = 0.05,
                        ergodic: Optional[torch.Tensor] = None, sat: Optional[torch.Tensor] = None,
-                       status: Optional[torch.Tensor] = None, stream=None):
+                       status: Optional[torch.Tensor] = None, stream=None, mlp=None, log_var_max: float = 0.0):
         n_snr = int(rho.shape[0])
         n_sch = bin(schemes).count("1")
         dev = batch.pos.device
@@ -204,10 +222,107 @@ class Context:
             status = torch.empty((len(nl), batch.n_drops), dtype=torch.int32, device=dev)
         a = make_array(arr)
         self._check(_lib.xlmimo_capacity_sweep(self.h, C.byref(a), len(nl), nl.ctypes.data_as(C.POINTER(C.c_int64)),
-                                               C.byref(batch.struct), form, n_snr, _ptr(rho.contiguous()), schemes,
+                                               C.byref(batch.struct), form, mlp.h if mlp is not None else None,
+                                               float(log_var_max), n_snr, _ptr(rho.contiguous()), schemes,
                                                float(t_sat), float(eps_sat), _ptr(ergodic), _ptr(sat), _ptr(status),
                                                _stream(stream)), "xlmimo_capacity_sweep")
         return ergodic, sat, status
+
+
+    def gram_closedform_mlp(self, arr, batch: "Batch", mlp, variant: int = CF_GATED, log_var_max: float = 0.0,
+                            out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None, stream=None):
+        if out is None:
+            out = torch.empty(2 * batch.gram_elems, dtype=torch.float64, device=batch.pos.device)
+        if status is None:
+            status = torch.empty(batch.n_drops, dtype=torch.int32, device=batch.pos.device)
+        a = make_array(arr)
+        self._check(_lib.xlmimo_gram_closedform_mlp(self.h, C.byref(a), C.byref(batch.struct), variant, mlp.h,
+                                                    float(log_var_max), _ptr(out), _ptr(status), _stream(stream)),
+                    "xlmimo_gram_closedform_mlp")
+        return out, status
+
+
+class PairInputs:
+    """Per-pair network inputs (device): bf16 features, float aux, optional targets, pair map."""
+
+    def __init__(self, feat, aux, target, pmap):
+        self.feat, self.aux, self.target, self.pmap = feat, aux, target, pmap
+
+    @property
+    def n(self) -> int:
+        return int(self.feat.shape[0])
+
+    def slice(self, a: int, b: int) -> "PairInputs":
+        return PairInputs(self.feat[a:b], self.aux[a:b], None if self.target is None else self.target[a:b],
+                          self.pmap[a:b])
+
+
+class MLP:
+    """Device-resident network of the learned correction (include/xlmimo.h)."""
+
+    def __init__(self, ctx: Context, width: int = 256, depth: int = 4):
+        self.ctx, self.width, self.depth = ctx, width, depth
+        h = C.c_void_p()
+        ctx._check(_lib.xlmimo_mlp_create(ctx.h, width, depth, C.byref(h)), "xlmimo_mlp_create")
+        self.h = h
+        self.n_params = int(_lib.xlmimo_mlp_param_count(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.xlmimo_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == self.n_params
+        self.ctx._check(_lib.xlmimo_mlp_set_params(self.h, p.ctypes.data_as(C.c_void_p)), "xlmimo_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, np.float32)
+        self.ctx._check(_lib.xlmimo_mlp_get_params(self.h, p.ctypes.data_as(C.c_void_p)), "xlmimo_mlp_get_params")
+        return p
+
+    def pair_inputs(self, arr, batch: Batch, gram_cf: torch.Tensor, gram_exact: Optional[torch.Tensor] = None,
+                    stream=None) -> PairInputs:
+        n = int(_lib.xlmimo_pair_count(C.byref(batch.struct)))
+        dev = gram_cf.device
+        feat = torch.empty((n, PAIR_FEAT_PITCH), dtype=torch.bfloat16, device=dev)
+        aux = torch.empty((n, PAIR_AUX_PITCH), dtype=torch.float32, device=dev)
+        target = torch.empty((n, 2), dtype=torch.float32, device=dev) if gram_exact is not None else None
+        pmap = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        a = make_array(arr)
+        self.ctx._check(_lib.xlmimo_mlp_pair_inputs(self.ctx.h, C.byref(a), C.byref(batch.struct), _ptr(gram_cf),
+                                                    _ptr(gram_exact), _ptr(feat), _ptr(aux), _ptr(target), _ptr(pmap),
+                                                    _stream(stream)), "xlmimo_mlp_pair_inputs")
+        return PairInputs(feat, aux, target, pmap)
+
+    def loss_grad(self, pi: PairInputs, stream=None):
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=pi.aux.device)
+        loss = torch.empty(1, dtype=torch.float64, device=pi.aux.device)
+        self.ctx._check(_lib.xlmimo_mlp_loss_grad(self.ctx.h, self.h, pi.n, _ptr(pi.feat), _ptr(pi.aux),
+                                                  _ptr(pi.target), _ptr(grad), _ptr(loss), _stream(stream)),
+                        "xlmimo_mlp_loss_grad")
+        return loss, grad
+
+    def train_step(self, pi: PairInputs, lr: float, loss: Optional[torch.Tensor] = None, stream=None):
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=pi.aux.device)
+        self.ctx._check(_lib.xlmimo_mlp_train_step(self.ctx.h, self.h, pi.n, _ptr(pi.feat), _ptr(pi.aux),
+                                                   _ptr(pi.target), float(lr), _ptr(loss), _stream(stream)),
+                        "xlmimo_mlp_train_step")
+        return loss
+
+    def forward(self, pi: PairInputs, stream=None) -> torch.Tensor:
+        out = torch.empty((pi.n, MLP_OUT), dtype=torch.float32, device=pi.aux.device)
+        self.ctx._check(_lib.xlmimo_mlp_forward(self.ctx.h, self.h, pi.n, _ptr(pi.feat), _ptr(out), _stream(stream)),
+                        "xlmimo_mlp_forward")
+        return out
 
 
 def version() -> str:

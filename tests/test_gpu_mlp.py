@@ -1,0 +1,143 @@
+"""Learned correction on the GPU against the FP64 MLP reference.
+
+Forward outputs and gradients are compared with the oracle evaluated at the
+same BF16-rounded weights and inputs; the GPU also rounds every activation and
+back-propagated gradient to BF16 between layers, so the tolerance is a
+relative Frobenius error of 2e-2 per parameter tensor (5e-2 for the first
+layer's weights, whose inputs are six BF16 features).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import channel as och
+from oracle import closedform as ocf
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+
+WIDTH, DEPTH = 256, 4
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2503_18118_amd import xlmimo
+    return xlmimo
+
+
+@pytest.fixture(scope="module")
+def ctx(X):
+    c = X.Context(0)
+    yield c
+    c.close()
+
+
+def bf16_round(a):
+    """Round float64 values to the nearest bfloat16 (ties to even)."""
+    f = np.asarray(a, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _pairs(X, ctx, mlp, n_drops=6, k=7, stream=9):
+    arr, drops = W.learned_drops(n_drops, stream=stream, k=k)
+    b = X.Batch(drops)
+    gcf, _ = ctx.gram_closedform(arr, b, X.CF_GATED)
+    gex = ctx.gram_exact(arr, b, X.FP64)
+    return arr, drops, mlp.pair_inputs(arr, b, gcf, gex), gcf, gex, b
+
+
+def test_pair_inputs_match_oracle(X, ctx):
+    mlp = X.MLP(ctx, WIDTH, DEPTH)
+    arr, drops, pi, gcf, gex, b = _pairs(X, ctx, mlp)
+    torch.cuda.synchronize()
+    feat = pi.feat.float().cpu().numpy()
+    aux = pi.aux.cpu().numpy()
+    tgt = pi.target.cpu().numpy()
+    pm = pi.pmap.cpu().numpy()
+    p = 0
+    for d in range(drops.n_drops):
+        u = drops.users_of(d)
+        n = int(drops.n_elems[d])
+        a = arr.with_n(n)
+        g_ex = och.gram_exact(a, u)
+        g_cf = ocf.gram_closedform(a, u, n, ocf.VARIANT_GATED)
+        k = len(u)
+        for i in range(k):
+            for j in range(i + 1, k):
+                f, ph = OM.pair_inputs(u[i, 0], u[i, 1], u[j, 0], u[j, 1], n, a.spacing, a.wavelength)
+                assert np.allclose(feat[p, :6], bf16_round(f), rtol=0, atol=1e-12)
+                assert np.all(feat[p, 6:] == 0)
+                assert np.allclose(aux[p, 0:6:2] + 1j * aux[p, 1:6:2], ph, atol=2e-6)
+                assert aux[p, 6] == pytest.approx(math.sqrt(g_cf[i, i].real * g_cf[j, j].real), rel=1e-6)
+                want = g_ex[i, j] / math.sqrt(g_ex[i, i].real * g_ex[j, j].real) \
+                    - g_cf[i, j] / math.sqrt(g_cf[i, i].real * g_cf[j, j].real)
+                assert abs(tgt[p, 0] + 1j * tgt[p, 1] - want) < 1e-6
+                assert pm[p, 0] == d and pm[p, 1] == 64 * i + j
+                p += 1
+    assert p == pi.n
+    mlp.close()
+
+
+def test_forward_and_gradients_match_oracle(X, ctx):
+    rng = np.random.default_rng(11)
+    mlp = X.MLP(ctx, WIDTH, DEPTH)
+    params = OM.init_params(rng, WIDTH, DEPTH)
+    params[-OM.N_OUT:] = rng.normal(size=OM.N_OUT) * 0.1
+    params[-1] = -4.0
+    mlp.set_params(params.astype(np.float32))
+    assert np.array_equal(mlp.get_params(), params.astype(np.float32))
+    arr, drops, pi, *_ = _pairs(X, ctx, mlp, n_drops=40, k=16, stream=12)   # 4800 pairs: several tiles, ragged
+    out = mlp.forward(pi)
+    loss, grad = mlp.loss_grad(pi)
+    torch.cuda.synchronize()
+    pb = bf16_round(params)
+    # biases stay FP32 on the GPU
+    for (o, i), off in zip(OM.layer_shapes(WIDTH, DEPTH), np.cumsum([0] + [o * i + o for o, i in OM.layer_shapes(WIDTH, DEPTH)])):
+        pb[off + o * i: off + o * i + o] = params[off + o * i: off + o * i + o].astype(np.float32)
+    x = pi.feat.float().cpu().numpy()[:, :6].astype(np.float64)
+    ph = (pi.aux[:, 0:6:2] + 1j * pi.aux[:, 1:6:2]).cpu().numpy().astype(np.complex128)
+    tg = (pi.target[:, 0] + 1j * pi.target[:, 1]).cpu().numpy().astype(np.complex128)
+    ref_out, _ = OM.forward(pb, x, WIDTH, DEPTH)
+    o = out.cpu().numpy()
+    assert np.linalg.norm(o - ref_out) / np.linalg.norm(ref_out) < 2e-2
+    ref_loss, ref_g = OM.loss_grad(pb, x, ph, tg, WIDTH, DEPTH)
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-2)
+    g = grad.cpu().numpy()
+    off = 0
+    for li, (o_, i_) in enumerate(OM.layer_shapes(WIDTH, DEPTH)):
+        for name, size in (("W", o_ * i_), ("b", o_)):
+            a, r = g[off:off + size], ref_g[off:off + size]
+            err = np.linalg.norm(a - r) / np.linalg.norm(r)
+            tol = 5e-2 if (li == 0 and name == "W") else 2e-2
+            assert err < tol, (li, name, err)
+            off += size
+
+
+def test_training_reduces_loss_and_adam_matches(X, ctx):
+    rng = np.random.default_rng(13)
+    mlp = X.MLP(ctx, 64, 2)
+    params = OM.init_params(rng, 64, 2).astype(np.float32)
+    mlp.set_params(params)
+    arr, drops, pi, *_ = _pairs(X, ctx, mlp, n_drops=60, k=16, stream=14)
+    # one Adam step equals the reference update at the same gradient: first step moves by ~lr * sign(g)
+    loss, grad = mlp.loss_grad(pi)
+    mlp.train_step(pi, 1e-3)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    opt = OM.Adam(params.size, lr=1e-3)
+    want = opt.step(params.astype(np.float64), g)
+    got = mlp.get_params()
+    assert np.allclose(got, want, rtol=0, atol=2e-6)
+    losses = []
+    for s in range(300):
+        l = mlp.train_step(pi, 2e-3)
+        if s % 50 == 0:
+            losses.append(l.item())
+    assert losses[-1] < losses[0] - 1.0, losses

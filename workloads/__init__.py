@@ -215,3 +215,14 @@ def paper_sec5(n_drops: int = 100, n: int = 16384):
     arr = ula(n, LAMBDA_100GHZ, AMP_PNUSW)
     drops = rect_drops(rng_for(11), n_drops, 10, n, (1.0, 2.0), (-7.5, 7.5))
     return arr, drops, dict(t=0.9, rx_snr_limit_db=33.0, ref_point=(1.5, 0.0))
+
+
+def learned_drops(n_drops: int, stream: int = 0, k: int = 16, n_list=SWEEP_N):
+    """Drops of K users over the sweep's user law, N drawn per drop from the sweep's N set
+    (training and evaluation pairs of the learned correction: K(K-1)/2 pairs per drop)."""
+    rng = rng_for(4, stream)
+    ns = rng.choice(np.asarray(n_list, np.int64), size=n_drops)
+    r = rng.uniform(5.0, 50.0, size=(n_drops, k))
+    th = np.deg2rad(rng.uniform(-60.0, 60.0, size=(n_drops, k)))
+    pos = np.stack([r * np.cos(th), r * np.sin(th), np.zeros_like(r)], axis=-1).reshape(-1, 3)
+    return ula(n_list[-1], LAMBDA_28GHZ), _pack(ns, np.full(n_drops, k), pos)
