@@ -11,14 +11,22 @@ quadratic, and by the exact channel phases at the aperture ends (phasors).
 Pair inputs (user i, user j of one drop; x = perpendicular distance, y along the array):
   features  f = (r_i / 50, theta_i / (pi/3), r_j / 50, theta_j / (pi/3), log4(N) - 6, d/lambda - 1/2),
             r = sqrt(x^2 + y^2), theta = atan2(y, x) (polar coordinates about the array centre)
-  phasors   e^{j phi(y_top)}, e^{j phi(y_bot)}, e^{j phi(y*)} with
-            phi(y) = (2 pi / lambda) (r_i(y) - r_j(y)), r_u(y) = sqrt(x_u^2 + (y - y_u)^2),
-            y_top = -y_bot = (N - 1) d / 2 (end elements), y* the stationary point
-            (y_i x_j - x_i y_j) / (x_j - x_i)  (phasor 1 when x_i == x_j)
+  basis     three complex terms in correlation units (divided by sqrt(G~_ii G~_jj)):
+            b_top, b_bot = the end-element contributions of the discrete sum
+              sum_n f(y_n) e^{j phi(y_n)}: locally linear phase at the end element y_e gives the
+              geometric series f(y_e) e^{j phi(y_e)} / D, D = 1 - e^{-+ j phi'(y_e) d}
+              (- at the top end y_top = (N-1) d/2, + at the bottom end y_bot = -y_top);
+              1/D is regularised as conj(D) / (|D|^2 + eps^2) with the Fresnel scale
+              eps = d sqrt(|phi''(y_e)| / (2 pi)): |b| never exceeds f / (2 eps) (reached at
+              |D| = eps) and the term fades out where the phase becomes stationary at the end
+              (D -> 0), the regime the network and the exact fallback handle;
+            b_spm = e^{j phi(y*)}, y* the stationary point (y_i x_j - x_i y_j)/(x_j - x_i)
+              (1 when x_i == x_j);
+            phi(y) = (2 pi/lambda)(r_i(y) - r_j(y)), f = |h_i(y)| |h_j(y)| of the channel model.
   target    delta = rho_exact_ij - rho~_ij (complex)
 Network: 6 -> [Linear(w) + GELU] x depth -> Linear(7); GELU(z) = z (1 + erf(z / sqrt 2)) / 2.
 Output o: coefficients c_m = o[2m] + j o[2m+1] (m = top, bot, star) and s = o[6] = log sigma^2;
-  prediction  p = sum_m c_m e^{j phi_m}
+  prediction  p = sum_m c_m b_m   (c_top = c_bot = 1, c_spm = 0 is the analytic end correction)
   loss        mean over pairs of |delta - p|^2 e^{-s} + s        (Gaussian negative log-likelihood)
 Parameters, flat, layer by layer: W (out x in, row-major) then b (out).
 Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
@@ -78,15 +86,34 @@ def gelu_grad(z):
     return 0.5 * (1.0 + special.erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def pair_inputs(xp_i, y_i, xp_j, y_j, n, spacing, lam):
-    """Features [6], phasors [3] (complex) of one pair; x are perpendicular distances."""
+def pair_inputs(xp_i, y_i, xp_j, y_j, n, spacing, lam, cf_scale, amp_model=0, beta0=1.0):
+    """Features [6] and basis [3] (complex) of one pair; x are perpendicular distances,
+    cf_scale = sqrt(G~_ii G~_jj) of the closed form."""
     k = 2.0 * math.pi / lam
     r_i, r_j = math.hypot(xp_i, y_i), math.hypot(xp_j, y_j)
     f = np.array([r_i / R_NORM, math.atan2(y_i, xp_i) / THETA_NORM, r_j / R_NORM,
                   math.atan2(y_j, xp_j) / THETA_NORM, math.log(n) / math.log(4.0) - 6.0, spacing / lam - 0.5])
 
+    def dist(y):
+        return math.hypot(xp_i, y - y_i), math.hypot(xp_j, y - y_j)
+
     def phi(y):
-        return k * (math.hypot(xp_i, y - y_i) - math.hypot(xp_j, y - y_j))
+        a, b = dist(y)
+        return k * (a - b)
+
+    def amp(y):
+        a, b = dist(y)
+        if amp_model == 0:
+            return (lam / (4.0 * math.pi)) ** 2 / (a * b)
+        return beta0 * math.sqrt(xp_i * xp_j) / (a * b) ** 1.5
+
+    def end_term(y, sign):
+        a, b = dist(y)
+        d1 = k * ((y - y_i) / a - (y - y_j) / b)
+        d2 = k * (xp_i ** 2 / a ** 3 - xp_j ** 2 / b ** 3)
+        den = 1.0 - np.exp(-1j * sign * d1 * spacing)
+        eps2 = spacing ** 2 * abs(d2) / (2.0 * math.pi)
+        return amp(y) * np.exp(1j * phi(y)) * np.conj(den) / (abs(den) ** 2 + eps2) / cf_scale
 
     y_top = (n - 1) * spacing / 2.0
     if xp_i == xp_j:
@@ -94,7 +121,7 @@ def pair_inputs(xp_i, y_i, xp_j, y_j, n, spacing, lam):
     else:
         ys = (y_i * xp_j - xp_i * y_j) / (xp_j - xp_i)
         ps = np.exp(1j * phi(ys))
-    return f, np.array([np.exp(1j * phi(y_top)), np.exp(1j * phi(-y_top)), ps])
+    return f, np.array([end_term(y_top, 1.0), end_term(-y_top, -1.0), ps])
 
 
 def forward(params, x, width=256, depth=4):

@@ -321,7 +321,7 @@ struct xlmimo_mlp {
   float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
   __bf16* wbf = nullptr;
   int64_t t = 0;
-  DevBuf act, partial;
+  DevBuf act, partial, split;
 };
 
 namespace {
@@ -396,7 +396,13 @@ int mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, con
   return XLMIMO_OK;
 }
 
+// Split of the batch dimension for the weight-gradient GEMMs (dZ^T X reduces over pairs).
+constexpr int kGradSplits = 32;
+
 int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, hipStream_t s) {
+  int rc = ensure(c, M->split, sizeof(float) * (size_t)kGradSplits * M->width * std::max(M->width, XLMIMO_MLP_IN), s);
+  if (rc) return rc;
+  float* part = (float*)M->split.p;
   const __bf16* dz = a.dout;
   int64_t ldz = kOut;
   __bf16* bufs[2] = {a.da, a.db};
@@ -415,10 +421,9 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
     gw.B = x;
     gw.b_k = ldx;
     gw.b_n = 1;
-    gw.out_f = M->grad + M->w_off[l];
     gw.ldo = in;
-    HIP_TRY(c, launch_gemm(EPI_STORE_F32, gw, s));
-    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], s));
+    HIP_TRY(c, launch_gemm_splitk(gw, kGradSplits, part, M->grad + M->w_off[l], s));
+    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], part, kGradSplits, s));
     if (l > 0) {
       GemmArgs gx{};
       gx.M = (int)n;
@@ -564,6 +569,7 @@ int xlmimo_mlp_destroy(xlmimo_mlp* M) {
   (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
   if (M->act.p) (void)hipFree(M->act.p);
   if (M->partial.p) (void)hipFree(M->partial.p);
+  if (M->split.p) (void)hipFree(M->split.p);
   delete M;
   return XLMIMO_OK;
 }

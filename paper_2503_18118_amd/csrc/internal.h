@@ -60,8 +60,9 @@ struct GemmArgs {
   const float* bias;  // [N]: FWD_HIDDEN, FWD_OUT
   float* Z;           // FWD_HIDDEN: pre-activations out (may be null); BWD_DX: pre-activations in
   __bf16* out_bf;     // FWD_HIDDEN: GELU(z); BWD_DX: dZ of the previous layer
-  float* out_f;       // FWD_OUT, STORE_F32
+  float* out_f;       // FWD_OUT, STORE_F32 (split-K: [splits][M][ldo] partials)
   int64_t ldo;
+  int k_chunk;        // STORE_F32 split-K: K range per grid.z slice (0 = whole K)
 };
 
 // Launchers (stream-ordered, no host synchronisation).
@@ -91,7 +92,9 @@ hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_dro
                               int32_t* pmap, hipStream_t s);
 hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
                            double* partial, double* loss, hipStream_t s);
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, hipStream_t s);
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int splits,
+                         hipStream_t s);
+hipError_t launch_gemm_splitk(const GemmArgs& g, int splits, float* partial, float* out, hipStream_t s);
 hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s);
 hipError_t launch_to_bf16(int64_t n, const float* w, __bf16* wbf, hipStream_t s);

@@ -4,11 +4,13 @@
 // Not in the paper: the correction targets the regime where the paper notes the
 // modified ZF is worse (before saturation, Sec. V-C).  Per user pair (i < j):
 //   features  (r_i/50, theta_i/(pi/3), r_j/50, theta_j/(pi/3), log4 N - 6, d/lambda - 1/2)
-//   phasors   e^{j phi(y)} at the two end elements and at the stationary point,
-//             phi(y) = (2 pi/lambda)(r_i(y) - r_j(y))
+//   basis     b_top, b_bot: end-element terms of the discrete sum, f e^{j phi} / D with
+//             D = 1 - e^{-+ j phi' d} (geometric series of the locally linear phase),
+//             regularised by the Fresnel scale eps^2 = d^2 |phi''| / (2 pi);
+//             b_spm = e^{j phi(y*)} at the stationary point; phi(y) = (2 pi/lambda)(r_i(y) - r_j(y))
 //   network   6 -> [Linear(w) + GELU] x depth -> Linear(7)
 //   output    coefficients c_m (3 complex) and s = log sigma^2;
-//             delta_rho = sum_m c_m e^{j phi_m};  G_ij += delta_rho sqrt(G~_ii G~_jj)
+//             delta_rho = sum_m c_m b_m;  G_ij += delta_rho sqrt(G~_ii G~_jj)
 //   loss      mean |target - delta_rho|^2 e^{-s} + s   (Gaussian negative log-likelihood)
 //   optimiser Adam on FP32 master weights, BF16 copies for the matrix cores.
 //
@@ -49,19 +51,24 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8 k-values
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  int kb = 0, ke = g.K;
+  if (EPI == EPI_STORE_F32 && g.k_chunk > 0) {
+    kb = blockIdx.z * g.k_chunk;
+    ke = min(g.K, kb + g.k_chunk);
+  }
+  for (int k0 = kb; k0 < ke; k0 += TK) {
     {
       const int m = m0 + lr;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int k = k0 + lk + q;
-        sA[lr * LDS_K + lk + q] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.a_m + (int64_t)k * g.a_k] : (__bf16)0.0f;
+        sA[lr * LDS_K + lk + q] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.a_m + (int64_t)k * g.a_k] : (__bf16)0.0f;
       }
       const int n = n0 + lr;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int k = k0 + lk + q;
-        sB[lr * LDS_K + lk + q] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (__bf16)0.0f;
+        sB[lr * LDS_K + lk + q] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (__bf16)0.0f;
       }
     }
     __syncthreads();
@@ -98,11 +105,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         } else if constexpr (EPI == EPI_BWD_DX) {
           g.out_bf[o] = (__bf16)(v * gelu_grad(g.Z[o]));
         } else {
-          g.out_f[o] = v;
+          g.out_f[(int64_t)blockIdx.z * g.M * g.ldo + o] = v;
         }
       }
     }
   }
+}
+
+// out[i] = sum over splits of partial[split][i], in split order.
+__global__ void k_reduce_splits(const float* __restrict__ partial, int splits, int64_t n, float* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.0f;
+  for (int z = 0; z < splits; ++z) acc += partial[(int64_t)z * n + i];
+  out[i] = acc;
+}
+
+hipError_t launch_gemm_splitk(const GemmArgs& g0, int splits, float* partial, float* out, hipStream_t s) {
+  GemmArgs g = g0;
+  g.k_chunk = ((g.K + splits - 1) / splits + TK - 1) / TK * TK;
+  splits = (g.K + g.k_chunk - 1) / g.k_chunk;
+  g.out_f = partial;
+  dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
+  k_gemm_bf16<EPI_STORE_F32><<<grid, 256, 0, s>>>(g);
+  const int64_t n = (int64_t)g.M * g.ldo;
+  k_reduce_splits<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, splits, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s) {
@@ -158,12 +186,35 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
       const double di = y - yi, dj = y - yj;
       return (sqrt(fma(di, di, xi * xi)) - sqrt(fma(dj, dj, xj * xj))) * arr.inv_lambda;
     };
+    const double* gc = gram_cf + 2 * dp.gram_off;
+    const double scale = sqrt(gc[2 * (i * K + i)] * gc[2 * (j * K + j)]);
+    const double kw = 2.0 * kPiD * arr.inv_lambda;
+    const double c_fs = (lam / (4.0 * kPiD)) * (lam / (4.0 * kPiD));
+    // End-element term of the discrete sum: f e^{j phi} conj(D) / (|D|^2 + eps^2),
+    // D = 1 - e^{-j sign phi' d}, eps^2 = d^2 |phi''| / (2 pi), in correlation units.
+    auto end_term = [&](double y, double sign, float& br, float& bi) {
+      const double di = y - yi, dj = y - yj;
+      const double ra = sqrt(fma(di, di, xi * xi)), rb = sqrt(fma(dj, dj, xj * xj));
+      const double d1 = kw * (di / ra - dj / rb);
+      const double d2 = kw * (xi * xi / (ra * ra * ra) - xj * xj / (rb * rb * rb));
+      const double ang = sign * d1 * arr.spacing;
+      const double dre = 1.0 - cos(ang), dim = sin(ang);
+      const double den = dre * dre + dim * dim + arr.spacing * arr.spacing * fabs(d2) / (2.0 * kPiD);
+      const double amp = (arr.amp == XLMIMO_AMP_FREESPACE) ? c_fs / (ra * rb)
+                                                           : arr.beta0 * sqrt(xi * xj) / ((ra * rb) * sqrt(ra * rb));
+      float pr, pi;
+      phasor_turns(dphase(y), pr, pi);
+      const double g = amp / (den * scale);
+      // (pr + j pi)(dre - j dim)
+      br = (float)(g * ((double)pr * dre + (double)pi * dim));
+      bi = (float)(g * ((double)pi * dre - (double)pr * dim));
+    };
     const double ytop = 0.5 * (double)(dp.n_elems - 1) * arr.spacing;
     float pr, pi;
-    phasor_turns(dphase(ytop), pr, pi);
+    end_term(ytop, 1.0, pr, pi);
     aux[p * 8 + 0] = pr;
     aux[p * 8 + 1] = pi;
-    phasor_turns(dphase(-ytop), pr, pi);
+    end_term(-ytop, -1.0, pr, pi);
     aux[p * 8 + 2] = pr;
     aux[p * 8 + 3] = pi;
     if (xi != xj) {
@@ -174,9 +225,6 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
     }
     aux[p * 8 + 4] = pr;
     aux[p * 8 + 5] = pi;
-    const double* gc = gram_cf + 2 * dp.gram_off;
-    const double cii = gc[2 * (i * K + i)], cjj = gc[2 * (j * K + j)];
-    const double scale = sqrt(cii * cjj);
     aux[p * 8 + 6] = (float)scale;
     aux[p * 8 + 7] = 0.0f;
     if (target != nullptr) {
@@ -260,17 +308,25 @@ hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const 
   return hipGetLastError();
 }
 
-// db[c] = sum over rows of dZ[row][c] (fixed row order).
-__global__ void k_colsum(const __bf16* __restrict__ dz, int64_t rows, int cols, float* __restrict__ db) {
+// db[c] = sum over rows of dZ[row][c]: row slices in parallel, then the slices
+// in fixed order.
+__global__ void k_colsum_part(const __bf16* __restrict__ dz, int64_t rows, int cols, int64_t rows_per,
+                              float* __restrict__ partial) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  const int64_t r0 = blockIdx.y * rows_per, r1 = min(rows, r0 + rows_per);
   float acc = 0.0f;
-  for (int64_t r = 0; r < rows; ++r) acc += (float)dz[r * cols + c];
-  db[c] = acc;
+  for (int64_t r = r0; r < r1; ++r) acc += (float)dz[r * cols + c];
+  partial[(int64_t)blockIdx.y * cols + c] = acc;
 }
 
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, hipStream_t s) {
-  k_colsum<<<(cols + 255) / 256, 256, 0, s>>>(dz, rows, cols, db);
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int splits,
+                         hipStream_t s) {
+  const int64_t rows_per = (rows + splits - 1) / splits;
+  splits = (int)((rows + rows_per - 1) / rows_per);
+  dim3 grid((cols + 255) / 256, splits);
+  k_colsum_part<<<grid, 256, 0, s>>>(dz, rows, cols, rows_per, partial);
+  k_reduce_splits<<<(cols + 255) / 256, 256, 0, s>>>(partial, splits, cols, db);
   return hipGetLastError();
 }
 

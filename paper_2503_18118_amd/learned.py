@@ -18,8 +18,9 @@ from . import xlmimo as X
 
 
 def init_params(width: int, depth: int, rng: np.random.Generator, log_var0: float) -> np.ndarray:
-    """He-normal weights, zero biases; the output layer is scaled by 1e-2 and its
-    log-variance bias starts at log_var0 (the log of the targets' mean square)."""
+    """He-normal weights, zero biases; the output layer is scaled by 1e-2, its end-term
+    coefficients start at 1 (the analytic end correction) and its log-variance bias at
+    log_var0."""
     dims = [X.MLP_IN] + [width] * depth + [X.MLP_OUT]
     parts = []
     for li in range(len(dims) - 1):
@@ -28,6 +29,8 @@ def init_params(width: int, depth: int, rng: np.random.Generator, log_var0: floa
         b = np.zeros(fan_out)
         if li == len(dims) - 2:
             w *= 1e-2
+            b[0] = 1.0   # c_top = 1
+            b[2] = 1.0   # c_bot = 1
             b[6] = log_var0
         parts += [w.ravel(), b]
     return np.concatenate(parts).astype(np.float32)

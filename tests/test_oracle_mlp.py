@@ -63,22 +63,70 @@ def test_param_layout():
     assert w0.shape == (4, 6) and b0[0] == 24 and w2.shape == (7, 4)
 
 
-def test_phasors_are_exact_end_element_phases():
-    # e^{j phi(y_end)} equals the phase of conj(h_i) h_j at the end elements (channel oracle)
+def test_basis_phases_and_end_correction():
+    # the end terms carry the exact channel phase of conj(h_i) h_j at the end elements, and
+    # with c_top = c_bot = 1 they remove most of the closed form's error (the discrete sum's
+    # end contributions): pinned against the exact Gram of the channel oracle
     lam = W.LAMBDA_28GHZ
-    n = 1000
+    n = 256
     arr = W.ula(n, lam)
-    u = np.array([[7.0, 1.5, 0.0], [12.0, -3.0, 0.0]])
+    rng = np.random.default_rng(4)
+    errs_cf, errs_end = [], []
+    for _ in range(30):
+        r = rng.uniform(5, 50, 2)
+        th = np.deg2rad(rng.uniform(-60, 60, 2))
+        u = np.stack([r * np.cos(th), r * np.sin(th), np.zeros(2)], axis=-1)
+        g = och.gram_exact(arr, u)
+        gc = ocf.gram_closedform(arr, u, n, ocf.VARIANT_GATED)
+        sc = math.sqrt(gc[0, 0].real * gc[1, 1].real)
+        f, b = M.pair_inputs(u[0, 0], u[0, 1], u[1, 0], u[1, 1], n, arr.spacing, lam, sc)
+        ref = math.sqrt(g[0, 0].real * g[1, 1].real)
+        errs_cf.append(abs(gc[0, 1] - g[0, 1]) / ref)
+        errs_end.append(abs(gc[0, 1] + (b[0] + b[1]) * sc - g[0, 1]) / ref)
+    assert np.median(errs_end) < 1e-3 * np.median(errs_cf)
+    assert f[4] == pytest.approx(math.log(256) / math.log(4) - 6)
+
+
+def test_basis_end_term_matches_geometric_series():
+    # far from phi' = 0 the regularisation is negligible and b_top * cf_scale equals the
+    # geometric series f e^{j phi} / (1 - e^{-j phi' d}) evaluated from the channel itself
+    lam = W.LAMBDA_28GHZ
+    n = 64
+    arr = W.ula(n, lam)
+    u = np.array([[3.0, -2.0, 0.0], [9.0, 4.0, 0.0]])
     h = och.channel_matrix(arr, u)
-    f, ph = M.pair_inputs(7.0, 1.5, 12.0, -3.0, n, arr.spacing, lam)
-    top = h[-1, 0].conj() * h[-1, 1]
-    bot = h[0, 0].conj() * h[0, 1]
-    assert abs(ph[0] - top / abs(top)) < 1e-9
-    assert abs(ph[1] - bot / abs(bot)) < 1e-9
+    p_end = h[-1, 0].conj() * h[-1, 1]
+    p_prev = h[-2, 0].conj() * h[-2, 1]
+    ratio = p_prev / p_end                    # ~ e^{-j phi' d} |...| for the locally linear phase
+    series = p_end / (1 - ratio / abs(ratio))
+    f, b = M.pair_inputs(3.0, -2.0, 9.0, 4.0, n, arr.spacing, lam, 1.0)
+    assert abs(b[0] - series) < 2e-2 * abs(series)
     # the stationary-point phasor carries the eq. (6) phase before the -pi/4 offset
-    rho = ocf.rho_eq6(7.0, 1.5, 12.0, -3.0, n, lam)
-    assert abs(ph[2] * np.exp(-1j * math.copysign(1, 7.0 - 12.0) * math.pi / 4) - rho / abs(rho)) < 1e-9
-    assert f[4] == pytest.approx(math.log(1000) / math.log(4) - 6)
+    rho = ocf.rho_eq6(3.0, -2.0, 9.0, 4.0, n, lam)
+    assert abs(b[2] * np.exp(-1j * math.copysign(1, 3.0 - 9.0) * math.pi / 4) - rho / abs(rho)) < 1e-9
+
+
+def test_basis_end_term_is_bounded_where_phase_is_stationary():
+    # users on one ray leaving the top element make phi'(y_top) = 0: the geometric series
+    # would diverge; the regularised term is bounded by f / (2 eps), eps = d sqrt(|phi''| / 2 pi),
+    # and vanishes at the singular point itself
+    lam = W.LAMBDA_28GHZ
+    n = 101
+    d = lam / 2
+    yt = (n - 1) * d / 2
+    ang = math.radians(30)
+    k = 2 * math.pi / lam
+    for shift in (0.0, 1e-4, 1e-3, 1e-2):
+        xi, yi = 4 * math.cos(ang), yt - 4 * math.sin(ang) + shift
+        xj, yj = 9 * math.cos(ang), yt - 9 * math.sin(ang)
+        f, b = M.pair_inputs(xi, yi, xj, yj, n, d, lam, 1.0)
+        a, bb = math.hypot(xi, yt - yi), math.hypot(xj, yt - yj)
+        amp = (lam / (4 * math.pi)) ** 2 / (a * bb)
+        d2 = k * (xi ** 2 / a ** 3 - xj ** 2 / bb ** 3)
+        eps = d * math.sqrt(abs(d2) / (2 * math.pi))
+        assert abs(b[0]) <= amp / (2 * eps) * (1 + 1e-9)
+        if shift == 0.0:
+            assert abs(b[0]) < 1e-6 * amp / (2 * eps)
 
 
 def test_loss_is_minimised_by_the_target():
