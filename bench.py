@@ -4,11 +4,15 @@ One step = the capacity sweep workload (ULA at 28 GHz, N in {256, 1024, ...,
 262144}, K = 16 users, 10^4 seeded drops reused at every N, SNR {0, 10, 20} dB):
   * exact Gram in the FP32-compensated form for every (N, drop), ZF and MMSE
     sum-rates, ergodic means and the saturation point (xlmimo_capacity_sweep);
-  * the same sweep with the paper's closed-form (modified-ZF) Gram.
-The value is the unique Gram entries K(K+1)/2 produced per second over the
-whole step (both forms); per-form rates, accuracies against the FP64 exact
-form, the roofline of the exact-Gram kernel (timed live with HIP events on its
-launch stream) and the FP64 CPU oracle on a bounded sample are reported beside.
+  * the same sweep with the paper's closed-form (modified-ZF) Gram;
+  * the same sweep with the learned-corrected closed form (exact fallback for
+    drops whose predicted uncertainty exceeds the threshold).
+The network is trained before timing, on the GPU, from exact Grams of separate
+training drops.  The value is the unique Gram entries K(K+1)/2 produced per
+second over the whole step (all three forms); per-form rates, accuracies
+against the FP64 exact form, the roofline of the exact-Gram kernel (timed live
+with HIP events on its launch stream), the network's training and inference
+throughput, and the FP64 CPU oracle on a bounded sample are reported beside.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
 """
@@ -52,6 +56,10 @@ def traffic_per_launch():
     return rec["bytes_per_launch"] if rec.get("kernel_source_sha256") == h else None
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +68,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mlp-train-drops", type=int, default=20000)
+    ap.add_argument("--mlp-train-steps", type=int, default=3000)
+    ap.add_argument("--mlp-log-var-max", type=float, default=-11.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -103,6 +114,7 @@ def main():
     import torch
 
     import workloads as W
+    from paper_2503_18118_amd import learned as Lr
     from paper_2503_18118_amd import xlmimo as X
 
     if not torch.cuda.is_available():
@@ -127,7 +139,15 @@ def main():
     st_c = torch.empty_like(st_e)
     stream = torch.cuda.current_stream()
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(max(args.steps, args.warmup))]
+    log("training the learned correction")
+    mlp, mlp_info = train_mlp(ctx, X, Lr, W, args)
+    log(f"trained: {mlp_info['steps']} steps in {mlp_info['train_seconds']:.2f} s")
+    erg_m = torch.empty_like(erg_e)
+    sat_m = torch.empty_like(sat_e)
+    st_m = torch.empty_like(st_e)
+    lvmax = args.mlp_log_var_max
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(max(args.steps, args.warmup))]
 
     def step(e):
         e[0].record(stream)
@@ -135,10 +155,15 @@ def main():
         e[1].record(stream)
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED, rho, schemes, 0.9, 0.05, erg_c, sat_c, st_c)
         e[2].record(stream)
+        ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED_MLP, rho, schemes, 0.9, 0.05, erg_m, sat_m, st_m,
+                           mlp=mlp, log_var_max=lvmax)
+        e[3].record(stream)
 
+    log("warm-up")
     for i in range(args.warmup):
         step(ev[i])
     torch.cuda.synchronize()
+    log("timed steps")
 
     ctx.timing_enable(True)
     torch.cuda.synchronize()
@@ -149,11 +174,12 @@ def main():
     wall = time.perf_counter() - t0
     t_exact = sum(e[0].elapsed_time(e[1]) for e in ev[:args.steps])
     t_cf = sum(e[1].elapsed_time(e[2]) for e in ev[:args.steps])
+    t_mlp = sum(e[2].elapsed_time(e[3]) for e in ev[:args.steps])
     kern_ms, n_launch = ctx.timing_read()
     ctx.timing_enable(False)
     ms_per_step = wall * 1e3 / args.steps
 
-    value = 2 * entries_per_form / (ms_per_step * 1e-3)
+    value = 3 * entries_per_form / (ms_per_step * 1e-3)
     evals = n_drops * sum(n_list) * k
     pair_macs = n_drops * sum(n_list) * k * (k + 1) // 2
     flops_per_step = FLOP_PER_ENTRY_EVAL * evals + FLOP_PER_PAIR_MAC * pair_macs
@@ -169,12 +195,18 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "capacity sweep: ULA 28 GHz half-wavelength, N in {256..262144} (powers of 4), "
-                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32C + closed form",
+                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32C, closed form, "
+                                  "learned-corrected closed form",
                       "n_list": n_list, "drops": n_drops, "users": k, "snr_db": list(meta["snr_db"])},
            "forms": {"exact_fp32c": {"entries_per_s": entries_per_form / (t_exact * 1e-3 / args.steps),
                                      "ms": t_exact / args.steps},
                      "closedform_gated": {"entries_per_s": entries_per_form / (t_cf * 1e-3 / args.steps),
-                                          "ms": t_cf / args.steps}},
+                                          "ms": t_cf / args.steps},
+                     "mlp_corrected": {"entries_per_s": entries_per_form / (t_mlp * 1e-3 / args.steps),
+                                       "ms": t_mlp / args.steps, "log_var_max": lvmax,
+                                       "fallback_fraction_by_n": [float(x) for x in
+                                                                  (st_m & X.ST_FELL_BACK).ne(0).float().mean(dim=1).cpu()]}},
+           "mlp": mlp_info,
            "roofline": roofline}
 
     if args.copy_calibration:
@@ -184,20 +216,74 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 256 << 20
     if not args.no_accuracy:
-        out["accuracy"] = accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, out["forms"])
+        log("accuracy against the FP64 exact Gram")
+        out["accuracy"] = accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, out["forms"], mlp, lvmax)
+        log("network inference throughput")
+        out["mlp"]["inference"] = mlp_inference(ctx, X, Lr, W, mlp)
     if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(arr, drops, n_list, rho.cpu().numpy(), args.cpu_seconds)
+    mlp.close()
     ctx.close()
     print(json.dumps(out))
 
 
-def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms):
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+
+
+def mlp_flops_per_pair(width=256, depth=4, n_in=6, n_out=7):
+    dims = [n_in] + [width] * depth + [n_out]
+    return 2 * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+
+
+def train_mlp(ctx, X, Lr, W, args):
+    """Train the learned correction on exact Grams of separate drops (outside the timed region)."""
+    import torch
+    mlp = X.MLP(ctx, 256, 4)
+    tarr, tdrops = W.learned_drops(args.mlp_train_drops, stream=1)
+    t0 = time.perf_counter()
+    data, *_ = Lr.pair_set(ctx, mlp, tarr, tdrops)
+    var0 = float((data.target[:, 0] ** 2 + data.target[:, 1] ** 2).mean())
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    mlp.set_params(Lr.init_params(256, 4, np.random.default_rng(0), math.log(var0)))
+    batch = 8192
+    hist, secs = Lr.train(mlp, data, args.mlp_train_steps, batch=batch, lr_max=1e-3, lr_min=1e-5, log_every=500)
+    fl = 3 * mlp_flops_per_pair() * batch  # forward + two backward GEMMs per layer
+    return mlp, {"train_pairs": data.n, "train_drops": args.mlp_train_drops, "steps": args.mlp_train_steps,
+                 "batch": batch, "data_seconds": prep, "train_seconds": secs,
+                 "steps_per_s": args.mlp_train_steps / secs, "train_tflops": fl * args.mlp_train_steps / secs / 1e12,
+                 "loss_history": hist}
+
+
+def mlp_inference(ctx, X, Lr, W, mlp):
+    """Forward pass over 10^6 pairs (BF16 MFMA), timed with events on the launch stream."""
+    import torch
+    arr, drops = W.learned_drops(8334, stream=3)
+    pi, *_ = Lr.pair_set(ctx, mlp, arr, drops, with_targets=False)
+    pi = pi.slice(0, 1_000_000)
+    mlp.forward(pi)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(5):
+        mlp.forward(pi)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    tf = mlp_flops_per_pair() * pi.n / (ms * 1e-3) / 1e12
+    return {"pairs": pi.n, "ms": ms, "pairs_per_s": pi.n / (ms * 1e-3), "tflops": tf,
+            "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS, "frac_of_peak": tf / PEAK_BF16_MFMA_TFLOPS}
+
+
+def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=None, lvmax=0.0):
     """Per-drop sum-rate errors of the FP32C and closed-form Grams against the FP64 exact Gram."""
     import torch
     schemes = X.ZF | X.MMSE
     res = {"reference": "exact FP64 Gram on the GPU (parity-tested against the FP64 oracle)", "per_n": []}
-    admissible = []
+    admissible, admissible_mlp = [], []
     for n in n_list:
+        log(f"accuracy N={n}")
         b = X.Batch(drops.with_n(n), pos=batch.pos)
         a = arr.with_n(n)
         g64 = ctx.gram_exact(a, b, X.FP64)
@@ -207,6 +293,8 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms):
         r32, _ = ctx.sumrate(b, g32, rho, schemes)
         rcf, _ = ctx.sumrate(b, gcf, rho, schemes)
         rm, _ = ctx.sumrate(b, g64, rho, X.MZF_MISM, gram_filter=gcf)
+        gml, stm = ctx.gram_closedform_mlp(a, b, mlp, X.CF_GATED, log_var_max=lvmax)
+        rml, _ = ctx.sumrate(b, gml, rho, schemes)
         torch.cuda.synchronize()
         k = int(drops.n_users[0])
         gm = g64.view(-1, k, k, 2)
@@ -217,17 +305,24 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms):
         e32 = torch.abs(r32 / r64 - 1)
         ecf = torch.abs(rcf / r64 - 1)
         emm = torch.abs(rm[..., 0] / r64[..., 0] - 1)
+        eml = torch.abs(rml / r64 - 1)
         row = {"n": n, "fp32c_gram_normwise_max": gram_err,
                "fp32c_sumrate_rel_max": float(e32.max()),
                "closedform_sumrate_rel_max": float(torch.nan_to_num(ecf, nan=float("inf")).max()),
                "closedform_sumrate_rel_median": float(torch.nanmedian(ecf)),
-               "closedform_mismatched_zf_rel_max": float(torch.nan_to_num(emm, nan=float("inf")).max())}
+               "closedform_mismatched_zf_rel_max": float(torch.nan_to_num(emm, nan=float("inf")).max()),
+               "mlp_sumrate_rel_max": float(torch.nan_to_num(eml, nan=float("inf")).max()),
+               "mlp_sumrate_rel_median": float(torch.nanmedian(eml)),
+               "mlp_fallback_fraction": float((stm & X.ST_FELL_BACK).ne(0).float().mean())}
         res["per_n"].append(row)
         if row["closedform_sumrate_rel_max"] <= 1e-3:
             admissible.append(n)
+        if row["mlp_sumrate_rel_max"] <= 1e-3:
+            admissible_mlp.append(n)
     res["fp32c_meets_1e-5_gram_and_1e-3_rate"] = all(r["fp32c_gram_normwise_max"] <= 1e-5 and
                                                       r["fp32c_sumrate_rel_max"] <= 1e-3 for r in res["per_n"])
     res["closedform_admissible_n"] = admissible
+    res["mlp_admissible_n"] = admissible_mlp
     erg_rel = (erg_e - erg_c).abs() / erg_e.abs()
     res["closedform_ergodic_rel_err_by_n"] = [float(x) for x in erg_rel.amax(dim=(1, 2)).cpu()]
     return res

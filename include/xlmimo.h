@@ -215,6 +215,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N,
  * GELU] x depth -> Linear(XLMIMO_MLP_OUT); BF16 weights and activations on the
  * matrix cores, FP32 accumulation; FP32 master weights and Adam state.
  * Parameters, flat FP32: per layer W (out x in, row-major) then b (out). */
+/* An MLP belongs to its context: destroy it before the context. */
 int     xlmimo_mlp_create(xlmimo_ctx* ctx, int32_t width, int32_t depth, xlmimo_mlp** out);
 int     xlmimo_mlp_destroy(xlmimo_mlp* mlp);
 int64_t xlmimo_mlp_param_count(const xlmimo_mlp* mlp);
@@ -242,7 +243,8 @@ int xlmimo_mlp_loss_grad(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void
 /* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the loss above. */
 int xlmimo_mlp_train_step(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
                           const float* target, float lr, double* loss_out, void* stream);
-/* Network outputs, DEVICE float [n][XLMIMO_MLP_OUT]. */
+/* Network outputs, DEVICE float [n][XLMIMO_MLP_OUT].  Widths 64, 128 and 256 run
+ * one fused kernel (64 pairs per workgroup, activations kept in LDS). */
 int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, float* out,
                        void* stream);
 

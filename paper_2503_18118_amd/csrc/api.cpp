@@ -320,6 +320,7 @@ struct xlmimo_mlp {
   int64_t n_params = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
   __bf16* wbf = nullptr;
+  int64_t* d_offs = nullptr;  // per layer: weight offset, bias offset (fused inference)
   int64_t t = 0;
   DevBuf act, partial, split;
 };
@@ -398,6 +399,25 @@ int mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, con
 
 // Split of the batch dimension for the weight-gradient GEMMs (dZ^T X reduces over pairs).
 constexpr int kGradSplits = 32;
+
+// Inference outputs [n][XLMIMO_MLP_OUT] into `out`: fused single-kernel path for
+// widths 64/128/256, layer-by-layer GEMMs otherwise.
+int mlp_infer(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, float* out, hipStream_t s) {
+  if (M->width == 64 || M->width == 128 || M->width == 256) {
+    HIP_TRY(c, launch_mlp_fused_forward(M->width, M->depth, n, feat, M->wbf, M->master, M->d_offs, out, s));
+    return XLMIMO_OK;
+  }
+  const int64_t chunk = 1 << 20;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    Acts acts;
+    int rc = mlp_acts(c, M, m, false, acts, s);
+    if (rc) return rc;
+    if ((rc = mlp_forward(c, M, m, feat + off * kFeatPitch, acts, false, s))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(out + off * kOut, acts.out, sizeof(float) * m * kOut, hipMemcpyDeviceToDevice, s));
+  }
+  return XLMIMO_OK;
+}
 
 int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, hipStream_t s) {
   int rc = ensure(c, M->split, sizeof(float) * (size_t)kGradSplits * M->width * std::max(M->width, XLMIMO_MLP_IN), s);
@@ -491,24 +511,19 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   const size_t ab = (sizeof(float) * kAuxPitch * np + 255) / 256 * 256;
   const size_t pb = (sizeof(int32_t) * 2 * np + 255) / 256 * 256;
   const size_t flb = (sizeof(int32_t) * p->n_drops + 255) / 256 * 256;
-  if ((rc = ensure(c, c->scratch_pairs, fb + ab + pb + flb, s))) return rc;
+  const size_t ob = (sizeof(float) * kOut * np + 255) / 256 * 256;
+  if ((rc = ensure(c, c->scratch_pairs, fb + ab + pb + flb + ob, s))) return rc;
   char* base = (char*)c->scratch_pairs.p;
   __bf16* feat = (__bf16*)base;
   float* aux = (float*)(base + fb);
   int32_t* pmap = (int32_t*)(base + fb + ab);
   int32_t* flags = (int32_t*)(base + fb + ab + pb);
+  float* net_out = (float*)(base + fb + ab + pb + flb);
   HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 0, s));
   HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_out, nullptr, feat, aux,
                                 nullptr, pmap, s));
-  const int64_t chunk = 1 << 20;
-  for (int64_t off = 0; off < np; off += chunk) {
-    const int64_t n = std::min(chunk, np - off);
-    Acts acts;
-    if ((rc = mlp_acts(c, M, n, false, acts, s))) return rc;
-    if ((rc = mlp_forward(c, M, n, feat + off * kFeatPitch, acts, false, s))) return rc;
-    HIP_TRY(c, launch_mlp_apply(n, acts.out, aux + off * kAuxPitch, pmap + 2 * off, p->d_drops, gram_out, flags,
-                                (float)log_var_max, s));
-  }
+  if ((rc = mlp_infer(c, M, np, feat, net_out, s))) return rc;
+  HIP_TRY(c, launch_mlp_apply(np, net_out, aux, pmap, p->d_drops, gram_out, flags, (float)log_var_max, s));
   if ((rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s))) return rc;
   const int grid = std::min(p->grid_fp32, std::max(p->n_items, 1));
   HIP_TRY(c, launch_gram_exact(XLMIMO_FP32C, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
@@ -556,6 +571,19 @@ int xlmimo_mlp_create(xlmimo_ctx* c, int32_t width, int32_t depth, xlmimo_mlp** 
     delete M;
     return set_err(c, XLMIMO_ENOMEM, "MLP parameter allocation failed");
   }
+  std::vector<int64_t> offs;
+  for (int l = 0; l < M->n_layers; ++l) {
+    offs.push_back(M->w_off[l]);
+    offs.push_back(M->b_off[l]);
+  }
+  if (hipMalloc(&M->d_offs, sizeof(int64_t) * offs.size()) ||
+      hipMemcpy(M->d_offs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice)) {
+    (void)hipGetLastError();
+    (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
+    (void)hipFree(M->d_offs);
+    delete M;
+    return set_err(c, XLMIMO_ENOMEM, "MLP offset table allocation failed");
+  }
   *out = M;
   return XLMIMO_OK;
 }
@@ -570,6 +598,7 @@ int xlmimo_mlp_destroy(xlmimo_mlp* M) {
   if (M->act.p) (void)hipFree(M->act.p);
   if (M->partial.p) (void)hipFree(M->partial.p);
   if (M->split.p) (void)hipFree(M->split.p);
+  (void)hipFree(M->d_offs);
   delete M;
   return XLMIMO_OK;
 }
@@ -671,16 +700,7 @@ int xlmimo_mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* feat
   if (n == 0) return XLMIMO_OK;
   if (!out) return set_err(c, XLMIMO_EINVAL, "out is NULL");
   if ((rc = set_device(c))) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t chunk = 1 << 20;
-  for (int64_t off = 0; off < n; off += chunk) {
-    const int64_t m = std::min(chunk, n - off);
-    Acts acts;
-    if ((rc = mlp_acts(c, M, m, false, acts, s))) return rc;
-    if ((rc = mlp_forward(c, M, m, (const __bf16*)features + off * kFeatPitch, acts, false, s))) return rc;
-    HIP_TRY(c, hipMemcpyAsync(out + off * kOut, acts.out, sizeof(float) * m * kOut, hipMemcpyDeviceToDevice, s));
-  }
-  return XLMIMO_OK;
+  return mlp_infer(c, M, n, (const __bf16*)features, out, (hipStream_t)stream);
 }
 
 int xlmimo_gram_closedform_mlp(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t variant,

@@ -102,6 +102,8 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit, hipStream_t s);
 hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const int32_t* pmap, const DropK* d_drops,
                             double* gram, int32_t* flags, float log_var_max, hipStream_t s);
+hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
+                                    const float* master, const int64_t* d_offs, float* out, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;
 
 }  // namespace xl

@@ -415,4 +415,110 @@ hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const
   return hipGetLastError();
 }
 
+// Fused forward pass for inference: one workgroup carries a tile of 64 pairs
+// through every layer.  Activations stay in LDS (bf16, two buffers of
+// 64 x (W + 8)); weights are read from L2 as 16-byte fragments straight into
+// MFMA operand registers (W[o][k] is k-contiguous).  Wave w owns output columns
+// [w W/4, (w+1) W/4) of the hidden layers (4 x (W/64) blocks of 16 x 16) and row
+// block w of the output layer.
+template <int W>
+__global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth, const __bf16* __restrict__ feat,
+                                                           const __bf16* __restrict__ wbf,
+                                                           const float* __restrict__ master,
+                                                           const int64_t* __restrict__ offs, float* __restrict__ out) {
+  constexpr int P = W + 8;           // LDS row pitch (bf16): 16-byte aligned rows
+  constexpr int CB = W / 64;         // 16-column blocks per wave
+  __shared__ __attribute__((aligned(16))) __bf16 act[2][64 * P];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int kg = lane >> 4, li = lane & 15;
+  const bf16x8 zero8 = {};
+
+  // layer-0 input: 8 feature slots (6 used) per pair, zero up to K = 32
+  for (int i = tid; i < 64 * 32; i += 256) {
+    const int r = i >> 5, k = i & 31;
+    act[0][r * P + k] = (k < 8 && row0 + r < n) ? feat[(row0 + r) * 8 + k] : (__bf16)0.0f;
+  }
+  __syncthreads();
+
+  int cur = 0;
+  for (int l = 0; l < depth; ++l) {  // hidden layers
+    const int K = (l == 0) ? 32 : W;
+    const int in = (l == 0) ? XLMIMO_MLP_IN : W;
+    const __bf16* Wl = wbf + offs[2 * l];
+    const float* bl = master + offs[2 * l + 1];
+    floatx4 acc[4][CB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kk = k0 + 8 * kg;
+      bf16x8 af[4], bfr[CB];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&act[cur][(i * 16 + li) * P + kk]);
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int col = wave * (W / 4) + j * 16 + li;
+        if (l == 0) {
+          bf16x8 v = zero8;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (kk + q < in) v[q] = Wl[col * in + kk + q];
+          bfr[j] = v;
+        } else {
+          bfr[j] = *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)col * W + kk]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    const int nxt = cur ^ 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int col = wave * (W / 4) + j * 16 + li;
+        const float b = bl[col];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) act[nxt][(i * 16 + 4 * kg + r) * P + col] = (__bf16)gelu(acc[i][j][r] + b);
+      }
+    __syncthreads();
+    cur = nxt;
+  }
+
+  // output layer: XLMIMO_MLP_OUT columns (one 16-column block), wave w takes rows 16w..16w+15
+  {
+    const __bf16* Wl = wbf + offs[2 * depth];
+    const float* bl = master + offs[2 * depth + 1];
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < W; k0 += 32) {
+      const int kk = k0 + 8 * kg;
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[cur][(wave * 16 + li) * P + kk]);
+      const bf16x8 bfr = (li < XLMIMO_MLP_OUT) ? *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)li * W + kk]) : zero8;
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc, 0, 0, 0);
+    }
+    if (li < XLMIMO_MLP_OUT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wave * 16 + 4 * kg + r;
+        if (row < n) out[row * XLMIMO_MLP_OUT + li] = acc[r] + bl[li];
+      }
+    }
+  }
+}
+
+hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
+                                    const float* master, const int64_t* d_offs, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 63) / 64);
+  if (width == 256) k_mlp_fused_forward<256><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
+  else if (width == 128) k_mlp_fused_forward<128><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
+  else if (width == 64) k_mlp_fused_forward<64><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace xl

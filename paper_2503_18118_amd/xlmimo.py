@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -144,9 +145,12 @@ class Context:
         if rc != OK:
             raise XlmimoError(f"xlmimo_ctx_create failed ({rc})")
         self.h = h
+        self._children = weakref.WeakSet()   # MLPs of this context, destroyed before it
 
     def close(self):
         if getattr(self, "h", None):
+            for child in list(self._children):
+                child.close()
             _lib.xlmimo_ctx_destroy(self.h)
             self.h = None
 
@@ -266,11 +270,13 @@ class MLP:
         ctx._check(_lib.xlmimo_mlp_create(ctx.h, width, depth, C.byref(h)), "xlmimo_mlp_create")
         self.h = h
         self.n_params = int(_lib.xlmimo_mlp_param_count(h))
+        ctx._children.add(self)
 
     def close(self):
-        if getattr(self, "h", None):
+        # the context destroys its MLPs first; after that this handle is gone
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             _lib.xlmimo_mlp_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

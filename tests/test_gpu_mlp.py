@@ -143,3 +143,25 @@ def test_training_reduces_loss_and_adam_matches(X, ctx):
         if s % 50 == 0:
             losses.append(l.item())
     assert losses[-1] < losses[0] - 1.0, losses
+
+
+@pytest.mark.parametrize("width,depth,n_drops", [(64, 2, 3), (128, 3, 5), (256, 1, 2)])
+def test_fused_forward_other_shapes(X, ctx, width, depth, n_drops):
+    # the fused inference kernel at every width it supports, with a ragged last tile
+    rng = np.random.default_rng(width + depth)
+    mlp = X.MLP(ctx, width, depth)
+    params = OM.init_params(rng, width, depth)
+    params[-OM.N_OUT:] = rng.normal(size=OM.N_OUT) * 0.1
+    mlp.set_params(params.astype(np.float32))
+    arr, drops, pi, *_ = _pairs(X, ctx, mlp, n_drops=n_drops, k=11, stream=20 + width)   # 55 pairs per drop
+    out = mlp.forward(pi).cpu().numpy()
+    pb = bf16_round(params)
+    shapes = OM.layer_shapes(width, depth)
+    off = 0
+    for o, i in shapes:
+        pb[off + o * i: off + o * i + o] = params[off + o * i: off + o * i + o].astype(np.float32)
+        off += o * i + o
+    x = pi.feat.float().cpu().numpy()[:, :6].astype(np.float64)
+    ref, _ = OM.forward(pb, x, width, depth)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 2e-2
+    mlp.close()
