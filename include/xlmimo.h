@@ -64,6 +64,12 @@ extern "C" {
  *        of at most 256 elements whose partial sums are carried in FP64. */
 #define XLMIMO_FP64  0
 #define XLMIMO_FP32C 1
+/* FP32H: FP32C entries, each scaled per user by a power of two (|x| <= 1) and
+ *        split as hi + lo (FP16 each, rounded to nearest); products hi hi +
+ *        hi lo + lo hi on the FP16 matrix cores with FP32 accumulation, carried
+ *        in FP64 as for FP32C.  Each product is exact to ~2^-22 relative
+ *        (FP32 level); users need x_perp >= 2^-100 wavelengths. */
+#define XLMIMO_FP32H 2
 
 /* Closed-form variants (eqs. (4), (6), (22), (23); see xlmimo_gram_closedform). */
 #define XLMIMO_CF_PAPER 0      /* formulas as printed, for every pair */
@@ -92,6 +98,7 @@ extern "C" {
 #define XLMIMO_FORM_CF_PAPER    2
 #define XLMIMO_FORM_CF_GATED    3
 #define XLMIMO_FORM_CF_GATED_MLP 4  /* gated closed form + learned residual + exact fallback */
+#define XLMIMO_FORM_EXACT_FP32H 5   /* exact Gram at XLMIMO_FP32H precision */
 
 #define XLMIMO_MAX_USERS 64
 
@@ -143,7 +150,7 @@ int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
 /* Exact Gram G = H^H H (Sec. III: G_ii = P_i / P, rho_ij = G_ij / sqrt(G_ii G_jj);
  * Sec. V-B: the inner products the paper accelerates).  H is generated on the
  * fly from the geometry and user positions and never stored.
- *   precision  XLMIMO_FP64 or XLMIMO_FP32C
+ *   precision  XLMIMO_FP64, XLMIMO_FP32C or XLMIMO_FP32H
  *   gram_out   DEVICE complex128, layout above
  * Drops with a non-finite position or a user at distance 0 from an element
  * get NaN entries (no status array here; xlmimo_zf_mmse_sumrate flags them). */

@@ -33,7 +33,7 @@ struct Plan {
   int64_t gram_elems = 0;    // complex elements of the whole Gram output
   int64_t n_pairs = 0;       // user pairs i < j over all drops
   int64_t partial_doubles = 0;
-  int grid_fp32 = 0, grid_fp64 = 0;
+  int grid_fp32 = 0, grid_fp64 = 0, grid_fp32h = 0;
   DropK* d_drops = nullptr;
   ItemK* d_items = nullptr;
 };
@@ -161,7 +161,7 @@ int64_t chunk_length(int64_t total_elems, int grid) {
   int64_t target = total_elems / (8LL * std::max(grid, 1));
   target = std::max<int64_t>(target, 2048);
   target = std::min<int64_t>(target, 65536);
-  return (target + 15) / 16 * 16;
+  return (target + 127) / 128 * 128;  // whole rounds of both FP32 kernels (16 and 128 elements)
 }
 
 // Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
@@ -218,6 +218,7 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   p.n_pairs = pairs;
   p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
+  p.grid_fp32h = gram_exact_grid(XLMIMO_FP32H, p.nb_max, a->geometry, a->amp_model);
   const int64_t ch = chunk_length(total_elems, std::min(p.grid_fp32, p.grid_fp64));
   std::vector<ItemK> items;
   std::vector<int64_t> cost;
@@ -281,7 +282,8 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   if (rc) return rc;
   rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s);
   if (rc) return rc;
-  const int grid = std::min(precision == XLMIMO_FP64 ? p->grid_fp64 : p->grid_fp32, std::max(p->n_items, 1));
+  const int g_prec = precision == XLMIMO_FP64 ? p->grid_fp64 : (precision == XLMIMO_FP32H ? p->grid_fp32h : p->grid_fp32);
+  const int grid = std::min(g_prec, std::max(p->n_items, 1));
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
@@ -806,7 +808,8 @@ int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* 
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
-  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C) return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
+  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C && precision != XLMIMO_FP32H)
+    return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
   if ((rc = set_device(c))) return rc;
@@ -870,7 +873,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   int rc = check_array(c, a);
   if (rc) return rc;
   if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the capacity sweep varies a ULA's N");
-  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_CF_GATED_MLP) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
+  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_EXACT_FP32H) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
   if (form == XLMIMO_FORM_CF_GATED_MLP && (!mlp || mlp->ctx != c)) return set_err(c, XLMIMO_EINVAL, "the MLP form needs an mlp of this context");
   if (n_N < 1 || !N_list) return set_err(c, XLMIMO_EINVAL, "N_list is empty");
   for (int i = 0; i < n_N; ++i) {
@@ -879,7 +882,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   }
   if (!(t_sat > 0.0 && t_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "t_sat must lie in (0, 1)");
   if (!(eps_sat >= 0.0 && eps_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "eps_sat must lie in [0, 1)");
-  const bool cf = form >= XLMIMO_FORM_CF_PAPER;
+  const bool cf = form >= XLMIMO_FORM_CF_PAPER && form <= XLMIMO_FORM_CF_GATED_MLP;
   if (!cf && (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM)))
     return set_err(c, XLMIMO_EINVAL, "modified-ZF schemes need a closed-form sweep");
   if ((rc = check_rates_args(c, b, (const double*)1, (const double*)1, n_snr, rho, schemes))) return rc;
@@ -917,7 +920,9 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
     const int64_t nn = N_list[i];
     int32_t* st = status_out ? status_out + (int64_t)i * nd : nullptr;
     if (!cf) {
-      if ((rc = gram_exact_impl(c, a, b, &nn, form == XLMIMO_FORM_EXACT_FP64 ? XLMIMO_FP64 : XLMIMO_FP32C, g, s))) return rc;
+      const int prec = form == XLMIMO_FORM_EXACT_FP64 ? XLMIMO_FP64
+                       : (form == XLMIMO_FORM_EXACT_FP32H ? XLMIMO_FP32H : XLMIMO_FP32C);
+      if ((rc = gram_exact_impl(c, a, b, &nn, prec, g, s))) return rc;
     } else {
       const int variant = form == XLMIMO_FORM_CF_PAPER ? XLMIMO_CF_PAPER : XLMIMO_CF_GATED;
       if (form == XLMIMO_FORM_CF_GATED_MLP) {

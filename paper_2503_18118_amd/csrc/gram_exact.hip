@@ -72,8 +72,10 @@ struct Mfma<double> {
 // gfx950: |error| <= 1.3e-7 over a full turn).  Lanes with nothing to contribute
 // (users beyond K, elements past the end) carry a coordinate of 1e30:
 // rsq(inf) = 0 makes their entry exactly zero.
+// us scales the amplitude (a power of two: exact).
 template <int GEOM, int AMP>
-__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im) {
+__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im,
+                                              float us = 1.0f) {
   double r2 = fma(dy, dy, xp2);
   if constexpr (GEOM == XLMIMO_UPA) r2 = fma(dz, dz, r2);
   const float yf = __builtin_amdgcn_rsqf((float)r2);
@@ -83,6 +85,7 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
   const float t = (float)__builtin_amdgcn_fract(r);
   float a = yf;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * __builtin_amdgcn_sqrtf(a);
+  a = a * us;
   re = a * __builtin_amdgcn_cosf(t);
   im = -a * __builtin_amdgcn_sinf(t);
 }
@@ -104,6 +107,28 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
   if (((int)qd) & 1) a = -a;
   re = a * c;
   im = a * ns;
+}
+
+// Squared distance of a user from the array line (ULA) or plane (UPA); the
+// finalize pass recomputes it bit for bit for the split-half scales.
+__device__ __forceinline__ double perp2(int geom, double x, double z) {
+  return geom == XLMIMO_ULA ? fma(x, x, z * z) : x * x;
+}
+
+// Fixed-order sum of the 4 waves' partials through LDS, then one coalesced store.
+template <int NV>
+__device__ __forceinline__ void store_partial(const double* fin, double* s_red, double* __restrict__ part_out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int w = 0; w < kGramThreads / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_red[v * 64 + lane] = (w == 0) ? fin[v] : s_red[v * 64 + lane] + fin[v];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < NV * 64; i += kGramThreads) part_out[i] = s_red[i];
+  __syncthreads();
 }
 
 template <int NB, typename T, int GEOM, int AMP>
@@ -131,7 +156,7 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
       y = p[1] * sc;
       z = p[2] * sc;
     }
-    u[b].xp2 = (GEOM == XLMIMO_ULA) ? fma(x, x, z * z) : x * x;
+    u[b].xp2 = perp2(GEOM, x, z);
     u[b].uy = y;
     u[b].uz = z;
   }
@@ -262,19 +287,203 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
     for (int c = 0; c < 4; ++c) fin[(NRE + i) * 4 + c] = F32 ? carry[(NRE + i) * 4 + c] : (double)ax[i][c];
   }
 
-  // Fixed-order reduction over the 4 waves through LDS.
-  for (int w = 0; w < kGramThreads / 64; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) s_red[v * 64 + lane] = (w == 0) ? fin[v] : s_red[v * 64 + lane] + fin[v];
-    }
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < NV * 64; i += kGramThreads) part_out[i] = s_red[i];
-  __syncthreads();
+  store_partial<NV>(fin, s_red, part_out);
 }
 
-template <int NBMAX, typename T, int GEOM, int AMP>
+// ---------------------------------------------------------------------------
+// FP32H: FP32C channel entries, products on the FP16 matrix cores.
+//
+// Each entry x (scaled per user by 2^q, a power of two chosen from the user's
+// distance to the array so that |x| <= 1) is split as x = hi + lo with
+// hi = f16(x), lo = f16(x - hi), both rounded to nearest; then
+//   x_i x_j = hi_i hi_j + hi_i lo_j + lo_i hi_j + (lo_i lo_j, dropped)
+// with |dropped| + rounding of lo <= ~2^-22 |x_i x_j| (or 2^-25 absolute where
+// lo is subnormal), i.e. FP32-level products.  Three 16x16x32 FP16 MFMA per
+// product stream cover 32 elements where FP32 MFMA needs eight.
+// Work layout: a round covers 128 elements; wave w takes 32 of them and lane l
+// evaluates user 16b + (l % 16) at the 8 consecutive elements 8 (l / 16) + m,
+// m = 0..7 (the 16x16x32 operand layout: lane l holds row l % 16, k-block l / 16).
+// Products accumulate in FP32 over 8 rounds (256 elements per wave), then in FP64.
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+constexpr int kSplitRound = 128;
+constexpr int kSplitFlush = 8;
+constexpr int kSplitMaxNb = 2;  // user blocks of 16 handled by the split kernel
+
+__device__ __forceinline__ floatx4 mfma_h(halfx8 a, halfx8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Exponent q of the per-user scale 2^q: max over the array of |h| 2^q <= 1, from
+// |h| <= xp2^{-1/2} (free space) or xp2^{-3/4} (PNUSW), xp2 the squared
+// perpendicular distance in wavelengths.  Shared with the finalize pass.
+__device__ __forceinline__ int split_exp(double xp2, int amp) {
+  const int e = (xp2 > 0.0 && xp2 < 1e300) ? ilogb(xp2) : 0;
+  const int q = amp == XLMIMO_AMP_FREESPACE ? (e >> 1) : ((3 * e) >> 2);
+  return min(max(q, -100), 100);
+}
+
+// entries m, m + 1 of the hi and lo operands
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split2(float x0, float x1, halfx8& h, halfx8& l, int m) {
+  // hi and lo must both come from the same FP32 value: the empty asm stops the
+  // compiler from folding the product that made x into either conversion
+  asm volatile("" : "+v"(x0), "+v"(x1));
+  const halfx2 hv = __builtin_convertvector((floatx2){x0, x1}, halfx2);
+  h[m] = hv[0];
+  h[m + 1] = hv[1];
+  // x - hi is exact in FP32; one rounding to FP16
+  l[m] = (_Float16)__builtin_fmaf((float)hv[0], -1.0f, x0);
+  l[m + 1] = (_Float16)__builtin_fmaf((float)hv[1], -1.0f, x1);
+}
+
+template <int NB, int GEOM, int AMP>
+__device__ void process_item_split(const ArrayK& arr, const DropK& dp, const ItemK& it,
+                                   const double* __restrict__ pos, double* __restrict__ part_out, double* s_red) {
+  constexpr int NRE = NB * (NB + 1) / 2;
+  constexpr int NX = NB * NB;
+  constexpr int NV = (NRE + NX) * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const double sc = arr.inv_lambda;  // wavelengths: r counts turns
+  constexpr double kFar = 1e30;
+
+  UserLane u[NB];
+  float us[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int k = 16 * b + (lane & 15);
+    double x = kFar, y = 0.0, z = 0.0;
+    if (k < dp.k) {
+      const double* p = pos + (dp.user_off + k) * 3;
+      x = p[0] * sc;
+      y = p[1] * sc;
+      z = p[2] * sc;
+    }
+    u[b].xp2 = perp2(GEOM, x, z);
+    u[b].uy = y;
+    u[b].uz = z;
+    us[b] = k < dp.k ? __builtin_ldexpf(1.0f, split_exp(u[b].xp2, AMP)) : 1.0f;
+  }
+
+  floatx4 are[NRE], ax[NX];
+#pragma unroll
+  for (int i = 0; i < NRE; ++i) are[i] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < NX; ++i) ax[i] = floatx4{0, 0, 0, 0};
+  double carry[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) carry[i] = 0.0;
+
+  const int len = it.e_end - it.e_begin;
+  const int n_full = len / kSplitRound;
+  const int n_rounds = (len + kSplitRound - 1) / kSplitRound;
+  const int sub = 32 * wave + 8 * (lane >> 4);  // lane's first element within a round
+  const int ny = (GEOM == XLMIMO_ULA) ? dp.n_elems : arr.n_y;
+  const double ds = arr.spacing * sc;
+  const double cy = 0.5 * (double)(ny - 1) * ds;
+  const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
+
+  // One round: the lane's 8 elements start at element index e; elements at or
+  // past e_end (only in the last round, TAIL) take the far coordinate.
+  auto round = [&](int e, auto tail_tag) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
+    halfx8 rh[NB], rl[NB], ih[NB], il[NB];
+    if constexpr (GEOM == XLMIMO_ULA) {
+      const double ey = fma((double)e, ds, -cy);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        double dy = u[b].uy - ey;
+#pragma unroll
+        for (int m = 0; m < 8; m += 2) {
+          double d0 = dy, d1 = dy - ds;
+          dy -= 2.0 * ds;
+          if constexpr (TAIL) {
+            d0 = e + m < it.e_end ? d0 : kFar;
+            d1 = e + m + 1 < it.e_end ? d1 : kFar;
+          }
+          float re0, im0, re1, im1;
+          channel_entry<GEOM, AMP>(d0, 0.0, u[b].xp2, re0, im0, us[b]);
+          channel_entry<GEOM, AMP>(d1, 0.0, u[b].xp2, re1, im1, us[b]);
+          split2(re0, re1, rh[b], rl[b], m);
+          split2(im0, im1, ih[b], il[b], m);
+        }
+      }
+    } else {
+      int ea = e / arr.n_z;
+      int eb = e - ea * arr.n_z;
+      float re[NB][2], im[NB][2];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        double ey = fma((double)ea, ds, -cy);
+        const double ez = fma((double)eb, ds, -cz);
+        if constexpr (TAIL) ey = e + m < it.e_end ? ey : kFar;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          channel_entry<GEOM, AMP>(u[b].uy - ey, u[b].uz - ez, u[b].xp2, re[b][m & 1], im[b][m & 1], us[b]);
+        if (m & 1) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            split2(re[b][0], re[b][1], rh[b], rl[b], m - 1);
+            split2(im[b][0], im[b][1], ih[b], il[b], m - 1);
+          }
+        }
+        if (++eb == arr.n_z) {
+          eb = 0;
+          ++ea;
+        }
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+      for (int bj = bi; bj < NB; ++bj) {
+        floatx4& c = are[tri_index(bi, bj, NB)];
+        c = mfma_h(rh[bi], rh[bj], c);
+        c = mfma_h(ih[bi], ih[bj], c);
+        c = mfma_h(rh[bi], rl[bj], c);
+        c = mfma_h(ih[bi], il[bj], c);
+        c = mfma_h(rl[bi], rh[bj], c);
+        c = mfma_h(il[bi], ih[bj], c);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+      for (int bj = 0; bj < NB; ++bj) {
+        floatx4& c = ax[bi * NB + bj];
+        c = mfma_h(rh[bi], ih[bj], c);
+        c = mfma_h(rh[bi], il[bj], c);
+        c = mfma_h(rl[bi], ih[bj], c);
+      }
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < NRE; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) carry[i * 4 + c] += (double)are[i][c];
+      are[i] = floatx4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) carry[(NRE + i) * 4 + c] += (double)ax[i][c];
+      ax[i] = floatx4{0, 0, 0, 0};
+    }
+  };
+
+  const int e0 = it.e_begin + sub;
+  for (int r0 = 0; r0 < n_rounds; r0 += kSplitFlush) {
+    const int r1 = min(r0 + kSplitFlush, n_full);
+    for (int r = r0; r < r1; ++r) round(e0 + kSplitRound * r, std::false_type{});
+    if (r0 + kSplitFlush >= n_rounds && n_rounds > n_full) round(e0 + kSplitRound * n_full, std::true_type{});
+    flush();
+  }
+  store_partial<NV>(carry, s_red, part_out);
+}
+
+template <int NBMAX, typename T, int GEOM, int AMP, bool SPLIT>
 __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
                                                                const double* __restrict__ pos,
                                                                const ItemK* __restrict__ items, int n_items,
@@ -293,12 +502,23 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
     if (mask != nullptr && mask[it.drop] == 0) continue;  // drop not selected: skip its items
     const DropK dp = drops[it.drop];
     double* out = partials + dp.part_off + it.chunk * (int64_t)(partial_values(dp.nb) * 64);
-    switch (dp.nb) {
-      case 1: process_item<1, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-      case 2: if constexpr (NBMAX >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-      case 3: if constexpr (NBMAX >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-      case 4: if constexpr (NBMAX >= 4) process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-      default: break;
+    if constexpr (SPLIT) {
+      switch (dp.nb) {
+        case 1: process_item_split<1, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 2: if constexpr (NBMAX >= 2) process_item_split<2, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        // more than 32 users: the split operands do not fit beside the FP64 carries; FP32C products
+        case 3: if constexpr (NBMAX >= 3) process_item<3, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 4: if constexpr (NBMAX >= 4) process_item<4, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        default: break;
+      }
+    } else {
+      switch (dp.nb) {
+        case 1: process_item<1, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 2: if constexpr (NBMAX >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 3: if constexpr (NBMAX >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 4: if constexpr (NBMAX >= 4) process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        default: break;
+      }
     }
   }
 }
@@ -324,7 +544,7 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
                                                        const double* __restrict__ pos,
                                                        const double* __restrict__ partials,
                                                        double* __restrict__ gram,
-                                                       const int32_t* __restrict__ mask) {
+                                                       const int32_t* __restrict__ mask, int split) {
   if (mask != nullptr && mask[blockIdx.x] == 0) return;
   const DropK dp = drops[blockIdx.x];
   const int K = dp.k, NB = dp.nb;
@@ -360,42 +580,52 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
       const double xq = (arr.geom == XLMIMO_ULA) ? sqrt(fma(uq[0], uq[0], uq[2] * uq[2])) : fabs(uq[0]);
       scale = arr.beta0 * sqrt(xp * xq) * su * su * su;
     }
+    if (split && NB <= kSplitMaxNb) {
+      // undo the per-user scales 2^q of the split-half entries (exact powers of two)
+      const double* up = pos + (dp.user_off + p) * 3;
+      const double* uq = pos + (dp.user_off + q) * 3;
+      const int qp = split_exp(perp2(arr.geom, up[0] * su, up[2] * su), arr.amp);
+      const int qq = split_exp(perp2(arr.geom, uq[0] * su, uq[2] * su), arr.amp);
+      scale = ldexp(scale, -(qp + qq));
+    }
     if (i > j) im = -im;  // G_ji = conj(G_ij)
     gram[(dp.gram_off + idx) * 2] = re * scale;
     gram[(dp.gram_off + idx) * 2 + 1] = im * scale;
   }
 }
 
-template <int NBMAX, typename T, int GEOM, int AMP>
+template <int NBMAX, typename T, int GEOM, int AMP, bool SPLIT>
 static int occupancy_grid() {
   static int cached = 0;
   if (!cached) {
     int dev = 0, n_cu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gram_exact<NBMAX, T, GEOM, AMP>, kGramThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gram_exact<NBMAX, T, GEOM, AMP, SPLIT>, kGramThreads, 0);
     cached = (n_cu > 0 ? n_cu : 256) * (per_cu > 0 ? per_cu : 1);
   }
   return cached;
 }
 
-template <typename T, int GEOM, int AMP>
+template <typename T, int GEOM, int AMP, bool SPLIT>
 static int grid_nb(int nb_max) {
-  return nb_max <= 1 ? occupancy_grid<1, T, GEOM, AMP>()
-                     : (nb_max <= 2 ? occupancy_grid<2, T, GEOM, AMP>() : occupancy_grid<4, T, GEOM, AMP>());
+  return nb_max <= 1 ? occupancy_grid<1, T, GEOM, AMP, SPLIT>()
+                     : (nb_max <= 2 ? occupancy_grid<2, T, GEOM, AMP, SPLIT>() : occupancy_grid<4, T, GEOM, AMP, SPLIT>());
 }
 
-template <typename T>
+template <typename T, bool SPLIT>
 static int grid_t(int nb_max, int geom, int amp) {
   if (geom == XLMIMO_ULA)
-    return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE>(nb_max)
-                                       : grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW>(nb_max);
-  return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE>(nb_max)
-                                     : grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW>(nb_max);
+    return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE, SPLIT>(nb_max)
+                                       : grid_nb<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW, SPLIT>(nb_max);
+  return amp == XLMIMO_AMP_FREESPACE ? grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE, SPLIT>(nb_max)
+                                     : grid_nb<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW, SPLIT>(nb_max);
 }
 
 int gram_exact_grid(int precision, int nb_max, int geom, int amp) {
-  return precision == XLMIMO_FP64 ? grid_t<double>(nb_max, geom, amp) : grid_t<float>(nb_max, geom, amp);
+  if (precision == XLMIMO_FP64) return grid_t<double, false>(nb_max, geom, amp);
+  if (precision == XLMIMO_FP32H) return grid_t<float, true>(nb_max, geom, amp);
+  return grid_t<float, false>(nb_max, geom, amp);
 }
 
 struct MainArgs {
@@ -409,24 +639,24 @@ struct MainArgs {
   const int32_t* mask;
 };
 
-template <typename T, int GEOM, int AMP>
+template <typename T, int GEOM, int AMP, bool SPLIT>
 static void launch_main(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
   if (nb_max <= 1)
-    k_gram_exact<1, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<1, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
   else if (nb_max <= 2)
-    k_gram_exact<2, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<2, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
   else
-    k_gram_exact<4, T, GEOM, AMP><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<4, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
 }
 
-template <typename T>
+template <typename T, bool SPLIT>
 static void launch_t(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
   if (a.arr.geom == XLMIMO_ULA) {
-    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE>(nb_max, grid, s, a);
-    else launch_main<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW>(nb_max, grid, s, a);
+    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_ULA, XLMIMO_AMP_FREESPACE, SPLIT>(nb_max, grid, s, a);
+    else launch_main<T, XLMIMO_ULA, XLMIMO_AMP_PNUSW, SPLIT>(nb_max, grid, s, a);
   } else {
-    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE>(nb_max, grid, s, a);
-    else launch_main<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW>(nb_max, grid, s, a);
+    if (a.arr.amp == XLMIMO_AMP_FREESPACE) launch_main<T, XLMIMO_UPA, XLMIMO_AMP_FREESPACE, SPLIT>(nb_max, grid, s, a);
+    else launch_main<T, XLMIMO_UPA, XLMIMO_AMP_PNUSW, SPLIT>(nb_max, grid, s, a);
   }
 }
 
@@ -439,11 +669,15 @@ hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const
   if (grid < 1) grid = 1;
   const MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials, d_mask};
   if (ev0) (void)hipEventRecord(ev0, s);
-  if (precision == XLMIMO_FP64) launch_t<double>(nb_max, grid, s, a);
-  else launch_t<float>(nb_max, grid, s, a);
+  if (precision == XLMIMO_FP64) launch_t<double, false>(nb_max, grid, s, a);
+  else if (precision == XLMIMO_FP32H) launch_t<float, true>(nb_max, grid, s, a);
+  else launch_t<float, false>(nb_max, grid, s, a);
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (precision == XLMIMO_FP64) k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask);
-  else k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask);
+  if (precision == XLMIMO_FP64)
+    k_gram_finalize<double><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask, 0);
+  else
+    k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask,
+                                                   precision == XLMIMO_FP32H);
   return hipGetLastError();
 }
 

@@ -20,11 +20,11 @@ LIB_PATH = os.path.join(_HERE, "libxlmimo.so")
 OK, EINVAL, EDEVICE, ENOMEM, ENOTIMPL = 0, -1, -2, -3, -4
 ULA, UPA = 0, 1
 AMP_FREESPACE, AMP_PNUSW = 0, 1
-FP64, FP32C = 0, 1
+FP64, FP32C, FP32H = 0, 1, 2
 CF_PAPER, CF_GATED = 0, 1
 ZF, MMSE, MRC, CAP, MZF, MZF_MISM = 1, 2, 4, 8, 16, 32
 ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE, ST_FELL_BACK = 1, 2, 4, 8, 16, 32
-FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED, FORM_CF_GATED_MLP = 0, 1, 2, 3, 4
+FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED, FORM_CF_GATED_MLP, FORM_EXACT_FP32H = 0, 1, 2, 3, 4, 5
 MAX_USERS = 64
 MLP_IN, MLP_OUT, PAIR_FEAT_PITCH, PAIR_AUX_PITCH = 6, 7, 8, 8
 

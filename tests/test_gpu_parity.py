@@ -4,6 +4,7 @@ Tolerances (normwise |dG_ij| / sqrt(G_ii G_jj) for Grams):
   exact FP64    1e-9   the oracle rounds its phase 2 pi r / lambda (<= 7e5 rad) to
                        ~1e-10 rad; both sides are otherwise FP64
   exact FP32C   1e-5   the accuracy target of the FP32-compensated form
+  exact FP32H   1e-5   the same target: FP32C entries, split-half (FP16 hi + lo) products
   closed form   1e-10 relative per entry (same formulas, FP64 on both sides)
   rates         1e-9 relative (FP64 Cholesky vs LAPACK inverse)
 """
@@ -56,7 +57,7 @@ def _custom_drops(ns, ks, seed, r=(2.0, 40.0), th=(-70.0, 70.0), z=False):
     return W._pack(ns, ks, np.concatenate(pos))
 
 
-@pytest.mark.parametrize("precision,tol", [("FP64", TOL_FP64), ("FP32C", TOL_FP32C)])
+@pytest.mark.parametrize("precision,tol", [("FP64", TOL_FP64), ("FP32C", TOL_FP32C), ("FP32H", TOL_FP32C)])
 def test_exact_ragged_ula(X, ctx, precision, tol):
     # N spans one partial tile up to many tiles with ragged tails; K crosses the
     # 16-user block boundaries (1, 15, 16, 17, 32, 33, 64).
@@ -81,10 +82,27 @@ def test_exact_pnusw_and_3d_users(X, ctx, amp):
     drops = _custom_drops([700, 2048, 33], [3, 20, 9], seed=6, r=(0.5, 8.0), z=True)
     arr = W.ula(1, W.LAMBDA_100GHZ, amp)
     b = X.Batch(drops)
-    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C)):
+    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C), (X.FP32H, TOL_FP32C)):
         g = b.split(ctx.gram_exact(arr, b, prec))
         for d in range(drops.n_drops):
-            assert och.normwise_error(g[d], _exact_ref(arr, drops, d)) < tol
+            assert och.normwise_error(g[d], _exact_ref(arr, drops, d)) < tol, (prec, d)
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+def test_fp32h_amplitude_range(X, ctx, amp):
+    # split-half entries are scaled per user by a power of two from the user's
+    # perpendicular distance: users from 1 mm to 10 km of the array in one drop
+    # (amplitudes over 7 decades; far elements' lo parts fall to FP16 subnormals)
+    rng = np.random.default_rng(21)
+    x = np.array([1e-3, 3e-2, 0.7, 5.0, 40.0, 300.0, 2e3, 1e4])
+    y = rng.uniform(-1.0, 1.0, x.size)
+    pos = np.stack([x, y, np.zeros_like(x)], axis=-1)
+    drops = W._pack([3000, 3000], [8, 8], np.concatenate([pos, pos[::-1] * [1, -1, 1]]))
+    arr = W.ula(1, W.LAMBDA_28GHZ, amp)
+    b = X.Batch(drops)
+    g = b.split(ctx.gram_exact(arr, b, X.FP32H))
+    for d in range(drops.n_drops):
+        assert och.normwise_error(g[d], _exact_ref(arr, drops, d)) < TOL_FP32C, d
 
 
 @pytest.mark.parametrize("ny,nz,k", [(32, 24, 5), (7, 50, 40), (64, 1, 17), (1, 64, 3)])
@@ -93,19 +111,20 @@ def test_exact_upa(X, ctx, ny, nz, k):
     arr = W.ArraySpec(W.GEOM_UPA, ny, nz, lam / 2, lam)
     drops = W.cone_drops(np.random.default_rng(ny * 100 + nz), 3, k, ny * nz, (0.3, 5.0), (-60, 60), (-60, 60))
     b = X.Batch(drops)
-    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C)):
+    for prec, tol in ((X.FP64, TOL_FP64), (X.FP32C, TOL_FP32C), (X.FP32H, TOL_FP32C)):
         g = b.split(ctx.gram_exact(arr, b, prec))
         for d in range(drops.n_drops):
-            assert och.normwise_error(g[d], och.gram_exact(arr, drops.users_of(d))) < tol
+            assert och.normwise_error(g[d], och.gram_exact(arr, drops.users_of(d))) < tol, (prec, d)
 
 
 def test_exact_deterministic_and_empty(X, ctx):
     arr, drops, _ = W.plain_fp64(64)
     b = X.Batch(drops)
-    a1 = ctx.gram_exact(arr, b, X.FP32C).clone()
-    a2 = ctx.gram_exact(arr, b, X.FP32C)
-    torch.cuda.synchronize()
-    assert torch.equal(a1, a2)
+    for prec in (X.FP32C, X.FP32H):
+        a1 = ctx.gram_exact(arr, b, prec).clone()
+        a2 = ctx.gram_exact(arr, b, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2)
     empty = X.Batch(drops.subset([]))
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
     ctx.gram_exact(arr, empty, X.FP32C, out=out)
@@ -225,7 +244,7 @@ def test_capacity_sweep_small(X, ctx):
     n_list = [64, 256, 1024, 4096]
     rho = X.rho_for_snr(arr, (0.0, 20.0), 27.5, b.total_users)
     schemes = X.ZF | X.MMSE
-    for form in (X.FORM_EXACT_FP64, X.FORM_EXACT_FP32C):
+    for form in (X.FORM_EXACT_FP64, X.FORM_EXACT_FP32C, X.FORM_EXACT_FP32H):
         erg, sat, status = ctx.capacity_sweep(arr, n_list, b, form, rho, schemes, t_sat=0.9, eps_sat=0.05)
         torch.cuda.synchronize()
         erg = erg.cpu().numpy()
@@ -260,9 +279,11 @@ def test_full_size_sweep_samples(X, ctx):
     arr, drops, meta = W.sweep()
     b = X.Batch(drops, use_n_elems=True)
     g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    gh = b.split(ctx.gram_exact(arr, b, X.FP32H))
     for d in (0, 4999, 9999):
         ref = och.gram_exact(arr, drops.users_of(d))
         assert och.normwise_error(g[d], ref) < TOL_FP32C
+        assert och.normwise_error(gh[d], ref) < TOL_FP32C
 
 
 @pytest.mark.slow
@@ -280,6 +301,8 @@ def test_uneven_batch_samples(X, ctx):
     arr, drops, meta = W.uneven()
     b = X.Batch(drops)
     g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    gh = b.split(ctx.gram_exact(arr, b, X.FP32H))
     for d in (0, 1, 2047, 4095):
         ref = _exact_ref(arr, drops, d)
         assert och.normwise_error(g[d], ref) < TOL_FP32C
+        assert och.normwise_error(gh[d], ref) < TOL_FP32C
