@@ -72,10 +72,10 @@ struct Mfma<double> {
 // gfx950: |error| <= 1.3e-7 over a full turn).  Lanes with nothing to contribute
 // (users beyond K, elements past the end) carry a coordinate of 1e30:
 // rsq(inf) = 0 makes their entry exactly zero.
-// us scales the amplitude (a power of two: exact).
+// Amplitude a (times us, a power of two: exact) and cos / sin of the phase in turns.
 template <int GEOM, int AMP>
-__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im,
-                                              float us = 1.0f) {
+__device__ __forceinline__ void channel_parts(double dy, double dz, double xp2, float us, float& a, float& c,
+                                              float& sn) {
   double r2 = fma(dy, dy, xp2);
   if constexpr (GEOM == XLMIMO_UPA) r2 = fma(dz, dz, r2);
   const float yf = __builtin_amdgcn_rsqf((float)r2);
@@ -83,11 +83,19 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
   const double r0 = r2 * y0;
   const double r = fma(0.5 * y0, fma(-r0, r0, r2), r0);
   const float t = (float)__builtin_amdgcn_fract(r);
-  float a = yf;
+  a = yf;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * __builtin_amdgcn_sqrtf(a);
   a = a * us;
-  re = a * __builtin_amdgcn_cosf(t);
-  im = -a * __builtin_amdgcn_sinf(t);
+  c = __builtin_amdgcn_cosf(t);
+  sn = __builtin_amdgcn_sinf(t);
+}
+
+template <int GEOM, int AMP>
+__device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im) {
+  float a, c, sn;
+  channel_parts<GEOM, AMP>(dy, dz, xp2, 1.0f, a, c, sn);
+  re = a * c;
+  im = -a * sn;
 }
 
 // FP64: distances in units of lambda / 2 (r counts half turns),
@@ -322,19 +330,25 @@ __device__ __forceinline__ int split_exp(double xp2, int amp) {
   return min(max(q, -100), 100);
 }
 
-// entries m, m + 1 of the hi and lo operands
+// Entries m, m + 1 of the hi and lo operands from amplitudes a and cos / sin:
+// hi = f16(a c) (two at a time), lo = f16(a c - hi) with the product exact inside
+// the FMA, so hi + lo = a c to ~2^-22 relative.
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void split2(float x0, float x1, halfx8& h, halfx8& l, int m) {
-  // hi and lo must both come from the same FP32 value: the empty asm stops the
-  // compiler from folding the product that made x into either conversion
-  asm volatile("" : "+v"(x0), "+v"(x1));
-  const halfx2 hv = __builtin_convertvector((floatx2){x0, x1}, halfx2);
-  h[m] = hv[0];
-  h[m + 1] = hv[1];
-  // x - hi is exact in FP32; one rounding to FP16
-  l[m] = (_Float16)__builtin_fmaf((float)hv[0], -1.0f, x0);
-  l[m + 1] = (_Float16)__builtin_fmaf((float)hv[1], -1.0f, x1);
+__device__ __forceinline__ void split_pair(const float* a, const float* c, const float* sn, halfx8& rh, halfx8& rl,
+                                           halfx8& ih, halfx8& il, int m) {
+  halfx2 hr = __builtin_convertvector((floatx2){a[0] * c[0], a[1] * c[1]}, halfx2);
+  halfx2 hi = __builtin_convertvector((floatx2){-a[0] * sn[0], -a[1] * sn[1]}, halfx2);
+  // opaque from here: lo must be formed from these very hi values (the
+  // compiler would otherwise re-derive hi from the product for the FMA)
+  asm volatile("" : "+v"(hr), "+v"(hi));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    rh[m + q] = hr[q];
+    ih[m + q] = hi[q];
+    rl[m + q] = (_Float16)__builtin_fmaf(a[q], c[q], -(float)hr[q]);
+    il[m + q] = (_Float16)__builtin_fmaf(-a[q], sn[q], -(float)hi[q]);
+  }
 }
 
 template <int NB, int GEOM, int AMP>
@@ -396,23 +410,21 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
         double dy = u[b].uy - ey;
 #pragma unroll
         for (int m = 0; m < 8; m += 2) {
-          double d0 = dy, d1 = dy - ds;
-          dy -= 2.0 * ds;
-          if constexpr (TAIL) {
-            d0 = e + m < it.e_end ? d0 : kFar;
-            d1 = e + m + 1 < it.e_end ? d1 : kFar;
+          float a[2], c[2], sn[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            double d = dy;
+            dy -= ds;
+            if constexpr (TAIL) d = e + m + q < it.e_end ? d : kFar;
+            channel_parts<GEOM, AMP>(d, 0.0, u[b].xp2, us[b], a[q], c[q], sn[q]);
           }
-          float re0, im0, re1, im1;
-          channel_entry<GEOM, AMP>(d0, 0.0, u[b].xp2, re0, im0, us[b]);
-          channel_entry<GEOM, AMP>(d1, 0.0, u[b].xp2, re1, im1, us[b]);
-          split2(re0, re1, rh[b], rl[b], m);
-          split2(im0, im1, ih[b], il[b], m);
+          split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], m);
         }
       }
     } else {
       int ea = e / arr.n_z;
       int eb = e - ea * arr.n_z;
-      float re[NB][2], im[NB][2];
+      float a[NB][2], c[NB][2], sn[NB][2];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         double ey = fma((double)ea, ds, -cy);
@@ -420,13 +432,11 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
         if constexpr (TAIL) ey = e + m < it.e_end ? ey : kFar;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          channel_entry<GEOM, AMP>(u[b].uy - ey, u[b].uz - ez, u[b].xp2, re[b][m & 1], im[b][m & 1], us[b]);
+          channel_parts<GEOM, AMP>(u[b].uy - ey, u[b].uz - ez, u[b].xp2, us[b], a[b][m & 1], c[b][m & 1],
+                                   sn[b][m & 1]);
         if (m & 1) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            split2(re[b][0], re[b][1], rh[b], rl[b], m - 1);
-            split2(im[b][0], im[b][1], ih[b], il[b], m - 1);
-          }
+          for (int b = 0; b < NB; ++b) split_pair(a[b], c[b], sn[b], rh[b], rl[b], ih[b], il[b], m - 1);
         }
         if (++eb == arr.n_z) {
           eb = 0;
