@@ -2,8 +2,9 @@
 
 One step = the capacity sweep workload (ULA at 28 GHz, N in {256, 1024, ...,
 262144}, K = 16 users, 10^4 seeded drops reused at every N, SNR {0, 10, 20} dB):
-  * exact Gram in the FP32-compensated form for every (N, drop), ZF and MMSE
-    sum-rates, ergodic means and the saturation point (xlmimo_capacity_sweep);
+  * exact Gram in the FP32H form (FP32-compensated entries, split-half FP16
+    matrix-core products) for every (N, drop), ZF and MMSE sum-rates, ergodic
+    means and the saturation point (xlmimo_capacity_sweep);
   * the same sweep with the paper's closed-form (modified-ZF) Gram;
   * the same sweep with the learned-corrected closed form (exact fallback for
     drops whose predicted uncertainty exceeds the threshold).
@@ -40,7 +41,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
 #   per unique user pair and element: conj(h_i) h_j complex multiply-add      = 8
 FLOP_PER_ENTRY_EVAL = 11
 FLOP_PER_PAIR_MAC = 8
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gram_exact_fp32c_sweep_traffic.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gram_exact_fp32h_sweep_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_18118_amd", "csrc", f) for f in ("gram_exact.hip", "device_math.h")]
 
 
@@ -151,7 +152,7 @@ def main():
 
     def step(e):
         e[0].record(stream)
-        ctx.capacity_sweep(arr, n_list, batch, X.FORM_EXACT_FP32C, rho, schemes, 0.9, 0.05, erg_e, sat_e, st_e)
+        ctx.capacity_sweep(arr, n_list, batch, X.FORM_EXACT_FP32H, rho, schemes, 0.9, 0.05, erg_e, sat_e, st_e)
         e[1].record(stream)
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED, rho, schemes, 0.9, 0.05, erg_c, sat_c, st_c)
         e[2].record(stream)
@@ -179,6 +180,18 @@ def main():
     ctx.timing_enable(False)
     ms_per_step = wall * 1e3 / args.steps
 
+    # the FP32C exact form on the same sweep, outside the timed steps (for comparison)
+    log("FP32C exact sweep (comparison, untimed steps)")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    erg_f = torch.empty_like(erg_e)
+    e0.record(stream)
+    ctx.capacity_sweep(arr, n_list, batch, X.FORM_EXACT_FP32C, rho, schemes, 0.9, 0.05, erg_f, torch.empty_like(sat_e),
+                       torch.empty_like(st_e))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fp32c_ref = {"entries_per_s": entries_per_form / (e0.elapsed_time(e1) * 1e-3), "ms": e0.elapsed_time(e1),
+                 "ergodic_rel_diff_vs_fp32h": float(((erg_f - erg_e).abs() / erg_e.abs()).max())}
+
     value = 3 * entries_per_form / (ms_per_step * 1e-3)
     evals = n_drops * sum(n_list) * k
     pair_macs = n_drops * sum(n_list) * k * (k + 1) // 2
@@ -186,7 +199,9 @@ def main():
     achieved = flops_per_step * args.steps / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic_per_launch(),
-                "kernel": "k_gram_exact<1,float> (exact Gram, FP32C)",
+                "kernel": "k_gram_exact<1,float,ULA,FREESPACE,split> (exact Gram, FP32H)",
+                "note": "FP32-equivalent algorithmic FLOPs; the pair products run on the FP16 matrix cores "
+                        "as hi/lo splits beside the vector ALU",
                 "launches": n_launch, "avg_launch_ms": kern_ms / max(n_launch, 1),
                 "entry_evals_per_s": evals * args.steps / (kern_ms * 1e-3),
                 "pair_macs_per_s": pair_macs * args.steps / (kern_ms * 1e-3)}
@@ -195,11 +210,12 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "capacity sweep: ULA 28 GHz half-wavelength, N in {256..262144} (powers of 4), "
-                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32C, closed form, "
+                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32H, closed form, "
                                   "learned-corrected closed form",
                       "n_list": n_list, "drops": n_drops, "users": k, "snr_db": list(meta["snr_db"])},
-           "forms": {"exact_fp32c": {"entries_per_s": entries_per_form / (t_exact * 1e-3 / args.steps),
+           "forms": {"exact_fp32h": {"entries_per_s": entries_per_form / (t_exact * 1e-3 / args.steps),
                                      "ms": t_exact / args.steps},
+                     "exact_fp32c_untimed": fp32c_ref,
                      "closedform_gated": {"entries_per_s": entries_per_form / (t_cf * 1e-3 / args.steps),
                                           "ms": t_cf / args.steps},
                      "mlp_corrected": {"entries_per_s": entries_per_form / (t_mlp * 1e-3 / args.steps),
@@ -277,7 +293,8 @@ def mlp_inference(ctx, X, Lr, W, mlp):
 
 
 def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=None, lvmax=0.0):
-    """Per-drop sum-rate errors of the FP32C and closed-form Grams against the FP64 exact Gram."""
+    """Per-drop Gram and sum-rate errors of the FP32H, FP32C, closed-form and learned-corrected Grams
+    against the FP64 exact Gram."""
     import torch
     schemes = X.ZF | X.MMSE
     res = {"reference": "exact FP64 Gram on the GPU (parity-tested against the FP64 oracle)", "per_n": []}
@@ -288,9 +305,11 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
         a = arr.with_n(n)
         g64 = ctx.gram_exact(a, b, X.FP64)
         g32 = ctx.gram_exact(a, b, X.FP32C)
+        g16 = ctx.gram_exact(a, b, X.FP32H)
         gcf, _ = ctx.gram_closedform(a, b, X.CF_GATED)
         r64, _ = ctx.sumrate(b, g64, rho, schemes)
         r32, _ = ctx.sumrate(b, g32, rho, schemes)
+        r16, _ = ctx.sumrate(b, g16, rho, schemes)
         rcf, _ = ctx.sumrate(b, gcf, rho, schemes)
         rm, _ = ctx.sumrate(b, g64, rho, X.MZF_MISM, gram_filter=gcf)
         gml, stm = ctx.gram_closedform_mlp(a, b, mlp, X.CF_GATED, log_var_max=lvmax)
@@ -300,13 +319,18 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
         gm = g64.view(-1, k, k, 2)
         d64 = torch.sqrt(torch.diagonal(gm[..., 0], dim1=1, dim2=2))
         den = d64[:, :, None] * d64[:, None, :]
-        dg = (g32 - g64).view(-1, k, k, 2)
-        gram_err = float(torch.max(torch.sqrt(dg[..., 0] ** 2 + dg[..., 1] ** 2) / den))
+
+        def gram_err(g):
+            dg = (g - g64).view(-1, k, k, 2)
+            return float(torch.max(torch.sqrt(dg[..., 0] ** 2 + dg[..., 1] ** 2) / den))
         e32 = torch.abs(r32 / r64 - 1)
+        e16 = torch.abs(r16 / r64 - 1)
         ecf = torch.abs(rcf / r64 - 1)
         emm = torch.abs(rm[..., 0] / r64[..., 0] - 1)
         eml = torch.abs(rml / r64 - 1)
-        row = {"n": n, "fp32c_gram_normwise_max": gram_err,
+        row = {"n": n, "fp32h_gram_normwise_max": gram_err(g16),
+               "fp32h_sumrate_rel_max": float(e16.max()),
+               "fp32c_gram_normwise_max": gram_err(g32),
                "fp32c_sumrate_rel_max": float(e32.max()),
                "closedform_sumrate_rel_max": float(torch.nan_to_num(ecf, nan=float("inf")).max()),
                "closedform_sumrate_rel_median": float(torch.nanmedian(ecf)),
@@ -319,8 +343,9 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
             admissible.append(n)
         if row["mlp_sumrate_rel_max"] <= 1e-3:
             admissible_mlp.append(n)
-    res["fp32c_meets_1e-5_gram_and_1e-3_rate"] = all(r["fp32c_gram_normwise_max"] <= 1e-5 and
-                                                      r["fp32c_sumrate_rel_max"] <= 1e-3 for r in res["per_n"])
+    for f in ("fp32h", "fp32c"):
+        res[f"{f}_meets_1e-5_gram_and_1e-3_rate"] = all(r[f"{f}_gram_normwise_max"] <= 1e-5 and
+                                                         r[f"{f}_sumrate_rel_max"] <= 1e-3 for r in res["per_n"])
     res["closedform_admissible_n"] = admissible
     res["mlp_admissible_n"] = admissible_mlp
     erg_rel = (erg_e - erg_c).abs() / erg_e.abs()

@@ -196,7 +196,7 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
  *             sat_out[2] = (E[y_up] - E[y_down]) / spacing  (antennas);
  *   empirical sat_out[3 + s * n_sch + c] = first N, log-interpolated, with
  *             ergodic(N) / ergodic(N_max) >= 1 - eps_sat, for SNR s, scheme c.
- * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32C
+ * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32H
  * Gram as the true channel; every other scheme uses the chosen form's Gram.
  *   form         XLMIMO_FORM_*; XLMIMO_FORM_CF_GATED_MLP needs mlp and log_var_max
  *                (see xlmimo_gram_closedform_mlp), otherwise mlp may be NULL
@@ -258,7 +258,7 @@ int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* 
 /* Closed form (variant as in xlmimo_gram_closedform) + learned residual:
  * G_ij = G~_ij + delta_rho sqrt(G~_ii G~_jj) for every pair.  A drop with any
  * pair whose predicted log-variance exceeds log_var_max is recomputed with the
- * exact FP32C Gram and gets XLMIMO_ST_FELL_BACK in status_out (ULA only). */
+ * exact FP32H Gram and gets XLMIMO_ST_FELL_BACK in status_out (ULA only). */
 int xlmimo_gram_closedform_mlp(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                                int32_t variant, xlmimo_mlp* mlp, double log_var_max, double* gram_out,
                                int32_t* status_out, void* stream);

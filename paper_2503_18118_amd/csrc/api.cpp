@@ -219,7 +219,7 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp32h = gram_exact_grid(XLMIMO_FP32H, p.nb_max, a->geometry, a->amp_model);
-  const int64_t ch = chunk_length(total_elems, std::min(p.grid_fp32, p.grid_fp64));
+  const int64_t ch = chunk_length(total_elems, std::min(std::min(p.grid_fp32, p.grid_fp64), p.grid_fp32h));
   std::vector<ItemK> items;
   std::vector<int64_t> cost;
   int64_t poff = 0;
@@ -498,7 +498,7 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
 namespace {
 
 // Closed form, then the learned residual for every pair; drops whose predicted
-// log-variance exceeds log_var_max anywhere are recomputed with the exact FP32C
+// log-variance exceeds log_var_max anywhere are recomputed with the exact FP32H
 // Gram (same launch plan, drop mask) and flagged XLMIMO_ST_FELL_BACK.
 int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
                         int32_t variant, xlmimo_mlp* M, double log_var_max, double* gram_out, int32_t* status,
@@ -527,8 +527,8 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   if ((rc = mlp_infer(c, M, np, feat, net_out, s))) return rc;
   HIP_TRY(c, launch_mlp_apply(np, net_out, aux, pmap, p->d_drops, gram_out, flags, (float)log_var_max, s));
   if ((rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s))) return rc;
-  const int grid = std::min(p->grid_fp32, std::max(p->n_items, 1));
-  HIP_TRY(c, launch_gram_exact(XLMIMO_FP32C, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
+  const int grid = std::min(p->grid_fp32h, std::max(p->n_items, 1));
+  HIP_TRY(c, launch_gram_exact(XLMIMO_FP32H, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
                                p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, nullptr, nullptr,
                                flags));
   if (status) HIP_TRY(c, launch_or_flags(status, flags, p->n_drops, XLMIMO_ST_FELL_BACK, s));
@@ -930,7 +930,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
       } else if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) {
         return rc;
       }
-      if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP32C, g2, s))) return rc;
+      if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP32H, g2, s))) return rc;
     }
     if ((rc = get_plan(c, a, b, &nn, &p))) return rc;
     const double* gtrue = need_exact_true ? g2 : g;
