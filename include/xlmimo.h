@@ -26,7 +26,8 @@
  *     per stream for concurrent work).
  *   - The first call with a new batch shape builds and uploads a launch plan
  *     synchronously; later calls with the same shape enqueue kernels only, so
- *     a warmed-up call sequence can be captured into a hipGraph.
+ *     a warmed-up call sequence can be captured into a hipGraph
+ *     (xlmimo_graph_begin / xlmimo_graph_end below).
  */
 #ifndef XLMIMO_H
 #define XLMIMO_H
@@ -262,6 +263,56 @@ int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* 
 int xlmimo_gram_closedform_mlp(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                                int32_t variant, xlmimo_mlp* mlp, double log_var_max, double* gram_out,
                                int32_t* status_out, void* stream);
+
+/* ---- Batching: graph capture and autotuned launch shapes (not part of the method) ----
+ *
+ * Graph capture records every call made on `stream` between xlmimo_graph_begin
+ * and xlmimo_graph_end into one executable hipGraph that replays the whole
+ * sequence with a single launch (for example a capacity sweep over
+ * thousands of drops: its persistent Gram launches, rates and reductions).
+ *   - `stream` must be a created (non-default) stream; while the capture is
+ *     open, calls of this context on any other stream fail with XLMIMO_EINVAL.
+ *   - Captured calls must be warm: run the same calls once before capturing
+ *     them, so that their launch plans exist and the workspace is large enough.
+ *     A call that would need a new plan, a larger workspace or a new N list,
+ *     and the synchronising calls (xlmimo_mlp_create, xlmimo_mlp_set_params,
+ *     xlmimo_mlp_get_params, xlmimo_mlp_train_step, xlmimo_timing_read,
+ *     xlmimo_autotune_exact), fail with XLMIMO_EINVAL; xlmimo_graph_end then
+ *     fails as well and no graph is made.
+ *   - A graph reads and writes the same device buffers at every launch (the
+ *     caller's inputs and outputs, the context's workspace): keep the
+ *     caller's buffers alive and in place while the graph is used.  Replays
+ *     share the context's workspace with its other calls; they are ordered on
+ *     their stream like any other call.
+ *   - While any graph of a context exists, workspace the context would free
+ *     is kept until the context is destroyed; xlmimo_mlp_destroy and
+ *     xlmimo_ctx_destroy fail with XLMIMO_EINVAL until its graphs are
+ *     destroyed.
+ *   - The exact-Gram kernel timing (xlmimo_timing_enable) is not recorded
+ *     inside a graph. */
+typedef struct xlmimo_graph xlmimo_graph;
+int     xlmimo_graph_begin(xlmimo_ctx* ctx, void* stream);
+int     xlmimo_graph_end(xlmimo_ctx* ctx, void* stream, xlmimo_graph** out);
+int     xlmimo_graph_launch(xlmimo_graph* graph, void* stream);
+int64_t xlmimo_graph_node_count(const xlmimo_graph* graph);   /* -1 for NULL */
+int     xlmimo_graph_destroy(xlmimo_graph* graph);           /* waits for the device */
+
+/* Autotune the exact-Gram launch of one batch shape.  Candidate work-item
+ * lengths (1024 ... 131072 elements, powers of two) and persistent grid sizes
+ * (all resident workgroups, 3/4 and 1/2 of them) are timed on `stream` (median
+ * of three launches after one warm-up; the call synchronises the stream).  The
+ * fastest shape is kept in the context and used by every later exact-Gram
+ * launch of that shape and precision (xlmimo_gram_exact, the sweep's per-N
+ * launches, the learned form's fallback).
+ *   n_elems    0: the batch's own N; > 0: every drop with N = n_elems (a ULA
+ *              sweep point, as xlmimo_capacity_sweep launches it)
+ *   chunk_out  HOST, optional: chosen work-item length in elements
+ *   grid_out   HOST, optional: chosen number of workgroups
+ *   ms_out     HOST, optional: median launch time of the chosen shape
+ * Results depend on the shape only through FP32/FP64 summation order (the
+ * work-item partition); they stay deterministic for a given shape. */
+int xlmimo_autotune_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch, int64_t n_elems,
+                          int32_t precision, int64_t* chunk_out, int32_t* grid_out, double* ms_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -34,6 +34,8 @@ struct Plan {
   int64_t n_pairs = 0;       // user pairs i < j over all drops
   int64_t partial_doubles = 0;
   int grid_fp32 = 0, grid_fp64 = 0, grid_fp32h = 0;
+  int64_t chunk = 0;         // work-item length in elements
+  uint64_t key = 0;          // plan_key of the batch shape
   DropK* d_drops = nullptr;
   ItemK* d_items = nullptr;
 };
@@ -54,6 +56,22 @@ struct xlmimo_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  // graph capture (xlmimo_graph_*): while any graph of this context exists, device
+  // buffers it may reference are retired (freed with the context) instead of freed
+  bool capturing = false;
+  bool cap_failed = false;
+  hipStream_t cap_stream = nullptr;
+  int graphs = 0;
+  std::vector<void*> retired;
+  // autotuned exact-Gram launch shapes (xlmimo_autotune_exact), keyed by plan
+  std::unordered_map<uint64_t, int64_t> tuned_chunk;
+  std::unordered_map<uint64_t, int> tuned_grid;   // key ^ precision
+};
+
+struct xlmimo_graph {
+  xlmimo_ctx* ctx = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t n_nodes = 0;
 };
 
 namespace {
@@ -64,7 +82,10 @@ int set_err(xlmimo_ctx* c, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
-  if (c) c->err = buf;
+  if (c) {
+    c->err = buf;
+    if (c->capturing) c->cap_failed = true;  // the graph being captured is incomplete
+  }
   return code;
 }
 
@@ -74,11 +95,26 @@ int set_err(xlmimo_ctx* c, int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return set_err((ctx), XLMIMO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Free device memory that a live graph of the context might still reference.
+int release(xlmimo_ctx* c, void* p) {
+  if (!p) return XLMIMO_OK;
+  if (c->graphs > 0) {
+    c->retired.push_back(p);
+    return XLMIMO_OK;
+  }
+  HIP_TRY(c, hipFree(p));
+  return XLMIMO_OK;
+}
+
 int ensure(xlmimo_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
   if (b.n >= bytes) return XLMIMO_OK;
+  if (c->capturing)
+    return set_err(c, XLMIMO_EINVAL, "workspace must grow to %zu bytes during graph capture: "
+                   "run the same calls once before capturing them", bytes);
   if (b.p) {
     HIP_TRY(c, hipStreamSynchronize(s));
-    HIP_TRY(c, hipFree(b.p));
+    int rc = release(c, b.p);
+    if (rc) return rc;
     b.p = nullptr;
     b.n = 0;
   }
@@ -164,9 +200,7 @@ int64_t chunk_length(int64_t total_elems, int grid) {
   return (target + 127) / 128 * 128;  // whole rounds of both FP32 kernels (16 and 128 elements)
 }
 
-// Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
-// descriptors synchronously; warm the cache before capturing a graph.
-int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override, Plan** out) {
+uint64_t plan_key(const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override) {
   uint64_t h = 1469598103934665603ULL;
   h = fnv(h, &a->geometry, sizeof(a->geometry));
   h = fnv(h, &a->amp_model, sizeof(a->amp_model));
@@ -177,17 +211,31 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   h = fnv(h, &flag, sizeof(flag));
   if (b->n_elems && !n_override) h = fnv(h, b->n_elems, sizeof(int64_t) * b->n_drops);
   h = fnv(h, b->n_users, sizeof(int32_t) * b->n_drops);
+  return h;
+}
+
+void drop_plan_buffers(xlmimo_ctx* c, Plan& p) {
+  (void)release(c, p.d_drops);
+  (void)release(c, p.d_items);
+  p.d_drops = nullptr;
+  p.d_items = nullptr;
+}
+
+// Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
+// descriptors synchronously; warm the cache before capturing a graph.
+int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override, Plan** out) {
+  const uint64_t h = plan_key(a, b, n_override);
   auto it = c->plans.find(h);
   if (it != c->plans.end()) {
     *out = &it->second;
     return XLMIMO_OK;
   }
+  if (c->capturing)
+    return set_err(c, XLMIMO_EINVAL, "a new batch shape needs a launch plan during graph capture: "
+                   "run the same calls once before capturing them");
   if (c->plans.size() >= 64) {
     HIP_TRY(c, hipDeviceSynchronize());
-    for (auto& kv : c->plans) {
-      (void)hipFree(kv.second.d_drops);
-      (void)hipFree(kv.second.d_items);
-    }
+    for (auto& kv : c->plans) drop_plan_buffers(c, kv.second);
     c->plans.clear();
   }
   const int n = (int)b->n_drops;
@@ -219,7 +267,12 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
   p.grid_fp32h = gram_exact_grid(XLMIMO_FP32H, p.nb_max, a->geometry, a->amp_model);
-  const int64_t ch = chunk_length(total_elems, std::min(std::min(p.grid_fp32, p.grid_fp64), p.grid_fp32h));
+  auto tc = c->tuned_chunk.find(h);
+  const int64_t ch = tc != c->tuned_chunk.end()
+                         ? tc->second
+                         : chunk_length(total_elems, std::min(std::min(p.grid_fp32, p.grid_fp64), p.grid_fp32h));
+  p.chunk = ch;
+  p.key = h;
   std::vector<ItemK> items;
   std::vector<int64_t> cost;
   int64_t poff = 0;
@@ -275,6 +328,28 @@ int set_device(xlmimo_ctx* c) {
   return XLMIMO_OK;
 }
 
+// During graph capture every call must be enqueued on the capturing stream.
+int stream_ok(xlmimo_ctx* c, void* stream) {
+  if (c->capturing && (hipStream_t)stream != c->cap_stream)
+    return set_err(c, XLMIMO_EINVAL, "during graph capture, calls must use the capturing stream");
+  return XLMIMO_OK;
+}
+
+// Calls that synchronise or keep host-side state cannot be captured.
+int no_capture(xlmimo_ctx* c, const char* what) {
+  if (c->capturing) return set_err(c, XLMIMO_EINVAL, "%s cannot run during graph capture", what);
+  return XLMIMO_OK;
+}
+
+// Persistent grid of the exact-Gram kernel: all resident workgroups, or the
+// autotuned size, never more than there are work items.
+int exact_grid(xlmimo_ctx* c, const Plan* p, int precision) {
+  int g = precision == XLMIMO_FP64 ? p->grid_fp64 : (precision == XLMIMO_FP32H ? p->grid_fp32h : p->grid_fp32);
+  auto tg = c->tuned_grid.find(p->key ^ (uint64_t)precision);
+  if (tg != c->tuned_grid.end()) g = tg->second;
+  return std::min(g, std::max(p->n_items, 1));
+}
+
 int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
                     int32_t precision, double* gram_out, hipStream_t s) {
   Plan* p = nullptr;
@@ -282,10 +357,9 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   if (rc) return rc;
   rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s);
   if (rc) return rc;
-  const int g_prec = precision == XLMIMO_FP64 ? p->grid_fp64 : (precision == XLMIMO_FP32H ? p->grid_fp32h : p->grid_fp32);
-  const int grid = std::min(g_prec, std::max(p->n_items, 1));
+  const int grid = exact_grid(c, p, precision);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (c->timing) {
+  if (c->timing && !c->capturing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
       hipEvent_t e;
       HIP_TRY(c, hipEventCreate(&e));
@@ -527,7 +601,7 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   if ((rc = mlp_infer(c, M, np, feat, net_out, s))) return rc;
   HIP_TRY(c, launch_mlp_apply(np, net_out, aux, pmap, p->d_drops, gram_out, flags, (float)log_var_max, s));
   if ((rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s))) return rc;
-  const int grid = std::min(p->grid_fp32h, std::max(p->n_items, 1));
+  const int grid = exact_grid(c, p, XLMIMO_FP32H);
   HIP_TRY(c, launch_gram_exact(XLMIMO_FP32H, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
                                p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, nullptr, nullptr,
                                flags));
@@ -543,6 +617,7 @@ extern "C" {
 int xlmimo_mlp_create(xlmimo_ctx* c, int32_t width, int32_t depth, xlmimo_mlp** out) {
   if (!c || !out) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_mlp_create")) return rc0;
   *out = nullptr;
   if (width < 16 || width > 4096 || width % 16) return set_err(c, XLMIMO_EINVAL, "width must be a multiple of 16 in 16..4096");
   if (depth < 1 || depth > 16) return set_err(c, XLMIMO_EINVAL, "depth must lie in 1..16");
@@ -594,6 +669,8 @@ int xlmimo_mlp_destroy(xlmimo_mlp* M) {
   if (!M) return XLMIMO_OK;
   xlmimo_ctx* c = M->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (c->capturing || c->graphs > 0)
+    return set_err(c, XLMIMO_EINVAL, "destroy the context's graphs before its networks");
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
@@ -611,6 +688,7 @@ int xlmimo_mlp_set_params(xlmimo_mlp* M, const float* host) {
   if (!M || !host) return XLMIMO_EINVAL;
   xlmimo_ctx* c = M->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_mlp_set_params")) return rc0;
   int rc = set_device(c);
   if (rc) return rc;
   const size_t fb = sizeof(float) * M->n_params;
@@ -628,6 +706,7 @@ int xlmimo_mlp_get_params(xlmimo_mlp* M, float* host) {
   if (!M || !host) return XLMIMO_EINVAL;
   xlmimo_ctx* c = M->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_mlp_get_params")) return rc0;
   int rc = set_device(c);
   if (rc) return rc;
   HIP_TRY(c, hipDeviceSynchronize());
@@ -647,6 +726,7 @@ int xlmimo_mlp_pair_inputs(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_ba
                            void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
@@ -666,6 +746,7 @@ int xlmimo_mlp_loss_grad(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* fe
                          const float* target, float* grad_out, double* loss_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_mlp_args(c, M, n, features, aux);
   if (rc) return rc;
   if (n < 1 || !target || !loss_out) return set_err(c, XLMIMO_EINVAL, "need n >= 1, targets and loss_out");
@@ -680,6 +761,7 @@ int xlmimo_mlp_train_step(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* f
                           const float* target, float lr, double* loss_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_mlp_train_step (its Adam step count lives on the host)")) return rc0;
   int rc = check_mlp_args(c, M, n, features, aux);
   if (rc) return rc;
   if (n < 1 || !target || !loss_out) return set_err(c, XLMIMO_EINVAL, "need n >= 1, targets and loss_out");
@@ -697,6 +779,7 @@ int xlmimo_mlp_train_step(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* f
 int xlmimo_mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, float* out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_mlp_args(c, M, n, features, (const void*)1);
   if (rc) return rc;
   if (n == 0) return XLMIMO_OK;
@@ -710,6 +793,7 @@ int xlmimo_gram_closedform_mlp(xlmimo_ctx* c, const xlmimo_array* a, const xlmim
                                void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
@@ -758,8 +842,13 @@ int xlmimo_ctx_create(xlmimo_ctx** out, int device) {
 
 int xlmimo_ctx_destroy(xlmimo_ctx* c) {
   if (!c) return XLMIMO_OK;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->capturing || c->graphs > 0) return set_err(c, XLMIMO_EINVAL, "destroy the context's graphs first");
+  }
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (void* p : c->retired) (void)hipFree(p);
   for (auto& kv : c->plans) {
     (void)hipFree(kv.second.d_drops);
     (void)hipFree(kv.second.d_items);
@@ -788,6 +877,7 @@ int xlmimo_timing_enable(xlmimo_ctx* c, int on) {
 int xlmimo_timing_read(xlmimo_ctx* c, double* total_ms, int64_t* n_launches) {
   if (!c || !total_ms || !n_launches) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_timing_read")) return rc0;
   double tot = 0.0;
   for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
     HIP_TRY(c, hipEventSynchronize(c->ev_pool[i + 1]));
@@ -805,6 +895,7 @@ int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* 
                       double* gram_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
@@ -820,6 +911,7 @@ int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_ba
                            double* gram_out, int32_t* status_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
@@ -848,6 +940,7 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* c, const xlmimo_batch* b, const double* g
                            void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_rates_args(c, b, gram_true, gram_filter, n_snr, rho, schemes);
   if (rc) return rc;
   if (b->n_drops == 0) return XLMIMO_OK;
@@ -869,6 +962,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
                           double* sat_out, int32_t* status_out, void* stream) {
   if (!c) return XLMIMO_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
   hipStream_t s = (hipStream_t)stream;
   int rc = check_array(c, a);
   if (rc) return rc;
@@ -908,6 +1002,9 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   std::vector<double> nl(N_list, N_list + n_N);
   if (nl != c->nlist_host) {
     // synchronous upload, skipped when the list is unchanged (so a warmed-up sweep can be graph-captured)
+    if (c->capturing)
+      return set_err(c, XLMIMO_EINVAL, "a new N list needs an upload during graph capture: "
+                     "run the same sweep once before capturing it");
     HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, hipMemcpy(c->scratch_nlist.p, nl.data(), sizeof(double) * n_N, hipMemcpyHostToDevice));
     c->nlist_host = nl;
@@ -942,6 +1039,192 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   HIP_TRY(c, launch_y_bounds(b->user_pos, p->d_drops, nd, a->geometry, t_sat, (double*)c->scratch_bounds.p, s));
   HIP_TRY(c, launch_saturation((double*)c->scratch_bounds.p, nd, ergodic_out, (double*)c->scratch_nlist.p, n_N, n_vals,
                                a->spacing_m, eps_sat, sat_out, s));
+  return XLMIMO_OK;
+}
+
+
+// ---- graph capture --------------------------------------------------------
+
+int xlmimo_graph_begin(xlmimo_ctx* c, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->capturing) return set_err(c, XLMIMO_EINVAL, "a graph capture is already open on this context");
+  if (!stream) return set_err(c, XLMIMO_EINVAL, "graph capture needs a created (non-default) stream");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  c->cap_failed = false;
+  c->cap_stream = (hipStream_t)stream;
+  return XLMIMO_OK;
+}
+
+int xlmimo_graph_end(xlmimo_ctx* c, void* stream, xlmimo_graph** out) {
+  if (!c || !out) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  *out = nullptr;
+  if (!c->capturing || (hipStream_t)stream != c->cap_stream)
+    return set_err(c, XLMIMO_EINVAL, "no graph capture is open on this stream");
+  c->capturing = false;
+  c->cap_stream = nullptr;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g);
+  if (e != hipSuccess || !g || c->cap_failed) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    const bool failed = c->cap_failed;
+    c->cap_failed = false;
+    return set_err(c, XLMIMO_EINVAL, "graph capture failed: %s",
+                   failed ? "a call made during the capture returned an error" : hipGetErrorString(e));
+  }
+  size_t n_nodes = 0;
+  (void)hipGraphGetNodes(g, nullptr, &n_nodes);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return set_err(c, XLMIMO_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  xlmimo_graph* G = new xlmimo_graph();
+  G->ctx = c;
+  G->exec = ex;
+  G->n_nodes = n_nodes;
+  c->graphs += 1;
+  *out = G;
+  return XLMIMO_OK;
+}
+
+int xlmimo_graph_launch(xlmimo_graph* G, void* stream) {
+  if (!G) return XLMIMO_EINVAL;
+  xlmimo_ctx* c = G->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->capturing) return set_err(c, XLMIMO_EINVAL, "cannot launch a graph while a capture is open");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipGraphLaunch(G->exec, (hipStream_t)stream));
+  return XLMIMO_OK;
+}
+
+int64_t xlmimo_graph_node_count(const xlmimo_graph* G) { return G ? (int64_t)G->n_nodes : -1; }
+
+int xlmimo_graph_destroy(xlmimo_graph* G) {
+  if (!G) return XLMIMO_OK;
+  xlmimo_ctx* c = G->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();  // a replay may still be running
+  (void)hipGraphExecDestroy(G->exec);
+  c->graphs -= 1;
+  delete G;
+  return XLMIMO_OK;
+}
+
+// ---- autotuner --------------------------------------------------------------
+
+int xlmimo_autotune_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int64_t n_elems,
+                          int32_t precision, int64_t* chunk_out, int32_t* grid_out, double* ms_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = no_capture(c, "xlmimo_autotune_exact");
+  if (!rc) rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true);
+  if (rc) return rc;
+  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C && precision != XLMIMO_FP32H)
+    return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
+  if (n_elems < 0 || n_elems > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "bad n_elems");
+  if (n_elems > 0 && a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "n_elems overrides a ULA's N only");
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if ((rc = set_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t* nov = n_elems > 0 ? &n_elems : nullptr;
+  const uint64_t key = plan_key(a, b, nov);
+  const uint64_t gkey = key ^ (uint64_t)precision;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  const bool timing = c->timing;
+  c->timing = false;
+  auto rebuild = [&](Plan** p) -> int {
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+      HIP_TRY(c, hipStreamSynchronize(s));
+      drop_plan_buffers(c, it->second);
+      c->plans.erase(it);
+    }
+    return get_plan(c, a, b, nov, p);
+  };
+  // median of 3 timed launches after one warm-up
+  auto time_it = [&](double* ms) -> int {
+    Plan* p = nullptr;
+    int r = get_plan(c, a, b, nov, &p);
+    if (r) return r;
+    if ((r = ensure(c, c->scratch_gram, sizeof(double) * 2 * std::max<int64_t>(p->gram_elems, 1), s))) return r;
+    double t[3];
+    for (int k = 0; k < 4; ++k) {
+      HIP_TRY(c, hipEventRecord(e0, s));
+      if ((r = gram_exact_impl(c, a, b, nov, precision, (double*)c->scratch_gram.p, s))) return r;
+      HIP_TRY(c, hipEventRecord(e1, s));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      float f = 0.0f;
+      HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+      if (k) t[k - 1] = f;
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return XLMIMO_OK;
+  };
+  c->tuned_grid.erase(gkey);
+  double best = 1e300;
+  int64_t best_chunk = 0;
+  int last_items = -1;
+  for (int64_t ch = 1024; ch <= 131072 && !rc; ch *= 2) {
+    c->tuned_chunk[key] = ch;
+    Plan* p = nullptr;
+    if ((rc = rebuild(&p))) break;
+    if (p->n_items == last_items) continue;  // same work list as the previous candidate
+    last_items = p->n_items;
+    double ms = 0.0;
+    if ((rc = time_it(&ms))) break;
+    if (ms < best) {
+      best = ms;
+      best_chunk = ch;
+    }
+  }
+  Plan* p = nullptr;
+  if (!rc) {
+    c->tuned_chunk[key] = best_chunk;
+    rc = rebuild(&p);
+  }
+  int best_grid = 0;
+  if (!rc) {
+    const int g0 = precision == XLMIMO_FP64 ? p->grid_fp64 : (precision == XLMIMO_FP32H ? p->grid_fp32h : p->grid_fp32);
+    best_grid = g0;
+    const int cand[3] = {g0, (3 * g0) / 4, g0 / 2};
+    double best_g = 1e300;
+    for (int i = 0; i < 3 && !rc; ++i) {
+      if (cand[i] < 1) continue;
+      c->tuned_grid[gkey] = cand[i];
+      double ms = 0.0;
+      if ((rc = time_it(&ms))) break;
+      if (ms < best_g) {
+        best_g = ms;
+        best_grid = cand[i];
+      }
+    }
+    if (!rc) {
+      c->tuned_grid[gkey] = best_grid;
+      best = best_g;
+    }
+  }
+  c->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    c->tuned_chunk.erase(key);
+    c->tuned_grid.erase(gkey);
+    return rc;
+  }
+  if (chunk_out) *chunk_out = best_chunk;
+  if (grid_out) *grid_out = best_grid;
+  if (ms_out) *ms_out = best;
   return XLMIMO_OK;
 }
 

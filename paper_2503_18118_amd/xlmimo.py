@@ -33,7 +33,9 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_capacity_sweep", "xlmimo_timing_enable", "xlmimo_timing_read",
             "xlmimo_mlp_create", "xlmimo_mlp_destroy", "xlmimo_mlp_param_count", "xlmimo_mlp_set_params",
             "xlmimo_mlp_get_params", "xlmimo_pair_count", "xlmimo_mlp_pair_inputs", "xlmimo_mlp_loss_grad",
-            "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp")
+            "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
+            "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
+            "xlmimo_graph_destroy", "xlmimo_autotune_exact")
 
 
 class XlArray(C.Structure):
@@ -78,6 +80,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                                vp, vp]
     lib.xlmimo_timing_enable.argtypes = [vp, C.c_int]
     lib.xlmimo_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.xlmimo_graph_begin.argtypes = [vp, vp]
+    lib.xlmimo_graph_end.argtypes = [vp, vp, C.POINTER(vp)]
+    lib.xlmimo_graph_launch.argtypes = [vp, vp]
+    lib.xlmimo_graph_node_count.argtypes = [vp]
+    lib.xlmimo_graph_node_count.restype = i64
+    lib.xlmimo_graph_destroy.argtypes = [vp]
+    lib.xlmimo_autotune_exact.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i64, i32,
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double), vp]
     return lib
 
 
@@ -149,7 +159,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            for child in list(self._children):
+            # graphs first, then networks, then the context
+            for child in sorted(self._children, key=lambda c: not isinstance(c, Graph)):
                 child.close()
             _lib.xlmimo_ctx_destroy(self.h)
             self.h = None
@@ -173,6 +184,24 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         self._check(_lib.xlmimo_timing_read(self.h, C.byref(ms), C.byref(n)), "xlmimo_timing_read")
         return ms.value, n.value
+
+    # -- batching: graph capture and autotuning ---------------------------------
+    def graph_begin(self, stream):
+        """Open a capture on `stream` (a torch.cuda.Stream other than the default one)."""
+        self._check(_lib.xlmimo_graph_begin(self.h, _stream(stream)), "xlmimo_graph_begin")
+
+    def graph_end(self, stream) -> "Graph":
+        h = C.c_void_p()
+        self._check(_lib.xlmimo_graph_end(self.h, _stream(stream), C.byref(h)), "xlmimo_graph_end")
+        return Graph(self, h)
+
+    def autotune_exact(self, arr, batch: "Batch", precision: int = FP32H, n_elems: int = 0, stream=None) -> dict:
+        ch, g, ms = C.c_int64(), C.c_int32(), C.c_double()
+        a = make_array(arr)
+        self._check(_lib.xlmimo_autotune_exact(self.h, C.byref(a), C.byref(batch.struct), int(n_elems), precision,
+                                               C.byref(ch), C.byref(g), C.byref(ms), _stream(stream)),
+                    "xlmimo_autotune_exact")
+        return {"chunk": ch.value, "grid": g.value, "ms": ms.value}
 
     # -- entry points ------------------------------------------------------
     def gram_exact(self, arr, batch: Batch, precision: int = FP32C, out: Optional[torch.Tensor] = None,
@@ -244,6 +273,32 @@ class Context:
                                                     float(log_var_max), _ptr(out), _ptr(status), _stream(stream)),
                     "xlmimo_gram_closedform_mlp")
         return out, status
+
+
+class Graph:
+    """Executable graph of library calls captured with Context.graph_begin / graph_end."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        ctx._children.add(self)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(_lib.xlmimo_graph_node_count(self.h))
+
+    def launch(self, stream=None):
+        self.ctx._check(_lib.xlmimo_graph_launch(self.h, _stream(stream)), "xlmimo_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            _lib.xlmimo_graph_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class PairInputs:
