@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--mlp-train-drops", type=int, default=20000)
     ap.add_argument("--mlp-train-steps", type=int, default=3000)
     ap.add_argument("--mlp-log-var-max", type=float, default=-11.0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="run the closed-form and learned legs eagerly instead of replaying captured graphs")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -122,6 +125,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
+    # every launch of this run goes to one created stream (graph capture needs a non-default stream)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     arr, drops, meta = W.sweep()
     n_list = list(meta["n_list"])
     ctx = X.Context(0)
@@ -138,7 +144,6 @@ def main():
     sat_c = torch.empty_like(sat_e)
     st_e = torch.empty((len(n_list), n_drops), dtype=torch.int32, device=dev)
     st_c = torch.empty_like(st_e)
-    stream = torch.cuda.current_stream()
 
     log("training the learned correction")
     mlp, mlp_info = train_mlp(ctx, X, Lr, W, args)
@@ -150,14 +155,45 @@ def main():
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(max(args.steps, args.warmup))]
 
-    def step(e):
-        e[0].record(stream)
+    def exact_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_EXACT_FP32H, rho, schemes, 0.9, 0.05, erg_e, sat_e, st_e)
-        e[1].record(stream)
+
+    def cf_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED, rho, schemes, 0.9, 0.05, erg_c, sat_c, st_c)
-        e[2].record(stream)
+
+    def mlp_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED_MLP, rho, schemes, 0.9, 0.05, erg_m, sat_m, st_m,
                            mlp=mlp, log_var_max=lvmax)
+
+    batching = {"autotune": []}
+    if not args.no_autotune:
+        log("autotuning the exact-Gram launch shape per N")
+        for n in n_list:
+            r = ctx.autotune_exact(arr, batch, X.FP32H, n_elems=n)
+            batching["autotune"].append({"n": n, **r})
+    legs = {"cf": cf_leg, "mlp": mlp_leg}
+    if not args.no_graph:
+        # the two launch-heavy legs replay as captured graphs; the exact leg runs eagerly so that
+        # its kernel launches can be timed with events (events are not recorded inside graphs)
+        log("capturing the closed-form and learned legs")
+        cf_leg()
+        mlp_leg()
+        graphs = {}
+        for name, fn in (("cf", cf_leg), ("mlp", mlp_leg)):
+            ctx.graph_begin(stream)
+            fn()
+            graphs[name] = ctx.graph_end(stream)
+        legs = {name: g.launch for name, g in graphs.items()}
+        batching["graph"] = {"closedform_gated_nodes": graphs["cf"].n_nodes,
+                             "mlp_corrected_nodes": graphs["mlp"].n_nodes}
+
+    def step(e):
+        e[0].record(stream)
+        exact_leg()
+        e[1].record(stream)
+        legs["cf"]()
+        e[2].record(stream)
+        legs["mlp"]()
         e[3].record(stream)
 
     log("warm-up")
@@ -223,6 +259,7 @@ def main():
                                        "fallback_fraction_by_n": [float(x) for x in
                                                                   (st_m & X.ST_FELL_BACK).ne(0).float().mean(dim=1).cpu()]}},
            "mlp": mlp_info,
+           "batching": batching,
            "roofline": roofline}
 
     if args.copy_calibration:
@@ -239,8 +276,7 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(arr, drops, n_list, rho.cpu().numpy(), args.cpu_seconds)
-    mlp.close()
-    ctx.close()
+    ctx.close()   # graphs, then the network, then the context
     print(json.dumps(out))
 
 

@@ -519,7 +519,8 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
     gw.b_n = 1;
     gw.ldo = in;
     HIP_TRY(c, launch_gemm_splitk(gw, kGradSplits, part, M->grad + M->w_off[l], s));
-    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], part, kGradSplits, s));
+    const int max_splits = (int)std::min<int64_t>(4096, (int64_t)kGradSplits * M->width * std::max(M->width, XLMIMO_MLP_IN) / o);
+    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], part, max_splits, s));
     if (l > 0) {
       GemmArgs gx{};
       gx.M = (int)n;

@@ -92,7 +92,9 @@ hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_dro
                               int32_t* pmap, hipStream_t s);
 hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
                            double* partial, double* loss, hipStream_t s);
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int splits,
+// Column sums of dz [rows x cols] into db [cols], in a fixed order over at most
+// max_splits row blocks (partial holds max_splits * cols floats).
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int max_splits,
                          hipStream_t s);
 hipError_t launch_gemm_splitk(const GemmArgs& g, int splits, float* partial, float* out, hipStream_t s);
 hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,

@@ -21,6 +21,8 @@
 // bias + GELU (forward), the last-layer bias, and GELU' (backward).
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "device_math.h"
 #include "internal.h"
 #include "xlmimo.h"
@@ -320,10 +322,11 @@ __global__ void k_colsum_part(const __bf16* __restrict__ dz, int64_t rows, int c
   partial[(int64_t)blockIdx.y * cols + c] = acc;
 }
 
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int splits,
+hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int max_splits,
                          hipStream_t s) {
-  const int64_t rows_per = (rows + splits - 1) / splits;
-  splits = (int)((rows + rows_per - 1) / rows_per);
+  // about 32 rows per thread: enough workgroups to fill the chip at a few thousand rows
+  const int64_t rows_per = std::max<int64_t>(32, (rows + max_splits - 1) / max_splits);
+  const int splits = (int)((rows + rows_per - 1) / rows_per);
   dim3 grid((cols + 255) / 256, splits);
   k_colsum_part<<<grid, 256, 0, s>>>(dz, rows, cols, rows_per, partial);
   k_reduce_splits<<<(cols + 255) / 256, 256, 0, s>>>(partial, splits, cols, db);
