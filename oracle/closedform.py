@@ -34,15 +34,43 @@ Readings taken where the paper is silent:
     zero when that point lies outside the aperture.
   * |x_i| == |x_j| or coincident users: the off-diagonal is defined as 0.
 
-Pins (tests/test_oracle_closedform.py): eq. (4) against the direct sum and
-against adaptive quadrature of the integrand; eq. (5) as the M -> inf limit;
-eq. (6) against the exact Gram at large M; eq. (8) as the limit of eq. (6);
-free-space and UPA diagonals against quadrature.
+Variant UNIFORM (ULA; an extension beyond the paper's formulas, not one of them):
+  The paper's eq. (6) is the leading stationary-phase term of the aperture
+  integral and stands alone; here the discrete sum
+  S = sum_n f(y_n) e^{j phi(y_n)},  f = |h_i| |h_j|,  phi = k (r_i - r_j),
+  is approximated uniformly in the position of the stationary point y*:
+  * the continuum integral over the element cells [-L, L], L = N d / 2, by the
+    uniform asymptotic expansion about y* (the exact change of variable
+    phi(y) - phi* = sigma s^2 / 2, sigma = sgn phi''(y*), s of the sign of y - y*):
+      I = G0 e^{j phi*} [F(s_b) - F(s_a)]
+          + sum over the ends e = b (+), a (-) of
+            +- e^{j phi(e)} [ f(e) / (j phi'(e)) - G0 / (j sigma s_e) ]
+    with G0 = f(y*) / sqrt|phi''(y*)|, s_e = sgn(e - y*) sqrt(2 |phi(e) - phi*|)
+    and F(s) = int_0^s e^{j sigma t^2 / 2} dt (Fresnel integrals).  With y* deep
+    inside the aperture this is eq. (6)'s term plus the two end terms; with y*
+    outside, the end terms alone; and it stays finite as y* crosses an end.
+    x_i = x_j (no stationary point): the end terms alone.
+  * S = I / d plus, at each end element y_e, the difference between the discrete
+    half-infinite sum and its cell integral for a locally linear phase
+    theta = phi'(y_e) d:  +- f(y_e) e^{j phi(y_e)} e^{+- j theta/2} / j
+    [1 / (2 sin(theta/2)) - 1 / theta]  (+ at the top end y_top = (N-1) d / 2).
+  * Slow-phase pairs: when k |u_i - u_j| times the angular span of the aperture
+    seen from the pair's midpoint is at most QUAD_RAD_PER_PANEL * QUAD_MAX_PANELS
+    radians (users a fraction of a metre apart), stationary phase has no
+    asymptotic regime; the entry is then the aperture integral
+    (1/d) int_{-L}^{L} conj(h_i(y)) h_j(y) dy (the continuum limit of the sum,
+    as eq. (4) is for the diagonal), evaluated by composite Gauss-Legendre
+    quadrature in the angle theta seen from the midpoint (y = y_m + x_m tan theta),
+    in panels over which the phase changes by at most QUAD_RAD_PER_PANEL rad,
+    plus the same discrete end corrections.
+  The diagonal is the closed form above.  end_term() (the regularised
+  geometric-series end term) is the learned correction's basis, not part of
+  this variant.
 """
 from __future__ import annotations
 
 import numpy as np
-from scipy import integrate
+from scipy import integrate, special
 
 from workloads import AMP_FREESPACE, AMP_PNUSW, GEOM_ULA, GEOM_UPA, ArraySpec
 
@@ -50,6 +78,12 @@ from .geometry import perpendicular_distance
 
 VARIANT_PAPER = 0
 VARIANT_GATED = 1
+VARIANT_UNIFORM = 2
+
+QUAD_NODES = 64            # Gauss-Legendre nodes per panel
+QUAD_RAD_PER_PANEL = 40.0  # phase change allowed over one panel
+QUAD_MAX_PANELS = 16
+S_GUARD = 1e-2             # |s| below which the uniform end bracket is interpolated
 
 
 def sgn(x):
@@ -145,6 +179,143 @@ def stationary_point(ui, uj):
     return [(ui[c] * xj - uj[c] * xi) / (xj - xi) for c in range(1, len(ui))]
 
 
+def _amp_product(arr: ArraySpec, xp_i, xp_j, ri, rj):
+    """|h_i| |h_j| at distances ri, rj (free space or PNUSW, eq. (3))."""
+    if arr.amp_model == AMP_PNUSW:
+        return arr.beta0 * np.sqrt(xp_i * xp_j) / (ri * rj) ** 1.5
+    return (arr.wavelength / (4.0 * np.pi)) ** 2 / (ri * rj)
+
+
+def end_term(arr: ArraySpec, xp_i, y_i, xp_j, y_j, y_e, side):
+    """End-element term of sum_n conj(h_i) h_j at the array end y_e (side +1 top, -1 bottom), regularised."""
+    k = 2.0 * np.pi / arr.wavelength
+    d = arr.spacing
+    ri, rj = np.hypot(xp_i, y_e - y_i), np.hypot(xp_j, y_e - y_j)
+    d1 = k * ((y_e - y_i) / ri - (y_e - y_j) / rj)
+    d2 = k * (xp_i ** 2 / ri ** 3 - xp_j ** 2 / rj ** 3)
+    den = 1.0 - np.exp(-1j * side * d1 * d)
+    eps2 = d * d * abs(d2) / (2.0 * np.pi)
+    return _amp_product(arr, xp_i, xp_j, ri, rj) * np.exp(1j * k * (ri - rj)) * np.conj(den) / (abs(den) ** 2 + eps2)
+
+
+def slow_pair_panels(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
+    """Panels of the aperture quadrature for a slow-phase pair, 0 for a fast-phase pair."""
+    k = 2.0 * np.pi / arr.wavelength
+    L = n * arr.spacing / 2.0
+    xm, ym = 0.5 * (xp_i + xp_j), 0.5 * (y_i + y_j)
+    span = np.arctan((L - ym) / xm) - np.arctan((-L - ym) / xm)
+    v = k * np.hypot(xp_i - xp_j, y_i - y_j) * span
+    p = max(1, int(np.ceil(v / QUAD_RAD_PER_PANEL)))
+    return p if p <= QUAD_MAX_PANELS else 0
+
+
+def aperture_integral(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n, panels):
+    """(1/d) int_{-L}^{L} conj(h_i(y)) h_j(y) dy by composite Gauss-Legendre in the midpoint's angle."""
+    k = 2.0 * np.pi / arr.wavelength
+    L = n * arr.spacing / 2.0
+    xm, ym = 0.5 * (xp_i + xp_j), 0.5 * (y_i + y_j)
+    ta, tb = np.arctan((-L - ym) / xm), np.arctan((L - ym) / xm)
+    nodes, weights = np.polynomial.legendre.leggauss(QUAD_NODES)
+    edges = ta + (tb - ta) * np.arange(panels + 1) / panels
+    total = 0.0 + 0.0j
+    for a, b in zip(edges[:-1], edges[1:]):
+        th = 0.5 * (a + b) + 0.5 * (b - a) * nodes
+        y = ym + xm * np.tan(th)
+        jac = xm / np.cos(th) ** 2
+        ri, rj = np.hypot(xp_i, y - y_i), np.hypot(xp_j, y - y_j)
+        total += 0.5 * (b - a) * np.sum(weights * jac * _amp_product(arr, xp_i, xp_j, ri, rj) * np.exp(1j * k * (ri - rj)))
+    return total / arr.spacing
+
+
+def fresnel_f(s, sigma):
+    """F(s) = int_0^s e^{j sigma t^2 / 2} dt from the Fresnel integrals C and S (scipy)."""
+    sv, cv = special.fresnel(s / np.sqrt(np.pi))
+    return np.sqrt(np.pi) * (cv + 1j * sigma * sv)
+
+
+def uniform_pair(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
+    """Entry (i, j) of variant UNIFORM for a fast-phase pair (see the module notes)."""
+    k = 2.0 * np.pi / arr.wavelength
+    d = arr.spacing
+    L = n * d / 2.0
+    y_top = (n - 1) * d / 2.0
+
+    def dist(y):
+        return np.hypot(xp_i, y - y_i), np.hypot(xp_j, y - y_j)
+
+    def phi(y):
+        a, b = dist(y)
+        return k * (a - b)
+
+    def dphi(y):
+        a, b = dist(y)
+        return k * ((y - y_i) / a - (y - y_j) / b)
+
+    def f(y):
+        a, b = dist(y)
+        return _amp_product(arr, xp_i, xp_j, a, b)
+
+    ends = ((L, 1.0), (-L, -1.0))
+    integral = 0.0 + 0.0j
+    if xp_i == xp_j:
+        for e, se in ends:
+            integral += se * f(e) * np.exp(1j * phi(e)) / (1j * dphi(e))
+    else:
+        ys = (y_i * xp_j - xp_i * y_j) / (xp_j - xp_i)
+        a, b = dist(ys)
+        p2 = k * (xp_i ** 2 / a ** 3 - xp_j ** 2 / b ** 3)
+        sigma = 1.0 if p2 > 0 else -1.0
+        g0 = f(ys) / np.sqrt(abs(p2))
+        ph = phi(ys)
+
+        ai_s, aj_s = dist(ys)
+
+        def s_of(y):
+            # phi(y) - phi* from r(y) - r(y*) = (y - y*)(y + y* - 2 y_u) / (r(y) + r(y*)), which keeps its
+            # relative precision as y -> y* (the plain difference of the phases would not)
+            ai, aj = dist(y)
+            dr = (y - ys) * ((y + ys - 2.0 * y_i) / (ai + ai_s) - (y + ys - 2.0 * y_j) / (aj + aj_s))
+            return np.copysign(np.sqrt(2.0 * k * abs(dr)), y - ys)
+
+        def bracket(y):
+            # the end term minus its stationary-point singularity (both diverge as y -> y*; the difference is smooth)
+            return np.exp(1j * phi(y)) * (f(y) / (1j * dphi(y)) - g0 / (1j * sigma * s_of(y)))
+
+        for e, se in ends:
+            s_e = s_of(e)
+            if abs(s_e) < S_GUARD:
+                # too close to the stationary point for the difference: interpolate it linearly in y
+                h = S_GUARD / np.sqrt(abs(p2))
+                bm, bp = bracket(ys - h), bracket(ys + h)
+                br = bm + (e - (ys - h)) / (2.0 * h) * (bp - bm)
+            else:
+                br = bracket(e)
+            integral += se * (g0 * np.exp(1j * ph) * fresnel_f(s_e, sigma) + br)
+    return integral / d + discrete_end_corrections(arr, xp_i, y_i, xp_j, y_j, n)
+
+
+def _half_cosec_minus_inverse(th):
+    """1 / (2 sin(th/2)) - 1/th, by its series th/24 + 7 th^3/5760 + 31 th^5/967680 near 0."""
+    if abs(th) < 1e-2:
+        t2 = th * th
+        return th * (1.0 / 24.0 + t2 * (7.0 / 5760.0 + t2 * 31.0 / 967680.0))
+    return 1.0 / (2.0 * np.sin(th / 2.0)) - 1.0 / th
+
+
+def discrete_end_corrections(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
+    """Sum minus cell integral at both end elements for a locally linear phase theta = phi'(y_e) d."""
+    k = 2.0 * np.pi / arr.wavelength
+    d = arr.spacing
+    y_top = (n - 1) * d / 2.0
+    total = 0.0 + 0.0j
+    for e, side in ((y_top, 1.0), (-y_top, -1.0)):
+        a, b = np.hypot(xp_i, e - y_i), np.hypot(xp_j, e - y_j)
+        th = k * ((e - y_i) / a - (e - y_j) / b) * d
+        total += side * _amp_product(arr, xp_i, xp_j, a, b) * np.exp(1j * k * (a - b)) \
+            * np.exp(1j * side * th / 2.0) / 1j * _half_cosec_minus_inverse(th)
+    return total
+
+
 def gram_closedform(arr: ArraySpec, users: np.ndarray, n: int = None, variant: int = VARIANT_PAPER) -> np.ndarray:
     """Modified-ZF Gram G~ (eqs. (22)-(23)) for one drop; K x K complex128."""
     users = np.asarray(users, np.float64)
@@ -165,6 +336,19 @@ def gram_closedform(arr: ArraySpec, users: np.ndarray, n: int = None, variant: i
         two_d = np.stack([xp, users[:, 1], users[:, 2]], axis=-1)
         for i in range(k):
             g[i, i] = diag_upa(arr, users[i])
+    if variant == VARIANT_UNIFORM:
+        assert arr.geometry == GEOM_ULA, "the uniform variant is defined for a ULA"
+        for i in range(k):
+            for j in range(i + 1, k):
+                p = slow_pair_panels(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                if p:
+                    v = aperture_integral(arr, xp[i], users[i, 1], xp[j], users[j, 1], n, p) \
+                        + discrete_end_corrections(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                else:
+                    v = uniform_pair(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                g[i, j] = v
+                g[j, i] = np.conj(v)
+        return g
     for i in range(k):
         for j in range(k):
             if i == j:

@@ -150,3 +150,117 @@ def test_upa_offdiag_vs_exact_large_panel():
     # while a wrong pi/4 offset or a dropped 2 pi / lambda factor would be off by far more.
     assert abs(g[0, 1] - gc[0, 1]) < 0.15 * abs(gc[0, 1])
     assert abs(np.angle(g[0, 1] / gc[0, 1])) < 0.1
+
+
+# ---------------------------------------------------------------- variant UNIFORM
+
+def test_fresnel_wrapper_is_the_quadratic_phase_integral():
+    # F(s) = int_0^s e^{j sigma t^2/2} dt: direct quadrature, the infinite limit, oddness
+    for sigma in (1.0, -1.0):
+        for s in (0.3, 2.5, 7.0):
+            re, _ = integrate.quad(lambda t: math.cos(sigma * t * t / 2), 0, s, epsabs=0, epsrel=1e-13, limit=200)
+            im, _ = integrate.quad(lambda t: math.sin(sigma * t * t / 2), 0, s, epsabs=0, epsrel=1e-13, limit=200)
+            assert abs(cf.fresnel_f(s, sigma) - (re + 1j * im)) < 1e-12
+            assert cf.fresnel_f(-s, sigma) == pytest.approx(-cf.fresnel_f(s, sigma), abs=1e-15)
+        lim = math.sqrt(math.pi / 2) * complex(math.cos(math.pi / 4), sigma * math.sin(math.pi / 4))
+        assert abs(cf.fresnel_f(1e7, sigma) - lim) < 1e-7
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+def test_aperture_integral_pins(amp):
+    lam = W.LAMBDA_28GHZ
+    n = 4096
+    arr = W.ula(n, lam, amp)
+    L = n * arr.spacing / 2
+    # zero separation: the quadrature in the midpoint's angle equals the analytic diagonal
+    for x, y in ((3.0, 0.5), (12.0, -4.0), (0.8, 11.0)):
+        v = cf.aperture_integral(arr, x, y, x, y, n, 1)
+        assert v.real == pytest.approx(cf.diag_ula(arr, x, y, n), rel=1e-12) and abs(v.imag) < 1e-14 * v.real
+    # a slow pair: the same integral by adaptive quadrature in y
+    xi, yi, xj, yj = 9.0, 2.0, 9.07, 2.05
+    k = 2 * math.pi / lam
+
+    def integrand(yv, part):
+        a, b = math.hypot(xi, yv - yi), math.hypot(xj, yv - yj)
+        f = (arr.beta0 * math.sqrt(xi * xj) / (a * b) ** 1.5) if amp == W.AMP_PNUSW else (lam / (4 * math.pi)) ** 2 / (a * b)
+        return f * (math.cos(k * (a - b)) if part == 0 else math.sin(k * (a - b)))
+    re, _ = integrate.quad(integrand, -L, L, args=(0,), points=[yi], epsabs=0, epsrel=1e-12, limit=400)
+    im, _ = integrate.quad(integrand, -L, L, args=(1,), points=[yi], epsabs=0, epsrel=1e-12, limit=400)
+    p = cf.slow_pair_panels(arr, xi, yi, xj, yj, n)
+    assert p >= 1
+    v = cf.aperture_integral(arr, xi, yi, xj, yj, n, p)
+    assert abs(v - (re + 1j * im) / arr.spacing) < 1e-10 * abs(v)
+
+
+def test_slow_pairs_match_the_exact_sum():
+    # users a few centimetres to 0.3 m apart: no stationary-phase regime; the quadrature plus the
+    # discrete end corrections reproduces the exact discrete sum
+    lam = W.LAMBDA_28GHZ
+    rng = np.random.default_rng(3)
+    for n in (256, 4096, 65536):
+        arr = W.ula(n, lam)
+        for sep in (0.0, 0.02, 0.15, 0.3):
+            ang = rng.uniform(0, 2 * np.pi)
+            u = _users([(7.0, -2.0), (7.0 + sep * math.cos(ang), -2.0 + sep * math.sin(ang))])
+            g = ch.gram_exact(arr, u)
+            assert cf.slow_pair_panels(arr, u[0, 0], u[0, 1], u[1, 0], u[1, 1], n) > 0
+            gu = cf.gram_closedform(arr, u, n, cf.VARIANT_UNIFORM)
+            assert ch.normwise_error(gu, g) < 1e-6, (n, sep)
+            gg = cf.gram_closedform(arr, u, n, cf.VARIANT_GATED)
+            if sep > 0:
+                assert ch.normwise_error(gg, g) > 1e-3   # the paper's form has no answer here
+
+
+@pytest.mark.parametrize("n", [256, 4096])
+def test_uniform_matches_exact_on_sweep_drops(n):
+    arr0, drops, _ = W.sweep(400)
+    arr = arr0.with_n(n)
+    errs_u, errs_g = [], []
+    for d in range(0, 400, 20):
+        u = drops.users_of(d)
+        g = ch.gram_exact(arr, u)
+        errs_u.append(ch.normwise_error(cf.gram_closedform(arr, u, n, cf.VARIANT_UNIFORM), g))
+        errs_g.append(ch.normwise_error(cf.gram_closedform(arr, u, n, cf.VARIANT_GATED), g))
+    assert max(errs_u) < 1e-4
+    assert np.median(errs_u) < 1e-3 * np.median(errs_g)
+
+
+def test_uniform_is_continuous_as_the_stationary_point_crosses_the_end():
+    # move user j so that y* sweeps through the top end: the gated form jumps by the whole
+    # stationary-phase term, the uniform form follows the exact sum
+    lam = W.LAMBDA_28GHZ
+    n = 4096
+    arr = W.ula(n, lam)
+    L = n * arr.spacing / 2
+    xi, yi, xj = 6.0, 2.0, 18.0
+    worst_u, worst_g = 0.0, 0.0
+    for ys in list(np.linspace(L - 0.6, L + 0.6, 13)) + [L + 1e-6, L - 1e-9]:
+        yj = ys + (yi - ys) * xj / xi   # user j on the line through user i and (0, ys)
+        u = _users([(xi, yi), (xj, yj)])
+        g = ch.gram_exact(arr, u)
+        worst_u = max(worst_u, ch.normwise_error(cf.gram_closedform(arr, u, n, cf.VARIANT_UNIFORM), g))
+        worst_g = max(worst_g, ch.normwise_error(cf.gram_closedform(arr, u, n, cf.VARIANT_GATED), g))
+    assert worst_u < 1e-5 and worst_g > 3e-3
+
+
+def test_uniform_far_outside_is_the_discrete_end_series():
+    # stationary point far off the aperture: what remains are the two end contributions, i.e. the
+    # geometric series of a locally linear phase at each end
+    lam = W.LAMBDA_28GHZ
+    n = 1024
+    arr = W.ula(n, lam)
+    d = arr.spacing
+    k = 2 * math.pi / lam
+    y_top = (n - 1) * d / 2
+    xi, yi, xj, yj = 44.6, -0.1, 14.0, -19.1
+    u = _users([(xi, yi), (xj, yj)])
+
+    def geo(ye, side):
+        a, b = math.hypot(xi, ye - yi), math.hypot(xj, ye - yj)
+        th = side * k * ((ye - yi) / a - (ye - yj) / b) * d
+        return (lam / (4 * math.pi)) ** 2 / (a * b) * np.exp(1j * k * (a - b)) / (1 - np.exp(-1j * th))
+    s_geo = geo(y_top, 1.0) + geo(-y_top, -1.0)
+    gu = cf.gram_closedform(arr, u, n, cf.VARIANT_UNIFORM)[0, 1]
+    g = ch.gram_exact(arr, u)[0, 1]
+    assert abs(gu - s_geo) < 2e-4 * abs(s_geo)
+    assert abs(gu - g) < 2e-4 * abs(g)
