@@ -75,6 +75,17 @@ extern "C" {
 /* Closed-form variants (eqs. (4), (6), (22), (23); see xlmimo_gram_closedform). */
 #define XLMIMO_CF_PAPER 0      /* formulas as printed, for every pair */
 #define XLMIMO_CF_GATED 1      /* off-diagonal set to 0 when the stationary point is off the aperture */
+/* The next two are ULA-only extensions beyond the paper's formulas.  A pair is
+ * "slow-phase" when k |u_i - u_j| times the angle the aperture subtends at the
+ * pair's midpoint is at most 640 rad (users a fraction of a metre apart): it has
+ * no stationary-phase regime, and its entry is the aperture integral
+ * (1/d) int conj(h_i) h_j dy by composite Gauss-Legendre quadrature plus the
+ * discrete end corrections. */
+#define XLMIMO_CF_UNIFORM 2    /* uniform stationary-phase form of the discrete sum: the stationary term
+                                  weighted by the Fresnel integral between the array ends, end terms
+                                  without their stationary singularity, discrete end corrections;
+                                  slow-phase pairs by quadrature */
+#define XLMIMO_CF_GATED_QUAD 3 /* GATED, slow-phase pairs by quadrature (the learned correction's base) */
 
 /* Rate schemes (bitmask).  rates_out holds one value per set bit, in
  * increasing bit order. */
@@ -100,6 +111,7 @@ extern "C" {
 #define XLMIMO_FORM_CF_GATED    3
 #define XLMIMO_FORM_CF_GATED_MLP 4  /* gated closed form + learned residual + exact fallback */
 #define XLMIMO_FORM_EXACT_FP32H 5   /* exact Gram at XLMIMO_FP32H precision */
+#define XLMIMO_FORM_CF_UNIFORM  6   /* closed form, variant XLMIMO_CF_UNIFORM */
 
 #define XLMIMO_MAX_USERS 64
 
@@ -166,7 +178,8 @@ int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_bat
  *   G~_ij = rho_ij sqrt(G~_ii G~_jj) with rho_ij of eq. (6) (sgn of eq. (7)),
  *           or the corresponding stationary-phase term for the free-space
  *           ULA and the UPA (phase offset -pi/2 on the panel).
- *   variant     XLMIMO_CF_PAPER or XLMIMO_CF_GATED
+ *   variant     XLMIMO_CF_PAPER or XLMIMO_CF_GATED; for a ULA also XLMIMO_CF_UNIFORM
+ *               or XLMIMO_CF_GATED_QUAD (see their definitions; not the paper's formulas)
  *   gram_out    DEVICE complex128, layout above
  *   status_out  DEVICE int32 [n_drops] or NULL: XLMIMO_ST_BAD_INPUT,
  *               XLMIMO_ST_CF_DEGENERATE bits (overwritten, not or-ed). */
@@ -199,7 +212,8 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
  *             ergodic(N) / ergodic(N_max) >= 1 - eps_sat, for SNR s, scheme c.
  * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32H
  * Gram as the true channel; every other scheme uses the chosen form's Gram.
- *   form         XLMIMO_FORM_*; XLMIMO_FORM_CF_GATED_MLP needs mlp and log_var_max
+ *   form         XLMIMO_FORM_*; XLMIMO_FORM_CF_GATED_MLP (closed form XLMIMO_CF_GATED_QUAD +
+ *                learned residual) needs mlp and log_var_max
  *                (see xlmimo_gram_closedform_mlp), otherwise mlp may be NULL
  *   N_list       HOST int64 [n_N], strictly ascending, each >= 1
  *   rho          DEVICE double [n_snr][total_users]

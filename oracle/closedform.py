@@ -79,6 +79,7 @@ from .geometry import perpendicular_distance
 VARIANT_PAPER = 0
 VARIANT_GATED = 1
 VARIANT_UNIFORM = 2
+VARIANT_GATED_QUAD = 3     # GATED, slow-phase pairs by the aperture quadrature (the learned correction's base)
 
 QUAD_NODES = 64            # Gauss-Legendre nodes per panel
 QUAD_RAD_PER_PANEL = 40.0  # phase change allowed over one panel
@@ -336,16 +337,19 @@ def gram_closedform(arr: ArraySpec, users: np.ndarray, n: int = None, variant: i
         two_d = np.stack([xp, users[:, 1], users[:, 2]], axis=-1)
         for i in range(k):
             g[i, i] = diag_upa(arr, users[i])
-    if variant == VARIANT_UNIFORM:
-        assert arr.geometry == GEOM_ULA, "the uniform variant is defined for a ULA"
+    if variant in (VARIANT_UNIFORM, VARIANT_GATED_QUAD):
+        assert arr.geometry == GEOM_ULA, "variants UNIFORM and GATED_QUAD are defined for a ULA"
+        g_sp = gram_closedform(arr, users, n, VARIANT_GATED) if variant == VARIANT_GATED_QUAD else None
         for i in range(k):
             for j in range(i + 1, k):
                 p = slow_pair_panels(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
                 if p:
                     v = aperture_integral(arr, xp[i], users[i, 1], xp[j], users[j, 1], n, p) \
                         + discrete_end_corrections(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
-                else:
+                elif variant == VARIANT_UNIFORM:
                     v = uniform_pair(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                else:
+                    v = g_sp[i, j]
                 g[i, j] = v
                 g[j, i] = np.conj(v)
         return g

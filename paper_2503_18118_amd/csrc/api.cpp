@@ -799,7 +799,9 @@ int xlmimo_gram_closedform_mlp(xlmimo_ctx* c, const xlmimo_array* a, const xlmim
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
   if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the learned correction is defined for a ULA");
-  if (variant != XLMIMO_CF_PAPER && variant != XLMIMO_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (variant < XLMIMO_CF_PAPER || variant > XLMIMO_CF_GATED_QUAD) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (variant >= XLMIMO_CF_UNIFORM && a->geometry != XLMIMO_ULA)
+    return set_err(c, XLMIMO_EINVAL, "closed-form variant %d is defined for a ULA", variant);
   if (!M || M->ctx != c) return set_err(c, XLMIMO_EINVAL, "mlp is NULL or belongs to another context");
   if (std::isnan(log_var_max)) return set_err(c, XLMIMO_EINVAL, "log_var_max is NaN");
   if (b->n_drops == 0) return XLMIMO_OK;
@@ -916,7 +918,9 @@ int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_ba
   int rc = check_array(c, a);
   if (!rc) rc = check_batch(c, b, true);
   if (rc) return rc;
-  if (variant != XLMIMO_CF_PAPER && variant != XLMIMO_CF_GATED) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (variant < XLMIMO_CF_PAPER || variant > XLMIMO_CF_GATED_QUAD) return set_err(c, XLMIMO_EINVAL, "bad variant %d", variant);
+  if (variant >= XLMIMO_CF_UNIFORM && a->geometry != XLMIMO_ULA)
+    return set_err(c, XLMIMO_EINVAL, "closed-form variant %d is defined for a ULA", variant);
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
   if ((rc = set_device(c))) return rc;
@@ -968,7 +972,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   int rc = check_array(c, a);
   if (rc) return rc;
   if (a->geometry != XLMIMO_ULA) return set_err(c, XLMIMO_EINVAL, "the capacity sweep varies a ULA's N");
-  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_EXACT_FP32H) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
+  if (form < XLMIMO_FORM_EXACT_FP64 || form > XLMIMO_FORM_CF_UNIFORM) return set_err(c, XLMIMO_EINVAL, "bad form %d", form);
   if (form == XLMIMO_FORM_CF_GATED_MLP && (!mlp || mlp->ctx != c)) return set_err(c, XLMIMO_EINVAL, "the MLP form needs an mlp of this context");
   if (n_N < 1 || !N_list) return set_err(c, XLMIMO_EINVAL, "N_list is empty");
   for (int i = 0; i < n_N; ++i) {
@@ -977,7 +981,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   }
   if (!(t_sat > 0.0 && t_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "t_sat must lie in (0, 1)");
   if (!(eps_sat >= 0.0 && eps_sat < 1.0)) return set_err(c, XLMIMO_EINVAL, "eps_sat must lie in [0, 1)");
-  const bool cf = form >= XLMIMO_FORM_CF_PAPER && form <= XLMIMO_FORM_CF_GATED_MLP;
+  const bool cf = (form >= XLMIMO_FORM_CF_PAPER && form <= XLMIMO_FORM_CF_GATED_MLP) || form == XLMIMO_FORM_CF_UNIFORM;
   if (!cf && (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM)))
     return set_err(c, XLMIMO_EINVAL, "modified-ZF schemes need a closed-form sweep");
   if ((rc = check_rates_args(c, b, (const double*)1, (const double*)1, n_snr, rho, schemes))) return rc;
@@ -1022,7 +1026,10 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
                        : (form == XLMIMO_FORM_EXACT_FP32H ? XLMIMO_FP32H : XLMIMO_FP32C);
       if ((rc = gram_exact_impl(c, a, b, &nn, prec, g, s))) return rc;
     } else {
-      const int variant = form == XLMIMO_FORM_CF_PAPER ? XLMIMO_CF_PAPER : XLMIMO_CF_GATED;
+      const int variant = form == XLMIMO_FORM_CF_PAPER     ? XLMIMO_CF_PAPER
+                          : form == XLMIMO_FORM_CF_UNIFORM ? XLMIMO_CF_UNIFORM
+                          : form == XLMIMO_FORM_CF_GATED   ? XLMIMO_CF_GATED
+                                                           : XLMIMO_CF_GATED_QUAD;
       if (form == XLMIMO_FORM_CF_GATED_MLP) {
         if ((rc = closedform_mlp_impl(c, a, b, &nn, variant, mlp, log_var_max, g, nullptr, s, &fb_flags))) return rc;
       } else if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) {

@@ -17,9 +17,15 @@
 //   UPA FREESPACE  (lambda/4pi)^2 lambda / (d^2 |x_i - x_j|) e^{j s (k d_ij - pi/2)}
 //   with s = sgn(|x_i| - |x_j|).  Variant GATED zeroes the entry when the
 //   stationary point is off the aperture; |x_i| == |x_j| or d_ij == 0 gives 0.
+// Variant GATED_QUAD (ULA): GATED, except pairs without a stationary-phase regime
+//   (slow-phase pairs, pair_math.h), which take the aperture quadrature.
+// Variant UNIFORM (ULA): the uniform stationary-phase form of the discrete sum
+//   for fast-phase pairs and the aperture quadrature for slow-phase pairs
+//   (pair_math.h); one thread per pair.
 // All arithmetic is FP64; the phase d_ij / lambda is reduced in revolutions.
 #include "device_math.h"
 #include "internal.h"
+#include "pair_math.h"
 #include "xlmimo.h"
 
 namespace xl {
@@ -106,6 +112,72 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
   __syncthreads();
 
   double* out = gram + 2 * dp.gram_off;
+  if (ula && (variant == XLMIMO_CF_UNIFORM || variant == XLMIMO_CF_GATED_QUAD)) {
+    // one thread per pair p < q (a slow-phase pair costs up to 1024 quadrature nodes)
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+      out[2 * (i * K + i)] = s_diag[i];
+      out[2 * (i * K + i) + 1] = 0.0;
+    }
+    const int np = K * (K - 1) / 2;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+      int p = 0, rem = t;
+      while (rem >= K - 1 - p) {
+        rem -= K - 1 - p;
+        ++p;
+      }
+      const int q = p + 1 + rem;
+      double re = 0.0, im = 0.0;
+      if (!(isfinite(s_diag[p]) && isfinite(s_diag[q]))) {
+        re = im = __builtin_nan("");
+      } else {
+        const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], 2.0 * kPi * arr.inv_lambda, arr.inv_lambda, arr.amp,
+                         arr.beta0, c_fs};
+        const int n = dp.n_elems;
+        const int panels = slow_panels(g, n, d);
+        if (panels > 0) {
+          const Cplx v = cadd(aperture_quadrature(g, n, d, panels, gl, n_gl), discrete_end_corrections(g, n, d));
+          re = v.re;
+          im = v.im;
+        } else if (variant == XLMIMO_CF_UNIFORM) {
+          const Cplx v = uniform_pair(g, n, d, gl, n_gl);
+          re = v.re;
+          im = v.im;
+        } else {
+          // stationary-phase entry of variant GATED (free space or eq. (6)), zero off the aperture
+          const double xp = s_x[p], xq = s_x[q];
+          const double dx = xp - xq, dy = s_y[p] - s_y[q];
+          const double dist = sqrt(dx * dx + dy * dy);
+          if (dx == 0.0 || dist == 0.0) {
+            atomicOr(&s_status, XLMIMO_ST_CF_DEGENERATE);
+          } else if (fabs((s_y[p] * xq - xp * s_y[q]) / (xq - xp)) <= Ly) {
+            const double sg = dx > 0.0 ? 1.0 : -1.0;
+            double mag;
+            if (arr.amp == XLMIMO_AMP_PNUSW) {
+              const double rho = sqrt(lam) * fabs(dx) / (dist * sqrt(dist)) / sqrt(s_sfac[p] * s_sfac[q]);
+              mag = rho * sqrt(s_diag[p] * s_diag[q]);
+            } else {
+              mag = c_fs * sqrt(lam) / (d * sqrt(xp * xq * dist));
+            }
+            double tt;
+            int qd;
+            reduce_quarter(dist * arr.inv_lambda - 0.125, tt, qd);
+            double sn, cs, cre, cim;
+            sincos_rev(tt, sn, cs);
+            rotate_conj(1.0, sn, cs, qd, cre, cim);
+            re = mag * cre;
+            im = -sg * mag * cim;
+          }
+        }
+      }
+      out[2 * (p * K + q)] = re;
+      out[2 * (p * K + q) + 1] = im;
+      out[2 * (q * K + p)] = re;
+      out[2 * (q * K + p) + 1] = -im;
+    }
+    __syncthreads();
+    if (status != nullptr && threadIdx.x == 0) status[blockIdx.x] = s_status;
+    return;
+  }
   for (int idx = threadIdx.x; idx < K * K; idx += blockDim.x) {
     const int i = idx / K, j = idx - (idx / K) * K;
     double re = 0.0, im = 0.0;

@@ -25,6 +25,7 @@
 
 #include "device_math.h"
 #include "internal.h"
+#include "pair_math.h"
 #include "xlmimo.h"
 
 namespace xl {
@@ -227,6 +228,15 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
     }
     aux[p * 8 + 4] = pr;
     aux[p * 8 + 5] = pi;
+    {
+      // slow-phase pairs have no stationary-phase regime: their closed-form entry is the aperture
+      // quadrature (variants GATED_QUAD, UNIFORM) and the network does not correct them
+      const PairGeom pg{xi, yi, xj, yj, kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+      if (slow_panels(pg, dp.n_elems, arr.spacing) > 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) aux[p * 8 + q] = 0.0f;
+      }
+    }
     aux[p * 8 + 6] = (float)scale;
     aux[p * 8 + 7] = 0.0f;
     if (target != nullptr) {

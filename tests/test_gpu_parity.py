@@ -173,6 +173,50 @@ def test_closedform(X, ctx, geom, amp, variant):
     assert torch.all(status == 0)
 
 
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_closedform_uniform_and_gated_quad(X, ctx, amp, variant):
+    # ULA extensions: sweep-like drops, co-located users (slow-phase pairs, quadrature) and a pair whose
+    # stationary point sits on the array end (the uniform form's guarded bracket)
+    arr = W.ula(1, W.LAMBDA_28GHZ, amp)
+    base = _custom_drops([256, 4096, 65536, 262144, 1000], [4, 16, 33, 64, 2], seed=17, r=(0.8, 40.0))
+    n_end = 4096
+    L = n_end * arr.spacing / 2
+    xi, yi, xj = 6.0, 2.0, 18.0
+    extra = np.array([[7.0, -2.0, 0.0], [7.01, -2.005, 0.0], [7.2, -1.9, 0.0], [20.0, 5.0, 0.0],
+                      [xi, yi, 0.0], [xj, L + (yi - L) * xj / xi, 0.0]])
+    drops = W._pack(list(base.n_elems) + [n_end], list(base.n_users) + [6], np.concatenate([base.pos, extra]))
+    b = X.Batch(drops)
+    out, status = ctx.gram_closedform(arr, b, variant)
+    torch.cuda.synchronize()
+    g = b.split(out)
+    for d in range(drops.n_drops):
+        ref = ocf.gram_closedform(arr, drops.users_of(d), int(drops.n_elems[d]), variant)
+        scale = np.sqrt(np.outer(np.abs(np.diag(ref)), np.abs(np.diag(ref))))
+        # UNIFORM: the oracle evaluates G0 e^{j phi*} F(s) - G0 e^{j phi(e)} / (j sigma s) directly from
+        # the Fresnel integrals, two terms of size G0/s whose phases carry a rounding of ~s^2 eps with
+        # |s| up to ~1e3 at N = 262144; the HIP side folds F's asymptotic series analytically.  Normwise
+        # 1e-8 covers that conditioning; GATED_QUAD has no Fresnel term and keeps 1e-10.
+        tol = 1e-8 if variant == 2 else 1e-10
+        assert np.max(np.abs(g[d] - ref) / scale) < tol, d
+        assert np.array_equal(g[d], g[d].conj().T)
+    assert torch.all(status == 0)
+
+
+def test_closedform_uniform_accuracy_on_sweep_drops(X, ctx):
+    # the uniform form against the exact FP64 Gram on the sweep workload's user law (5-50 m)
+    arr, drops, _ = W.sweep(64)
+    for n in (256, 4096, 65536):
+        b = X.Batch(drops.with_n(n))
+        a = arr.with_n(n)
+        gu = b.split(ctx.gram_closedform(a, b, 2)[0])
+        gg = b.split(ctx.gram_closedform(a, b, 1)[0])
+        ge = b.split(ctx.gram_exact(a, b, X.FP64))
+        eu = [och.normwise_error(gu[d], ge[d]) for d in range(drops.n_drops)]
+        eg = [och.normwise_error(gg[d], ge[d]) for d in range(drops.n_drops)]
+        assert max(eu) < 1e-3 and np.median(eu) < 1e-2 * np.median(eg), (n, max(eu), np.median(eu), np.median(eg))
+
+
 def test_closedform_bad_and_degenerate_inputs(X, ctx):
     arr = W.ula(1024, W.LAMBDA_28GHZ)
     pos = np.array([[0.0, 1.0, 0.0], [3.0, 1.0, 0.0],      # user on the array line

@@ -68,7 +68,7 @@ def test_basis_phases_and_end_correction():
     # with c_top = c_bot = 1 they remove most of the closed form's error (the discrete sum's
     # end contributions): pinned against the exact Gram of the channel oracle
     lam = W.LAMBDA_28GHZ
-    n = 256
+    n = 4096
     arr = W.ula(n, lam)
     rng = np.random.default_rng(4)
     errs_cf, errs_end = [], []
@@ -84,14 +84,14 @@ def test_basis_phases_and_end_correction():
         errs_cf.append(abs(gc[0, 1] - g[0, 1]) / ref)
         errs_end.append(abs(gc[0, 1] + (b[0] + b[1]) * sc - g[0, 1]) / ref)
     assert np.median(errs_end) < 1e-3 * np.median(errs_cf)
-    assert f[4] == pytest.approx(math.log(256) / math.log(4) - 6)
+    assert f[4] == pytest.approx(math.log(4096) / math.log(4) - 6)
 
 
 def test_basis_end_term_matches_geometric_series():
     # far from phi' = 0 the regularisation is negligible and b_top * cf_scale equals the
     # geometric series f e^{j phi} / (1 - e^{-j phi' d}) evaluated from the channel itself
     lam = W.LAMBDA_28GHZ
-    n = 64
+    n = 1024
     arr = W.ula(n, lam)
     u = np.array([[3.0, -2.0, 0.0], [9.0, 4.0, 0.0]])
     h = och.channel_matrix(arr, u)
@@ -111,7 +111,7 @@ def test_basis_end_term_is_bounded_where_phase_is_stationary():
     # would diverge; the regularised term is bounded by f / (2 eps), eps = d sqrt(|phi''| / 2 pi),
     # and vanishes at the singular point itself
     lam = W.LAMBDA_28GHZ
-    n = 101
+    n = 2001
     d = lam / 2
     yt = (n - 1) * d / 2
     ang = math.radians(30)
@@ -141,3 +141,15 @@ def test_loss_is_minimised_by_the_target():
     loss, dout = M.loss_and_dout(out, ph, t)
     assert loss == pytest.approx(0.0)
     assert np.allclose(dout[:, :6], 0.0)
+
+
+def test_basis_is_zero_for_slow_phase_pairs():
+    # users a few centimetres apart have no stationary-phase regime: the base closed form integrates
+    # them (variant GATED_QUAD) and the network gets a zero basis there
+    lam = W.LAMBDA_28GHZ
+    arr = W.ula(4096, lam)
+    f, b = M.pair_inputs(9.0, 1.0, 9.03, 1.02, 4096, arr.spacing, lam, 1.0)
+    assert np.all(b == 0)
+    assert ocf.slow_pair_panels(arr, 9.0, 1.0, 9.03, 1.02, 4096) > 0
+    f, b = M.pair_inputs(9.0, 1.0, 20.0, 7.0, 4096, arr.spacing, lam, 1.0)
+    assert np.all(b != 0) and ocf.slow_pair_panels(arr, 9.0, 1.0, 20.0, 7.0, 4096) == 0
