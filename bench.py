@@ -5,12 +5,15 @@ One step = the capacity sweep workload (ULA at 28 GHz, N in {256, 1024, ...,
   * exact Gram in the FP32H form (FP32-compensated entries, split-half FP16
     matrix-core products) for every (N, drop), ZF and MMSE sum-rates, ergodic
     means and the saturation point (xlmimo_capacity_sweep);
-  * the same sweep with the paper's closed-form (modified-ZF) Gram;
-  * the same sweep with the learned-corrected closed form (exact fallback for
+  * the same sweep with the paper's closed-form (modified-ZF) Gram (gated eq. (6));
+  * the same sweep with the uniform closed form (uniform stationary-phase form of
+    the discrete sum, aperture quadrature for slow-phase pairs);
+  * the same sweep with the learned-corrected closed form (gated eq. (6) with
+    slow-phase pairs integrated, plus the network's residual; exact fallback for
     drops whose predicted uncertainty exceeds the threshold).
 The network is trained before timing, on the GPU, from exact Grams of separate
 training drops.  The value is the unique Gram entries K(K+1)/2 produced per
-second over the whole step (all three forms); per-form rates, accuracies
+second over the whole step (all four forms); per-form rates, accuracies
 against the FP64 exact form, the roofline of the exact-Gram kernel (timed live
 with HIP events on its launch stream), the network's training and inference
 throughput, and the FP64 CPU oracle on a bounded sample are reported beside.
@@ -140,10 +143,13 @@ def main():
     dev = batch.pos.device
     erg_e = torch.empty((len(n_list), 3, 2), dtype=torch.float64, device=dev)
     erg_c = torch.empty_like(erg_e)
+    erg_u = torch.empty_like(erg_e)
     sat_e = torch.empty(3 + 6, dtype=torch.float64, device=dev)
     sat_c = torch.empty_like(sat_e)
+    sat_u = torch.empty_like(sat_e)
     st_e = torch.empty((len(n_list), n_drops), dtype=torch.int32, device=dev)
     st_c = torch.empty_like(st_e)
+    st_u = torch.empty_like(st_e)
 
     log("training the learned correction")
     mlp, mlp_info = train_mlp(ctx, X, Lr, W, args)
@@ -153,13 +159,16 @@ def main():
     st_m = torch.empty_like(st_e)
     lvmax = args.mlp_log_var_max
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(max(args.steps, args.warmup))]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(max(args.steps, args.warmup))]
 
     def exact_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_EXACT_FP32H, rho, schemes, 0.9, 0.05, erg_e, sat_e, st_e)
 
     def cf_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED, rho, schemes, 0.9, 0.05, erg_c, sat_c, st_c)
+
+    def uniform_leg():
+        ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_UNIFORM, rho, schemes, 0.9, 0.05, erg_u, sat_u, st_u)
 
     def mlp_leg():
         ctx.capacity_sweep(arr, n_list, batch, X.FORM_CF_GATED_MLP, rho, schemes, 0.9, 0.05, erg_m, sat_m, st_m,
@@ -171,20 +180,22 @@ def main():
         for n in n_list:
             r = ctx.autotune_exact(arr, batch, X.FP32H, n_elems=n)
             batching["autotune"].append({"n": n, **r})
-    legs = {"cf": cf_leg, "mlp": mlp_leg}
+    legs = {"cf": cf_leg, "uniform": uniform_leg, "mlp": mlp_leg}
     if not args.no_graph:
         # the two launch-heavy legs replay as captured graphs; the exact leg runs eagerly so that
         # its kernel launches can be timed with events (events are not recorded inside graphs)
         log("capturing the closed-form and learned legs")
         cf_leg()
+        uniform_leg()
         mlp_leg()
         graphs = {}
-        for name, fn in (("cf", cf_leg), ("mlp", mlp_leg)):
+        for name, fn in (("cf", cf_leg), ("uniform", uniform_leg), ("mlp", mlp_leg)):
             ctx.graph_begin(stream)
             fn()
             graphs[name] = ctx.graph_end(stream)
         legs = {name: g.launch for name, g in graphs.items()}
         batching["graph"] = {"closedform_gated_nodes": graphs["cf"].n_nodes,
+                             "closedform_uniform_nodes": graphs["uniform"].n_nodes,
                              "mlp_corrected_nodes": graphs["mlp"].n_nodes}
 
     def step(e):
@@ -193,8 +204,10 @@ def main():
         e[1].record(stream)
         legs["cf"]()
         e[2].record(stream)
-        legs["mlp"]()
+        legs["uniform"]()
         e[3].record(stream)
+        legs["mlp"]()
+        e[4].record(stream)
 
     log("warm-up")
     for i in range(args.warmup):
@@ -211,7 +224,8 @@ def main():
     wall = time.perf_counter() - t0
     t_exact = sum(e[0].elapsed_time(e[1]) for e in ev[:args.steps])
     t_cf = sum(e[1].elapsed_time(e[2]) for e in ev[:args.steps])
-    t_mlp = sum(e[2].elapsed_time(e[3]) for e in ev[:args.steps])
+    t_uni = sum(e[2].elapsed_time(e[3]) for e in ev[:args.steps])
+    t_mlp = sum(e[3].elapsed_time(e[4]) for e in ev[:args.steps])
     kern_ms, n_launch = ctx.timing_read()
     ctx.timing_enable(False)
     ms_per_step = wall * 1e3 / args.steps
@@ -228,7 +242,7 @@ def main():
     fp32c_ref = {"entries_per_s": entries_per_form / (e0.elapsed_time(e1) * 1e-3), "ms": e0.elapsed_time(e1),
                  "ergodic_rel_diff_vs_fp32h": float(((erg_f - erg_e).abs() / erg_e.abs()).max())}
 
-    value = 3 * entries_per_form / (ms_per_step * 1e-3)
+    value = 4 * entries_per_form / (ms_per_step * 1e-3)
     evals = n_drops * sum(n_list) * k
     pair_macs = n_drops * sum(n_list) * k * (k + 1) // 2
     flops_per_step = FLOP_PER_ENTRY_EVAL * evals + FLOP_PER_PAIR_MAC * pair_macs
@@ -246,7 +260,8 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "capacity sweep: ULA 28 GHz half-wavelength, N in {256..262144} (powers of 4), "
-                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32H, closed form, "
+                                  "K=16, 10^4 seeded drops, SNR {0,10,20} dB, ZF+MMSE; exact FP32H, closed form (paper, gated), "
+                                  "uniform closed form, "
                                   "learned-corrected closed form",
                       "n_list": n_list, "drops": n_drops, "users": k, "snr_db": list(meta["snr_db"])},
            "forms": {"exact_fp32h": {"entries_per_s": entries_per_form / (t_exact * 1e-3 / args.steps),
@@ -254,6 +269,8 @@ def main():
                      "exact_fp32c_untimed": fp32c_ref,
                      "closedform_gated": {"entries_per_s": entries_per_form / (t_cf * 1e-3 / args.steps),
                                           "ms": t_cf / args.steps},
+                     "closedform_uniform": {"entries_per_s": entries_per_form / (t_uni * 1e-3 / args.steps),
+                                            "ms": t_uni / args.steps},
                      "mlp_corrected": {"entries_per_s": entries_per_form / (t_mlp * 1e-3 / args.steps),
                                        "ms": t_mlp / args.steps, "log_var_max": lvmax,
                                        "fallback_fraction_by_n": [float(x) for x in
@@ -270,7 +287,7 @@ def main():
         out["copy_calibration_bytes"] = 256 << 20
     if not args.no_accuracy:
         log("accuracy against the FP64 exact Gram")
-        out["accuracy"] = accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, out["forms"], mlp, lvmax)
+        out["accuracy"] = accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, erg_u, out["forms"], mlp, lvmax)
         log("network inference throughput")
         out["mlp"]["inference"] = mlp_inference(ctx, X, Lr, W, mlp)
     if not args.no_cpu_baseline:
@@ -328,13 +345,13 @@ def mlp_inference(ctx, X, Lr, W, mlp):
             "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS, "frac_of_peak": tf / PEAK_BF16_MFMA_TFLOPS}
 
 
-def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=None, lvmax=0.0):
+def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, erg_u, forms, mlp=None, lvmax=0.0):
     """Per-drop Gram and sum-rate errors of the FP32H, FP32C, closed-form and learned-corrected Grams
     against the FP64 exact Gram."""
     import torch
     schemes = X.ZF | X.MMSE
     res = {"reference": "exact FP64 Gram on the GPU (parity-tested against the FP64 oracle)", "per_n": []}
-    admissible, admissible_mlp = [], []
+    admissible, admissible_uni, admissible_mlp = [], [], []
     for n in n_list:
         log(f"accuracy N={n}")
         b = X.Batch(drops.with_n(n), pos=batch.pos)
@@ -348,7 +365,9 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
         r16, _ = ctx.sumrate(b, g16, rho, schemes)
         rcf, _ = ctx.sumrate(b, gcf, rho, schemes)
         rm, _ = ctx.sumrate(b, g64, rho, X.MZF_MISM, gram_filter=gcf)
-        gml, stm = ctx.gram_closedform_mlp(a, b, mlp, X.CF_GATED, log_var_max=lvmax)
+        gml, stm = ctx.gram_closedform_mlp(a, b, mlp, X.CF_GATED_QUAD, log_var_max=lvmax)
+        guf, _ = ctx.gram_closedform(a, b, X.CF_UNIFORM)
+        ruf, _ = ctx.sumrate(b, guf, rho, schemes)
         rml, _ = ctx.sumrate(b, gml, rho, schemes)
         torch.cuda.synchronize()
         k = int(drops.n_users[0])
@@ -364,6 +383,7 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
         ecf = torch.abs(rcf / r64 - 1)
         emm = torch.abs(rm[..., 0] / r64[..., 0] - 1)
         eml = torch.abs(rml / r64 - 1)
+        euf = torch.abs(ruf / r64 - 1)
         row = {"n": n, "fp32h_gram_normwise_max": gram_err(g16),
                "fp32h_sumrate_rel_max": float(e16.max()),
                "fp32c_gram_normwise_max": gram_err(g32),
@@ -371,21 +391,29 @@ def accuracy(ctx, X, arr, batch, drops, n_list, rho, erg_e, erg_c, forms, mlp=No
                "closedform_sumrate_rel_max": float(torch.nan_to_num(ecf, nan=float("inf")).max()),
                "closedform_sumrate_rel_median": float(torch.nanmedian(ecf)),
                "closedform_mismatched_zf_rel_max": float(torch.nan_to_num(emm, nan=float("inf")).max()),
+               "uniform_gram_normwise_max": gram_err(guf),
+               "uniform_sumrate_rel_max": float(torch.nan_to_num(euf, nan=float("inf")).max()),
+               "uniform_sumrate_rel_median": float(torch.nanmedian(euf)),
                "mlp_sumrate_rel_max": float(torch.nan_to_num(eml, nan=float("inf")).max()),
                "mlp_sumrate_rel_median": float(torch.nanmedian(eml)),
                "mlp_fallback_fraction": float((stm & X.ST_FELL_BACK).ne(0).float().mean())}
         res["per_n"].append(row)
         if row["closedform_sumrate_rel_max"] <= 1e-3:
             admissible.append(n)
+        if row["uniform_sumrate_rel_max"] <= 1e-3:
+            admissible_uni.append(n)
         if row["mlp_sumrate_rel_max"] <= 1e-3:
             admissible_mlp.append(n)
     for f in ("fp32h", "fp32c"):
         res[f"{f}_meets_1e-5_gram_and_1e-3_rate"] = all(r[f"{f}_gram_normwise_max"] <= 1e-5 and
                                                          r[f"{f}_sumrate_rel_max"] <= 1e-3 for r in res["per_n"])
     res["closedform_admissible_n"] = admissible
+    res["uniform_admissible_n"] = admissible_uni
     res["mlp_admissible_n"] = admissible_mlp
     erg_rel = (erg_e - erg_c).abs() / erg_e.abs()
     res["closedform_ergodic_rel_err_by_n"] = [float(x) for x in erg_rel.amax(dim=(1, 2)).cpu()]
+    erg_rel = (erg_e - erg_u).abs() / erg_e.abs()
+    res["uniform_ergodic_rel_err_by_n"] = [float(x) for x in erg_rel.amax(dim=(1, 2)).cpu()]
     return res
 
 

@@ -54,15 +54,18 @@ Variant UNIFORM (ULA; an extension beyond the paper's formulas, not one of them)
     half-infinite sum and its cell integral for a locally linear phase
     theta = phi'(y_e) d:  +- f(y_e) e^{j phi(y_e)} e^{+- j theta/2} / j
     [1 / (2 sin(theta/2)) - 1 / theta]  (+ at the top end y_top = (N-1) d / 2).
-  * Slow-phase pairs: when k |u_i - u_j| times the angular span of the aperture
-    seen from the pair's midpoint is at most QUAD_RAD_PER_PANEL * QUAD_MAX_PANELS
-    radians (users a fraction of a metre apart), stationary phase has no
-    asymptotic regime; the entry is then the aperture integral
+  * Numeric pairs (numeric_route): slow-phase pairs, for which k |u_i - u_j|
+    times the angular span of the aperture seen from the pair's midpoint is at
+    most QUAD_RAD_PER_PANEL * QUAD_MAX_PANELS radians (users a fraction of a
+    metre apart: no asymptotic regime), and pairs whose stationary zone is broad
+    (Fresnel width >= L / BROAD_FRACTION: the phase is far from quadratic over it)
+    when that is affordable.  Their entry is the aperture integral
     (1/d) int_{-L}^{L} conj(h_i(y)) h_j(y) dy (the continuum limit of the sum,
     as eq. (4) is for the diagonal), evaluated by composite Gauss-Legendre
     quadrature in the angle theta seen from the midpoint (y = y_m + x_m tan theta),
     in panels over which the phase changes by at most QUAD_RAD_PER_PANEL rad,
-    plus the same discrete end corrections.
+    plus the same discrete end corrections; or the direct sum over the N
+    elements when that costs no more.
   The diagonal is the closed form above.  end_term() (the regularised
   geometric-series end term) is the learned correction's basis, not part of
   this variant.
@@ -85,6 +88,8 @@ QUAD_NODES = 64            # Gauss-Legendre nodes per panel
 QUAD_RAD_PER_PANEL = 40.0  # phase change allowed over one panel
 QUAD_MAX_PANELS = 16
 S_GUARD = 1e-2             # |s| below which the uniform end bracket is interpolated
+BROAD_FRACTION = 8.0       # a stationary zone of Fresnel width >= L / BROAD_FRACTION is "broad"
+ROUTE_NONE, ROUTE_DIRECT, ROUTE_QUAD = 0, 1, 2
 
 
 def sgn(x):
@@ -199,15 +204,55 @@ def end_term(arr: ArraySpec, xp_i, y_i, xp_j, y_j, y_e, side):
     return _amp_product(arr, xp_i, xp_j, ri, rj) * np.exp(1j * k * (ri - rj)) * np.conj(den) / (abs(den) ** 2 + eps2)
 
 
-def slow_pair_panels(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
-    """Panels of the aperture quadrature for a slow-phase pair, 0 for a fast-phase pair."""
-    k = 2.0 * np.pi / arr.wavelength
-    L = n * arr.spacing / 2.0
+def quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n):
+    """Panels of QUAD_NODES nodes for the aperture quadrature: |d phi / d theta| <= k |u_i - u_j|."""
+    k = 2.0 * np.pi / lam
+    L = n * spacing / 2.0
     xm, ym = 0.5 * (xp_i + xp_j), 0.5 * (y_i + y_j)
     span = np.arctan((L - ym) / xm) - np.arctan((-L - ym) / xm)
     v = k * np.hypot(xp_i - xp_j, y_i - y_j) * span
-    p = max(1, int(np.ceil(v / QUAD_RAD_PER_PANEL)))
+    return max(1, int(np.ceil(v / QUAD_RAD_PER_PANEL)))
+
+
+def numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n):
+    """(route, panels): route ROUTE_DIRECT / ROUTE_QUAD for a pair the closed forms UNIFORM and GATED_QUAD
+    evaluate numerically, ROUTE_NONE otherwise.  Numeric pairs: slow-phase pairs (<= QUAD_MAX_PANELS
+    panels) and pairs whose stationary zone is broad (Fresnel width sqrt(2 pi / |phi''(y*)|) >= L / 8, or
+    x_i == x_j) when the quadrature costs at most N / 4 nodes; the direct sum over the N elements is used
+    when it costs no more than the quadrature."""
+    p = quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n)
+    L = n * spacing / 2.0
+    broad = True
+    if xp_i != xp_j:
+        k = 2.0 * np.pi / lam
+        ys = (y_i * xp_j - xp_i * y_j) / (xp_j - xp_i)
+        a, b = np.hypot(xp_i, ys - y_i), np.hypot(xp_j, ys - y_j)
+        p2 = k * (xp_i ** 2 / a ** 3 - xp_j ** 2 / b ** 3)
+        broad = p2 == 0.0 or 2.0 * np.pi / abs(p2) >= (L / BROAD_FRACTION) ** 2
+    if p <= QUAD_MAX_PANELS or (broad and p * QUAD_NODES * 4 <= n):
+        return (ROUTE_DIRECT if n <= p * QUAD_NODES else ROUTE_QUAD), p
+    return ROUTE_NONE, 0
+
+
+def slow_pair_panels(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
+    """Panels of the aperture quadrature for a slow-phase pair, 0 for a fast-phase pair."""
+    p = quad_panels(arr.spacing, arr.wavelength, xp_i, y_i, xp_j, y_j, n)
     return p if p <= QUAD_MAX_PANELS else 0
+
+
+def direct_sum(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n):
+    """sum_n conj(h_i(y_n)) h_j(y_n) over the elements (the definition, for one pair)."""
+    k = 2.0 * np.pi / arr.wavelength
+    y = (np.arange(n) - (n - 1) / 2.0) * arr.spacing
+    ri, rj = np.hypot(xp_i, y - y_i), np.hypot(xp_j, y - y_j)
+    return np.sum(_amp_product(arr, xp_i, xp_j, ri, rj) * np.exp(1j * k * (ri - rj)))
+
+
+def numeric_entry(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n, route, panels):
+    if route == ROUTE_DIRECT:
+        return direct_sum(arr, xp_i, y_i, xp_j, y_j, n)
+    return aperture_integral(arr, xp_i, y_i, xp_j, y_j, n, panels) \
+        + discrete_end_corrections(arr, xp_i, y_i, xp_j, y_j, n)
 
 
 def aperture_integral(arr: ArraySpec, xp_i, y_i, xp_j, y_j, n, panels):
@@ -342,10 +387,9 @@ def gram_closedform(arr: ArraySpec, users: np.ndarray, n: int = None, variant: i
         g_sp = gram_closedform(arr, users, n, VARIANT_GATED) if variant == VARIANT_GATED_QUAD else None
         for i in range(k):
             for j in range(i + 1, k):
-                p = slow_pair_panels(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
-                if p:
-                    v = aperture_integral(arr, xp[i], users[i, 1], xp[j], users[j, 1], n, p) \
-                        + discrete_end_corrections(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                route, p = numeric_route(arr.spacing, lam, xp[i], users[i, 1], xp[j], users[j, 1], n)
+                if route != ROUTE_NONE:
+                    v = numeric_entry(arr, xp[i], users[i, 1], xp[j], users[j, 1], n, route, p)
                 elif variant == VARIANT_UNIFORM:
                     v = uniform_pair(arr, xp[i], users[i, 1], xp[j], users[j, 1], n)
                 else:

@@ -23,8 +23,8 @@ Pair inputs (user i, user j of one drop; x = perpendicular distance, y along the
             b_spm = e^{j phi(y*)}, y* the stationary point (y_i x_j - x_i y_j)/(x_j - x_i)
               (1 when x_i == x_j);
             phi(y) = (2 pi/lambda)(r_i(y) - r_j(y)), f = |h_i(y)| |h_j(y)| of the channel model;
-            all three are 0 for a slow-phase pair (closedform.slow_pair_panels > 0: no stationary-phase
-            regime; the base closed form GATED_QUAD integrates it numerically).
+            all three are 0 for a pair the base closed form (GATED_QUAD) evaluates numerically
+            (closedform.numeric_route: slow-phase pairs and broad stationary zones).
   target    delta = rho_exact_ij - rho~_ij (complex)
 Network: 6 -> [Linear(w) + GELU] x depth -> Linear(7); GELU(z) = z (1 + erf(z / sqrt 2)) / 2.
 Output o: coefficients c_m = o[2m] + j o[2m+1] (m = top, bot, star) and s = o[6] = log sigma^2;
@@ -41,7 +41,7 @@ import math
 import numpy as np
 from scipy import special
 
-from .closedform import QUAD_MAX_PANELS, QUAD_RAD_PER_PANEL
+from .closedform import ROUTE_NONE, numeric_route
 
 N_IN = 6
 N_OUT = 7
@@ -120,12 +120,8 @@ def pair_inputs(xp_i, y_i, xp_j, y_j, n, spacing, lam, cf_scale, amp_model=0, be
         return amp(y) * np.exp(1j * phi(y)) * np.conj(den) / (abs(den) ** 2 + eps2) / cf_scale
 
     y_top = (n - 1) * spacing / 2.0
-    # slow-phase pairs (no stationary-phase regime; the base closed form integrates them): no correction
-    L = n * spacing / 2.0
-    xm, ym = 0.5 * (xp_i + xp_j), 0.5 * (y_i + y_j)
-    span = math.atan((L - ym) / xm) - math.atan((-L - ym) / xm)
-    v = k * math.hypot(xp_i - xp_j, y_i - y_j) * span
-    if max(1, math.ceil(v / QUAD_RAD_PER_PANEL)) <= QUAD_MAX_PANELS:
+    # pairs the base closed form evaluates numerically (GATED_QUAD, UNIFORM): no correction
+    if numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n)[0] != ROUTE_NONE:
         return f, np.zeros(3, np.complex128)
     if xp_i == xp_j:
         ps = 1.0 + 0j

@@ -1,7 +1,8 @@
 """Training and use of the learned closed-form correction.
 
 Sequences library calls only (every computation is a kernel of libxlmimo):
-exact FP32H Grams and gated closed-form Grams of training drops give per-pair
+exact FP32H Grams and closed-form Grams (variant GATED_QUAD, the learned form's base)
+of training drops give per-pair
 inputs and targets (xlmimo_mlp_pair_inputs); Adam steps run on contiguous
 slices of the pair set (xlmimo_mlp_train_step).  Drops are generated in random
 order, so a slice mixes many geometries without any gather.
@@ -39,7 +40,7 @@ def init_params(width: int, depth: int, rng: np.random.Generator, log_var0: floa
 def pair_set(ctx: X.Context, mlp: X.MLP, arr, drops, with_targets: bool = True):
     """Pair inputs (and targets rho_exact - rho~) of every drop; also returns the batch and Grams."""
     b = X.Batch(drops)
-    g_cf, _ = ctx.gram_closedform(arr, b, X.CF_GATED)
+    g_cf, _ = ctx.gram_closedform(arr, b, X.CF_GATED_QUAD)
     g_ex = ctx.gram_exact(arr, b, X.FP32H) if with_targets else None
     return mlp.pair_inputs(arr, b, g_cf, g_ex), b, g_cf, g_ex
 

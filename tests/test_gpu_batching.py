@@ -54,7 +54,8 @@ def test_graph_replays_match_eager(X, ctx):
     params[-1] = -30.0  # confident network: no fallback, the corrected Grams go straight to the rates
     mlp.set_params(params.astype(np.float32))
     s = torch.cuda.Stream()
-    forms = [(X.FORM_EXACT_FP32H, {}), (X.FORM_CF_GATED, {}), (X.FORM_CF_GATED_MLP, {"mlp": mlp, "log_var_max": 0.0})]
+    forms = [(X.FORM_EXACT_FP32H, {}), (X.FORM_CF_GATED, {}), (X.FORM_CF_UNIFORM, {}),
+             (X.FORM_CF_GATED_MLP, {"mlp": mlp, "log_var_max": 0.0})]
     outs = [_outputs(b, len(n_list), 2, 2, dev) for _ in forms]
     gram = torch.empty(2 * b.gram_elems, dtype=torch.float64, device=dev)
 

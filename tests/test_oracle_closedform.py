@@ -264,3 +264,36 @@ def test_uniform_far_outside_is_the_discrete_end_series():
     g = ch.gram_exact(arr, u)[0, 1]
     assert abs(gu - s_geo) < 2e-4 * abs(s_geo)
     assert abs(gu - g) < 2e-4 * abs(g)
+
+
+def test_numeric_routes():
+    lam = W.LAMBDA_28GHZ
+    # the direct route is the definition of the entry for one pair
+    arr = W.ula(60, lam)
+    u = _users([(6.0, 1.0), (6.02, 1.01)])
+    route, p = cf.numeric_route(arr.spacing, lam, 6.0, 1.0, 6.02, 1.01, 60)
+    assert route == cf.ROUTE_DIRECT
+    assert abs(cf.direct_sum(arr, 6.0, 1.0, 6.02, 1.01, 60) - ch.gram_exact(arr, u)[0, 1]) < 1e-12 * ch.gram_exact(arr, u)[0, 0].real
+    # a broad stationary zone (nearly equal perpendicular distances, a 1.4 km aperture): the uniform
+    # expansion misses the non-quadratic phase, the quadrature route reproduces the exact sum
+    n = 262144
+    arr = W.ula(n, lam)
+    xi, yi, xj, yj = 7.1, 3.0, 7.2, 0.55
+    route, p = cf.numeric_route(arr.spacing, lam, xi, yi, xj, yj, n)
+    assert route == cf.ROUTE_QUAD and p > cf.QUAD_MAX_PANELS
+    g = ch.gram_exact(arr, _users([(xi, yi), (xj, yj)]))
+    den = math.sqrt(g[0, 0].real * g[1, 1].real)
+    v = cf.numeric_entry(arr, xi, yi, xj, yj, n, route, p)
+    assert abs(v - g[0, 1]) < 1e-10 * den
+    assert abs(cf.uniform_pair(arr, xi, yi, xj, yj, n) - g[0, 1]) > 1e-4 * den
+    # a typical pair keeps the analytic route
+    assert cf.numeric_route(arr.spacing, lam, 9.0, 4.0, 31.0, -12.0, n)[0] == cf.ROUTE_NONE
+
+
+def test_uniform_matches_exact_at_the_largest_aperture():
+    arr0, drops, _ = W.sweep(200)
+    n = 262144
+    arr = arr0.with_n(n)
+    errs = [ch.normwise_error(cf.gram_closedform(arr, drops.users_of(d), n, cf.VARIANT_UNIFORM),
+                              ch.gram_exact(arr, drops.users_of(d))) for d in range(0, 200, 25)]
+    assert max(errs) < 3e-4
