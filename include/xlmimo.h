@@ -75,17 +75,20 @@ extern "C" {
 /* Closed-form variants (eqs. (4), (6), (22), (23); see xlmimo_gram_closedform). */
 #define XLMIMO_CF_PAPER 0      /* formulas as printed, for every pair */
 #define XLMIMO_CF_GATED 1      /* off-diagonal set to 0 when the stationary point is off the aperture */
-/* The next two are ULA-only extensions beyond the paper's formulas.  A pair is
- * "slow-phase" when k |u_i - u_j| times the angle the aperture subtends at the
- * pair's midpoint is at most 640 rad (users a fraction of a metre apart): it has
- * no stationary-phase regime, and its entry is the aperture integral
- * (1/d) int conj(h_i) h_j dy by composite Gauss-Legendre quadrature plus the
- * discrete end corrections. */
+/* The next two are ULA-only extensions beyond the paper's formulas.  Some pairs
+ * are evaluated numerically: "slow-phase" pairs, for which k |u_i - u_j| times
+ * the angle the aperture subtends at the pair's midpoint is at most 960 rad
+ * (users a fraction of a metre apart: no stationary-phase regime), and pairs
+ * whose stationary zone is broad (Fresnel width >= 1/2 of the half-aperture: the
+ * phase is far from quadratic over it) when that costs at most N/4 quadrature
+ * nodes.  Their entry is the aperture integral (1/d) int conj(h_i) h_j dy by
+ * composite Gauss-Legendre quadrature plus the discrete end corrections, or the
+ * direct sum over the N elements when that costs no more. */
 #define XLMIMO_CF_UNIFORM 2    /* uniform stationary-phase form of the discrete sum: the stationary term
                                   weighted by the Fresnel integral between the array ends, end terms
                                   without their stationary singularity, discrete end corrections;
-                                  slow-phase pairs by quadrature */
-#define XLMIMO_CF_GATED_QUAD 3 /* GATED, slow-phase pairs by quadrature (the learned correction's base) */
+                                  numeric pairs as above */
+#define XLMIMO_CF_GATED_QUAD 3 /* GATED, numeric pairs as above (the learned correction's base) */
 
 /* Rate schemes (bitmask).  rates_out holds one value per set bit, in
  * increasing bit order. */

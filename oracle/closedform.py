@@ -85,10 +85,10 @@ VARIANT_UNIFORM = 2
 VARIANT_GATED_QUAD = 3     # GATED, slow-phase pairs by the aperture quadrature (the learned correction's base)
 
 QUAD_NODES = 64            # Gauss-Legendre nodes per panel
-QUAD_RAD_PER_PANEL = 40.0  # phase change allowed over one panel
+QUAD_RAD_PER_PANEL = 60.0  # phase change allowed over one panel
 QUAD_MAX_PANELS = 16
 S_GUARD = 1e-2             # |s| below which the uniform end bracket is interpolated
-BROAD_FRACTION = 8.0       # a stationary zone of Fresnel width >= L / BROAD_FRACTION is "broad"
+BROAD_FRACTION = 2.0       # a stationary zone of Fresnel width >= L / BROAD_FRACTION is "broad"
 ROUTE_NONE, ROUTE_DIRECT, ROUTE_QUAD = 0, 1, 2
 
 

@@ -17,11 +17,14 @@
 //   UPA FREESPACE  (lambda/4pi)^2 lambda / (d^2 |x_i - x_j|) e^{j s (k d_ij - pi/2)}
 //   with s = sgn(|x_i| - |x_j|).  Variant GATED zeroes the entry when the
 //   stationary point is off the aperture; |x_i| == |x_j| or d_ij == 0 gives 0.
-// Variant GATED_QUAD (ULA): GATED, except pairs without a stationary-phase regime
-//   (slow-phase pairs, pair_math.h), which take the aperture quadrature.
-// Variant UNIFORM (ULA): the uniform stationary-phase form of the discrete sum
-//   for fast-phase pairs and the aperture quadrature for slow-phase pairs
-//   (pair_math.h); one thread per pair.
+// Variant GATED_QUAD (ULA): GATED, except the numerically routed pairs
+//   (slow-phase pairs and broad stationary zones, pair_math.h), which take the
+//   aperture quadrature or the direct sum.
+// Variant UNIFORM (ULA): the uniform stationary-phase form of the discrete sum,
+//   with the same numeric routes (pair_math.h).  Analytic pairs take one thread
+//   each; direct sums one wave each; quadratures the whole workgroup, one at a
+//   time (nodes strided over the threads, fixed-order wave sums, waves summed
+//   in order).
 // All arithmetic is FP64; the phase d_ij / lambda is reduced in revolutions.
 #include "device_math.h"
 #include "internal.h"
@@ -113,31 +116,44 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
 
   double* out = gram + 2 * dp.gram_off;
   if (ula && (variant == XLMIMO_CF_UNIFORM || variant == XLMIMO_CF_GATED_QUAD)) {
-    // one thread per pair p < q (a slow-phase pair costs up to 1024 quadrature nodes)
+    // Analytic pairs: one thread per pair.  Numeric pairs (slow-phase pairs, broad stationary zones)
+    // are queued and then evaluated by the whole workgroup, one pair at a time.
+    __shared__ int s_nq;
+    __shared__ int s_queue[XLMIMO_MAX_USERS * (XLMIMO_MAX_USERS - 1) / 2][3];  // pair, route, panels
+    if (threadIdx.x == 0) s_nq = 0;
     for (int i = threadIdx.x; i < K; i += blockDim.x) {
       out[2 * (i * K + i)] = s_diag[i];
       out[2 * (i * K + i) + 1] = 0.0;
     }
+    __syncthreads();
     const int np = K * (K - 1) / 2;
-    for (int t = threadIdx.x; t < np; t += blockDim.x) {
-      int p = 0, rem = t;
+    const int n = dp.n_elems;
+    const double kw = 2.0 * kPi * arr.inv_lambda;
+    auto pair_of = [K](int t, int& p, int& q) {
+      p = 0;
+      int rem = t;
       while (rem >= K - 1 - p) {
         rem -= K - 1 - p;
         ++p;
       }
-      const int q = p + 1 + rem;
+      q = p + 1 + rem;
+    };
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+      int p, q;
+      pair_of(t, p, q);
       double re = 0.0, im = 0.0;
       if (!(isfinite(s_diag[p]) && isfinite(s_diag[q]))) {
         re = im = __builtin_nan("");
       } else {
-        const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], 2.0 * kPi * arr.inv_lambda, arr.inv_lambda, arr.amp,
-                         arr.beta0, c_fs};
-        const int n = dp.n_elems;
-        const int panels = slow_panels(g, n, d);
-        if (panels > 0) {
-          const Cplx v = cadd(aperture_quadrature(g, n, d, panels, gl, n_gl), discrete_end_corrections(g, n, d));
-          re = v.re;
-          im = v.im;
+        const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+        int panels = 0;
+        const int route = numeric_route(g, n, d, n_gl, panels);
+        if (route != ROUTE_NONE) {
+          const int slot = atomicAdd(&s_nq, 1);
+          s_queue[slot][0] = t;
+          s_queue[slot][1] = route;
+          s_queue[slot][2] = panels;
+          continue;  // written by the cooperative pass below
         } else if (variant == XLMIMO_CF_UNIFORM) {
           const Cplx v = uniform_pair(g, n, d, gl, n_gl);
           re = v.re;
@@ -175,6 +191,48 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
       out[2 * (q * K + p) + 1] = -im;
     }
     __syncthreads();
+    const int nq = s_nq;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    // direct sums (N <= 1024): one wave per pair, fixed-order wave sum
+    for (int e = wave; e < nq; e += n_waves) {
+      if (s_queue[e][1] != ROUTE_DIRECT) continue;
+      int p, q;
+      pair_of(s_queue[e][0], p, q);
+      const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+      const Cplx v = wave_sum_c(numeric_share(g, n, d, ROUTE_DIRECT, 0, gl, n_gl, lane, 64));
+      if (lane == 0) {
+        out[2 * (p * K + q)] = v.re;
+        out[2 * (p * K + q) + 1] = v.im;
+        out[2 * (q * K + p)] = v.re;
+        out[2 * (q * K + p) + 1] = -v.im;
+      }
+    }
+    // quadratures (up to N/4 nodes), one pair at a time: every thread takes a share of the nodes;
+    // wave sums, then the waves' sums in order
+    __shared__ double s_wsum[2 * 16];
+    for (int e = 0; e < nq; ++e) {
+      const int t = s_queue[e][0], route = s_queue[e][1], panels = s_queue[e][2];
+      if (route != ROUTE_QUAD) continue;
+      int p, q;
+      pair_of(t, p, q);
+      const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+      const Cplx v = wave_sum_c(numeric_share(g, n, d, route, panels, gl, n_gl, threadIdx.x, blockDim.x));
+      if (lane == 0) {
+        s_wsum[2 * wave] = v.re;
+        s_wsum[2 * wave + 1] = v.im;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        Cplx tot = {0.0, 0.0};
+        for (int w = 0; w < n_waves; ++w) tot = cadd(tot, Cplx{s_wsum[2 * w], s_wsum[2 * w + 1]});
+        tot = cadd(cscale(tot, 1.0 / d), discrete_end_corrections(g, n, d));
+        out[2 * (p * K + q)] = tot.re;
+        out[2 * (p * K + q) + 1] = tot.im;
+        out[2 * (q * K + p)] = tot.re;
+        out[2 * (q * K + p) + 1] = -tot.im;
+      }
+      __syncthreads();
+    }
     if (status != nullptr && threadIdx.x == 0) status[blockIdx.x] = s_status;
     return;
   }

@@ -229,10 +229,11 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
     aux[p * 8 + 4] = pr;
     aux[p * 8 + 5] = pi;
     {
-      // slow-phase pairs have no stationary-phase regime: their closed-form entry is the aperture
-      // quadrature (variants GATED_QUAD, UNIFORM) and the network does not correct them
+      // pairs the base closed form evaluates numerically (variants GATED_QUAD, UNIFORM: slow-phase
+      // pairs and broad stationary zones) are not corrected by the network
       const PairGeom pg{xi, yi, xj, yj, kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
-      if (slow_panels(pg, dp.n_elems, arr.spacing) > 0) {
+      int panels = 0;
+      if (numeric_route(pg, dp.n_elems, arr.spacing, 64, panels) != ROUTE_NONE) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) aux[p * 8 + q] = 0.0f;
       }

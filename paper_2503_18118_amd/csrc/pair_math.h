@@ -7,13 +7,15 @@
 // array) the entry is S = sum_n f(y_n) e^{j phi(y_n)}, f = |h_i| |h_j|,
 // phi = k (r_i - r_j), elements y_n = (n - (N-1)/2) d.
 //
-// Slow-phase pairs (k |u_i - u_j| times the angular span of the aperture seen
-// from the pair's midpoint <= kQuadRadPerPanel * kQuadMaxPanels):
+// Numeric pairs (numeric_route below: slow-phase pairs, for which k |u_i - u_j|
+// times the angular span of the aperture seen from the pair's midpoint is at most
+// kQuadRadPerPanel * kQuadMaxPanels, and affordable pairs with a broad stationary zone):
 //   S = (1/d) int_{-L}^{L} f e^{j phi} dy  + discrete end corrections,
 //   the integral by composite 64-node Gauss-Legendre in the angle theta seen
 //   from the midpoint (y = y_m + x_m tan theta), one panel per kQuadRadPerPanel
-//   radians of phase (|d phi / d theta| <= k |u_i - u_j|).
-// Fast-phase pairs: the uniform expansion about the stationary point y* (the
+//   radians of phase (|d phi / d theta| <= k |u_i - u_j|); or the direct sum
+//   over the N elements when it costs no more.
+// Other pairs: the uniform expansion about the stationary point y* (the
 // change of variable phi - phi* = sigma s^2 / 2, sigma = sgn phi''(y*)):
 //   (1/d) sum over the ends e = L (+), -L (-) of
 //      +- [ G0 e^{j phi*} F(s_e) + e^{j phi(e)} (f(e) / (j phi'(e)) - G0 / (j sigma s_e)) ]
@@ -38,7 +40,7 @@
 namespace xl {
 
 constexpr double kPiPair = 3.14159265358979323846264338327950288;
-constexpr double kQuadRadPerPanel = 40.0;
+constexpr double kQuadRadPerPanel = 60.0;
 constexpr int kQuadMaxPanels = 16;
 constexpr double kSGuard = 1e-2;
 constexpr double kFresnelSplit = 8.0;
@@ -123,43 +125,6 @@ __device__ Cplx discrete_end_corrections(const PairGeom& g, int n, double d) {
     total = cadd(total, cscale(Cplx{t.im, -t.re}, side * c));
   }
   return total;
-}
-
-// Panels of the aperture quadrature, 0 for a fast-phase pair.
-__device__ __forceinline__ int slow_panels(const PairGeom& g, int n, double d) {
-  const double L = 0.5 * (double)n * d;
-  const double xm = 0.5 * (g.xi + g.xj), ym = 0.5 * (g.yi + g.yj);
-  const double span = atan((L - ym) / xm) - atan((-L - ym) / xm);
-  const double dx = g.xi - g.xj, dy = g.yi - g.yj;
-  const double v = g.k * sqrt(dx * dx + dy * dy) * span;
-  int p = (int)ceil(v / kQuadRadPerPanel);
-  if (p < 1) p = 1;
-  return p <= kQuadMaxPanels ? p : 0;
-}
-
-// (1/d) int_{-L}^{L} f e^{j phi} dy, composite Gauss-Legendre in the midpoint's angle.
-__device__ Cplx aperture_quadrature(const PairGeom& g, int n, double d, int panels, const double* __restrict__ gl,
-                                    int n_gl) {
-  const double L = 0.5 * (double)n * d;
-  const double xm = 0.5 * (g.xi + g.xj), ym = 0.5 * (g.yi + g.yj);
-  const double ta = atan((-L - ym) / xm), tb = atan((L - ym) / xm);
-  const double h = (tb - ta) / panels;
-  Cplx total = {0.0, 0.0};
-  for (int p = 0; p < panels; ++p) {
-    const double mid = ta + (p + 0.5) * h, half = 0.5 * h;
-    Cplx acc = {0.0, 0.0};
-    for (int q = 0; q < n_gl; ++q) {
-      const double th = fma(half, gl[2 * q], mid);
-      double s, c;
-      sincos(th, &s, &c);
-      const double y = fma(xm, s / c, ym);
-      const double jac = xm / (c * c);
-      const EndVals v = end_vals(g, y);
-      acc = cadd(acc, cscale(v.g, gl[2 * q + 1] * jac));
-    }
-    total = cadd(total, cscale(acc, half));
-  }
-  return cscale(total, 1.0 / d);
 }
 
 // F(s) = int_0^s e^{j sigma t^2 / 2} dt for |s| <= kFresnelSplit (Gauss-Legendre on [0, s]).
@@ -259,12 +224,91 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
   return cadd(cscale(integral, 1.0 / d), discrete_end_corrections(g, n, d));
 }
 
-// Uniform closed-form entry of any pair: quadrature if slow, uniform expansion if fast.
-__device__ __forceinline__ Cplx uniform_entry(const PairGeom& g, int n, double d, const double* __restrict__ gl,
-                                              int n_gl) {
-  const int p = slow_panels(g, n, d);
-  if (p > 0) return cadd(aperture_quadrature(g, n, d, p, gl, n_gl), discrete_end_corrections(g, n, d));
-  return uniform_pair(g, n, d, gl, n_gl);
+// ---- numeric routes -----------------------------------------------------------
+// Pairs evaluated numerically by the closed forms UNIFORM and GATED_QUAD: slow-phase
+// pairs (<= kQuadMaxPanels panels) and pairs whose stationary zone is broad
+// (Fresnel width sqrt(2 pi / |phi''(y*)|) >= L / kBroadFraction, or x_i == x_j) when
+// the quadrature costs at most N / 4 nodes; the direct sum over the N elements
+// replaces the quadrature when it costs no more.
+constexpr double kBroadFraction = 2.0;
+enum { ROUTE_NONE = 0, ROUTE_DIRECT = 1, ROUTE_QUAD = 2 };
+
+__device__ __forceinline__ int quad_panels(const PairGeom& g, int n, double d) {
+  const double L = 0.5 * (double)n * d;
+  const double xm = 0.5 * (g.xi + g.xj), ym = 0.5 * (g.yi + g.yj);
+  const double span = atan((L - ym) / xm) - atan((-L - ym) / xm);
+  const double dx = g.xi - g.xj, dy = g.yi - g.yj;
+  const double v = g.k * sqrt(dx * dx + dy * dy) * span;
+  const double p = ceil(v / kQuadRadPerPanel);
+  return p < 1.0 ? 1 : (p > 1e9 ? 1000000000 : (int)p);
+}
+
+__device__ __forceinline__ int numeric_route(const PairGeom& g, int n, double d, int n_gl, int& panels) {
+  const int p = quad_panels(g, n, d);
+  const double L = 0.5 * (double)n * d;
+  bool broad = true;
+  if (g.xi != g.xj) {
+    const double ys = (g.yi * g.xj - g.xi * g.yj) / (g.xj - g.xi);
+    const double a = sqrt(fma(ys - g.yi, ys - g.yi, g.xi * g.xi)), b = sqrt(fma(ys - g.yj, ys - g.yj, g.xj * g.xj));
+    const double p2 = g.k * (g.xi * g.xi / (a * a * a) - g.xj * g.xj / (b * b * b));
+    const double lb = L / kBroadFraction;
+    broad = p2 == 0.0 || 2.0 * kPiPair / fabs(p2) >= lb * lb;
+  }
+  panels = 0;
+  if (p <= kQuadMaxPanels || (broad && (double)p * n_gl * 4.0 <= (double)n)) {
+    panels = p;
+    return n <= (int64_t)p * n_gl ? ROUTE_DIRECT : ROUTE_QUAD;
+  }
+  return ROUTE_NONE;
+}
+
+// This thread's share of a numeric entry when `nthr` threads (a multiple of n_gl = 64) stride
+// the terms: elements t, t + nthr, ... of the direct sum, or the quadrature nodes q = t % 64 of
+// panels p = t / 64, t / 64 + nthr / 64, ... (angle theta seen from the midpoint; weights and
+// Jacobian included, without the 1/d).  A thread keeps one node q, so sin / cos of its offset
+// within a panel are taken once and the panel midpoints advance by rotation (re-taken exactly
+// every 16 steps).
+__device__ Cplx numeric_share(const PairGeom& g, int n, double d, int route, int panels,
+                              const double* __restrict__ gl, int n_gl, int t, int nthr) {
+  Cplx acc = {0.0, 0.0};
+  if (route == ROUTE_DIRECT) {
+    for (int m = t; m < n; m += nthr) acc = cadd(acc, end_vals(g, ((double)m - 0.5 * (double)(n - 1)) * d).g);
+    return acc;
+  }
+  const double L = 0.5 * (double)n * d;
+  const double xm = 0.5 * (g.xi + g.xj), ym = 0.5 * (g.yi + g.yj);
+  const double ta = atan((-L - ym) / xm), tb = atan((L - ym) / xm);
+  const double h = (tb - ta) / panels;
+  const int q = t % n_gl, pstep = nthr / n_gl;
+  double sd, cd;
+  sincos(0.5 * h * gl[2 * q], &sd, &cd);
+  const double wq = 0.5 * h * gl[2 * q + 1] * xm;
+  double ss, cs;
+  sincos(pstep * h, &ss, &cs);
+  double sm = 0.0, cm = 1.0;
+  int it = 0;
+  for (int p = t / n_gl; p < panels; p += pstep, ++it) {
+    if ((it & 15) == 0) {
+      sincos(ta + (p + 0.5) * h, &sm, &cm);
+    }
+    const double c = cm * cd - sm * sd, s = sm * cd + cm * sd;  // cos, sin of the node angle
+    const double y = fma(xm, s / c, ym);
+    acc = cadd(acc, cscale(end_vals(g, y).g, wq / (c * c)));
+    const double sn = sm * cs + cm * ss;
+    cm = cm * cs - sm * ss;
+    sm = sn;
+  }
+  return acc;
+}
+
+// Fixed-order sum over the 64 lanes of a wave (butterfly; every lane ends with the same value).
+__device__ __forceinline__ Cplx wave_sum_c(Cplx v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_xor(v.re, o, 64);
+    v.im += __shfl_xor(v.im, o, 64);
+  }
+  return v;
 }
 
 }  // namespace xl
