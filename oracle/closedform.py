@@ -65,7 +65,8 @@ Variant UNIFORM (ULA; an extension beyond the paper's formulas, not one of them)
     quadrature in the angle theta seen from the midpoint (y = y_m + x_m tan theta),
     in panels over which the phase changes by at most QUAD_RAD_PER_PANEL rad,
     plus the same discrete end corrections; or the direct sum over the N
-    elements when that costs no more.
+    elements (the definition itself) when the array has at most DIRECT_MAX_N
+    elements or the sum costs no more than the quadrature.
   The diagonal is the closed form above.  end_term() (the regularised
   geometric-series end term) is the learned correction's basis, not part of
   this variant.
@@ -85,10 +86,11 @@ VARIANT_UNIFORM = 2
 VARIANT_GATED_QUAD = 3     # GATED, slow-phase pairs by the aperture quadrature (the learned correction's base)
 
 QUAD_NODES = 64            # Gauss-Legendre nodes per panel
-QUAD_RAD_PER_PANEL = 60.0  # phase change allowed over one panel
-QUAD_MAX_PANELS = 16
+QUAD_RAD_PER_PANEL = 120.0  # phase change allowed over one panel (64 nodes resolve up to ~180 rad)
+QUAD_MAX_PANELS = 8          # slow-phase pairs: at most 960 rad over the aperture
 S_GUARD = 1e-2             # |s| below which the uniform end bracket is interpolated
 BROAD_FRACTION = 2.0       # a stationary zone of Fresnel width >= L / BROAD_FRACTION is "broad"
+DIRECT_MAX_N = 1024        # numeric pairs of arrays up to this size take the direct sum
 ROUTE_NONE, ROUTE_DIRECT, ROUTE_QUAD = 0, 1, 2
 
 
@@ -217,9 +219,9 @@ def quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n):
 def numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n):
     """(route, panels): route ROUTE_DIRECT / ROUTE_QUAD for a pair the closed forms UNIFORM and GATED_QUAD
     evaluate numerically, ROUTE_NONE otherwise.  Numeric pairs: slow-phase pairs (<= QUAD_MAX_PANELS
-    panels) and pairs whose stationary zone is broad (Fresnel width sqrt(2 pi / |phi''(y*)|) >= L / 8, or
-    x_i == x_j) when the quadrature costs at most N / 4 nodes; the direct sum over the N elements is used
-    when it costs no more than the quadrature."""
+    panels) and pairs whose stationary zone is broad (Fresnel width sqrt(2 pi / |phi''(y*)|) >=
+    L / BROAD_FRACTION, or x_i == x_j) when the quadrature costs at most N / 4 nodes; the direct sum over
+    the N elements is used when N <= DIRECT_MAX_N or it costs no more than the quadrature."""
     p = quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n)
     L = n * spacing / 2.0
     broad = True
@@ -230,7 +232,7 @@ def numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n):
         p2 = k * (xp_i ** 2 / a ** 3 - xp_j ** 2 / b ** 3)
         broad = p2 == 0.0 or 2.0 * np.pi / abs(p2) >= (L / BROAD_FRACTION) ** 2
     if p <= QUAD_MAX_PANELS or (broad and p * QUAD_NODES * 4 <= n):
-        return (ROUTE_DIRECT if n <= p * QUAD_NODES else ROUTE_QUAD), p
+        return (ROUTE_DIRECT if n <= max(p * QUAD_NODES, DIRECT_MAX_N) else ROUTE_QUAD), p
     return ROUTE_NONE, 0
 
 

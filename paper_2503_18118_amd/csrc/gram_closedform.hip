@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
   if (ula && (variant == XLMIMO_CF_UNIFORM || variant == XLMIMO_CF_GATED_QUAD)) {
     // Analytic pairs: one thread per pair.  Numeric pairs (slow-phase pairs, broad stationary zones)
     // are queued and then evaluated by the whole workgroup, one pair at a time.
-    __shared__ int s_nq;
-    __shared__ int s_queue[XLMIMO_MAX_USERS * (XLMIMO_MAX_USERS - 1) / 2][3];  // pair, route, panels
-    if (threadIdx.x == 0) s_nq = 0;
+    __shared__ int s_nq, s_nd;
+    __shared__ __align__(16) int s_queue[XLMIMO_MAX_USERS * (XLMIMO_MAX_USERS - 1) / 2][3];  // pair, route, panels
+    if (threadIdx.x == 0) s_nq = s_nd = 0;
     for (int i = threadIdx.x; i < K; i += blockDim.x) {
       out[2 * (i * K + i)] = s_diag[i];
       out[2 * (i * K + i) + 1] = 0.0;
@@ -150,6 +150,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
         const int route = numeric_route(g, n, d, n_gl, panels);
         if (route != ROUTE_NONE) {
           const int slot = atomicAdd(&s_nq, 1);
+          if (route == ROUTE_DIRECT) atomicAdd(&s_nd, 1);
           s_queue[slot][0] = t;
           s_queue[slot][1] = route;
           s_queue[slot][2] = panels;
@@ -193,8 +194,71 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
     __syncthreads();
     const int nq = s_nq;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    // direct sums (N <= 1024): one wave per pair, fixed-order wave sum
-    for (int e = wave; e < nq; e += n_waves) {
+    const int nd = s_nd;
+    const bool shared_chan = 2 * nd > K && nd <= (int)blockDim.x && nd == nq;
+    if (shared_chan) {
+      // Many direct sums and nothing else numeric (always so for N <= kDirectMaxN): each user's channel
+      // h_u(y) = a_u(r) e^{-j 2 pi r / lambda} is formed once per element chunk in LDS (over the queue,
+      // whose pairs are copied out first) and every direct pair sums conj(h_p) h_q from there.  A pair's
+      // elements are split into `sub` interleaved partial sums (a fixed split for the drop), combined in
+      // order.
+      constexpr int kChan = (int)sizeof(s_queue) / (2 * (int)sizeof(double));
+      double* s_h = reinterpret_cast<double*>(&s_queue[0][0]);
+      __shared__ double s_part[2 * 256];
+      __shared__ int s_dl[256];
+      for (int e = threadIdx.x; e < nq; e += blockDim.x) s_dl[e] = s_queue[e][0];
+      int sub = 1;
+      while (2 * sub * nd <= (int)blockDim.x && sub < 64) sub *= 2;
+      const int chunk = kChan / K;
+      const double sq_fs = sqrt(c_fs);
+      __syncthreads();
+      const int me = threadIdx.x / sub, ms = threadIdx.x % sub;
+      int p = 0, q = 0;
+      if (me < nd) pair_of(s_dl[me], p, q);
+      Cplx acc = {0.0, 0.0};
+      for (int n0 = 0; n0 < n; n0 += chunk) {
+        const int cn = min(chunk, n - n0);
+        for (int idx = threadIdx.x; idx < K * cn; idx += blockDim.x) {
+          const int u = idx / cn, e = idx - u * cn;
+          const double y = ((double)(n0 + e) - 0.5 * (double)(n - 1)) * d;
+          const double dy = y - s_y[u], x = s_x[u];
+          const double r = sqrt(fma(dy, dy, x * x));
+          const double a = arr.amp == XLMIMO_AMP_PNUSW ? sqrt(arr.beta0 * x) / (r * sqrt(r)) : sq_fs / r;
+          const Cplx ph = phasor_turns_d(r * arr.inv_lambda);
+          s_h[2 * (u * chunk + e)] = a * ph.re;
+          s_h[2 * (u * chunk + e) + 1] = -a * ph.im;
+        }
+        __syncthreads();
+        if (me < nd) {
+          const double* hp = s_h + 2 * p * chunk;
+          const double* hq = s_h + 2 * q * chunk;
+          for (int e = ms; e < cn; e += sub) {
+            // conj(h_p) h_q
+            const double pr = hp[2 * e], pi = hp[2 * e + 1], qr = hq[2 * e], qi = hq[2 * e + 1];
+            acc.re += pr * qr + pi * qi;
+            acc.im += pr * qi - pi * qr;
+          }
+        }
+        __syncthreads();
+      }
+      if (me < nd) {
+        s_part[2 * threadIdx.x] = acc.re;
+        s_part[2 * threadIdx.x + 1] = acc.im;
+      }
+      __syncthreads();
+      if (threadIdx.x < nd) {
+        int pp, qq;
+        pair_of(s_dl[threadIdx.x], pp, qq);
+        Cplx v = {0.0, 0.0};
+        for (int m = 0; m < sub; ++m) v = cadd(v, Cplx{s_part[2 * (threadIdx.x * sub + m)], s_part[2 * (threadIdx.x * sub + m) + 1]});
+        out[2 * (pp * K + qq)] = v.re;
+        out[2 * (pp * K + qq) + 1] = v.im;
+        out[2 * (qq * K + pp)] = v.re;
+        out[2 * (qq * K + pp) + 1] = -v.im;
+      }
+    }
+    // otherwise: direct sums one wave per pair, fixed-order wave sum
+    for (int e = wave; e < nq && !shared_chan; e += n_waves) {
       if (s_queue[e][1] != ROUTE_DIRECT) continue;
       int p, q;
       pair_of(s_queue[e][0], p, q);
@@ -210,7 +274,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
     // quadratures (up to N/4 nodes), one pair at a time: every thread takes a share of the nodes;
     // wave sums, then the waves' sums in order
     __shared__ double s_wsum[2 * 16];
-    for (int e = 0; e < nq; ++e) {
+    for (int e = 0; e < nq && !shared_chan; ++e) {
       const int t = s_queue[e][0], route = s_queue[e][1], panels = s_queue[e][2];
       if (route != ROUTE_QUAD) continue;
       int p, q;

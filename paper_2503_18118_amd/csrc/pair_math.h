@@ -14,7 +14,7 @@
 //   the integral by composite 64-node Gauss-Legendre in the angle theta seen
 //   from the midpoint (y = y_m + x_m tan theta), one panel per kQuadRadPerPanel
 //   radians of phase (|d phi / d theta| <= k |u_i - u_j|); or the direct sum
-//   over the N elements when it costs no more.
+//   over the N elements when N <= kDirectMaxN or it costs no more.
 // Other pairs: the uniform expansion about the stationary point y* (the
 // change of variable phi - phi* = sigma s^2 / 2, sigma = sgn phi''(y*)):
 //   (1/d) sum over the ends e = L (+), -L (-) of
@@ -40,10 +40,11 @@
 namespace xl {
 
 constexpr double kPiPair = 3.14159265358979323846264338327950288;
-constexpr double kQuadRadPerPanel = 60.0;
-constexpr int kQuadMaxPanels = 16;
+constexpr double kQuadRadPerPanel = 120.0;   // phase change over one 64-node panel
+constexpr int kQuadMaxPanels = 8;            // slow-phase pairs: at most 960 rad over the aperture
 constexpr double kSGuard = 1e-2;
 constexpr double kFresnelSplit = 8.0;
+constexpr int kDirectMaxN = 1024;   // numeric pairs of arrays up to this size take the direct sum
 
 struct Cplx {
   double re, im;
@@ -229,7 +230,7 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
 // pairs (<= kQuadMaxPanels panels) and pairs whose stationary zone is broad
 // (Fresnel width sqrt(2 pi / |phi''(y*)|) >= L / kBroadFraction, or x_i == x_j) when
 // the quadrature costs at most N / 4 nodes; the direct sum over the N elements
-// replaces the quadrature when it costs no more.
+// replaces the quadrature for N <= kDirectMaxN or when it costs no more.
 constexpr double kBroadFraction = 2.0;
 enum { ROUTE_NONE = 0, ROUTE_DIRECT = 1, ROUTE_QUAD = 2 };
 
@@ -257,7 +258,7 @@ __device__ __forceinline__ int numeric_route(const PairGeom& g, int n, double d,
   panels = 0;
   if (p <= kQuadMaxPanels || (broad && (double)p * n_gl * 4.0 <= (double)n)) {
     panels = p;
-    return n <= (int64_t)p * n_gl ? ROUTE_DIRECT : ROUTE_QUAD;
+    return (n <= kDirectMaxN || n <= (int64_t)p * n_gl) ? ROUTE_DIRECT : ROUTE_QUAD;
   }
   return ROUTE_NONE;
 }

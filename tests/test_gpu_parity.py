@@ -203,6 +203,43 @@ def test_closedform_uniform_and_gated_quad(X, ctx, amp, variant):
     assert torch.all(status == 0)
 
 
+@pytest.mark.parametrize("amp", ["FREESPACE", "PNUSW"])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_closedform_direct_sum_paths(X, ctx, amp, variant):
+    # Numeric pairs of arrays up to 1024 elements take the direct sum.  With many of them and no
+    # quadrature in the drop the kernel stages each user's channel in LDS once per element chunk;
+    # otherwise each direct pair takes one wave.  Drops chosen to reach both (checked below from the
+    # oracle's routing): sweep-like users at N = 256 and N = 700 (ragged chunks), a cluster of 32 users
+    # (496 direct pairs, more than one workgroup holds), and one slow pair among four users.
+    arr = W.ula(1, W.LAMBDA_28GHZ, getattr(W, "AMP_" + amp))
+    a = _custom_drops([256, 700], [16, 16], seed=23, r=(5.0, 50.0))
+    rng = np.random.default_rng(3)
+    cluster = np.concatenate([np.array([5.0, 0.5]) + rng.uniform(-0.4, 0.4, (32, 2)), np.zeros((32, 1))], axis=1)
+    few = np.array([[10.0, -20.0, 0.0], [10.1, -20.05, 0.0], [40.0, 25.0, 0.0], [15.0, 30.0, 0.0]])
+    drops = W._pack([256, 700, 1024, 1024], [16, 16, 32, 4], np.concatenate([a.pos, cluster, few]))
+    paths = []
+    for d in range(drops.n_drops):
+        u = drops.users_of(d)
+        n, k = int(drops.n_elems[d]), len(u)
+        x, y = np.hypot(u[:, 0], u[:, 2]), u[:, 1]
+        routes = [ocf.numeric_route(arr.spacing, arr.wavelength, x[p], y[p], x[q], y[q], n)[0]
+                  for p in range(k) for q in range(p + 1, k)]
+        nd = sum(r == ocf.ROUTE_DIRECT for r in routes)
+        nq = sum(r != ocf.ROUTE_NONE for r in routes)
+        paths.append("lds" if (2 * nd > k and nd <= 256 and nd == nq) else ("wave" if nd else "none"))
+    assert paths == ["lds", "lds", "wave", "wave"], paths
+    b = X.Batch(drops)
+    out, status = ctx.gram_closedform(arr, b, variant)
+    torch.cuda.synchronize()
+    g = b.split(out)
+    for d in range(drops.n_drops):
+        ref = ocf.gram_closedform(arr, drops.users_of(d), int(drops.n_elems[d]), variant)
+        scale = np.sqrt(np.outer(np.abs(np.diag(ref)), np.abs(np.diag(ref))))
+        assert np.max(np.abs(g[d] - ref) / scale) < 1e-10, (d, np.max(np.abs(g[d] - ref) / scale))
+        assert np.array_equal(g[d], g[d].conj().T)
+    assert torch.all(status == 0)
+
+
 def test_closedform_uniform_accuracy_on_sweep_drops(X, ctx):
     # the uniform form against the exact FP64 Gram on the sweep workload's user law (5-50 m)
     arr, drops, _ = W.sweep(64)
@@ -266,6 +303,78 @@ def test_rates_all_schemes(X, ctx, kset):
             ref = orates.rates(gh[d], rk, sum(order), g_filter=filt[d])
             for c, key in enumerate(order):
                 assert rates[d, s, c] == pytest.approx(ref[key], rel=1e-9), (d, s, key)
+
+
+@pytest.mark.parametrize("kset,n_snr,names", [
+    ([1, 2, 4, 9, 16, 16, 3], 2, ("ZF", "MMSE", "MRC", "CAP", "MZF")),   # 4 factorisations per drop
+    ([3, 16, 7, 1, 12], 3, ("MMSE",)),                                  # 3 per drop: one idle group per wave
+    ([5, 16, 2, 11, 16, 8, 13], 1, ("ZF", "MZF")),                        # 2 per drop: two drops per wave
+    ([16, 4, 9, 1, 16, 6, 2, 14, 10], 2, ("ZF",)),                        # 1 per drop: four drops per wave
+    ([6, 16, 3], 2, ("MRC", "MZF")),
+])
+def test_rates_small_k_path(X, ctx, kset, n_snr, names):
+    # K <= 16 without the mismatched scheme runs the register-resident kernel
+    # (one 16-lane group per factorisation); the generic kernel runs when the
+    # mismatched scheme is added.  Both against the oracle.
+    rng = np.random.default_rng(len(kset) + n_snr)
+    ns = [max(4 * k, 300) for k in kset]
+    drops = _custom_drops(ns, kset, seed=int(sum(kset)) + 7, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    gh = b.split(g)
+    filt = []
+    for m in gh:
+        e = rng.normal(size=m.shape) + 1j * rng.normal(size=m.shape)
+        filt.append(m + 0.02 * np.abs(m).max() / len(m) * (e + e.conj().T))
+    gf = torch.as_tensor(np.concatenate([f.ravel() for f in filt]).view(np.float64), device="cuda")
+    rho = torch.as_tensor(rng.uniform(0.5, 2.0, (n_snr, b.total_users)) * 1e4
+                          / np.mean([np.real(np.diag(m)).mean() for m in gh]), device="cuda")
+    schemes = 0
+    for n in names:
+        schemes |= getattr(X, n)
+    small, st_small = ctx.sumrate(b, g, rho, schemes, gram_filter=gf)
+    generic, st_gen = ctx.sumrate(b, g, rho, schemes | X.MZF_MISM, gram_filter=gf)
+    torch.cuda.synchronize()
+    assert torch.all(st_small == 0) and torch.all(st_gen == 0)
+    small = small.cpu().numpy()
+    generic = generic.cpu().numpy()
+    rh = rho.cpu().numpy()
+    canon = [("ZF", orates.SCHEME_ZF), ("MMSE", orates.SCHEME_MMSE), ("MRC", orates.SCHEME_MRC),
+             ("CAP", orates.SCHEME_CAP), ("MZF", orates.SCHEME_MZF)]
+    cols = [(n, key) for n, key in canon if n in names]
+    for d in range(drops.n_drops):
+        for s in range(n_snr):
+            rk = rh[s, drops.user_off[d]:drops.user_off[d + 1]]
+            ref = orates.rates(gh[d], rk, sum(key for _, key in cols), g_filter=filt[d])
+            for c, (n, key) in enumerate(cols):
+                assert small[d, s, c] == pytest.approx(ref[key], rel=1e-9), (d, s, n)
+                assert small[d, s, c] == pytest.approx(generic[d, s, c], rel=1e-12), (d, s, n)
+
+
+def test_rates_small_k_status_per_drop(X, ctx):
+    # four drops share a wave (ZF only); the rank-one drop is flagged alone
+    k = 3
+    rng = np.random.default_rng(3)
+    mats = []
+    for d in range(6):
+        if d == 1:
+            mats.append(np.ones((k, k), np.complex128))
+        else:
+            a = rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k))
+            mats.append(a @ a.conj().T + np.eye(k))
+    drops = W._pack([10] * 6, [k] * 6, np.ones((6 * k, 3)))
+    b = X.Batch(drops)
+    g = torch.as_tensor(np.concatenate([m.ravel() for m in mats]).view(np.float64), device="cuda")
+    rho = torch.ones((1, 6 * k), dtype=torch.float64, device="cuda")
+    rates, status = ctx.sumrate(b, g, rho, X.ZF)
+    st = status.cpu().numpy()
+    r = rates.cpu().numpy()
+    assert st[1] & X.ST_G_NOT_PD and np.all(np.delete(st, 1) == 0)
+    assert math.isnan(r[1, 0, 0])
+    for d in (0, 2, 3, 4, 5):
+        ref = orates.rates(mats[d], np.ones(k), orates.SCHEME_ZF)[orates.SCHEME_ZF]
+        assert r[d, 0, 0] == pytest.approx(ref, rel=1e-12)
 
 
 def test_rates_not_pd_flagged(X, ctx):
