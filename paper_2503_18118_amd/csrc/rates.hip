@@ -267,6 +267,196 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
   if (status != nullptr && lane == 0) status[blockIdx.x] = st;
 }
 
+// ---------------------------------------------------------------------------
+// K <= 16 without the mismatched scheme: every factorisation of a drop runs in
+// its own 16-lane group with the matrix in registers (lane i holds row i), so a
+// drop's ZF, nominal modified-ZF and per-SNR MMSE/CAP factorisations proceed in
+// parallel and no LDS or barrier is needed.  Matrices with K < 16 are padded
+// with an identity block: the Cholesky factor and the inverse's diagonal of the
+// leading K x K block are unchanged, operation by operation.  The arithmetic is
+// the generic kernel's in the same order.
+//
+// Jobs of a drop, in order: [G (ZF)] [G~ (MZF)] then one per SNR when MMSE, CAP
+// or MRC is asked for (MRC needs no factorisation and rides on that job).
+constexpr int kSmallK = 16;
+
+__device__ __forceinline__ cplx shfl16(cplx v, int src) {
+  return {__shfl(v.x, src, kSmallK), __shfl(v.y, src, kSmallK)};
+}
+
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = kSmallK / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kSmallK);
+  return v;
+}
+
+// Right-looking Cholesky of the padded 16 x 16 matrix whose row `li` is in a[]:
+// on return a[c] (c <= li) holds L_{li,c}; diag = L_{li,li}.  ok stays false
+// after a non-positive or non-finite pivot (the later arithmetic then runs on
+// NaNs harmlessly; the caller discards it).
+__device__ __forceinline__ bool chol_rows(cplx (&a)[kSmallK], int li, double& diag) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < kSmallK; ++j) {
+    const double djj = __shfl(a[j].x, j, kSmallK);
+    ok = ok && (djj > 0.0) && isfinite(djj);
+    const double l = sqrt(djj), il = 1.0 / l;
+    if (li > j) a[j] = {a[j].x * il, a[j].y * il};
+    if (li == j) {
+      a[j] = {l, 0.0};
+      diag = l;
+    }
+#pragma unroll
+    for (int c = j + 1; c < kSmallK; ++c) {
+      const cplx lcj = shfl16(a[j], c);
+      if (li >= c) {
+        const cplx t = cmulc(a[j], lcj);
+        a[c] = {a[c].x - t.x, a[c].y - t.y};
+      }
+    }
+  }
+  return ok;
+}
+
+// [ (L L^H)^-1 ]_{li,li} = sum_i |W_{i,li}|^2 with W = L^-1, built row by row
+// in place of L: at step m lane m completes row m of W (W_mm = 1 / L_mm, the
+// rest scaled by -1 / L_mm), the row is broadcast, and every later row i adds
+// L_{i,m} W_{m,k} to its running W_{i,k}.  L_{i,m} is read for the last time at
+// step m, where slot m of row i starts to accumulate W_{i,m}, so one array of
+// 16 values per lane holds both.
+__device__ __forceinline__ double inv_diag_inplace(cplx (&a)[kSmallK], int li) {
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < kSmallK; ++m) {
+    // a[m] is untouched by the earlier steps; tying it to the running sum keeps
+    // the compiler from evaluating every step's pivot up front (16 live
+    // reciprocals and multipliers would push the kernel to one wave per SIMD)
+    cplx am = a[m];
+    asm volatile("" : "+v"(am.x), "+v"(am.y) : "v"(s));
+    const double w0 = 1.0 / __shfl(am.x, m, kSmallK);     // 1 / L_mm
+    // L_{li,m} for the rows below m, zero elsewhere: adding t * W_{m,k} = 0
+    // leaves the other rows unchanged
+    const cplx t = li > m ? am : cplx{0.0, 0.0};
+    a[m] = {0.0, 0.0};
+    cplx own = {0.0, 0.0};                                 // W_{m,li}
+#pragma unroll
+    for (int k = 0; k <= m; ++k) {
+      // W_{m,k}: lane m holds the unscaled sum, every lane applies -1 / L_mm
+      const cplx raw = shfl16(a[k], m);
+      const cplx wmk = k == m ? cplx{w0, 0.0} : cplx{raw.x * -w0, raw.y * -w0};
+      if (li == k) own = wmk;
+      const cplx u = cmul(t, wmk);
+      a[k] = {a[k].x + u.x, a[k].y + u.y};
+    }
+    if (li <= m) s += own.x * own.x + own.y * own.y;
+  }
+  return s;
+}
+
+__device__ __forceinline__ void load_row(cplx (&a)[kSmallK], const double* g, int64_t off, int K, int li) {
+#pragma unroll
+  for (int j = 0; j < kSmallK; ++j)
+    a[j] = (li < K && j < K) ? gload(g, off, K, li, j) : cplx{li == j ? 1.0 : 0.0, 0.0};
+}
+
+__global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ drops, int n_drops,
+                                                      const double* __restrict__ gram,
+                                                      const double* __restrict__ filter, int n_snr,
+                                                      const double* __restrict__ rho, int64_t total_users,
+                                                      int schemes, int n_sch, int jobs, int drops_per_block,
+                                                      double* __restrict__ rates, int32_t* __restrict__ status) {
+  __shared__ int s_st[64];
+  const int group = threadIdx.x / kSmallK, li = threadIdx.x % kSmallK;
+  const int slot = group / jobs, job = group % jobs;
+  const int64_t d = (int64_t)blockIdx.x * drops_per_block + slot;
+  if (threadIdx.x < drops_per_block) s_st[threadIdx.x] = 0;
+  __syncthreads();
+  const bool zf = schemes & XLMIMO_ZF, mzf = schemes & XLMIMO_MZF;
+  const bool mmse = schemes & XLMIMO_MMSE, cap = schemes & XLMIMO_CAP, mrc = schemes & XLMIMO_MRC;
+  // rate column of each scheme: ZF, MMSE, MRC, CAP, MZF (the mismatched scheme is not handled here)
+  const int c_mmse = zf, c_mrc = c_mmse + mmse, c_cap = c_mrc + mrc, c_mzf = c_cap + cap;
+  const double nan = __builtin_nan("");
+  int st = 0;
+  if (slot < drops_per_block && d < n_drops) {   // groups past the last slot of the block idle
+    const DropK dp = drops[d];
+    const int K = dp.k;
+    const int64_t go = dp.gram_off;
+    const int64_t rbase = d * n_snr * n_sch;
+    int kind = job;                        // 0: G, 1: G~, 2 + s: SNR s
+    if (!zf) ++kind;
+    if (!mzf && kind >= 1) ++kind;
+    cplx a[kSmallK];
+    double diag = 1.0;
+    const int s = kind - 2;                 // SNR of an MMSE/CAP/MRC job
+    const double* rs = rho + (int64_t)(kind >= 2 ? s : 0) * total_users + dp.user_off;
+    const double rk = li < K ? rs[li] : 0.0;
+    const bool fact = kind <= 1 || mmse || cap;
+    if (kind <= 1) {
+      load_row(a, kind == 0 ? gram : filter, go, K, li);
+    } else if (fact) {
+      // I + D^1/2 G D^1/2, row li
+      const double sk = sqrt(rk);
+#pragma unroll
+      for (int j = 0; j < kSmallK; ++j) {
+        if (li < K && j < K) {
+          const cplx g = gload(gram, go, K, li, j);
+          const double sj = sqrt(rs[j]);
+          a[j] = {(li == j ? 1.0 : 0.0) + sk * sj * g.x, sk * sj * g.y};
+        } else {
+          a[j] = {li == j ? 1.0 : 0.0, 0.0};
+        }
+      }
+    }
+    bool ok = true;
+    double minv = nan;
+    if (fact) {
+      ok = chol_rows(a, li, diag);
+      minv = inv_diag_inplace(a, li);
+    }
+    if (kind <= 1) {
+      // ZF on the true Gram or nominal modified ZF on the filter Gram, all SNRs
+      if (!ok) st |= kind == 0 ? XLMIMO_ST_G_NOT_PD : XLMIMO_ST_FILTER_NOT_PD;
+      const double ginv = ok ? minv : nan;
+      for (int q = 0; q < n_snr; ++q) {
+        const double rq = li < K ? rho[(int64_t)q * total_users + dp.user_off + li] : 0.0;
+        const double tot = group_sum(li < K ? log2(1.0 + rq / ginv) : 0.0);
+        if (li == 0) rates[rbase + q * n_sch + (kind == 0 ? 0 : c_mzf)] = tot;
+      }
+    } else {
+      if (mrc) {
+        double v = 0.0;
+        if (li < K) {
+          const double gkk = gload(gram, go, K, li, li).x;
+          double interf = 0.0;
+          for (int j = 0; j < K; ++j) {
+            if (j == li) continue;
+            const cplx g = gload(gram, go, K, li, j);
+            interf += rs[j] * (g.x * g.x + g.y * g.y);
+          }
+          v = log2(1.0 + rk * gkk * gkk / (interf + gkk));
+        }
+        const double tot = group_sum(v);
+        if (li == 0) rates[rbase + s * n_sch + c_mrc] = tot;
+      }
+      if (fact) {
+        const double logd = group_sum(li < K ? log2(diag) : 0.0);
+        const double tm = group_sum(li < K ? -log2(minv) : 0.0);
+        if (!ok) st |= XLMIMO_ST_MMSE_NOT_PD;
+        if (li == 0) {
+          if (mmse) rates[rbase + s * n_sch + c_mmse] = ok ? tm : nan;
+          if (cap) rates[rbase + s * n_sch + c_cap] = ok ? 2.0 * logd : nan;
+        }
+      }
+    }
+    if (st != 0 && li == 0) atomicOr(&s_st[slot], st);   // bitwise OR: the order does not matter
+  }
+  __syncthreads();
+  if (status != nullptr && threadIdx.x < drops_per_block) {
+    const int64_t dd = (int64_t)blockIdx.x * drops_per_block + threadIdx.x;
+    if (dd < n_drops) status[dd] = s_st[threadIdx.x];
+  }
+}
+
 hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
                         int32_t* d_status, hipStream_t s) {
@@ -274,6 +464,17 @@ hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const doub
   int n_sch = __builtin_popcount(schemes);
   const int ld = k_max + 1;
   const bool mism = schemes & XLMIMO_MZF_MISM;
+  const int jobs = ((schemes & XLMIMO_ZF) ? 1 : 0) + ((schemes & XLMIMO_MZF) ? 1 : 0) +
+                   ((schemes & (XLMIMO_MMSE | XLMIMO_CAP | XLMIMO_MRC)) ? n_snr : 0);
+  if (k_max <= kSmallK && !mism && jobs >= 1 && jobs * kSmallK <= 256) {
+    // several drops per wave when a drop needs fewer than four factorisations
+    const int per = jobs >= 4 ? 1 : 4 / jobs;
+    const int threads = ((per * jobs * kSmallK + 63) / 64) * 64;
+    const int blocks = (int)((n_drops + per - 1) / per);
+    k_rates_small<<<blocks, threads, 0, s>>>(d_drops, n_drops, d_gram, d_filter, n_snr, d_rho, total_users, schemes,
+                                             n_sch, jobs, per, d_rates, d_status);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(mism ? 2 : 1) * k_max * ld * sizeof(cplx) + 64 * sizeof(double);
   k_rates<<<n_drops, 64, lds, s>>>(d_drops, d_gram, d_filter, n_snr, d_rho, total_users, schemes, n_sch, d_rates,
                                     d_status, ld);
