@@ -36,9 +36,22 @@ constexpr int TM = 64, TN = 64, TK = 32;
 constexpr int LDS_K = TK + 8;  // row pitch in bf16 (80 bytes: 16-byte aligned operand reads)
 constexpr double kPiD = 3.14159265358979323846264338327950288;
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by the rational-exponential approximation 7.1.26 of Abramowitz and Stegun
+// (Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2},
+// t = 1 / (1 + p x), x >= 0, odd extension; |error| <= 1.5e-7, far below the
+// BF16 rounding of the activations it feeds.  One reciprocal and one exp2.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                              0.254829592f);
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.44269504088896341f);
+  return copysignf(fmaf(-poly, e, 1.0f), x);
+}
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+         z * __builtin_amdgcn_exp2f(-0.5f * z * z * 1.44269504088896341f) * 0.39894228040143268f;
 }
 
 template <int EPI>
@@ -440,9 +453,13 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
                                                            const __bf16* __restrict__ wbf,
                                                            const float* __restrict__ master,
                                                            const int64_t* __restrict__ offs, float* __restrict__ out) {
+  // 64 pairs per workgroup, activations resident in one LDS buffer (pair-major, features contiguous).
+  // Hidden layers run as out^T = W act^T: the weights are the MFMA's A operand (16 features x 32 k),
+  // the activations its B operand (32 k x 16 pairs), so each lane's four results are four consecutive
+  // features of one pair and leave in one 8-byte LDS store.  Wave w owns features [w W/4, (w+1) W/4).
   constexpr int P = W + 8;           // LDS row pitch (bf16): 16-byte aligned rows
-  constexpr int CB = W / 64;         // 16-column blocks per wave
-  __shared__ __attribute__((aligned(16))) __bf16 act[2][64 * P];
+  constexpr int FB = W / 64;         // 16-feature blocks per wave
+  __shared__ __attribute__((aligned(16))) __bf16 act[64 * P];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * 64;
   const int kg = lane >> 4, li = lane & 15;
@@ -451,56 +468,67 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
   // layer-0 input: 8 feature slots (6 used) per pair, zero up to K = 32
   for (int i = tid; i < 64 * 32; i += 256) {
     const int r = i >> 5, k = i & 31;
-    act[0][r * P + k] = (k < 8 && row0 + r < n) ? feat[(row0 + r) * 8 + k] : (__bf16)0.0f;
+    act[r * P + k] = (k < 8 && row0 + r < n) ? feat[(row0 + r) * 8 + k] : (__bf16)0.0f;
   }
   __syncthreads();
 
-  int cur = 0;
   for (int l = 0; l < depth; ++l) {  // hidden layers
     const int K = (l == 0) ? 32 : W;
     const int in = (l == 0) ? XLMIMO_MLP_IN : W;
     const __bf16* Wl = wbf + offs[2 * l];
     const float* bl = master + offs[2 * l + 1];
-    floatx4 acc[4][CB];
+    floatx4 acc[FB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FB; ++i)
 #pragma unroll
-      for (int j = 0; j < CB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      const int kk = k0 + 8 * kg;
-      bf16x8 af[4], bfr[CB];
+      for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto load_w = [&](int kk, bf16x8 (&wf)[FB]) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&act[cur][(i * 16 + li) * P + kk]);
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int col = wave * (W / 4) + j * 16 + li;
+      for (int i = 0; i < FB; ++i) {
+        const int f = wave * (W / 4) + i * 16 + li;
         if (l == 0) {
           bf16x8 v = zero8;
 #pragma unroll
           for (int q = 0; q < 8; ++q)
-            if (kk + q < in) v[q] = Wl[col * in + kk + q];
-          bfr[j] = v;
+            if (kk + q < in) v[q] = Wl[f * in + kk + q];
+          wf[i] = v;
         } else {
-          bfr[j] = *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)col * W + kk]);
+          wf[i] = *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)f * W + kk]);
         }
       }
+    };
+    bf16x8 wcur[FB], wnext[FB];
+    load_w(8 * kg, wcur);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kk = k0 + 8 * kg;
+      if (k0 + 32 < K) load_w(kk + 32, wnext);   // the next step's weights are in flight during this one
+      bf16x8 af[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
 #pragma unroll
-        for (int j = 0; j < CB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < FB; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FB; ++i) wcur[i] = wnext[i];
     }
-    const int nxt = cur ^ 1;
+    __syncthreads();   // every wave has read this layer's input
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FB; ++i) {
+      const int f0 = wave * (W / 4) + i * 16 + 4 * kg;
+      const float b0 = bl[f0], b1 = bl[f0 + 1], b2 = bl[f0 + 2], b3 = bl[f0 + 3];
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int col = wave * (W / 4) + j * 16 + li;
-        const float b = bl[col];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) act[nxt][(i * 16 + 4 * kg + r) * P + col] = (__bf16)gelu(acc[i][j][r] + b);
+      for (int j = 0; j < 4; ++j) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 v;
+        v[0] = (__bf16)gelu(acc[i][j][0] + b0);
+        v[1] = (__bf16)gelu(acc[i][j][1] + b1);
+        v[2] = (__bf16)gelu(acc[i][j][2] + b2);
+        v[3] = (__bf16)gelu(acc[i][j][3] + b3);
+        *reinterpret_cast<bf16x4*>(&act[(j * 16 + li) * P + f0]) = v;
       }
+    }
     __syncthreads();
-    cur = nxt;
   }
 
   // output layer: XLMIMO_MLP_OUT columns (one 16-column block), wave w takes rows 16w..16w+15
@@ -510,7 +538,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < W; k0 += 32) {
       const int kk = k0 + 8 * kg;
-      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[cur][(wave * 16 + li) * P + kk]);
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(wave * 16 + li) * P + kk]);
       const bf16x8 bfr = (li < XLMIMO_MLP_OUT) ? *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)li * W + kk]) : zero8;
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc, 0, 0, 0);
     }
