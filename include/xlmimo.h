@@ -80,10 +80,10 @@ extern "C" {
  * the angle the aperture subtends at the pair's midpoint is at most 960 rad
  * (users a fraction of a metre apart: no stationary-phase regime), and pairs
  * whose stationary zone is broad (Fresnel width >= 1/2 of the half-aperture: the
- * phase is far from quadratic over it) when that costs at most N/4 quadrature
+ * phase is far from quadratic over it) when that costs at most N/8 quadrature
  * nodes.  Their entry is the aperture integral (1/d) int conj(h_i) h_j dy by
  * composite Gauss-Legendre quadrature plus the discrete end corrections, or the
- * direct sum over the N elements when that costs no more. */
+ * direct sum over the N elements when N <= 1024 or that costs no more. */
 #define XLMIMO_CF_UNIFORM 2    /* uniform stationary-phase form of the discrete sum: the stationary term
                                   weighted by the Fresnel integral between the array ends, end terms
                                   without their stationary singularity, discrete end corrections;

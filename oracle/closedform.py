@@ -220,7 +220,7 @@ def numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n):
     """(route, panels): route ROUTE_DIRECT / ROUTE_QUAD for a pair the closed forms UNIFORM and GATED_QUAD
     evaluate numerically, ROUTE_NONE otherwise.  Numeric pairs: slow-phase pairs (<= QUAD_MAX_PANELS
     panels) and pairs whose stationary zone is broad (Fresnel width sqrt(2 pi / |phi''(y*)|) >=
-    L / BROAD_FRACTION, or x_i == x_j) when the quadrature costs at most N / 4 nodes; the direct sum over
+    L / BROAD_FRACTION, or x_i == x_j) when the quadrature costs at most N / 8 nodes; the direct sum over
     the N elements is used when N <= DIRECT_MAX_N or it costs no more than the quadrature."""
     p = quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n)
     L = n * spacing / 2.0
@@ -231,7 +231,7 @@ def numeric_route(spacing, lam, xp_i, y_i, xp_j, y_j, n):
         a, b = np.hypot(xp_i, ys - y_i), np.hypot(xp_j, ys - y_j)
         p2 = k * (xp_i ** 2 / a ** 3 - xp_j ** 2 / b ** 3)
         broad = p2 == 0.0 or 2.0 * np.pi / abs(p2) >= (L / BROAD_FRACTION) ** 2
-    if p <= QUAD_MAX_PANELS or (broad and p * QUAD_NODES * 4 <= n):
+    if p <= QUAD_MAX_PANELS or (broad and p * QUAD_NODES * 8 <= n):
         return (ROUTE_DIRECT if n <= max(p * QUAD_NODES, DIRECT_MAX_N) else ROUTE_QUAD), p
     return ROUTE_NONE, 0
 

@@ -47,7 +47,7 @@ struct xlmimo_ctx {
   std::mutex mu;
   std::string err;
   int* d_counter = nullptr;
-  double* d_gl = nullptr;
+  double* d_gl = nullptr;  // Gauss-Legendre (node, weight) pairs: the n_gl-node rule, then kFresnelNodes nodes
   int n_gl = 0;
   DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist, scratch_pairs;
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
@@ -127,7 +127,8 @@ int ensure(xlmimo_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n from the
-// Chebyshev initial guess), used by the UPA free-space closed-form diagonal.
+// Chebyshev initial guess), used by the UPA free-space closed-form diagonal, the
+// aperture quadrature and the Fresnel integrals of the closed forms.
 void gauss_legendre(int n, std::vector<double>& out) {
   out.assign(2 * n, 0.0);
   const double pi = 3.14159265358979323846264338327950288;
@@ -589,13 +590,16 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   const size_t pb = (sizeof(int32_t) * 2 * np + 255) / 256 * 256;
   const size_t flb = (sizeof(int32_t) * p->n_drops + 255) / 256 * 256;
   const size_t ob = (sizeof(float) * kOut * np + 255) / 256 * 256;
-  if ((rc = ensure(c, c->scratch_pairs, fb + ab + pb + flb + ob, s))) return rc;
+  const size_t ib = (sizeof(ItemK) * std::max(p->n_items, 1) + 256 + 255) / 256 * 256;   // selected items + count
+  if ((rc = ensure(c, c->scratch_pairs, fb + ab + pb + flb + ob + ib, s))) return rc;
   char* base = (char*)c->scratch_pairs.p;
   __bf16* feat = (__bf16*)base;
   float* aux = (float*)(base + fb);
   int32_t* pmap = (int32_t*)(base + fb + ab);
   int32_t* flags = (int32_t*)(base + fb + ab + pb);
   float* net_out = (float*)(base + fb + ab + pb + flb);
+  ItemK* items_sel = (ItemK*)(base + fb + ab + pb + flb + ob);
+  int* n_sel = (int*)(base + fb + ab + pb + flb + ob + ib - 256);
   HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 0, s));
   HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_out, nullptr, feat, aux,
                                 nullptr, pmap, s));
@@ -605,7 +609,7 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   const int grid = exact_grid(c, p, XLMIMO_FP32H);
   HIP_TRY(c, launch_gram_exact(XLMIMO_FP32H, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
                                p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, nullptr, nullptr,
-                               flags));
+                               flags, items_sel, n_sel));
   if (status) HIP_TRY(c, launch_or_flags(status, flags, p->n_drops, XLMIMO_ST_FELL_BACK, s));
   if (flags_out) *flags_out = flags;
   return XLMIMO_OK;
@@ -830,9 +834,11 @@ int xlmimo_ctx_create(xlmimo_ctx** out, int device) {
     delete c;
     return XLMIMO_EDEVICE;
   }
-  std::vector<double> gl;
+  std::vector<double> gl, gl_f;
   c->n_gl = 64;
   gauss_legendre(c->n_gl, gl);
+  gauss_legendre(kFresnelNodes, gl_f);
+  gl.insert(gl.end(), gl_f.begin(), gl_f.end());
   if (hipMalloc(&c->d_gl, sizeof(double) * gl.size()) != hipSuccess ||
       hipMemcpy(c->d_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(c->d_counter);

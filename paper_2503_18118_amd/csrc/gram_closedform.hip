@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
           s_queue[slot][2] = panels;
           continue;  // written by the cooperative pass below
         } else if (variant == XLMIMO_CF_UNIFORM) {
-          const Cplx v = uniform_pair(g, n, d, gl, n_gl);
+          const Cplx v = uniform_pair(g, n, d, gl + 2 * n_gl);   // the Fresnel rule follows the n_gl-node one
           re = v.re;
           im = v.im;
         } else {

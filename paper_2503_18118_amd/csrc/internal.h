@@ -18,6 +18,10 @@ struct ArrayK {
 };
 
 // One drop of a batch, device resident.
+// Gauss-Legendre nodes of the closed forms' Fresnel integrals F(s), |s| <= 8
+// (at most 32 rad of phase over [0, s]); the table follows the 64-node rule.
+constexpr int kFresnelNodes = 32;
+
 struct DropK {
   int64_t user_off;   // first user in the position array
   int64_t gram_off;   // first complex element of the drop's K x K output
@@ -69,7 +73,8 @@ struct GemmArgs {
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
                              double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
-                             hipEvent_t ev1 = nullptr, const int32_t* d_mask = nullptr);
+                             hipEvent_t ev1 = nullptr, const int32_t* d_mask = nullptr,
+                             ItemK* d_items_sel = nullptr, int* d_n_sel = nullptr);
 int gram_exact_grid(int precision, int nb_max, int geom, int amp);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,

@@ -21,7 +21,8 @@
 //      +- [ G0 e^{j phi*} F(s_e) + e^{j phi(e)} (f(e) / (j phi'(e)) - G0 / (j sigma s_e)) ]
 //   + discrete end corrections,
 //   G0 = f(y*) / sqrt|phi''(y*)|, F(s) = int_0^s e^{j sigma t^2/2} dt.
-//   |s_e| <= 8: F by 64-node Gauss-Legendre on [0, s_e]; |s_e| > 8: F's
+//   |s_e| <= 8: F by kFresnelNodes-node Gauss-Legendre on [0, s_e] (at most 32 rad
+//   of phase: 32 nodes reach FP64 rounding); |s_e| > 8: F's
 //   asymptotic series sgn(s) sqrt(pi/2) e^{j sigma pi/4} + e^{j sigma s^2/2}
 //   / (j sigma s) (1 + Q(s)), Q = sum_{m>=1} (2m-1)!! / (j sigma s^2)^m, folded into
 //   the end term so that its leading part cancels analytically.
@@ -142,7 +143,8 @@ __device__ Cplx fresnel_small(double s, double sigma, const double* __restrict__
 }
 
 // Uniform stationary-phase entry of a fast-phase pair (see the file notes).
-__device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* __restrict__ gl, int n_gl) {
+// gl_f: the kFresnelNodes-node Gauss-Legendre rule ((node, weight) pairs)
+__device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* __restrict__ gl_f) {
   const double L = 0.5 * (double)n * d;
   Cplx integral = {0.0, 0.0};
   if (g.xi == g.xj) {
@@ -206,7 +208,7 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
         endt = cadd(endt, Cplx{qq.im * f, -qq.re * f});
         part = cadd(part, endt);
       } else {
-        const Cplx F = fresnel_small(s, sigma, gl, n_gl);
+        const Cplx F = fresnel_small(s, sigma, gl_f, kFresnelNodes);
         part = cmul(cscale(eph, g0), F);
         Cplx br;
         if (fabs(s) < kSGuard) {
@@ -229,7 +231,7 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
 // Pairs evaluated numerically by the closed forms UNIFORM and GATED_QUAD: slow-phase
 // pairs (<= kQuadMaxPanels panels) and pairs whose stationary zone is broad
 // (Fresnel width sqrt(2 pi / |phi''(y*)|) >= L / kBroadFraction, or x_i == x_j) when
-// the quadrature costs at most N / 4 nodes; the direct sum over the N elements
+// the quadrature costs at most N / 8 nodes; the direct sum over the N elements
 // replaces the quadrature for N <= kDirectMaxN or when it costs no more.
 constexpr double kBroadFraction = 2.0;
 enum { ROUTE_NONE = 0, ROUTE_DIRECT = 1, ROUTE_QUAD = 2 };
@@ -256,7 +258,7 @@ __device__ __forceinline__ int numeric_route(const PairGeom& g, int n, double d,
     broad = p2 == 0.0 || 2.0 * kPiPair / fabs(p2) >= lb * lb;
   }
   panels = 0;
-  if (p <= kQuadMaxPanels || (broad && (double)p * n_gl * 4.0 <= (double)n)) {
+  if (p <= kQuadMaxPanels || (broad && (double)p * n_gl * 8.0 <= (double)n)) {
     panels = p;
     return (n <= kDirectMaxN || n <= (int64_t)p * n_gl) ? ROUTE_DIRECT : ROUTE_QUAD;
   }
