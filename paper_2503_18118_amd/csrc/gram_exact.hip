@@ -499,9 +499,11 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
                                                                const ItemK* __restrict__ items, int n_items,
                                                                int* __restrict__ counter,
                                                                double* __restrict__ partials,
-                                                               const int32_t* __restrict__ mask) {
+                                                               const int32_t* __restrict__ mask,
+                                                               const int* __restrict__ n_items_dev) {
   __shared__ double s_red[partial_values(NBMAX) * 64];
   __shared__ int s_item;
+  if (n_items_dev != nullptr) n_items = *n_items_dev;   // a compacted item list: its length is on the device
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
@@ -535,6 +537,42 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
 
 __global__ void k_reset_counter(int* counter) {
   if (threadIdx.x == 0) *counter = 0;
+}
+
+// The work items of the selected drops, in their original order (one workgroup:
+// per 1024 items, a ballot prefix within each wave, then the waves in order).
+__global__ __launch_bounds__(1024) void k_compact_items(const ItemK* __restrict__ items, int n_items,
+                                                        const int32_t* __restrict__ mask, ItemK* __restrict__ out,
+                                                        int* __restrict__ count) {
+  __shared__ int s_wave[16], s_off[16], s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < n_items; i0 += 1024) {
+    const int i = i0 + tid;
+    ItemK it{};
+    bool keep = false;
+    if (i < n_items) {
+      it = items[i];
+      keep = mask[it.drop] != 0;
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wave] = __popcll(bal);
+    __syncthreads();
+    if (tid == 0) {
+      int acc = s_base;
+      for (int w = 0; w < 16; ++w) {
+        s_off[w] = acc;
+        acc += s_wave[w];
+      }
+      s_base = acc;
+    }
+    __syncthreads();
+    if (keep) out[s_off[wave] + before] = it;
+    __syncthreads();
+  }
+  if (tid == 0) *count = s_base;
 }
 
 // Position of C[row][col] of a 16x16 MFMA accumulator in the (value, lane) image.
@@ -647,16 +685,17 @@ struct MainArgs {
   int* counter;
   double* partials;
   const int32_t* mask;
+  const int* n_items_dev;
 };
 
 template <typename T, int GEOM, int AMP, bool SPLIT>
 static void launch_main(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
   if (nb_max <= 1)
-    k_gram_exact<1, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<1, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask, a.n_items_dev);
   else if (nb_max <= 2)
-    k_gram_exact<2, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<2, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask, a.n_items_dev);
   else
-    k_gram_exact<4, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask);
+    k_gram_exact<4, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask, a.n_items_dev);
 }
 
 template <typename T, bool SPLIT>
@@ -673,11 +712,17 @@ static void launch_t(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
 hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const DropK* d_drops, int n_drops,
                              const double* d_pos, const ItemK* d_items, int n_items, int* d_counter,
                              double* d_partials, double* d_gram, int grid, hipStream_t s, hipEvent_t ev0,
-                             hipEvent_t ev1, const int32_t* d_mask) {
+                             hipEvent_t ev1, const int32_t* d_mask, ItemK* d_items_sel, int* d_n_sel) {
   if (n_drops == 0) return hipSuccess;
   k_reset_counter<<<1, 64, 0, s>>>(d_counter);
   if (grid < 1) grid = 1;
-  const MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials, d_mask};
+  MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials, d_mask, nullptr};
+  if (d_mask != nullptr && d_items_sel != nullptr && d_n_sel != nullptr) {
+    // a few selected drops: pop only their items
+    k_compact_items<<<1, 1024, 0, s>>>(d_items, n_items, d_mask, d_items_sel, d_n_sel);
+    a.items = d_items_sel;
+    a.n_items_dev = d_n_sel;
+  }
   if (ev0) (void)hipEventRecord(ev0, s);
   if (precision == XLMIMO_FP64) launch_t<double, false>(nb_max, grid, s, a);
   else if (precision == XLMIMO_FP32H) launch_t<float, true>(nb_max, grid, s, a);

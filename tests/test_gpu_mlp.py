@@ -165,3 +165,34 @@ def test_fused_forward_other_shapes(X, ctx, width, depth, n_drops):
     ref, _ = OM.forward(pb, x, width, depth)
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 2e-2
     mlp.close()
+
+
+def test_fallback_recomputes_flagged_drops_exactly(X, ctx):
+    # Drops where the predicted log-variance exceeds log_var_max for some pair are recomputed by the
+    # exact FP32H kernel over their own work items only (selected on the device); the other drops keep
+    # the corrected closed form.  The threshold splits the drops about in half.
+    rng = np.random.default_rng(21)
+    mlp = X.MLP(ctx, 64, 2)
+    mlp.set_params(OM.init_params(rng, 64, 2).astype(np.float32))
+    arr, drops = W.learned_drops(24, stream=31, k=9)
+    b = X.Batch(drops)
+    gcf, _ = ctx.gram_closedform(arr, b, X.CF_GATED_QUAD)
+    pi = mlp.pair_inputs(arr, b, gcf)
+    s = mlp.forward(pi)[:, 6].cpu().numpy()
+    pm = pi.pmap.cpu().numpy()
+    smax = np.full(drops.n_drops, -np.inf, np.float32)
+    np.maximum.at(smax, pm[:, 0], s)
+    order = np.sort(smax)
+    thr = float(0.5 * (order[11] + order[12]))
+    assert order[11] < thr < order[12]
+    out, st = ctx.gram_closedform_mlp(arr, b, mlp, X.CF_GATED_QUAD, thr)
+    kept, st_kept = ctx.gram_closedform_mlp(arr, b, mlp, X.CF_GATED_QUAD, 1e30)
+    ex = ctx.gram_exact(arr, b, X.FP32H)
+    torch.cuda.synchronize()
+    fell = (st.cpu().numpy() & X.ST_FELL_BACK) != 0
+    assert np.array_equal(fell, smax > thr) and fell.sum() == 12
+    assert not np.any(st_kept.cpu().numpy() & X.ST_FELL_BACK)
+    g, gk, ge = b.split(out), b.split(kept), b.split(ex)
+    for d in range(drops.n_drops):
+        assert np.array_equal(g[d], ge[d] if fell[d] else gk[d]), d
+    mlp.close()
