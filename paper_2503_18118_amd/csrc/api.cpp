@@ -50,6 +50,7 @@ struct xlmimo_ctx {
   double* d_gl = nullptr;  // Gauss-Legendre (node, weight) pairs: the n_gl-node rule, then kFresnelNodes nodes
   int n_gl = 0;
   DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist, scratch_pairs;
+  DevBuf scratch_routes;   // per-pair route words of the ULA closed forms UNIFORM and GATED_QUAD
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
   std::unordered_map<uint64_t, Plan> plans;
   // kernel timing (xlmimo_timing_enable / xlmimo_timing_read)
@@ -380,8 +381,9 @@ int closedform_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   Plan* p = nullptr;
   int rc = get_plan(c, a, b, n_override, &p);
   if (rc) return rc;
+  if ((rc = ensure(c, c->scratch_routes, sizeof(int32_t) * std::max<int64_t>(p->n_pairs, 1), s))) return rc;
   HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
-                               gram_out, status, p->k_max, s));
+                               gram_out, status, p->k_max, s, p->n_pairs, (int32_t*)c->scratch_routes.p));
   return XLMIMO_OK;
 }
 
@@ -582,8 +584,9 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   Plan* p = nullptr;
   int rc = get_plan(c, a, b, n_override, &p);
   if (rc) return rc;
+  if ((rc = ensure(c, c->scratch_routes, sizeof(int32_t) * std::max<int64_t>(p->n_pairs, 1), s))) return rc;
   HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
-                               gram_out, status, p->k_max, s));
+                               gram_out, status, p->k_max, s, p->n_pairs, (int32_t*)c->scratch_routes.p));
   const int64_t np = p->n_pairs;
   const size_t fb = (sizeof(__bf16) * kFeatPitch * np + 255) / 256 * 256;
   const size_t ab = (sizeof(float) * kAuxPitch * np + 255) / 256 * 256;
@@ -863,7 +866,7 @@ int xlmimo_ctx_destroy(xlmimo_ctx* c) {
     (void)hipFree(kv.second.d_items);
   }
   DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds,
-                    &c->scratch_nlist, &c->scratch_pairs};
+                    &c->scratch_nlist, &c->scratch_pairs, &c->scratch_routes};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipFree(c->d_counter);

@@ -21,10 +21,13 @@
 //   (slow-phase pairs and broad stationary zones, pair_math.h), which take the
 //   aperture quadrature or the direct sum.
 // Variant UNIFORM (ULA): the uniform stationary-phase form of the discrete sum,
-//   with the same numeric routes (pair_math.h).  Analytic pairs take one thread
-//   each; direct sums one wave each; quadratures the whole workgroup, one at a
-//   time (nodes strided over the threads, fixed-order wave sums, waves summed
-//   in order).
+//   with the same numeric routes (pair_math.h).
+// For UNIFORM and GATED_QUAD two kernels run: k_cf_pairs takes every pair of the
+//   batch on its own thread (analytic entries, and each pair's route), then
+//   k_closedform takes each drop on a workgroup (the diagonal and the numeric
+//   pairs: direct sums from channels staged in LDS or one wave per pair,
+//   quadratures by the whole workgroup one at a time with nodes strided over the
+//   threads, fixed-order wave sums, waves summed in order).
 // All arithmetic is FP64; the phase d_ij / lambda is reduced in revolutions.
 #include "device_math.h"
 #include "internal.h"
@@ -65,10 +68,140 @@ __device__ double solid_angle_rect(double x, double u1, double u2, double v1, do
   return f(u2, v2) - f(u1, v2) - f(u2, v1) + f(u1, v1);
 }
 
+// ULA user i: perpendicular distance x, position y along the array, closed-form
+// diagonal G~_ii and (PNUSW) the aperture factor S of eq. (4).  ok is false for
+// a user on the array line or with non-finite coordinates.
+struct UlaUser {
+  double x, y, diag, sfac;
+  bool ok;
+};
+
+__device__ __forceinline__ UlaUser ula_user(const ArrayK& arr, const double* __restrict__ p, double Ly, double c_fs) {
+  UlaUser u;
+  const double px = p[0], py = p[1], pz = p[2];
+  u.x = sqrt(fma(px, px, pz * pz));
+  u.y = py;
+  u.sfac = 0.0;
+  u.ok = u.x > 0.0 && isfinite(u.x) && isfinite(py) && isfinite(pz);
+  const double d = arr.spacing;
+  if (!u.ok) {
+    u.diag = __builtin_nan("");
+  } else if (arr.amp == XLMIMO_AMP_PNUSW) {
+    const double a = Ly - py, b = Ly + py;
+    u.sfac = a / sqrt(fma(a, a, u.x * u.x)) + b / sqrt(fma(b, b, u.x * u.x));
+    u.diag = arr.beta0 / (d * u.x) * u.sfac;
+  } else {
+    u.diag = c_fs / (d * u.x) * (atan((Ly - py) / u.x) + atan((Ly + py) / u.x));
+  }
+  return u;
+}
+
+// Pair t (0-based, p < q, row by row) of K users.
+__device__ __forceinline__ void pair_of(int K, int t, int& p, int& q) {
+  p = 0;
+  int rem = t;
+  while (rem >= K - 1 - p) {
+    rem -= K - 1 - p;
+    ++p;
+  }
+  q = p + 1 + rem;
+}
+
+// Per-pair word written by k_cf_pairs for the per-drop pass: route in bits 0-1,
+// degenerate pair (GATED entry with x_i == x_j) in bit 2, panels from bit 3.
+constexpr int kPairDegenerate = 4;
+
+// GATED entry of an analytic ULA pair: the stationary-phase term (eq. (6) or its
+// free-space analogue), zero with the stationary point off the aperture.
+__device__ __forceinline__ Cplx gated_ula(const ArrayK& arr, const UlaUser& up, const UlaUser& uq, double Ly,
+                                          double c_fs, bool& degenerate) {
+  const double d = arr.spacing, lam = arr.lambda;
+  const double xp = up.x, xq = uq.x;
+  const double dx = xp - xq, dy = up.y - uq.y;
+  const double dist = sqrt(dx * dx + dy * dy);
+  degenerate = false;
+  if (dx == 0.0 || dist == 0.0) {
+    degenerate = true;
+    return Cplx{0.0, 0.0};
+  }
+  if (!(fabs((up.y * xq - xp * uq.y) / (xq - xp)) <= Ly)) return Cplx{0.0, 0.0};
+  const double sg = dx > 0.0 ? 1.0 : -1.0;
+  double mag;
+  if (arr.amp == XLMIMO_AMP_PNUSW) {
+    const double rho = sqrt(lam) * fabs(dx) / (dist * sqrt(dist)) / sqrt(up.sfac * uq.sfac);
+    mag = rho * sqrt(up.diag * uq.diag);
+  } else {
+    mag = c_fs * sqrt(lam) / (d * sqrt(xp * xq * dist));
+  }
+  double tt;
+  int qd;
+  reduce_quarter(dist * arr.inv_lambda - 0.125, tt, qd);
+  double sn, cs, cre, cim;
+  sincos_rev(tt, sn, cs);
+  rotate_conj(1.0, sn, cs, qd, cre, cim);
+  return Cplx{mag * cre, -sg * mag * cim};
+}
+
+// Analytic pairs of the ULA variants UNIFORM and GATED_QUAD, one thread per pair over the
+// whole batch (the drop found by bisection of the pairs' offsets).  Writes the entry and its
+// conjugate for analytic pairs and NaN for pairs with a bad user; records every pair's route
+// for k_closedform, which evaluates the numeric ones.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_cf_pairs(ArrayK arr, const DropK* __restrict__ drops, int n_drops,
+                                                  int64_t n_pairs, int variant, const double* __restrict__ pos,
+                                                  const double* __restrict__ gl, int n_gl,
+                                                  double* __restrict__ gram, int32_t* __restrict__ route_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pairs) return;
+  int lo = 0, hi = n_drops - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (drops[mid].pair_off <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const DropK dp = drops[lo];
+  const int K = dp.k;
+  int p, q;
+  pair_of(K, (int)(t - dp.pair_off), p, q);
+  const double d = arr.spacing, lam = arr.lambda;
+  const double c_fs = (lam / (4.0 * kPi)) * (lam / (4.0 * kPi));
+  const double Ly = 0.5 * (double)dp.n_elems * d;
+  const UlaUser up = ula_user(arr, pos + (dp.user_off + p) * 3, Ly, c_fs);
+  const UlaUser uq = ula_user(arr, pos + (dp.user_off + q) * 3, Ly, c_fs);
+  double* out = gram + 2 * dp.gram_off;
+  int word = ROUTE_NONE;
+  bool write = true;
+  Cplx v = {0.0, 0.0};
+  if (!(up.ok && uq.ok && isfinite(up.diag) && isfinite(uq.diag))) {
+    v = Cplx{__builtin_nan(""), __builtin_nan("")};
+  } else {
+    const PairGeom g{up.x, up.y, uq.x, uq.y, 2.0 * kPi * arr.inv_lambda, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+    int panels = 0;
+    const int route = numeric_route(g, dp.n_elems, d, n_gl, panels);
+    if (route != ROUTE_NONE) {
+      word = route | (panels << 3);
+      write = false;   // k_closedform evaluates it
+    } else if (variant == XLMIMO_CF_UNIFORM) {
+      v = uniform_pair(g, dp.n_elems, d, gl + 2 * n_gl);   // the Fresnel rule follows the n_gl-node one
+    } else {
+      bool degenerate;
+      v = gated_ula(arr, up, uq, Ly, c_fs, degenerate);
+      if (degenerate) word |= kPairDegenerate;
+    }
+  }
+  route_out[t] = word;
+  if (write) {
+    out[2 * (p * K + q)] = v.re;
+    out[2 * (p * K + q) + 1] = v.im;
+    out[2 * (q * K + p)] = v.re;
+    out[2 * (q * K + p) + 1] = -v.im;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __restrict__ drops, int variant,
                                                      const double* __restrict__ pos,
                                                      const double* __restrict__ gl, int n_gl,
-                                                     double* __restrict__ gram, int32_t* __restrict__ status) {
+                                                     double* __restrict__ gram, int32_t* __restrict__ status,
+                                                     const int32_t* __restrict__ route_in) {
   __shared__ double s_x[XLMIMO_MAX_USERS], s_y[XLMIMO_MAX_USERS], s_z[XLMIMO_MAX_USERS];
   __shared__ double s_diag[XLMIMO_MAX_USERS], s_sfac[XLMIMO_MAX_USERS];
   __shared__ int s_status;
@@ -116,8 +249,8 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
 
   double* out = gram + 2 * dp.gram_off;
   if (ula && (variant == XLMIMO_CF_UNIFORM || variant == XLMIMO_CF_GATED_QUAD)) {
-    // Analytic pairs: one thread per pair.  Numeric pairs (slow-phase pairs, broad stationary zones)
-    // are queued and then evaluated by the whole workgroup, one pair at a time.
+    // The diagonal, then the numeric pairs (slow-phase pairs, broad stationary zones) queued from
+    // k_cf_pairs' route words: direct sums and quadratures by the whole workgroup.
     __shared__ int s_nq, s_nd;
     __shared__ __align__(16) int s_queue[XLMIMO_MAX_USERS * (XLMIMO_MAX_USERS - 1) / 2][3];  // pair, route, panels
     if (threadIdx.x == 0) s_nq = s_nd = 0;
@@ -129,67 +262,20 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
     const int np = K * (K - 1) / 2;
     const int n = dp.n_elems;
     const double kw = 2.0 * kPi * arr.inv_lambda;
-    auto pair_of = [K](int t, int& p, int& q) {
-      p = 0;
-      int rem = t;
-      while (rem >= K - 1 - p) {
-        rem -= K - 1 - p;
-        ++p;
-      }
-      q = p + 1 + rem;
-    };
+    auto pair_of_k = [K](int t, int& p, int& q) { pair_of(K, t, p, q); };
+    // analytic pairs were written by k_cf_pairs; queue the numeric ones from its route words
+    const int32_t* rw = route_in + dp.pair_off;
     for (int t = threadIdx.x; t < np; t += blockDim.x) {
-      int p, q;
-      pair_of(t, p, q);
-      double re = 0.0, im = 0.0;
-      if (!(isfinite(s_diag[p]) && isfinite(s_diag[q]))) {
-        re = im = __builtin_nan("");
-      } else {
-        const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
-        int panels = 0;
-        const int route = numeric_route(g, n, d, n_gl, panels);
-        if (route != ROUTE_NONE) {
-          const int slot = atomicAdd(&s_nq, 1);
-          if (route == ROUTE_DIRECT) atomicAdd(&s_nd, 1);
-          s_queue[slot][0] = t;
-          s_queue[slot][1] = route;
-          s_queue[slot][2] = panels;
-          continue;  // written by the cooperative pass below
-        } else if (variant == XLMIMO_CF_UNIFORM) {
-          const Cplx v = uniform_pair(g, n, d, gl + 2 * n_gl);   // the Fresnel rule follows the n_gl-node one
-          re = v.re;
-          im = v.im;
-        } else {
-          // stationary-phase entry of variant GATED (free space or eq. (6)), zero off the aperture
-          const double xp = s_x[p], xq = s_x[q];
-          const double dx = xp - xq, dy = s_y[p] - s_y[q];
-          const double dist = sqrt(dx * dx + dy * dy);
-          if (dx == 0.0 || dist == 0.0) {
-            atomicOr(&s_status, XLMIMO_ST_CF_DEGENERATE);
-          } else if (fabs((s_y[p] * xq - xp * s_y[q]) / (xq - xp)) <= Ly) {
-            const double sg = dx > 0.0 ? 1.0 : -1.0;
-            double mag;
-            if (arr.amp == XLMIMO_AMP_PNUSW) {
-              const double rho = sqrt(lam) * fabs(dx) / (dist * sqrt(dist)) / sqrt(s_sfac[p] * s_sfac[q]);
-              mag = rho * sqrt(s_diag[p] * s_diag[q]);
-            } else {
-              mag = c_fs * sqrt(lam) / (d * sqrt(xp * xq * dist));
-            }
-            double tt;
-            int qd;
-            reduce_quarter(dist * arr.inv_lambda - 0.125, tt, qd);
-            double sn, cs, cre, cim;
-            sincos_rev(tt, sn, cs);
-            rotate_conj(1.0, sn, cs, qd, cre, cim);
-            re = mag * cre;
-            im = -sg * mag * cim;
-          }
-        }
+      const int w = rw[t];
+      if (w & kPairDegenerate) atomicOr(&s_status, XLMIMO_ST_CF_DEGENERATE);
+      const int route = w & 3;
+      if (route != ROUTE_NONE) {
+        const int slot = atomicAdd(&s_nq, 1);
+        if (route == ROUTE_DIRECT) atomicAdd(&s_nd, 1);
+        s_queue[slot][0] = t;
+        s_queue[slot][1] = route;
+        s_queue[slot][2] = w >> 3;
       }
-      out[2 * (p * K + q)] = re;
-      out[2 * (p * K + q) + 1] = im;
-      out[2 * (q * K + p)] = re;
-      out[2 * (q * K + p) + 1] = -im;
     }
     __syncthreads();
     const int nq = s_nq;
@@ -214,7 +300,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
       __syncthreads();
       const int me = threadIdx.x / sub, ms = threadIdx.x % sub;
       int p = 0, q = 0;
-      if (me < nd) pair_of(s_dl[me], p, q);
+      if (me < nd) pair_of_k(s_dl[me], p, q);
       Cplx acc = {0.0, 0.0};
       for (int n0 = 0; n0 < n; n0 += chunk) {
         const int cn = min(chunk, n - n0);
@@ -248,7 +334,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
       __syncthreads();
       if (threadIdx.x < nd) {
         int pp, qq;
-        pair_of(s_dl[threadIdx.x], pp, qq);
+        pair_of_k(s_dl[threadIdx.x], pp, qq);
         Cplx v = {0.0, 0.0};
         for (int m = 0; m < sub; ++m) v = cadd(v, Cplx{s_part[2 * (threadIdx.x * sub + m)], s_part[2 * (threadIdx.x * sub + m) + 1]});
         out[2 * (pp * K + qq)] = v.re;
@@ -261,7 +347,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
     for (int e = wave; e < nq && !shared_chan; e += n_waves) {
       if (s_queue[e][1] != ROUTE_DIRECT) continue;
       int p, q;
-      pair_of(s_queue[e][0], p, q);
+      pair_of_k(s_queue[e][0], p, q);
       const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
       const Cplx v = wave_sum_c(numeric_share(g, n, d, ROUTE_DIRECT, 0, gl, n_gl, lane, 64));
       if (lane == 0) {
@@ -278,7 +364,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
       const int t = s_queue[e][0], route = s_queue[e][1], panels = s_queue[e][2];
       if (route != ROUTE_QUAD) continue;
       int p, q;
-      pair_of(t, p, q);
+      pair_of_k(t, p, q);
       const PairGeom g{s_x[p], s_y[p], s_x[q], s_y[q], kw, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
       const Cplx v = wave_sum_c(numeric_share(g, n, d, route, panels, gl, n_gl, threadIdx.x, blockDim.x));
       if (lane == 0) {
@@ -360,11 +446,18 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
                              const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,
-                             int k_max, hipStream_t s) {
+                             int k_max, hipStream_t s, int64_t n_pairs, int32_t* d_route) {
   (void)d_diag;
   (void)k_max;
   if (n_drops == 0) return hipSuccess;
-  k_closedform<<<n_drops, 256, 0, s>>>(arr, d_drops, variant, d_pos, d_gl, n_gl, d_gram, d_status);
+  const bool split = arr.geom == XLMIMO_ULA && (variant == XLMIMO_CF_UNIFORM || variant == XLMIMO_CF_GATED_QUAD);
+  if (split) {
+    if (d_route == nullptr) return hipErrorInvalidValue;
+    if (n_pairs > 0)
+      k_cf_pairs<<<(unsigned)((n_pairs + 255) / 256), 256, 0, s>>>(arr, d_drops, n_drops, n_pairs, variant, d_pos, d_gl,
+                                                                  n_gl, d_gram, d_route);
+  }
+  k_closedform<<<n_drops, 256, 0, s>>>(arr, d_drops, variant, d_pos, d_gl, n_gl, d_gram, d_status, d_route);
   return hipGetLastError();
 }
 

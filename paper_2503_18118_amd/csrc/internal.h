@@ -79,7 +79,8 @@ int gram_exact_grid(int precision, int nb_max, int geom, int amp);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
                              const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,
-                             int k_max, hipStream_t s);
+                             int k_max, hipStream_t s, int64_t n_pairs = 0,
+                             int32_t* d_route = nullptr);
 
 hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,

@@ -254,18 +254,33 @@ def test_closedform_uniform_accuracy_on_sweep_drops(X, ctx):
         assert max(eu) < 1e-3 and np.median(eu) < 1e-2 * np.median(eg), (n, max(eu), np.median(eu), np.median(eg))
 
 
-def test_closedform_bad_and_degenerate_inputs(X, ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_closedform_bad_and_degenerate_inputs(X, ctx, variant):
+    # drop 0: a user on the array line (bad input: NaN diagonal and entries); drop 1: two users at the
+    # same perpendicular distance 4 m apart (no stationary point: the gated forms give 0 and flag the
+    # pair, UNIFORM takes the end terms; the pair is too far apart for a numeric route at N = 1024)
     arr = W.ula(1024, W.LAMBDA_28GHZ)
-    pos = np.array([[0.0, 1.0, 0.0], [3.0, 1.0, 0.0],      # user on the array line
-                    [3.0, 0.5, 0.0], [3.0, -0.5, 0.0]])    # equal x: degenerate pair
+    pos = np.array([[0.0, 1.0, 0.0], [3.0, 1.0, 0.0],
+                    [3.0, 2.0, 0.0], [3.0, -2.0, 0.0]])
     drops = W._pack([1024, 1024], [2, 2], pos)
     b = X.Batch(drops)
-    out, status = ctx.gram_closedform(arr, b, X.CF_PAPER)
+    out, status = ctx.gram_closedform(arr, b, variant)
+    torch.cuda.synchronize()
     st = status.cpu().numpy()
-    assert st[0] & X.ST_BAD_INPUT
-    assert st[1] & X.ST_CF_DEGENERATE and not st[1] & X.ST_BAD_INPUT
     g = b.split(out)
-    assert g[1][0, 1] == 0 and g[1][0, 0] > 0
+    assert st[0] & X.ST_BAD_INPUT
+    assert math.isnan(g[0][0, 0].real) and np.isfinite(g[0][1, 1].real)
+    assert np.isnan(g[0][0, 1].real) and np.isnan(g[0][1, 0].real)
+    assert not st[1] & X.ST_BAD_INPUT and g[1][0, 0].real > 0
+    x, y = pos[2:, 0], pos[2:, 1]
+    assert ocf.numeric_route(arr.spacing, arr.wavelength, x[0], y[0], x[1], y[1], 1024)[0] == ocf.ROUTE_NONE
+    if variant == 2:
+        assert not st[1] & X.ST_CF_DEGENERATE
+        ref = ocf.gram_closedform(arr, drops.users_of(1), 1024, variant)
+        assert abs(g[1][0, 1] - ref[0, 1]) < 1e-8 * ref[0, 0].real and g[1][0, 1] != 0
+    else:
+        assert st[1] & X.ST_CF_DEGENERATE
+        assert g[1][0, 1] == 0 and g[1][1, 0] == 0
 
 
 def _rho_host(X, rho):
