@@ -490,11 +490,13 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
         }
       }
     };
-    bf16x8 wcur[FB], wnext[FB];
+    // weights two k-steps ahead: steps k and k + 32 are in flight while step k - 32 computes
+    bf16x8 wcur[FB], wn1[FB], wn2[FB];
     load_w(8 * kg, wcur);
+    if (32 < K) load_w(32 + 8 * kg, wn1);
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kk = k0 + 8 * kg;
-      if (k0 + 32 < K) load_w(kk + 32, wnext);   // the next step's weights are in flight during this one
+      if (k0 + 64 < K) load_w(kk + 64, wn2);
       bf16x8 af[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
@@ -503,7 +505,10 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < FB; ++i) wcur[i] = wnext[i];
+      for (int i = 0; i < FB; ++i) {
+        wcur[i] = wn1[i];
+        wn1[i] = wn2[i];
+      }
     }
     __syncthreads();   // every wave has read this layer's input
 #pragma unroll
