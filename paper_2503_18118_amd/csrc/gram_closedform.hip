@@ -308,8 +308,9 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
           const int u = idx / cn, e = idx - u * cn;
           const double y = ((double)(n0 + e) - 0.5 * (double)(n - 1)) * d;
           const double dy = y - s_y[u], x = s_x[u];
-          const double r = sqrt(fma(dy, dy, x * x));
-          const double a = arr.amp == XLMIMO_AMP_PNUSW ? sqrt(arr.beta0 * x) / (r * sqrt(r)) : sq_fs / r;
+          double r, ir;
+          dist_inv(fma(dy, dy, x * x), r, ir);
+          const double a = arr.amp == XLMIMO_AMP_PNUSW ? sqrt(arr.beta0 * x) * ir * sqrt(ir) : sq_fs * ir;
           const Cplx ph = phasor_turns_d(r * arr.inv_lambda);
           s_h[2 * (u * chunk + e)] = a * ph.re;
           s_h[2 * (u * chunk + e) + 1] = -a * ph.im;

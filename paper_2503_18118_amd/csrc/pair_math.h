@@ -85,6 +85,34 @@ __device__ __forceinline__ double amp_product(const PairGeom& g, double ri, doub
   return g.c_fs / (ri * rj);
 }
 
+// r = sqrt(r2) and 1/r, both to FP64 accuracy, without a division: the
+// reciprocal square root from the FP32 estimate and two Newton steps, then one
+// correction of r = r2 / sqrt(r2).
+__device__ __forceinline__ void dist_inv(double r2, double& r, double& inv) {
+  inv = rsqrt_nr2(r2);
+  r = r2 * inv;
+  r = fma(0.5 * inv, fma(-r, r, r2), r);
+}
+
+// 1/c for c > 0 well inside the FP32 range: the FP32 estimate and two Newton steps.
+__device__ __forceinline__ double recip_nr2(double c) {
+  double y = (double)__builtin_amdgcn_rcpf((float)c);
+  y = fma(y, fma(-c, y, 1.0), y);
+  return fma(y, fma(-c, y, 1.0), y);
+}
+
+// f(y) e^{j phi(y)} for the numeric routes (no division: amplitudes from the
+// reciprocal distances); sq_ij = sqrt(x_i x_j) for PNUSW.
+__device__ __forceinline__ Cplx node_val(const PairGeom& g, double y, double sq_ij) {
+  const double di = y - g.yi, dj = y - g.yj;
+  double ri, rj, ii, ij;
+  dist_inv(fma(di, di, g.xi * g.xi), ri, ii);
+  dist_inv(fma(dj, dj, g.xj * g.xj), rj, ij);
+  const double u = ii * ij;
+  const double amp = g.amp == XLMIMO_AMP_PNUSW ? g.beta0 * sq_ij * u * sqrt(u) : g.c_fs * u;
+  return cscale(phasor_turns_d((ri - rj) * g.inv_lambda), amp);
+}
+
 // f(y) e^{j phi(y)}, phi'(y), and the distances
 struct EndVals {
   Cplx g;
@@ -274,8 +302,9 @@ __device__ __forceinline__ int numeric_route(const PairGeom& g, int n, double d,
 __device__ Cplx numeric_share(const PairGeom& g, int n, double d, int route, int panels,
                               const double* __restrict__ gl, int n_gl, int t, int nthr) {
   Cplx acc = {0.0, 0.0};
+  const double sq_ij = sqrt(g.xi * g.xj);
   if (route == ROUTE_DIRECT) {
-    for (int m = t; m < n; m += nthr) acc = cadd(acc, end_vals(g, ((double)m - 0.5 * (double)(n - 1)) * d).g);
+    for (int m = t; m < n; m += nthr) acc = cadd(acc, node_val(g, ((double)m - 0.5 * (double)(n - 1)) * d, sq_ij));
     return acc;
   }
   const double L = 0.5 * (double)n * d;
@@ -295,8 +324,9 @@ __device__ Cplx numeric_share(const PairGeom& g, int n, double d, int route, int
       sincos(ta + (p + 0.5) * h, &sm, &cm);
     }
     const double c = cm * cd - sm * sd, s = sm * cd + cm * sd;  // cos, sin of the node angle
-    const double y = fma(xm, s / c, ym);
-    acc = cadd(acc, cscale(end_vals(g, y).g, wq / (c * c)));
+    const double ic = recip_nr2(c);
+    const double y = fma(xm * s, ic, ym);
+    acc = cadd(acc, cscale(node_val(g, y, sq_ij), wq * ic * ic));
     const double sn = sm * cs + cm * ss;
     cm = cm * cs - sm * ss;
     sm = sn;
