@@ -271,18 +271,46 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
 // K <= 16 without the mismatched scheme: every factorisation of a drop runs in
 // its own 16-lane group with the matrix in registers (lane i holds row i), so a
 // drop's ZF, nominal modified-ZF and per-SNR MMSE/CAP factorisations proceed in
-// parallel and no LDS or barrier is needed.  Matrices with K < 16 are padded
-// with an identity block: the Cholesky factor and the inverse's diagonal of the
-// leading K x K block are unchanged, operation by operation.  The arithmetic is
-// the generic kernel's in the same order.
+// parallel; rows and pivots move by DPP row broadcasts, with no LDS or barrier.
+// Matrices with K < 16 are padded with an identity block: the Cholesky factor
+// and the inverse's diagonal of the leading K x K block are unchanged, operation
+// by operation.  The arithmetic is the generic kernel's in the same order.
 //
 // Jobs of a drop, in order: [G (ZF)] [G~ (MZF)] then one per SNR when MMSE, CAP
 // or MRC is asked for (MRC needs no factorisation and rides on that job).
 constexpr int kSmallK = 16;
 
-__device__ __forceinline__ cplx shfl16(cplx v, int src) {
-  return {__shfl(v.x, src, kSmallK), __shfl(v.y, src, kSmallK)};
+// Lane `src` of each 16-lane row to the whole row: a DPP row broadcast (a VALU
+// move, no LDS round trip).  src is a constant once the callers' loops unroll.
+__device__ __forceinline__ int row_bcast(int v, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, v, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, v, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, v, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, v, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, v, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, v, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, v, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, v, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, v, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, v, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0x15F, 0xF, 0xF, false);
+  }
 }
+
+__device__ __forceinline__ double bcast16(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)row_bcast((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)row_bcast((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ cplx shfl16(cplx v, int src) { return {bcast16(v.x, src), bcast16(v.y, src)}; }
 
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
@@ -298,7 +326,7 @@ __device__ __forceinline__ bool chol_rows(cplx (&a)[kSmallK], int li, double& di
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < kSmallK; ++j) {
-    const double djj = __shfl(a[j].x, j, kSmallK);
+    const double djj = bcast16(a[j].x, j);
     ok = ok && (djj > 0.0) && isfinite(djj);
     const double l = sqrt(djj), il = 1.0 / l;
     if (li > j) a[j] = {a[j].x * il, a[j].y * il};
@@ -333,7 +361,7 @@ __device__ __forceinline__ double inv_diag_inplace(cplx (&a)[kSmallK], int li) {
     // reciprocals and multipliers would push the kernel to one wave per SIMD)
     cplx am = a[m];
     asm volatile("" : "+v"(am.x), "+v"(am.y) : "v"(s));
-    const double w0 = 1.0 / __shfl(am.x, m, kSmallK);     // 1 / L_mm
+    const double w0 = 1.0 / bcast16(am.x, m);             // 1 / L_mm
     // L_{li,m} for the rows below m, zero elsewhere: adding t * W_{m,k} = 0
     // leaves the other rows unchanged
     const cplx t = li > m ? am : cplx{0.0, 0.0};
