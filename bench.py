@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--mlp-train-drops", type=int, default=20000)
+    ap.add_argument("--mlp-train-drops", type=int, default=83334)   # 120 pairs per drop: 1.0e7 training pairs
     ap.add_argument("--mlp-train-steps", type=int, default=3000)
     ap.add_argument("--mlp-log-var-max", type=float, default=-11.0)
     ap.add_argument("--no-graph", action="store_true",

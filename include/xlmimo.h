@@ -237,7 +237,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N,
  *   delta_rho = sum_m c_m e^{j phi_m},  phi(y) = (2 pi / lambda)(r_i(y) - r_j(y)),
  * at y = the two end elements and the stationary point (phasors computed in
  * FP64), plus s = log sigma^2.  Network: XLMIMO_MLP_IN -> [Linear(width) +
- * SiLU] x depth -> Linear(XLMIMO_MLP_OUT); BF16 weights and activations on the
+ * GELU] x depth -> Linear(XLMIMO_MLP_OUT); BF16 weights and activations on the
  * matrix cores, FP32 accumulation; FP32 master weights and Adam state.
  * Parameters, flat FP32: per layer W (out x in, row-major) then b (out). */
 /* An MLP belongs to its context: destroy it before the context. */

@@ -5,7 +5,7 @@ the residual rho_exact - rho~ of the closed-form correlation (eq. (6) and its
 free-space analogue, eq. (23)) where stationary phase is inaccurate (small N,
 users near the aperture ends; the paper notes the modified ZF is worse before
 saturation, Sec. V-C).  Parity of the HIP kernels against this module is
-pinned by finite differences (gradients), by SiLU's closed-form values, by Adam on a
+pinned by finite differences (gradients), by the erf form of GELU, by Adam on a
 quadratic, and by the exact channel phases at the aperture ends (phasors).
 
 Pair inputs (user i, user j of one drop; x = perpendicular distance, y along the array):
@@ -26,7 +26,7 @@ Pair inputs (user i, user j of one drop; x = perpendicular distance, y along the
             all three are 0 for a pair the base closed form (GATED_QUAD) evaluates numerically
             (closedform.numeric_route: slow-phase pairs and broad stationary zones).
   target    delta = rho_exact_ij - rho~_ij (complex)
-Network: 6 -> [Linear(w) + SiLU] x depth -> Linear(7); SiLU(z) = z / (1 + e^{-z}).
+Network: 6 -> [Linear(w) + GELU] x depth -> Linear(7); GELU(z) = z (1 + erf(z / sqrt 2)) / 2.
 Output o: coefficients c_m = o[2m] + j o[2m+1] (m = top, bot, star) and s = o[6] = log sigma^2;
   prediction  p = sum_m c_m b_m   (c_top = c_bot = 1, c_spm = 0 is the analytic end correction)
   loss        mean over pairs of |delta - p|^2 e^{-s} + s        (Gaussian negative log-likelihood)
@@ -82,15 +82,12 @@ def init_params(rng, width=256, depth=4):
     return np.concatenate(parts)
 
 
-def silu(z):
-    """SiLU(z) = z sigma(z), sigma the logistic function."""
-    return z * special.expit(z)
+def gelu(z):
+    return 0.5 * z * (1.0 + special.erf(z / math.sqrt(2.0)))
 
 
-def silu_grad(z):
-    """d/dz z sigma(z) = sigma(z) (1 + z (1 - sigma(z)))."""
-    sg = special.expit(z)
-    return sg * (1.0 + z * (1.0 - sg))
+def gelu_grad(z):
+    return 0.5 * (1.0 + special.erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
 def pair_inputs(xp_i, y_i, xp_j, y_j, n, spacing, lam, cf_scale, amp_model=0, beta0=1.0):
@@ -142,7 +139,7 @@ def forward(params, x, width=256, depth=4):
     for li, (w, b) in enumerate(layers):
         z = a @ w.T + b
         cache.append((a, z))
-        a = silu(z) if li < len(layers) - 1 else z
+        a = gelu(z) if li < len(layers) - 1 else z
     return a, cache
 
 
@@ -180,7 +177,7 @@ def backward(params, cache, dout, width=256, depth=4):
     for li in range(len(layers) - 1, -1, -1):
         a, z = cache[li]
         if li < len(layers) - 1:
-            d = d * silu_grad(z)
+            d = d * gelu_grad(z)
         w, _ = layers[li]
         grads[li] = (d.T @ a, d.sum(axis=0))
         d = d @ w

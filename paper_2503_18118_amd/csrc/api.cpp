@@ -410,7 +410,7 @@ constexpr int kFeatPitch = 8;   // features per pair (6 used)
 constexpr int kAuxPitch = 8;    // phasors (6), closed-form scale, pad
 constexpr int kOut = 7;
 
-// Activation layout for a batch of n pairs: per hidden layer, the SiLU output
+// Activation layout for a batch of n pairs: per hidden layer, the GELU output
 // (bf16, next layer's input) and the pre-activation (fp32); the network output;
 // two bf16 gradient buffers and the output gradient.
 struct Acts {

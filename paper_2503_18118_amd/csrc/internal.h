@@ -63,7 +63,7 @@ struct GemmArgs {
   int64_t b_k, b_n;
   const float* bias;  // [N]: FWD_HIDDEN, FWD_OUT
   float* Z;           // FWD_HIDDEN: pre-activations out (may be null); BWD_DX: pre-activations in
-  __bf16* out_bf;     // FWD_HIDDEN: SiLU(z); BWD_DX: dZ of the previous layer
+  __bf16* out_bf;     // FWD_HIDDEN: GELU(z); BWD_DX: dZ of the previous layer
   float* out_f;       // FWD_OUT, STORE_F32 (split-K: [splits][M][ldo] partials)
   int64_t ldo;
   int k_chunk;        // STORE_F32 split-K: K range per grid.z slice (0 = whole K)

@@ -8,7 +8,7 @@
 //             D = 1 - e^{-+ j phi' d} (geometric series of the locally linear phase),
 //             regularised by the Fresnel scale eps^2 = d^2 |phi''| / (2 pi);
 //             b_spm = e^{j phi(y*)} at the stationary point; phi(y) = (2 pi/lambda)(r_i(y) - r_j(y))
-//   network   6 -> [Linear(w) + SiLU] x depth -> Linear(7)
+//   network   6 -> [Linear(w) + GELU] x depth -> Linear(7)
 //   output    coefficients c_m (3 complex) and s = log sigma^2;
 //             delta_rho = sum_m c_m b_m;  G_ij += delta_rho sqrt(G~_ii G~_jj)
 //   loss      mean |target - delta_rho|^2 e^{-s} + s   (Gaussian negative log-likelihood)
@@ -18,7 +18,7 @@
 // per 256-thread workgroup (each wave 32 x 32 = 2 x 2 MFMA blocks), K in steps
 // of 32 staged through LDS with k contiguous, operands with arbitrary strides
 // (so the same kernel serves X W^T, dZ W and dZ^T X).  Epilogues fuse
-// bias + SiLU (forward), the last-layer bias, and SiLU' (backward).
+// bias + GELU (forward), the last-layer bias, and GELU' (backward).
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -36,15 +36,22 @@ constexpr int TM = 64, TN = 64, TK = 32;
 constexpr int LDS_K = TK + 8;  // row pitch in bf16 (80 bytes: 16-byte aligned operand reads)
 constexpr double kPiD = 3.14159265358979323846264338327950288;
 
-// SiLU(z) = z sigma(z), sigma(z) = 1 / (1 + e^{-z}): one exp2 and one reciprocal
-// (e^{-z} overflows to inf for z << 0, where the reciprocal gives the 0 it should).
-__device__ __forceinline__ float sigmoid(float z) {
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+// erf by the rational-exponential approximation 7.1.26 of Abramowitz and Stegun
+// (Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2},
+// t = 1 / (1 + p x), x >= 0, odd extension; |error| <= 1.5e-7, far below the
+// BF16 rounding of the activations it feeds.  One reciprocal and one exp2.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                              0.254829592f);
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.44269504088896341f);
+  return copysignf(fmaf(-poly, e, 1.0f), x);
 }
-__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
-__device__ __forceinline__ float silu_grad(float z) {
-  const float sg = sigmoid(z);
-  return sg * fmaf(z, 1.0f - sg, 1.0f);
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+         z * __builtin_amdgcn_exp2f(-0.5f * z * z * 1.44269504088896341f) * 0.39894228040143268f;
 }
 
 template <int EPI>
@@ -108,11 +115,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         if constexpr (EPI == EPI_FWD_HIDDEN) {
           const float z = v + g.bias[col];
           if (g.Z) g.Z[o] = z;
-          g.out_bf[o] = (__bf16)silu(z);
+          g.out_bf[o] = (__bf16)gelu(z);
         } else if constexpr (EPI == EPI_FWD_OUT) {
           g.out_f[o] = v + g.bias[col];
         } else if constexpr (EPI == EPI_BWD_DX) {
-          g.out_bf[o] = (__bf16)(v * silu_grad(g.Z[o]));
+          g.out_bf[o] = (__bf16)(v * gelu_grad(g.Z[o]));
         } else {
           g.out_f[(int64_t)blockIdx.z * g.M * g.ldo + o] = v;
         }
@@ -519,10 +526,10 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
       for (int j = 0; j < 4; ++j) {
         typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
         bf16x4 v;
-        v[0] = (__bf16)silu(acc[i][j][0] + b0);
-        v[1] = (__bf16)silu(acc[i][j][1] + b1);
-        v[2] = (__bf16)silu(acc[i][j][2] + b2);
-        v[3] = (__bf16)silu(acc[i][j][3] + b3);
+        v[0] = (__bf16)gelu(acc[i][j][0] + b0);
+        v[1] = (__bf16)gelu(acc[i][j][1] + b1);
+        v[2] = (__bf16)gelu(acc[i][j][2] + b2);
+        v[3] = (__bf16)gelu(acc[i][j][3] + b3);
         *reinterpret_cast<bf16x4*>(&act[(j * 16 + li) * P + f0]) = v;
       }
     }

@@ -1,4 +1,4 @@
-"""Pins of the FP64 MLP reference: finite-difference gradients, SiLU's closed-form values,
+"""Pins of the FP64 MLP reference: finite-difference gradients, GELU's erf form,
 Adam on a quadratic, and the phasor basis against the exact channel phases."""
 import math
 
@@ -18,19 +18,13 @@ def _batch(rng, n):
     return x, ph, t
 
 
-def test_silu_matches_closed_form_values():
-    # SiLU(z) = z / (1 + e^-z): SiLU(1) = e / (1 + e) = 0.731058578..., SiLU(-1) = -1 / (1 + e),
-    # SiLU(0) = 0 with slope 1/2, SiLU(z) -> z as z -> inf and -> 0 as z -> -inf
-    e = math.e
-    assert M.silu(np.array([1.0]))[0] == pytest.approx(e / (1.0 + e), rel=1e-15)
-    assert M.silu(np.array([-1.0]))[0] == pytest.approx(-1.0 / (1.0 + e), rel=1e-15)
-    assert M.silu(np.array([1.0]))[0] == pytest.approx(0.7310585786300049, rel=1e-15)
-    assert M.silu(np.array([0.0]))[0] == 0.0 and M.silu_grad(np.array([0.0]))[0] == 0.5
-    assert M.silu(np.array([40.0]))[0] == pytest.approx(40.0, rel=1e-15)
-    assert abs(M.silu(np.array([-40.0]))[0]) < 1e-15
-    z = np.linspace(-6, 6, 61)
+def test_gelu_matches_closed_form_values():
+    # GELU(z) = z Phi(z): Phi(1) = 0.841344746..., Phi(-1) = 0.158655253...
+    assert M.gelu(np.array([1.0]))[0] == pytest.approx(0.8413447460685429, rel=1e-14)
+    assert M.gelu(np.array([-1.0]))[0] == pytest.approx(-0.15865525393145707, rel=1e-14)
+    z = np.linspace(-4, 4, 41)
     h = 1e-6
-    assert np.allclose(M.silu_grad(z), (M.silu(z + h) - M.silu(z - h)) / (2 * h), rtol=1e-8, atol=1e-10)
+    assert np.allclose(M.gelu_grad(z), (M.gelu(z + h) - M.gelu(z - h)) / (2 * h), rtol=1e-8, atol=1e-10)
 
 
 @pytest.mark.parametrize("width,depth", [(8, 2), (16, 4)])
