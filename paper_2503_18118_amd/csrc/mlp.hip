@@ -36,22 +36,31 @@ constexpr int TM = 64, TN = 64, TK = 32;
 constexpr int LDS_K = TK + 8;  // row pitch in bf16 (80 bytes: 16-byte aligned operand reads)
 constexpr double kPiD = 3.14159265358979323846264338327950288;
 
-// erf by the rational-exponential approximation 7.1.26 of Abramowitz and Stegun
-// (Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2},
-// t = 1 / (1 + p x), x >= 0, odd extension; |error| <= 1.5e-7, far below the
-// BF16 rounding of the activations it feeds.  One reciprocal and one exp2.
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
-                              0.254829592f);
-  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.44269504088896341f);
-  return copysignf(fmaf(-poly, e, 1.0f), x);
+// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, with erfc(x) = t P(t) e^{-x^2},
+// t = 1 / (1 + p x), x >= 0: the rational-exponential approximation 7.1.26 of
+// Abramowitz and Stegun (Hastings), |error| <= 1.5e-7 in erf, far below the BF16
+// rounding of the activations it feeds.  Written for Phi directly:
+//   Q = erfc(|z| / sqrt 2) / 2 = t P(t) e^{-z^2/2} / 2,  Phi = 1 - Q (z >= 0), Q (z < 0)
+// with p / sqrt 2 and the halved coefficients folded in: one reciprocal, one exp2.
+// Then z Phi(z) = max(z, 0) - |z| Q for either sign of z.
+struct GeluParts {
+  float q;     // erfc(|z| / sqrt 2) / 2
+  float e;     // e^{-z^2/2}
+};
+__device__ __forceinline__ GeluParts gelu_parts(float z) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.2316418882663604f, fabsf(z), 1.0f));
+  const float p = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 0.5307027145f, -0.7265760135f), 0.7107068705f), -0.142248368f),
+                           0.127414796f);
+  GeluParts g;
+  g.e = __builtin_amdgcn_exp2f(z * z * -0.7213475204444817f);
+  g.q = p * g.e;
+  return g;
 }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return fmaf(-fabsf(z), gelu_parts(z).q, fmaxf(z, 0.0f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
-         z * __builtin_amdgcn_exp2f(-0.5f * z * z * 1.44269504088896341f) * 0.39894228040143268f;
+  const GeluParts g = gelu_parts(z);
+  const float phi = z >= 0.0f ? 1.0f - g.q : g.q;
+  return fmaf(z * 0.3989422804014327f, g.e, phi);   // Phi(z) + z phi(z)
 }
 
 template <int EPI>
