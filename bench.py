@@ -242,6 +242,23 @@ def main():
     fp32c_ref = {"entries_per_s": entries_per_form / (e0.elapsed_time(e1) * 1e-3), "ms": e0.elapsed_time(e1),
                  "ergodic_rel_diff_vs_fp32h": float(((erg_f - erg_e).abs() / erg_e.abs()).max())}
 
+    # the rate kernel alone on one resident Gram (10^4 drops, N = 4096): ZF + MMSE at every SNR
+    log("sum-rate kernel throughput")
+    g_rates = ctx.gram_exact(arr.with_n(4096), batch, X.FP32H, stream=stream)
+    times = []
+    for r in range(23):
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        ctx.sumrate(batch, g_rates, rho, schemes, stream=stream)
+        a1.record(stream)
+        a1.synchronize()
+        if r >= 3:
+            times.append(a0.elapsed_time(a1))
+    evals_per_sweep = n_drops * len(n_list) * int(rho.shape[0])   # (drop, N, SNR) with ZF + MMSE each
+    rates_kernel = {"evals": n_drops * int(rho.shape[0]), "ms_median": float(np.median(times)),
+                    "sumrate_evals_per_s": n_drops * int(rho.shape[0]) / (float(np.median(times)) * 1e-3),
+                    "repeats": len(times)}
+
     value = 4 * entries_per_form / (ms_per_step * 1e-3)
     evals = n_drops * sum(n_list) * k
     pair_macs = n_drops * sum(n_list) * k * (k + 1) // 2
@@ -265,16 +282,21 @@ def main():
                                   "learned-corrected closed form",
                       "n_list": n_list, "drops": n_drops, "users": k, "snr_db": list(meta["snr_db"])},
            "forms": {"exact_fp32h": {"entries_per_s": entries_per_form / (t_exact * 1e-3 / args.steps),
+                                     "sumrate_evals_per_s": evals_per_sweep / (t_exact * 1e-3 / args.steps),
                                      "ms": t_exact / args.steps},
                      "exact_fp32c_untimed": fp32c_ref,
                      "closedform_gated": {"entries_per_s": entries_per_form / (t_cf * 1e-3 / args.steps),
+                                          "sumrate_evals_per_s": evals_per_sweep / (t_cf * 1e-3 / args.steps),
                                           "ms": t_cf / args.steps},
                      "closedform_uniform": {"entries_per_s": entries_per_form / (t_uni * 1e-3 / args.steps),
+                                            "sumrate_evals_per_s": evals_per_sweep / (t_uni * 1e-3 / args.steps),
                                             "ms": t_uni / args.steps},
                      "mlp_corrected": {"entries_per_s": entries_per_form / (t_mlp * 1e-3 / args.steps),
+                                       "sumrate_evals_per_s": evals_per_sweep / (t_mlp * 1e-3 / args.steps),
                                        "ms": t_mlp / args.steps, "log_var_max": lvmax,
                                        "fallback_fraction_by_n": [float(x) for x in
                                                                   (st_m & X.ST_FELL_BACK).ne(0).float().mean(dim=1).cpu()]}},
+           "rates_kernel": rates_kernel,
            "mlp": mlp_info,
            "batching": batching,
            "roofline": roofline}
