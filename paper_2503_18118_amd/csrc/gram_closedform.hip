@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __r
         s_part[2 * threadIdx.x + 1] = acc.im;
       }
       __syncthreads();
-      if (threadIdx.x < nd) {
+      if ((int)threadIdx.x < nd) {
         int pp, qq;
         pair_of_k(s_dl[threadIdx.x], pp, qq);
         Cplx v = {0.0, 0.0};

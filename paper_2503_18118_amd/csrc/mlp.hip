@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_mlp_head(int64_t n, const float* __rest
   s_sum[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+    if ((int)threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = s_sum[0];
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
   s_sum[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+    if ((int)threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = s_sum[0] / (double)n;

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
   const int group = threadIdx.x / kSmallK, li = threadIdx.x % kSmallK;
   const int slot = group / jobs, job = group % jobs;
   const int64_t d = (int64_t)blockIdx.x * drops_per_block + slot;
-  if (threadIdx.x < drops_per_block) s_st[threadIdx.x] = 0;
+  if ((int)threadIdx.x < drops_per_block) s_st[threadIdx.x] = 0;
   __syncthreads();
   const bool zf = schemes & XLMIMO_ZF, mzf = schemes & XLMIMO_MZF;
   const bool mmse = schemes & XLMIMO_MMSE, cap = schemes & XLMIMO_CAP, mrc = schemes & XLMIMO_MRC;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
     if (st != 0 && li == 0) atomicOr(&s_st[slot], st);   // bitwise OR: the order does not matter
   }
   __syncthreads();
-  if (status != nullptr && threadIdx.x < drops_per_block) {
+  if (status != nullptr && (int)threadIdx.x < drops_per_block) {
     const int64_t dd = (int64_t)blockIdx.x * drops_per_block + threadIdx.x;
     if (dd < n_drops) status[dd] = s_st[threadIdx.x];
   }
