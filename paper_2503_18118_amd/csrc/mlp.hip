@@ -481,38 +481,40 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
   }
   __syncthreads();
 
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  // The weights of layer l's first two k-steps are in flight before its k-loop starts (for l > 0 they
+  // are loaded while layer l - 1 finishes); inside the loop they run two k-steps ahead.
+  auto load_w = [&](int l, int kk, bf16x8 (&wf)[FB]) {
+    const __bf16* Wl = wbf + offs[2 * l];
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+      const int f = wave * (W / 4) + i * 16 + li;
+      if (l == 0) {
+        bf16x8 v = zero8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (kk + q < XLMIMO_MLP_IN) v[q] = Wl[f * XLMIMO_MLP_IN + kk + q];
+        wf[i] = v;
+      } else {
+        wf[i] = *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)f * W + kk]);
+      }
+    }
+  };
+  bf16x8 wcur[FB], wn1[FB], wn2[FB];
+#pragma unroll
+  for (int i = 0; i < FB; ++i) wn1[i] = wn2[i] = zero8;   // layer 0 has a single k-step
+  load_w(0, 8 * kg, wcur);
   for (int l = 0; l < depth; ++l) {  // hidden layers
     const int K = (l == 0) ? 32 : W;
-    const int in = (l == 0) ? XLMIMO_MLP_IN : W;
-    const __bf16* Wl = wbf + offs[2 * l];
     const float* bl = master + offs[2 * l + 1];
     floatx4 acc[FB][4];
 #pragma unroll
     for (int i = 0; i < FB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    auto load_w = [&](int kk, bf16x8 (&wf)[FB]) {
-#pragma unroll
-      for (int i = 0; i < FB; ++i) {
-        const int f = wave * (W / 4) + i * 16 + li;
-        if (l == 0) {
-          bf16x8 v = zero8;
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (kk + q < in) v[q] = Wl[f * in + kk + q];
-          wf[i] = v;
-        } else {
-          wf[i] = *reinterpret_cast<const bf16x8*>(&Wl[(int64_t)f * W + kk]);
-        }
-      }
-    };
-    // weights two k-steps ahead: steps k and k + 32 are in flight while step k - 32 computes
-    bf16x8 wcur[FB], wn1[FB], wn2[FB];
-    load_w(8 * kg, wcur);
-    if (32 < K) load_w(32 + 8 * kg, wn1);
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kk = k0 + 8 * kg;
-      if (k0 + 64 < K) load_w(kk + 64, wn2);
+      if (k0 + 64 < K) load_w(l, kk + 64, wn2);
       bf16x8 af[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
@@ -526,21 +528,30 @@ __global__ __launch_bounds__(256) void k_mlp_fused_forward(int64_t n, int depth,
         wn1[i] = wn2[i];
       }
     }
-    __syncthreads();   // every wave has read this layer's input
+    if (l + 1 < depth) {   // the next layer's first two k-steps, in flight during this epilogue
+      load_w(l + 1, 8 * kg, wcur);
+      load_w(l + 1, 32 + 8 * kg, wn1);
+    }
+    // bias + GELU into packed BF16 before the barrier; only the stores wait for the other waves
+    bf16x4 outv[FB][4];
 #pragma unroll
     for (int i = 0; i < FB; ++i) {
       const int f0 = wave * (W / 4) + i * 16 + 4 * kg;
       const float b0 = bl[f0], b1 = bl[f0 + 1], b2 = bl[f0 + 2], b3 = bl[f0 + 3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-        bf16x4 v;
-        v[0] = (__bf16)gelu(acc[i][j][0] + b0);
-        v[1] = (__bf16)gelu(acc[i][j][1] + b1);
-        v[2] = (__bf16)gelu(acc[i][j][2] + b2);
-        v[3] = (__bf16)gelu(acc[i][j][3] + b3);
-        *reinterpret_cast<bf16x4*>(&act[(j * 16 + li) * P + f0]) = v;
+        outv[i][j][0] = (__bf16)gelu(acc[i][j][0] + b0);
+        outv[i][j][1] = (__bf16)gelu(acc[i][j][1] + b1);
+        outv[i][j][2] = (__bf16)gelu(acc[i][j][2] + b2);
+        outv[i][j][3] = (__bf16)gelu(acc[i][j][3] + b3);
       }
+    }
+    __syncthreads();   // every wave has read this layer's input
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+      const int f0 = wave * (W / 4) + i * 16 + 4 * kg;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) *reinterpret_cast<bf16x4*>(&act[(j * 16 + li) * P + f0]) = outv[i][j];
     }
     __syncthreads();
   }

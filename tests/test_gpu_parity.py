@@ -240,6 +240,25 @@ def test_closedform_direct_sum_paths(X, ctx, amp, variant):
     assert torch.all(status == 0)
 
 
+@pytest.mark.parametrize("variant", [2, 3])
+def test_closedform_pair_kernel_with_single_user_drops(X, ctx, variant):
+    # The pair kernel finds each pair's drop by bisection of the drops' pair offsets; single-user
+    # drops have no pairs and repeat the next drop's offset (first, middle and last positions here).
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    ks = [1, 3, 1, 1, 5, 2, 1, 16, 1]
+    ns = [256, 1024, 300, 4096, 700, 65536, 512, 4096, 1000]
+    drops = _custom_drops(ns, ks, seed=41, r=(0.8, 40.0))
+    b = X.Batch(drops)
+    out, status = ctx.gram_closedform(arr, b, variant)
+    torch.cuda.synchronize()
+    g = b.split(out)
+    assert torch.all(status == 0)
+    for d in range(drops.n_drops):
+        ref = ocf.gram_closedform(arr, drops.users_of(d), int(drops.n_elems[d]), variant)
+        scale = np.sqrt(np.outer(np.abs(np.diag(ref)), np.abs(np.diag(ref))))
+        assert np.max(np.abs(g[d] - ref) / scale) < (1e-8 if variant == 2 else 1e-10), d
+
+
 def test_closedform_uniform_accuracy_on_sweep_drops(X, ctx):
     # the uniform form against the exact FP64 Gram on the sweep workload's user law (5-50 m)
     arr, drops, _ = W.sweep(64)
