@@ -102,7 +102,9 @@ extern "C" {
 /* Per-drop status bits. */
 #define XLMIMO_ST_G_NOT_PD      1   /* Cholesky of the ZF Gram failed: ZF-type rates are NaN */
 #define XLMIMO_ST_MMSE_NOT_PD   2   /* Cholesky of I + A failed: MMSE/CAP are NaN */
-#define XLMIMO_ST_FILTER_NOT_PD 4   /* Cholesky of the filter Gram failed: MZF rates are NaN */
+#define XLMIMO_ST_FILTER_NOT_PD 4   /* Cholesky of the filter Gram failed: XLMIMO_MZF is NaN;
+                                       XLMIMO_MZF_MISM then inverts G~ by Gauss-Jordan with partial
+                                       pivoting (NaN only if G~ is singular) */
 #define XLMIMO_ST_BAD_INPUT     8   /* non-finite position or a user on the array line/plane */
 #define XLMIMO_ST_CF_DEGENERATE 16  /* closed form hit |x_i| == |x_j| or coincident users (entry set to 0) */
 #define XLMIMO_ST_FELL_BACK     32  /* learned correction was uncertain: the drop's Gram was computed exactly */
@@ -213,8 +215,11 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
  *             sat_out[2] = (E[y_up] - E[y_down]) / spacing  (antennas);
  *   empirical sat_out[3 + s * n_sch + c] = first N, log-interpolated, with
  *             ergodic(N) / ergodic(N_max) >= 1 - eps_sat, for SNR s, scheme c.
- * For the closed-form forms, XLMIMO_MZF_MISM also computes the exact FP32H
- * Gram as the true channel; every other scheme uses the chosen form's Gram.
+ * In a closed-form sweep the schemes evaluate the closed-form Gram, except
+ * when XLMIMO_MZF_MISM is asked for: then the exact FP64 Gram is computed as
+ * the true channel and ZF, MMSE, MRC, CAP and the mismatched modified ZF use
+ * it, while XLMIMO_MZF (nominal) keeps the closed form (one pass yields the
+ * paper's comparison of Sec. V-C).
  *   form         XLMIMO_FORM_*; XLMIMO_FORM_CF_GATED_MLP (closed form XLMIMO_CF_GATED_QUAD +
  *                learned residual) needs mlp and log_var_max
  *                (see xlmimo_gram_closedform_mlp), otherwise mlp may be NULL

@@ -89,6 +89,64 @@ __device__ double inverse_diag(cplx* A, double* wd, int K, int ld, int lane) {
   return s;
 }
 
+// Q = A^-1 by Gauss-Jordan elimination with partial pivoting (A is overwritten),
+// lane i owning row i.  The pivot is the largest |A_ic|, i >= c, by a fixed-order
+// wave reduction (ties to the lower row), so results are repeatable.  Returns
+// false (uniformly) for a zero or non-finite pivot.  Used for the mismatched
+// modified ZF when the filter Gram is not positive definite: the filter
+// G~^-1 H^H needs G~ invertible, not definite.
+__device__ bool gauss_jordan_inverse(cplx* A, cplx* Q, int K, int ld, int lane) {
+  if (lane < K)
+    for (int j = 0; j < K; ++j) Q[lane * ld + j] = {lane == j ? 1.0 : 0.0, 0.0};
+  __syncthreads();
+  for (int c = 0; c < K; ++c) {
+    double mag = -1.0;
+    int idx = lane;
+    if (lane >= c && lane < K) {
+      const cplx v = A[lane * ld + c];
+      mag = v.x * v.x + v.y * v.y;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double om = __shfl_xor(mag, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (om > mag || (om == mag && oi < idx)) {
+        mag = om;
+        idx = oi;
+      }
+    }
+    if (!(mag > 0.0) || !isfinite(mag)) return false;  // uniform: every lane holds the same maximum
+    const int pr = idx;
+    if (pr != c && lane < K) {
+      const cplx ta = A[c * ld + lane], tq = Q[c * ld + lane];
+      A[c * ld + lane] = A[pr * ld + lane];
+      Q[c * ld + lane] = Q[pr * ld + lane];
+      A[pr * ld + lane] = ta;
+      Q[pr * ld + lane] = tq;
+    }
+    __syncthreads();
+    const cplx pv = A[c * ld + c];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const cplx ip = {pv.x / den, -pv.y / den};
+    __syncthreads();  // every lane has read the pivot before row c changes
+    if (lane < K) {
+      A[c * ld + lane] = cmul(A[c * ld + lane], ip);
+      Q[c * ld + lane] = cmul(Q[c * ld + lane], ip);
+    }
+    __syncthreads();
+    if (lane < K && lane != c) {
+      const cplx f = A[lane * ld + c];
+      for (int j = 0; j < K; ++j) {
+        const cplx ta = cmul(f, A[c * ld + j]), tq = cmul(f, Q[c * ld + j]);
+        A[lane * ld + j] = {A[lane * ld + j].x - ta.x, A[lane * ld + j].y - ta.y};
+        Q[lane * ld + j] = {Q[lane * ld + j].x - tq.x, Q[lane * ld + j].y - tq.y};
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 __device__ __forceinline__ cplx gload(const double* g, int64_t off, int K, int i, int j) {
   const double* p = g + 2 * (off + (int64_t)i * K + j);
   return {p[0], p[1]};
@@ -135,6 +193,15 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
     } else {
       st |= XLMIMO_ST_FILTER_NOT_PD;
     }
+    bool have_q = ok;
+    if (!ok && mism) {
+      // an indefinite filter Gram is still a valid filter: Q = G~^-1 by Gauss-Jordan
+      __syncthreads();
+      if (lane < K)
+        for (int j = 0; j < K; ++j) A[lane * ld + j] = gload(filter, go, K, lane, j);
+      __syncthreads();
+      have_q = gauss_jordan_inverse(A, Q, K, ld, lane);
+    }
     if (ok && mism) {
       // Q = G~^-1 = W^H W, row `lane`: Q_kj = sum_{i >= max(k,j)} conj(W_ik) W_ij
       if (lane < K) {
@@ -152,6 +219,8 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
         }
       }
       __syncthreads();
+    }
+    if (have_q && mism) {
       // B = Q G (true Gram); |B_kj|^2 kept in A's real parts; noise_k = sum_j B_kj Q_jk
       if (lane < K) {
         double nz = 0.0;

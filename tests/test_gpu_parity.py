@@ -411,6 +411,47 @@ def test_rates_small_k_status_per_drop(X, ctx):
         assert r[d, 0, 0] == pytest.approx(ref, rel=1e-12)
 
 
+@pytest.mark.parametrize("kset", [[3, 10, 16], [33, 5]])
+def test_rates_mismatched_with_indefinite_filter(X, ctx, kset):
+    # An indefinite (invertible) filter Gram, as the printed closed form gives at small N: the
+    # mismatched modified ZF applies G~^-1 H^H all the same (Gauss-Jordan inverse on the GPU, a
+    # general inverse in the oracle); the nominal modified ZF is NaN and the drop is flagged (the
+    # Cholesky of G~ fails).  ZF and MMSE on the true Gram are unaffected.
+    rng = np.random.default_rng(7 + len(kset))
+    ns = [max(4 * k, 300) for k in kset]
+    drops = _custom_drops(ns, kset, seed=int(sum(kset)) + 3, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    gh = b.split(g)
+    filt = []
+    for m in gh:
+        v = rng.normal(size=len(m)) + 1j * rng.normal(size=len(m))
+        v /= np.linalg.norm(v)
+        f = m - 3.0 * np.linalg.norm(m, 2) * np.outer(v, v.conj())   # one negative eigenvalue
+        assert np.linalg.eigvalsh(f).min() < 0
+        filt.append(f)
+    gf = torch.as_tensor(np.concatenate([f.ravel() for f in filt]).view(np.float64), device="cuda")
+    rho = torch.as_tensor(rng.uniform(0.5, 2.0, (2, b.total_users)) * 1e3
+                          / np.mean([np.real(np.diag(m)).mean() for m in gh]), device="cuda")
+    schemes = X.ZF | X.MMSE | X.MZF | X.MZF_MISM
+    rates, status = ctx.sumrate(b, g, rho, schemes, gram_filter=gf)
+    torch.cuda.synchronize()
+    r = rates.cpu().numpy()
+    st = status.cpu().numpy()
+    rh = rho.cpu().numpy()
+    assert np.all(st & X.ST_FILTER_NOT_PD) and not np.any(st & (X.ST_G_NOT_PD | X.ST_MMSE_NOT_PD))
+    for d in range(drops.n_drops):
+        for s in range(2):
+            rk = rh[s, drops.user_off[d]:drops.user_off[d + 1]]
+            ref = orates.rates(gh[d], rk, orates.SCHEME_ZF | orates.SCHEME_MMSE | orates.SCHEME_MZF_MISMATCH,
+                               g_filter=filt[d])
+            assert r[d, s, 0] == pytest.approx(ref[orates.SCHEME_ZF], rel=1e-9)
+            assert r[d, s, 1] == pytest.approx(ref[orates.SCHEME_MMSE], rel=1e-9)
+            assert math.isnan(r[d, s, 2])
+            assert r[d, s, 3] == pytest.approx(ref[orates.SCHEME_MZF_MISMATCH], rel=1e-8), (d, s)
+
+
 def test_rates_not_pd_flagged(X, ctx):
     k = 3
     m = np.ones((k, k), np.complex128)   # rank one: not positive definite
