@@ -1044,7 +1044,9 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
       } else if ((rc = closedform_impl(c, a, b, &nn, variant, g, nullptr, s))) {
         return rc;
       }
-      if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP32H, g2, s))) return rc;
+      // the true channel of the mismatched scheme: FP64 (G~^-1 G amplifies the true Gram's error by
+      // the condition number when the filter is accurate)
+      if (need_exact_true && (rc = gram_exact_impl(c, a, b, &nn, XLMIMO_FP64, g2, s))) return rc;
     }
     if ((rc = get_plan(c, a, b, &nn, &p))) return rc;
     const double* gtrue = need_exact_true ? g2 : g;

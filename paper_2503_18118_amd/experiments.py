@@ -1,0 +1,159 @@
+"""The paper's numerical experiments (Sec. IV-C, Fig. 3; Sec. V-C, Fig. 4) on the GPU path.
+
+Both run through the library's capacity sweep (exact Gram, closed forms, FP64
+rates, ergodic means and the saturation point); nothing here computes.
+
+* ``fig3``: normalised capacity C(N) / C(N_max) of the Sec. IV scene (100 GHz
+  PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m, t = 0.9) at 0 dB and 200 dB,
+  beside the analytic saturation span E[y_up] - E[y_down] of eqs. (15)-(16).
+  The paper uses K = 100 users; the library's drops hold at most 64, so the
+  scene is run with K = 64 (the saturation span depends on the users' extreme
+  coordinates, which K = 64 already samples closely).
+* ``fig4``: ergodic sum-rates of the Sec. V scene (x ~ U(1,2) m, K = 10, received
+  SNR limit 33 dB for one user at (1.5 m, 0)) for ZF, MMSE, MRC and the capacity
+  on the exact Gram, and the modified ZF of eqs. (22)-(23): nominal (ZF formula on
+  the closed-form Gram) and as the paper scores it (the closed-form filter
+  applied to the true channel).  The closed form is eq. (6) as printed (variant
+  PAPER); the uniform closed form (UNIFORM) is run beside it.
+
+``python -m paper_2503_18118_amd.experiments [fig3|fig4] [--drops D] [--json PATH]``
+prints a table and optionally writes the numbers as JSON.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import torch
+
+from . import xlmimo as X
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if os.path.dirname(HERE) not in sys.path:
+    sys.path.insert(0, os.path.dirname(HERE))
+import workloads as W  # noqa: E402  (seeded input generators)
+
+# 64 ... 131072 antennas.  Below 64 the Sec. V scene's ten users give Grams with condition numbers up
+# to 1e12 (N = 32) and 1e17 (N = 16): ZF is then ill-posed even in FP64.
+FIG_N = [2 ** e for e in range(6, 18)]
+FIG3_N = [2 ** e for e in range(8, 18)]          # 256 ... 131072 (4 K and up, K = 64)
+
+
+def _timed_sweep(ctx, arr, n_list, batch, form, rho, schemes, t_sat=0.9, eps_sat=0.05):
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    erg, sat, st = ctx.capacity_sweep(arr, n_list, batch, form, rho, schemes, t_sat, eps_sat)
+    e1.record(s)
+    e1.synchronize()
+    return erg.cpu().numpy(), sat.cpu().numpy(), st.cpu().numpy(), e0.elapsed_time(e1)
+
+
+def fig3(ctx, n_drops: int = 200, n_list=FIG3_N, k: int = 64, snr_db=(0.0, 200.0), t: float = 0.9,
+         eps: float = 0.05) -> dict:
+    """Normalised capacity of the Sec. IV scene on the exact FP64 Gram (K = 64, see the module notes).
+
+    At 200 dB, log2 det(I + rho G) weighs G's smallest eigenvalues by rho ~ 1e20, so the Gram is
+    taken in FP64 and N starts at 4 K (N near K leaves G rank-deficient to rounding).
+    """
+    arr = W.ula(int(n_list[-1]), W.LAMBDA_100GHZ, W.AMP_PNUSW)
+    drops = W.rect_drops(W.rng_for(10), n_drops, k, int(n_list[-1]), (1.0, 10.0), (-7.5, 7.5))
+    b = X.Batch(drops)
+    rho = X.rho_for_snr(arr, snr_db, 5.5, b.total_users)       # reference user at the mean x
+    erg, sat, st, ms = _timed_sweep(ctx, arr, n_list, b, X.FORM_EXACT_FP64, rho, X.CAP, t, eps)
+    cap = erg[:, :, 0]
+    return {"scene": "Sec. IV: 100 GHz PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m, t = 0.9",
+            "users": k, "drops": n_drops, "n_list": [int(n) for n in n_list], "snr_db": list(snr_db),
+            "capacity": cap.tolist(), "normalised_capacity": (cap / cap[-1]).tolist(),
+            "e_y_up": float(sat[0]), "e_y_down": float(sat[1]), "analytic_saturation_n": float(sat[2]),
+            "empirical_saturation_n": [float(sat[3 + i]) for i in range(len(snr_db))], "eps": eps,
+            "flagged_drops": int((st != 0).sum()), "gpu_ms": ms}
+
+
+def fig4(ctx, n_drops: int = 200, n_list=FIG_N, rx_snr_db: float = 33.0, forms=("PAPER", "UNIFORM"),
+         t: float = 0.9, eps: float = 0.05) -> dict:
+    """Ergodic sum-rates of the Sec. V scene per scheme.
+
+    ZF, MMSE, MRC and the capacity come from the exact FP64 Gram: at small N the ten users'
+    Gram is ill-conditioned and ZF amplifies the FP32 Gram's rounding.  The modified ZF
+    (nominal and mismatched) comes from one closed-form sweep per variant, whose true channel for
+    the mismatched scheme is the exact FP64 Gram (G~^-1 G amplifies its error by the condition
+    number when the filter is accurate).
+    """
+    arr = W.ula(int(n_list[-1]), W.LAMBDA_100GHZ, W.AMP_PNUSW)
+    drops = W.rect_drops(W.rng_for(11), n_drops, 10, int(n_list[-1]), (1.0, 2.0), (-7.5, 7.5))
+    b = X.Batch(drops)
+    rho = X.rho_for_snr(arr, [rx_snr_db], 1.5, b.total_users)  # SNR limit of one user at (1.5 m, 0)
+    exact_schemes = (("ZF", X.ZF), ("MMSE", X.MMSE), ("MRC", X.MRC), ("CAP", X.CAP))
+    cf_schemes = (("MZF", X.MZF), ("MZF_MISM", X.MZF_MISM))
+    erg, sat, st, ms = _timed_sweep(ctx, arr, n_list, b, X.FORM_EXACT_FP64, rho,
+                                    X.ZF | X.MMSE | X.MRC | X.CAP, t, eps)
+    out = {"scene": "Sec. V: 100 GHz PNUSW ULA, x ~ U(1,2) m, y ~ U[-7.5,7.5] m, K = 10, "
+                    "received SNR limit 33 dB at (1.5 m, 0)",
+           "users": 10, "drops": n_drops, "n_list": [int(n) for n in n_list], "rx_snr_limit_db": rx_snr_db,
+           "analytic_saturation_n": float(sat[2]),
+           "exact": {"sum_rate": {name: erg[:, 0, i].tolist() for i, (name, _) in enumerate(exact_schemes)},
+                     "empirical_saturation_n": {name: float(sat[3 + i]) for i, (name, _) in
+                                                enumerate(exact_schemes)},
+                     "flagged_drops": int((st != 0).sum()), "gpu_ms": ms},
+           "forms": {}}
+    for name in forms:
+        form = {"PAPER": X.FORM_CF_PAPER, "UNIFORM": X.FORM_CF_UNIFORM}[name]
+        erg, sat, st, ms = _timed_sweep(ctx, arr, n_list, b, form, rho, X.MZF | X.MZF_MISM, t, eps)
+        out["forms"][name] = {"sum_rate": {sch: erg[:, 0, i].tolist() for i, (sch, _) in enumerate(cf_schemes)},
+                              "filter_not_pd_drops": [int(((st[i] & X.ST_FILTER_NOT_PD) != 0).sum())
+                                                      for i in range(len(n_list))],
+                              "gpu_ms": ms}
+    return out
+
+
+def _table_fig3(r):
+    lines = [f"Fig. 3 ({r['scene']}; K = {r['users']}, {r['drops']} drops): normalised capacity",
+             "| N | " + " | ".join(f"{s:g} dB" for s in r["snr_db"]) + " |",
+             "|---|" + "---|" * len(r["snr_db"])]
+    for i, n in enumerate(r["n_list"]):
+        lines.append(f"| {n} | " + " | ".join(f"{r['normalised_capacity'][i][j]:.4f}"
+                                                for j in range(len(r["snr_db"]))) + " |")
+    lines.append(f"analytic saturation (eqs. (15)-(16)): N = {r['analytic_saturation_n']:.0f}; "
+                 f"empirical (C >= (1 - {r['eps']}) C_max): " +
+                 ", ".join(f"{n:.0f}" for n in r["empirical_saturation_n"]))
+    return "\n".join(lines)
+
+
+def _table_fig4(r):
+    forms = list(r["forms"])
+    cols = list(r["exact"]["sum_rate"]) + [f"{sch} ({f})" for f in forms for sch in r["forms"][f]["sum_rate"]]
+    lines = [f"Fig. 4 ({r['scene']}; {r['drops']} drops): ergodic sum-rate [bit/s/Hz]",
+             "| N | " + " | ".join(cols) + " |", "|---|" + "---|" * len(cols)]
+    for i, n in enumerate(r["n_list"]):
+        vals = [r["exact"]["sum_rate"][s][i] for s in r["exact"]["sum_rate"]]
+        vals += [r["forms"][f]["sum_rate"][s][i] for f in forms for s in r["forms"][f]["sum_rate"]]
+        lines.append(f"| {n} | " + " | ".join(f"{v:.3f}" for v in vals) + " |")
+    lines.append(f"analytic saturation (eqs. (15)-(16)): N = {r['analytic_saturation_n']:.0f}; empirical "
+                 "(rate >= 0.95 of the last point): " +
+                 ", ".join(f"{k} {v:.0f}" for k, v in r["exact"]["empirical_saturation_n"].items()))
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("figure", choices=["fig3", "fig4"])
+    ap.add_argument("--drops", type=int, default=1000)
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args(argv)
+    ctx = X.Context(0)
+    t0 = time.perf_counter()
+    r = fig3(ctx, args.drops) if args.figure == "fig3" else fig4(ctx, args.drops)
+    r["wall_s"] = time.perf_counter() - t0
+    print(_table_fig3(r) if args.figure == "fig3" else _table_fig4(r))
+    if args.json:
+        with open(args.json, "w") as fh:
+            json.dump(r, fh, indent=1)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
