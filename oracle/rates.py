@@ -33,6 +33,7 @@ SCHEME_MRC = 4
 SCHEME_CAP = 8
 SCHEME_MZF = 16      # nominal modified ZF: ZF formula evaluated on G~
 SCHEME_MZF_MISMATCH = 32
+SCHEME_CORR_GAP = 64    # Appendix A: -(1/K) log2 det R, the normalised Hadamard / Schur-Horn gap
 
 
 def sinr_zf(g, rho):
@@ -75,6 +76,16 @@ def sum_rate(sinr):
     return float(np.sum(np.log2(1.0 + sinr)))
 
 
+def corr_gap(g):
+    """Appendix A, eq. (9): the largest normalised gap (U - L) / U between the Hadamard upper bound and
+    the Schur-Horn lower bound of the capacity, -(1/K) log2 det R, with R the correlation matrix
+    r_ij = G_ij / sqrt(G_ii G_jj).  Independent of the SNR."""
+    d = np.sqrt(np.real(np.diag(g)))
+    r = g / np.outer(d, d)
+    sign, logdet = np.linalg.slogdet(r)
+    return float(-logdet / np.log(2.0) / g.shape[0]) if sign > 0 else float("nan")
+
+
 def rates(g_true, rho, schemes=SCHEME_ZF | SCHEME_MMSE, g_filter=None):
     """Dict scheme -> sum-rate [bit/s/Hz] for one drop."""
     rho = np.asarray(rho, np.float64)
@@ -91,6 +102,8 @@ def rates(g_true, rho, schemes=SCHEME_ZF | SCHEME_MMSE, g_filter=None):
         out[SCHEME_MZF] = sum_rate(sinr_zf(g_filter, rho))
     if schemes & SCHEME_MZF_MISMATCH:
         out[SCHEME_MZF_MISMATCH] = sum_rate(sinr_mismatched(g_true, g_filter, rho))
+    if schemes & SCHEME_CORR_GAP:
+        out[SCHEME_CORR_GAP] = corr_gap(g_true)
     return out
 
 

@@ -100,3 +100,21 @@ def test_mmse_tends_to_zf_at_high_snr():
     h, g, rho = _drop()
     big = rho * 1e10
     assert np.allclose(R.sinr_mmse(g, big), R.sinr_zf(g, big), rtol=1e-6)
+
+
+def test_corr_gap_appendix_a():
+    # -(1/K) log2 det R (Appendix A, eq. (9)): zero for orthogonal users; for two users
+    # -1/2 log2(1 - |r12|^2); equal to the negative mean log2-eigenvalue of R (the paper's last form);
+    # and equal to the normalised log-gap between the Hadamard and Schur-Horn bounds at a_i = 1 (0 dB)
+    assert abs(R.corr_gap(np.diag([2.0, 5.0, 0.5]).astype(np.complex128))) < 1e-15   # sqrt rounding only
+    g2 = np.array([[4.0, 0.6 - 0.8j], [0.6 + 0.8j, 1.0]])
+    r12 = abs(g2[0, 1]) / np.sqrt(4.0 * 1.0)
+    assert R.corr_gap(g2) == pytest.approx(-0.5 * np.log2(1 - r12 ** 2), rel=1e-14)
+    for seed in (1, 2):
+        h, g, rho = _drop(seed=seed, amp=W.AMP_PNUSW)
+        d = np.sqrt(np.real(np.diag(g)))
+        lam = np.linalg.eigvalsh(g / np.outer(d, d))
+        assert R.corr_gap(g) == pytest.approx(-np.mean(np.log2(lam)), rel=1e-10)
+        unit = 1.0 / np.real(np.diag(g))                      # a_i = rho_i G_ii = 1
+        u, lo = R.hadamard_bound(g, unit), R.schur_horn_bound(g, unit)
+        assert R.corr_gap(g) == pytest.approx((u - lo) / u, rel=1e-10)
