@@ -98,6 +98,9 @@ extern "C" {
 #define XLMIMO_CAP        8    /* log2 det(I + D^1/2 G D^1/2), eq. (9) */
 #define XLMIMO_MZF       16    /* ZF formula evaluated on the filter Gram (nominal modified ZF) */
 #define XLMIMO_MZF_MISM  32    /* modified-ZF filter G~^-1 H^H applied to the true channel */
+#define XLMIMO_CORR_GAP  64    /* not a rate: -(1/K) log2 det R, R_ij = G_ij / sqrt(G_ii G_jj), the largest
+                                  normalised gap between the Hadamard and Schur-Horn capacity bounds
+                                  (Appendix A, eq. (9)); the same value at every SNR */
 
 /* Per-drop status bits. */
 #define XLMIMO_ST_G_NOT_PD      1   /* Cholesky of the ZF Gram failed: ZF-type rates are NaN */
@@ -198,7 +201,7 @@ int xlmimo_gram_closedform(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmim
  *   gram_filter  DEVICE complex128 Grams used by XLMIMO_MZF / XLMIMO_MZF_MISM; may be NULL otherwise
  *   n_snr        number of SNR points (>= 1)
  *   rho          DEVICE double [n_snr][total_users]: rho_k = P_k / sigma^2 (linear)
- *   schemes      bitmask of XLMIMO_ZF ... XLMIMO_MZF_MISM (non-zero)
+ *   schemes      bitmask of XLMIMO_ZF ... XLMIMO_CORR_GAP (non-zero); columns in that order
  *   rates_out    DEVICE double [n_drops][n_snr][popcount(schemes)] bit/s/Hz (NaN when not PD)
  *   status_out   DEVICE int32 [n_drops] or NULL: OR of XLMIMO_ST_* over the SNR points */
 int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,

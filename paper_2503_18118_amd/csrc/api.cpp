@@ -940,7 +940,7 @@ static int check_rates_args(xlmimo_ctx* c, const xlmimo_batch* b, const double* 
                             int32_t n_snr, const double* rho, int32_t schemes) {
   int rc = check_batch(c, b, false);
   if (rc) return rc;
-  if (schemes <= 0 || schemes > 63) return set_err(c, XLMIMO_EINVAL, "bad scheme mask %d", schemes);
+  if (schemes <= 0 || schemes > 127) return set_err(c, XLMIMO_EINVAL, "bad scheme mask %d", schemes);
   if (n_snr < 1) return set_err(c, XLMIMO_EINVAL, "n_snr must be >= 1");
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!gram_true || !rho) return set_err(c, XLMIMO_EINVAL, "gram_true and rho are required");

@@ -170,14 +170,20 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
   int st = 0;
   const double nan = __builtin_nan("");
 
-  // ZF: [G^-1]_kk (independent of the SNR)
-  double ginv = nan;
-  if (schemes & XLMIMO_ZF) {
+  // ZF: [G^-1]_kk; the correlation gap -(1/K) log2 det R from the same factor (both independent of
+  // the SNR)
+  double ginv = nan, gapv = nan;
+  if (schemes & (XLMIMO_ZF | XLMIMO_CORR_GAP)) {
     if (lane < K)
       for (int j = 0; j < K; ++j) A[lane * ld + j] = gload(gram, go, K, lane, j);
     __syncthreads();
-    if (chol_lower(A, K, ld, lane)) ginv = inverse_diag(A, wd, K, ld, lane);
-    else st |= XLMIMO_ST_G_NOT_PD;
+    if (chol_lower(A, K, ld, lane)) {
+      const double t = lane < K ? 2.0 * log2(A[lane * ld + lane].x) - log2(gload(gram, go, K, lane, lane).x) : 0.0;
+      gapv = -wave_sum(t) / K;
+      ginv = inverse_diag(A, wd, K, ld, lane);
+    } else {
+      st |= XLMIMO_ST_G_NOT_PD;
+    }
     __syncthreads();
   }
 
@@ -332,6 +338,10 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
       if (lane == 0) rates[rbase + s * n_sch + c] = tot;
       ++c;
     }
+    if (schemes & XLMIMO_CORR_GAP) {
+      if (lane == 0) rates[rbase + s * n_sch + c] = gapv;
+      ++c;
+    }
   }
   if (status != nullptr && lane == 0) status[blockIdx.x] = st;
 }
@@ -468,10 +478,11 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
   const int64_t d = (int64_t)blockIdx.x * drops_per_block + slot;
   if ((int)threadIdx.x < drops_per_block) s_st[threadIdx.x] = 0;
   __syncthreads();
-  const bool zf = schemes & XLMIMO_ZF, mzf = schemes & XLMIMO_MZF;
+  const bool zf = schemes & XLMIMO_ZF, mzf = schemes & XLMIMO_MZF, gap = schemes & XLMIMO_CORR_GAP;
   const bool mmse = schemes & XLMIMO_MMSE, cap = schemes & XLMIMO_CAP, mrc = schemes & XLMIMO_MRC;
-  // rate column of each scheme: ZF, MMSE, MRC, CAP, MZF (the mismatched scheme is not handled here)
-  const int c_mmse = zf, c_mrc = c_mmse + mmse, c_cap = c_mrc + mrc, c_mzf = c_cap + cap;
+  // rate column of each scheme: ZF, MMSE, MRC, CAP, MZF, CORR_GAP (the mismatched scheme is not
+  // handled here); the factorisation of G serves ZF and the correlation gap
+  const int c_mmse = zf, c_mrc = c_mmse + mmse, c_cap = c_mrc + mrc, c_mzf = c_cap + cap, c_gap = c_mzf + mzf;
   const double nan = __builtin_nan("");
   int st = 0;
   if (slot < drops_per_block && d < n_drops) {   // groups past the last slot of the block idle
@@ -480,7 +491,7 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
     const int64_t go = dp.gram_off;
     const int64_t rbase = d * n_snr * n_sch;
     int kind = job;                        // 0: G, 1: G~, 2 + s: SNR s
-    if (!zf) ++kind;
+    if (!(zf || gap)) ++kind;
     if (!mzf && kind >= 1) ++kind;
     cplx a[kSmallK];
     double diag = 1.0;
@@ -514,10 +525,19 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
       // ZF on the true Gram or nominal modified ZF on the filter Gram, all SNRs
       if (!ok) st |= kind == 0 ? XLMIMO_ST_G_NOT_PD : XLMIMO_ST_FILTER_NOT_PD;
       const double ginv = ok ? minv : nan;
-      for (int q = 0; q < n_snr; ++q) {
-        const double rq = li < K ? rho[(int64_t)q * total_users + dp.user_off + li] : 0.0;
-        const double tot = group_sum(li < K ? log2(1.0 + rq / ginv) : 0.0);
-        if (li == 0) rates[rbase + q * n_sch + (kind == 0 ? 0 : c_mzf)] = tot;
+      if (kind == 1 || zf) {
+        for (int q = 0; q < n_snr; ++q) {
+          const double rq = li < K ? rho[(int64_t)q * total_users + dp.user_off + li] : 0.0;
+          const double tot = group_sum(li < K ? log2(1.0 + rq / ginv) : 0.0);
+          if (li == 0) rates[rbase + q * n_sch + (kind == 0 ? 0 : c_mzf)] = tot;
+        }
+      }
+      if (kind == 0 && gap) {
+        // -(1/K) log2 det R = -(1/K) (2 sum log2 L_kk - sum log2 G_kk), the same for every SNR
+        const double t = li < K ? 2.0 * log2(diag) - log2(gload(gram, go, K, li, li).x) : 0.0;
+        const double v = ok ? -group_sum(t) / K : nan;
+        if (li == 0)
+          for (int q = 0; q < n_snr; ++q) rates[rbase + q * n_sch + c_gap] = v;
       }
     } else {
       if (mrc) {
@@ -561,7 +581,7 @@ hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const doub
   int n_sch = __builtin_popcount(schemes);
   const int ld = k_max + 1;
   const bool mism = schemes & XLMIMO_MZF_MISM;
-  const int jobs = ((schemes & XLMIMO_ZF) ? 1 : 0) + ((schemes & XLMIMO_MZF) ? 1 : 0) +
+  const int jobs = ((schemes & (XLMIMO_ZF | XLMIMO_CORR_GAP)) ? 1 : 0) + ((schemes & XLMIMO_MZF) ? 1 : 0) +
                    ((schemes & (XLMIMO_MMSE | XLMIMO_CAP | XLMIMO_MRC)) ? n_snr : 0);
   if (k_max <= kSmallK && !mism && jobs >= 1 && jobs * kSmallK <= 256) {
     // several drops per wave when a drop needs fewer than four factorisations

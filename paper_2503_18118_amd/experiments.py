@@ -1,4 +1,4 @@
-"""The paper's numerical experiments (Sec. IV-C, Fig. 3; Sec. V-C, Fig. 4) on the GPU path.
+"""The paper's numerical experiments (Sec. IV-C Fig. 3, Sec. V-C Fig. 4, Appendix A Fig. 5) on the GPU path.
 
 Both run through the library's capacity sweep (exact Gram, closed forms, FP64
 rates, ergodic means and the saturation point); nothing here computes.
@@ -16,7 +16,11 @@ rates, ergodic means and the saturation point); nothing here computes.
   applied to the true channel).  The closed form is eq. (6) as printed (variant
   PAPER); the uniform closed form (UNIFORM) is run beside it.
 
-``python -m paper_2503_18118_amd.experiments [fig3|fig4] [--drops D] [--json PATH]``
+* ``fig5``: Appendix A's normalised gap between the Hadamard and Schur-Horn capacity
+  bounds, -(1/K) log2 det R (eq. (9)), against K in the Sec. IV scene at N = 65536,
+  K up to the library's 64 (the paper goes to K = 1000).
+
+``python -m paper_2503_18118_amd.experiments [fig3|fig4|fig5] [--drops D] [--json PATH]``
 prints a table and optionally writes the numbers as JSON.
 """
 from __future__ import annotations
@@ -110,6 +114,29 @@ def fig4(ctx, n_drops: int = 200, n_list=FIG_N, rx_snr_db: float = 33.0, forms=(
     return out
 
 
+def fig5(ctx, n_drops: int = 200, k_list=(2, 4, 8, 16, 32, 64), n: int = 65536) -> dict:
+    """Appendix A, Fig. 5: the normalised bound gap -E[log2 lambda^R] = -(1/K) log2 det R against K
+    in the Sec. IV scene at N = 65536 antennas (beyond the saturation point of every K here)."""
+    arr = W.ula(n, W.LAMBDA_100GHZ, W.AMP_PNUSW)
+    gaps, ms_total = [], 0.0
+    for k in k_list:
+        drops = W.rect_drops(W.rng_for(10), n_drops, int(k), n, (1.0, 10.0), (-7.5, 7.5))
+        b = X.Batch(drops)
+        rho = torch.ones((1, b.total_users), dtype=torch.float64, device="cuda")   # the gap has no SNR
+        erg, sat, st, ms = _timed_sweep(ctx, arr, [n], b, X.FORM_EXACT_FP64, rho, X.CORR_GAP)
+        gaps.append(float(erg[0, 0, 0]))
+        ms_total += ms
+    return {"scene": "Sec. IV: 100 GHz PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m", "n": n, "drops": n_drops,
+            "k_list": [int(k) for k in k_list], "negative_mean_log2_eig_R": gaps, "gpu_ms": ms_total}
+
+
+def _table_fig5(r):
+    lines = [f"Fig. 5 ({r['scene']}; N = {r['n']}, {r['drops']} drops): -E[log2 lambda^R] against K",
+             "| K | " + " | ".join(str(k) for k in r["k_list"]) + " |", "|---|" + "---|" * len(r["k_list"]),
+             "| gap | " + " | ".join(f"{v:.5f}" for v in r["negative_mean_log2_eig_R"]) + " |"]
+    return "\n".join(lines)
+
+
 def _table_fig3(r):
     lines = [f"Fig. 3 ({r['scene']}; K = {r['users']}, {r['drops']} drops): normalised capacity",
              "| N | " + " | ".join(f"{s:g} dB" for s in r["snr_db"]) + " |",
@@ -140,15 +167,16 @@ def _table_fig4(r):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("figure", choices=["fig3", "fig4"])
+    ap.add_argument("figure", choices=["fig3", "fig4", "fig5"])
     ap.add_argument("--drops", type=int, default=1000)
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     ctx = X.Context(0)
     t0 = time.perf_counter()
-    r = fig3(ctx, args.drops) if args.figure == "fig3" else fig4(ctx, args.drops)
+    run, table = {"fig3": (fig3, _table_fig3), "fig4": (fig4, _table_fig4), "fig5": (fig5, _table_fig5)}[args.figure]
+    r = run(ctx, args.drops)
     r["wall_s"] = time.perf_counter() - t0
-    print(_table_fig3(r) if args.figure == "fig3" else _table_fig4(r))
+    print(table(r))
     if args.json:
         with open(args.json, "w") as fh:
             json.dump(r, fh, indent=1)

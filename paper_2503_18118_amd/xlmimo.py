@@ -22,7 +22,7 @@ ULA, UPA = 0, 1
 AMP_FREESPACE, AMP_PNUSW = 0, 1
 FP64, FP32C, FP32H = 0, 1, 2
 CF_PAPER, CF_GATED, CF_UNIFORM, CF_GATED_QUAD = 0, 1, 2, 3
-ZF, MMSE, MRC, CAP, MZF, MZF_MISM = 1, 2, 4, 8, 16, 32
+ZF, MMSE, MRC, CAP, MZF, MZF_MISM, CORR_GAP = 1, 2, 4, 8, 16, 32, 64
 ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE, ST_FELL_BACK = 1, 2, 4, 8, 16, 32
 FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED, FORM_CF_GATED_MLP, FORM_EXACT_FP32H, FORM_CF_UNIFORM = \
     0, 1, 2, 3, 4, 5, 6

@@ -132,3 +132,19 @@ def test_fig3_reproduces_the_papers_claims(X, E, ctx):
     at_m = [np.interp(np.log(m), np.log(n), c[:, s]) for s in range(2)]
     assert min(at_m) > 0.97, at_m
     assert r["empirical_saturation_n"][1] < r["empirical_saturation_n"][0]
+
+
+def test_fig5_matches_oracle_and_the_papers_trend(X, E, ctx):
+    # Appendix A: the normalised bound gap grows with K and stays below the paper's maximum of 0.064
+    # (reached at K = 1000); the small case against the oracle drop by drop
+    r = E.fig5(ctx, n_drops=100)
+    g = np.array(r["negative_mean_log2_eig_R"])
+    assert np.all(np.diff(g) > 0) and g[0] > 0
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    assert g[-1] < gold["appendix_a_max_gap"]["value"]
+    small = E.fig5(ctx, n_drops=5, k_list=(2, 8), n=1024)
+    arr = W.ula(1024, W.LAMBDA_100GHZ, W.AMP_PNUSW)
+    for k, got in zip((2, 8), small["negative_mean_log2_eig_R"]):
+        drops = W.rect_drops(W.rng_for(10), 5, k, 1024, (1.0, 10.0), (-7.5, 7.5))
+        want = np.mean([orates.corr_gap(och.gram_exact(arr, drops.users_of(d))) for d in range(5)])
+        assert got == pytest.approx(want, rel=1e-10)

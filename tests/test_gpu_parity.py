@@ -452,6 +452,36 @@ def test_rates_mismatched_with_indefinite_filter(X, ctx, kset):
             assert r[d, s, 3] == pytest.approx(ref[orates.SCHEME_MZF_MISMATCH], rel=1e-8), (d, s)
 
 
+@pytest.mark.parametrize("kset,names", [
+    ([1, 2, 5, 16, 9, 16], ("CORR_GAP",)),                           # small kernel, the G job alone
+    ([3, 16, 7, 12], ("ZF", "MMSE", "CORR_GAP")),                    # small kernel beside ZF and MMSE
+    ([33, 64, 20, 2], ("ZF", "CORR_GAP")),                           # generic kernel (K > 16)
+    ([4, 16, 9], ("ZF", "MMSE", "MZF_MISM", "CORR_GAP")),            # generic kernel (mismatched scheme)
+])
+def test_rates_corr_gap(X, ctx, kset, names):
+    # Appendix A's -(1/K) log2 det R from the Cholesky factor of G, written for every SNR
+    rng = np.random.default_rng(len(kset) + 50)
+    drops = _custom_drops([max(4 * k, 300) for k in kset], kset, seed=int(sum(kset)) + 11, r=(1.0, 20.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    gh = b.split(g)
+    rho = torch.as_tensor(rng.uniform(0.5, 2.0, (2, b.total_users)) * 1e3
+                          / np.mean([np.real(np.diag(m)).mean() for m in gh]), device="cuda")
+    schemes = 0
+    for n in names:
+        schemes |= getattr(X, n)
+    rates, status = ctx.sumrate(b, g, rho, schemes, gram_filter=g if "MZF_MISM" in names else None)
+    torch.cuda.synchronize()
+    r = rates.cpu().numpy()
+    assert torch.all(status == 0)
+    c = len(names) - 1   # the gap is the last column
+    for d in range(drops.n_drops):
+        want = orates.corr_gap(gh[d])
+        for s in range(2):
+            assert r[d, s, c] == pytest.approx(want, rel=1e-10, abs=1e-14), (d, s, r[d, s, c], want)
+
+
 def test_rates_not_pd_flagged(X, ctx):
     k = 3
     m = np.ones((k, k), np.complex128)   # rank one: not positive definite
