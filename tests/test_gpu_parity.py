@@ -302,6 +302,27 @@ def test_closedform_bad_and_degenerate_inputs(X, ctx, variant):
         assert g[1][0, 1] == 0 and g[1][1, 0] == 0
 
 
+def test_rate_and_sweep_arguments_rejected(X, ctx):
+    arr, drops, _ = W.plain_fp64(3)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    rho = torch.ones((1, b.total_users), dtype=torch.float64, device="cuda")
+    with pytest.raises(X.XlmimoError, match="scheme mask"):
+        ctx.sumrate(b, g, rho, 128)
+    with pytest.raises(X.XlmimoError, match="scheme mask"):
+        ctx.sumrate(b, g, rho, 0)
+    with pytest.raises(X.XlmimoError, match="filter"):
+        ctx.sumrate(b, g, rho, X.ZF | X.MZF_MISM)          # the modified ZF needs a filter Gram
+    with pytest.raises(X.XlmimoError, match="closed-form sweep"):
+        ctx.capacity_sweep(arr, [64, 256], b, X.FORM_EXACT_FP64, rho, X.ZF | X.MZF)
+    with pytest.raises(X.XlmimoError, match="ascending"):
+        ctx.capacity_sweep(arr, [256, 64], b, X.FORM_EXACT_FP64, rho, X.ZF)
+    with pytest.raises(X.XlmimoError, match="t_sat"):
+        ctx.capacity_sweep(arr, [64, 256], b, X.FORM_EXACT_FP64, rho, X.ZF, t_sat=1.0)
+    with pytest.raises(X.XlmimoError, match="form"):
+        ctx.capacity_sweep(arr, [64, 256], b, 9, rho, X.ZF)
+
+
 def _rho_host(X, rho):
     return rho.cpu().numpy()
 
