@@ -121,7 +121,12 @@ extern "C" {
 #define XLMIMO_FORM_EXACT_FP32H 5   /* exact Gram at XLMIMO_FP32H precision */
 #define XLMIMO_FORM_CF_UNIFORM  6   /* closed form, variant XLMIMO_CF_UNIFORM */
 
+/* Users per drop: at most XLMIMO_MAX_USERS for the closed forms and the learned
+ * form; the exact Gram, the sum-rates (all schemes but XLMIMO_MZF and
+ * XLMIMO_MZF_MISM) and the exact capacity sweeps take up to
+ * XLMIMO_MAX_USERS_EXACT (the Appendix A study runs to K = 1000). */
 #define XLMIMO_MAX_USERS 64
+#define XLMIMO_MAX_USERS_EXACT 1024
 
 /* Learned correction: network inputs and outputs per user pair. */
 #define XLMIMO_MLP_IN  6
@@ -146,7 +151,7 @@ typedef struct {
 typedef struct {
   int64_t        n_drops;  /* >= 0; 0 makes every call a no-op */
   const int64_t* n_elems;  /* HOST [n_drops]: ULA antennas per drop; NULL = array n_y. Ignored for UPA */
-  const int32_t* n_users;  /* HOST [n_drops]: users per drop, 1..XLMIMO_MAX_USERS */
+  const int32_t* n_users;  /* HOST [n_drops]: users per drop, 1..XLMIMO_MAX_USERS (_EXACT, see above) */
   const double*  user_pos; /* DEVICE [total_users][3]: x, y, z of each user, drops back to back */
 } xlmimo_batch;
 
@@ -174,7 +179,13 @@ int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
  *   precision  XLMIMO_FP64, XLMIMO_FP32C or XLMIMO_FP32H
  *   gram_out   DEVICE complex128, layout above
  * Drops with a non-finite position or a user at distance 0 from an element
- * get NaN entries (no status array here; xlmimo_zf_mmse_sumrate flags them). */
+ * get NaN entries (no status array here; xlmimo_zf_mmse_sumrate flags them).
+ * K up to XLMIMO_MAX_USERS_EXACT.  A drop with K > XLMIMO_MAX_USERS is split
+ * into groups of at most 32 users and every pair of groups runs as one
+ * work item of at most 64 users; the group-pair blocks are then copied into
+ * the drop's K x K output (a group's own block from its pair with the next
+ * group).  Workspace grows with the sum over such drops of (groups choose 2)
+ * x 64^2 complex values plus the per-item partial sums. */
 int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                       int32_t precision, double* gram_out, void* stream);
 
@@ -203,7 +214,12 @@ int xlmimo_gram_closedform(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmim
  *   rho          DEVICE double [n_snr][total_users]: rho_k = P_k / sigma^2 (linear)
  *   schemes      bitmask of XLMIMO_ZF ... XLMIMO_CORR_GAP (non-zero); columns in that order
  *   rates_out    DEVICE double [n_drops][n_snr][popcount(schemes)] bit/s/Hz (NaN when not PD)
- *   status_out   DEVICE int32 [n_drops] or NULL: OR of XLMIMO_ST_* over the SNR points */
+ *   status_out   DEVICE int32 [n_drops] or NULL: OR of XLMIMO_ST_* over the SNR points
+ * Batches with K up to XLMIMO_MAX_USERS run one wave per drop with the matrix
+ * in LDS (or registers for K <= 16).  A batch with a larger K (up to
+ * XLMIMO_MAX_USERS_EXACT) runs one 256-thread workgroup per drop with the
+ * matrix in a context workspace of the Gram's size (schemes XLMIMO_MZF and
+ * XLMIMO_MZF_MISM are rejected there with XLMIMO_EINVAL). */
 int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
                            const double* gram_true, const double* gram_filter,
                            int32_t n_snr, const double* rho, int32_t schemes,
@@ -231,7 +247,8 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,
  *   ergodic_out  DEVICE double [n_N][n_snr][n_sch]
  *   sat_out      DEVICE double [3 + n_snr * n_sch]
  *   status_out   DEVICE int32 [n_N][n_drops] or NULL
- * The batch's n_elems is ignored. */
+ * The batch's n_elems is ignored.  Exact forms take K up to
+ * XLMIMO_MAX_USERS_EXACT, closed forms up to XLMIMO_MAX_USERS. */
 int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N, const int64_t* N_list,
                           const xlmimo_batch* batch, int32_t form, xlmimo_mlp* mlp, double log_var_max,
                           int32_t n_snr, const double* rho, int32_t schemes, double t_sat, double eps_sat,

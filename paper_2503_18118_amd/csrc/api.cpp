@@ -38,6 +38,15 @@ struct Plan {
   uint64_t key = 0;          // plan_key of the batch shape
   DropK* d_drops = nullptr;
   ItemK* d_items = nullptr;
+  // K > XLMIMO_MAX_USERS: the exact Gram runs over group-pair virtual drops,
+  // whose plan is built on the first exact-Gram call of this shape
+  std::vector<int64_t> ne_host;   // per-drop N and K, kept only for that build
+  std::vector<int32_t> k_host;
+  struct Plan* vplan = nullptr;   // owned
+  int n_v = 0;
+  int64_t n_vusers = 0;
+  VDropK* d_v = nullptr;
+  int64_t* d_vmap = nullptr;
 };
 
 }  // namespace
@@ -51,6 +60,8 @@ struct xlmimo_ctx {
   int n_gl = 0;
   DevBuf partials, scratch_gram, scratch_gram2, scratch_rates, scratch_bounds, scratch_nlist, scratch_pairs;
   DevBuf scratch_routes;   // per-pair route words of the ULA closed forms UNIFORM and GATED_QUAD
+  DevBuf scratch_vpos, scratch_vgram;  // virtual drops of the exact Gram (K > XLMIMO_MAX_USERS)
+  DevBuf scratch_work;     // matrices of the workgroup-per-drop rate kernel (K > XLMIMO_MAX_USERS)
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
   std::unordered_map<uint64_t, Plan> plans;
   // kernel timing (xlmimo_timing_enable / xlmimo_timing_read)
@@ -169,14 +180,14 @@ int check_array(xlmimo_ctx* c, const xlmimo_array* a) {
   return XLMIMO_OK;
 }
 
-int check_batch(xlmimo_ctx* c, const xlmimo_batch* b, bool need_pos) {
+int check_batch(xlmimo_ctx* c, const xlmimo_batch* b, bool need_pos, int max_k = XLMIMO_MAX_USERS) {
   if (!b) return set_err(c, XLMIMO_EINVAL, "batch is NULL");
   if (b->n_drops < 0 || b->n_drops > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "bad n_drops");
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!b->n_users) return set_err(c, XLMIMO_EINVAL, "n_users is NULL");
   for (int64_t d = 0; d < b->n_drops; ++d) {
-    if (b->n_users[d] < 1 || b->n_users[d] > XLMIMO_MAX_USERS)
-      return set_err(c, XLMIMO_EINVAL, "drop %lld: K = %d outside 1..%d", (long long)d, b->n_users[d], XLMIMO_MAX_USERS);
+    if (b->n_users[d] < 1 || b->n_users[d] > max_k)
+      return set_err(c, XLMIMO_EINVAL, "drop %lld: K = %d outside 1..%d", (long long)d, b->n_users[d], max_k);
     if (b->n_elems && (b->n_elems[d] < 1 || b->n_elems[d] > 2147483647LL))
       return set_err(c, XLMIMO_EINVAL, "drop %lld: N = %lld outside 1..2^31-1", (long long)d, (long long)b->n_elems[d]);
   }
@@ -219,9 +230,21 @@ uint64_t plan_key(const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n
 void drop_plan_buffers(xlmimo_ctx* c, Plan& p) {
   (void)release(c, p.d_drops);
   (void)release(c, p.d_items);
+  (void)release(c, p.d_v);
+  (void)release(c, p.d_vmap);
   p.d_drops = nullptr;
   p.d_items = nullptr;
+  p.d_v = nullptr;
+  p.d_vmap = nullptr;
+  if (p.vplan) {
+    drop_plan_buffers(c, *p.vplan);
+    delete p.vplan;
+    p.vplan = nullptr;
+  }
 }
+
+// Fill a plan for drops with the given N and K and upload its descriptors.
+int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne, const int32_t* kk, uint64_t h, Plan& p);
 
 // Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
 // descriptors synchronously; warm the cache before capturing a graph.
@@ -241,17 +264,35 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
     c->plans.clear();
   }
   const int n = (int)b->n_drops;
+  std::vector<int64_t> ne(n);
+  for (int d = 0; d < n; ++d)
+    ne[d] = a->geometry == XLMIMO_UPA ? a->n_y * a->n_z
+                                      : (n_override ? *n_override : (b->n_elems ? b->n_elems[d] : a->n_y));
   Plan p;
+  int rc = build_plan(c, a, n, ne.data(), b->n_users, h, p);
+  if (rc) {
+    drop_plan_buffers(c, p);
+    return rc;
+  }
+  if (p.k_max > XLMIMO_MAX_USERS) {
+    p.ne_host = ne;
+    p.k_host.assign(b->n_users, b->n_users + n);
+  }
+  auto ins = c->plans.emplace(h, p);
+  *out = &ins.first->second;
+  return XLMIMO_OK;
+}
+
+int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of, const int32_t* kk, uint64_t h,
+               Plan& p) {
   p.n_drops = n;
   std::vector<DropK> drops(n);
   int64_t uoff = 0, goff = 0, total_elems = 0, pairs = 0;
   for (int d = 0; d < n; ++d) {
     DropK& dk = drops[d];
-    int64_t ne;
-    if (a->geometry == XLMIMO_UPA) ne = a->n_y * a->n_z;
-    else ne = n_override ? *n_override : (b->n_elems ? b->n_elems[d] : a->n_y);
+    const int64_t ne = ne_of[d];
     dk.n_elems = (int32_t)ne;
-    dk.k = b->n_users[d];
+    dk.k = kk[d];
     dk.nb = (dk.k + 15) / 16;
     dk.user_off = uoff;
     dk.gram_off = goff;
@@ -307,8 +348,74 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   HIP_TRY(c, hipMalloc(&p.d_items, sizeof(ItemK) * std::max<size_t>(sorted.size(), 1)));
   HIP_TRY(c, hipMemcpy(p.d_drops, drops.data(), sizeof(DropK) * n, hipMemcpyHostToDevice));
   if (!sorted.empty()) HIP_TRY(c, hipMemcpy(p.d_items, sorted.data(), sizeof(ItemK) * sorted.size(), hipMemcpyHostToDevice));
-  auto ins = c->plans.emplace(h, p);
-  *out = &ins.first->second;
+  return XLMIMO_OK;
+}
+
+// Virtual drops of a batch with K > XLMIMO_MAX_USERS.  A drop with K <=
+// XLMIMO_MAX_USERS is one virtual drop of its own; a larger one has
+// g = ceil(K / kGroupUsers) groups of near-equal size (group i holds users
+// [K i / g, K (i + 1) / g)) and one virtual drop per group pair a < b.  Group
+// a's own block is taken from the pair (a, a + 1), the last group's from
+// (g - 2, g - 1).
+int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
+  if (c->capturing)
+    return set_err(c, XLMIMO_EINVAL, "a new batch shape needs a launch plan during graph capture: "
+                   "run the same calls once before capturing them");
+  const int n = p.n_drops;
+  std::vector<VDropK> vd;
+  std::vector<int64_t> vmap, vne;
+  std::vector<int32_t> vk;
+  int64_t uoff = 0, goff = 0, vgoff = 0;
+  for (int d = 0; d < n; ++d) {
+    const int K = p.k_host[d];
+    auto add = [&](int a0, int ka, int b0, int kb, int flags) {
+      VDropK v;
+      v.gram_off = goff;
+      v.vgram_off = vgoff;
+      v.k = K;
+      v.a0 = a0;
+      v.ka = ka;
+      v.b0 = b0;
+      v.kb = kb;
+      v.flags = flags;
+      vd.push_back(v);
+      for (int i = 0; i < ka; ++i) vmap.push_back(uoff + a0 + i);
+      for (int i = 0; i < kb; ++i) vmap.push_back(uoff + b0 + i);
+      vne.push_back(p.ne_host[d]);
+      vk.push_back(ka + kb);
+      vgoff += (int64_t)(ka + kb) * (ka + kb);
+    };
+    if (K <= XLMIMO_MAX_USERS) {
+      add(0, K, 0, 0, kVCopyA);
+    } else {
+      const int g = (K + kGroupUsers - 1) / kGroupUsers;
+      auto first = [&](int i) { return (int)((int64_t)K * i / g); };
+      for (int ga = 0; ga < g; ++ga)
+        for (int gb = ga + 1; gb < g; ++gb) {
+          int flags = 0;
+          if (gb == ga + 1) flags |= kVCopyA;
+          if (ga == g - 2 && gb == g - 1) flags |= kVCopyB;
+          add(first(ga), first(ga + 1) - first(ga), first(gb), first(gb + 1) - first(gb), flags);
+        }
+    }
+    uoff += K;
+    goff += (int64_t)K * K;
+  }
+  if (vd.size() > 2147483647ULL) return set_err(c, XLMIMO_EINVAL, "too many user-group pairs");
+  Plan* vp = new Plan();
+  int rc = build_plan(c, a, (int)vd.size(), vne.data(), vk.data(), p.key ^ 0x9e3779b97f4a7c15ULL, *vp);
+  if (rc) {
+    drop_plan_buffers(c, *vp);
+    delete vp;
+    return rc;
+  }
+  p.vplan = vp;
+  p.n_v = (int)vd.size();
+  p.n_vusers = (int64_t)vmap.size();
+  HIP_TRY(c, hipMalloc(&p.d_v, sizeof(VDropK) * vd.size()));
+  HIP_TRY(c, hipMalloc(&p.d_vmap, sizeof(int64_t) * std::max<size_t>(vmap.size(), 1)));
+  HIP_TRY(c, hipMemcpy(p.d_v, vd.data(), sizeof(VDropK) * vd.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(p.d_vmap, vmap.data(), sizeof(int64_t) * vmap.size(), hipMemcpyHostToDevice));
   return XLMIMO_OK;
 }
 
@@ -357,9 +464,20 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   Plan* p = nullptr;
   int rc = get_plan(c, a, b, n_override, &p);
   if (rc) return rc;
-  rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s);
+  if (p->k_max > XLMIMO_MAX_USERS && !p->vplan && (rc = build_groups(c, a, *p))) return rc;
+  Plan* run = p->vplan ? p->vplan : p;   // the plan whose drops the kernels see
+  rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(run->partial_doubles, 1), s);
   if (rc) return rc;
-  const int grid = exact_grid(c, p, precision);
+  const double* pos = b->user_pos;
+  double* out = gram_out;
+  if (p->vplan) {
+    if ((rc = ensure(c, c->scratch_vpos, sizeof(double) * 3 * std::max<int64_t>(p->n_vusers, 1), s))) return rc;
+    if ((rc = ensure(c, c->scratch_vgram, sizeof(double) * 2 * std::max<int64_t>(run->gram_elems, 1), s))) return rc;
+    HIP_TRY(c, launch_gather_users(b->user_pos, p->d_vmap, p->n_vusers, (double*)c->scratch_vpos.p, s));
+    pos = (const double*)c->scratch_vpos.p;
+    out = (double*)c->scratch_vgram.p;
+  }
+  const int grid = exact_grid(c, run, precision);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (c->timing && !c->capturing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
@@ -371,8 +489,9 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
     ev1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
   }
-  HIP_TRY(c, launch_gram_exact(precision, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
-                               p->n_items, c->d_counter, (double*)c->partials.p, gram_out, grid, s, ev0, ev1));
+  HIP_TRY(c, launch_gram_exact(precision, run->nb_max, to_kernel(a), run->d_drops, run->n_drops, pos, run->d_items,
+                               run->n_items, c->d_counter, (double*)c->partials.p, out, grid, s, ev0, ev1));
+  if (p->vplan) HIP_TRY(c, launch_scatter_groups(p->d_v, p->n_v, (const double*)c->scratch_vgram.p, gram_out, s));
   return XLMIMO_OK;
 }
 
@@ -387,7 +506,17 @@ int closedform_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   return XLMIMO_OK;
 }
 
-int rates_k_max(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+int rates_k_max(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= XLMIMO_MAX_USERS ? XLMIMO_MAX_USERS : k)); }
+
+// Workspace of the workgroup-per-drop rate kernel: one K x K matrix per drop.
+int ensure_rates_work(xlmimo_ctx* c, const Plan* p, hipStream_t s, double** work) {
+  *work = nullptr;
+  if (p->k_max <= XLMIMO_MAX_USERS) return XLMIMO_OK;
+  int rc = ensure(c, c->scratch_work, sizeof(double) * 2 * std::max<int64_t>(p->gram_elems, 1), s);
+  if (rc) return rc;
+  *work = (double*)c->scratch_work.p;
+  return XLMIMO_OK;
+}
 
 }  // namespace
 
@@ -861,12 +990,10 @@ int xlmimo_ctx_destroy(xlmimo_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (void* p : c->retired) (void)hipFree(p);
-  for (auto& kv : c->plans) {
-    (void)hipFree(kv.second.d_drops);
-    (void)hipFree(kv.second.d_items);
-  }
+  for (auto& kv : c->plans) drop_plan_buffers(c, kv.second);   // no graphs: frees at once
   DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds,
-                    &c->scratch_nlist, &c->scratch_pairs, &c->scratch_routes};
+                    &c->scratch_nlist, &c->scratch_pairs, &c->scratch_routes, &c->scratch_vpos,
+                    &c->scratch_vgram, &c->scratch_work};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipFree(c->d_counter);
@@ -909,7 +1036,7 @@ int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* 
   std::lock_guard<std::mutex> lk(c->mu);
   if (int rc0 = stream_ok(c, stream)) return rc0;
   int rc = check_array(c, a);
-  if (!rc) rc = check_batch(c, b, true);
+  if (!rc) rc = check_batch(c, b, true, XLMIMO_MAX_USERS_EXACT);
   if (rc) return rc;
   if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C && precision != XLMIMO_FP32H)
     return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
@@ -937,10 +1064,15 @@ int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_ba
 }
 
 static int check_rates_args(xlmimo_ctx* c, const xlmimo_batch* b, const double* gram_true, const double* gram_filter,
-                            int32_t n_snr, const double* rho, int32_t schemes) {
-  int rc = check_batch(c, b, false);
+                            int32_t n_snr, const double* rho, int32_t schemes, int max_k = XLMIMO_MAX_USERS_EXACT) {
+  int rc = check_batch(c, b, false, max_k);
   if (rc) return rc;
   if (schemes <= 0 || schemes > 127) return set_err(c, XLMIMO_EINVAL, "bad scheme mask %d", schemes);
+  if (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM))
+    for (int64_t d = 0; d < b->n_drops; ++d)
+      if (b->n_users[d] > XLMIMO_MAX_USERS)
+        return set_err(c, XLMIMO_EINVAL, "drop %lld: modified-ZF schemes take K <= %d", (long long)d,
+                       XLMIMO_MAX_USERS);
   if (n_snr < 1) return set_err(c, XLMIMO_EINVAL, "n_snr must be >= 1");
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!gram_true || !rho) return set_err(c, XLMIMO_EINVAL, "gram_true and rho are required");
@@ -965,8 +1097,10 @@ int xlmimo_zf_mmse_sumrate(xlmimo_ctx* c, const xlmimo_batch* b, const double* g
   bb.n_elems = nullptr;
   Plan* p = nullptr;
   if ((rc = get_plan(c, &dummy, &bb, nullptr, &p))) return rc;
+  double* work = nullptr;
+  if ((rc = ensure_rates_work(c, p, (hipStream_t)stream, &work))) return rc;
   HIP_TRY(c, launch_rates(p->d_drops, p->n_drops, rates_k_max(p->k_max), gram_true, gram_filter, n_snr, rho,
-                          p->total_users, schemes, rates_out, status_out, (hipStream_t)stream));
+                          p->total_users, schemes, rates_out, status_out, (hipStream_t)stream, work));
   return XLMIMO_OK;
 }
 
@@ -993,7 +1127,9 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   const bool cf = (form >= XLMIMO_FORM_CF_PAPER && form <= XLMIMO_FORM_CF_GATED_MLP) || form == XLMIMO_FORM_CF_UNIFORM;
   if (!cf && (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM)))
     return set_err(c, XLMIMO_EINVAL, "modified-ZF schemes need a closed-form sweep");
-  if ((rc = check_rates_args(c, b, (const double*)1, (const double*)1, n_snr, rho, schemes))) return rc;
+  if ((rc = check_rates_args(c, b, (const double*)1, (const double*)1, n_snr, rho, schemes,
+                              cf ? XLMIMO_MAX_USERS : XLMIMO_MAX_USERS_EXACT)))
+    return rc;
   if (!b->user_pos && b->n_drops) return set_err(c, XLMIMO_EINVAL, "user_pos is NULL");
   if (b->n_drops == 0) return XLMIMO_OK;
   if (!ergodic_out || !sat_out) return set_err(c, XLMIMO_EINVAL, "ergodic_out and sat_out are required");
@@ -1009,6 +1145,8 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
   if ((rc = ensure(c, c->scratch_gram, gbytes, s))) return rc;
   const bool need_exact_true = cf && (schemes & XLMIMO_MZF_MISM);
   if (need_exact_true && (rc = ensure(c, c->scratch_gram2, gbytes, s))) return rc;
+  double* work = nullptr;
+  if ((rc = ensure_rates_work(c, p, s, &work))) return rc;
   if ((rc = ensure(c, c->scratch_rates, sizeof(double) * (size_t)nd * n_vals, s))) return rc;
   if ((rc = ensure(c, c->scratch_bounds, sizeof(double) * 2 * (size_t)nd, s))) return rc;
   if (c->scratch_nlist.n < sizeof(double) * n_N) c->nlist_host.clear();
@@ -1051,7 +1189,7 @@ int xlmimo_capacity_sweep(xlmimo_ctx* c, const xlmimo_array* a, int32_t n_N, con
     if ((rc = get_plan(c, a, b, &nn, &p))) return rc;
     const double* gtrue = need_exact_true ? g2 : g;
     HIP_TRY(c, launch_rates(p->d_drops, nd, rates_k_max(p->k_max), gtrue, g, n_snr, rho, p->total_users, schemes,
-                            (double*)c->scratch_rates.p, st, s));
+                            (double*)c->scratch_rates.p, st, s, work));
     if (st && fb_flags) HIP_TRY(c, launch_or_flags(st, fb_flags, nd, XLMIMO_ST_FELL_BACK, s));
     HIP_TRY(c, launch_ergodic((double*)c->scratch_rates.p, nd, n_vals, ergodic_out + (int64_t)i * n_vals, s));
   }

@@ -642,6 +642,53 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Drops with more users than one work item holds run as virtual drops, one per
+// pair of user groups: their positions are gathered in virtual-user order
+// first, and every virtual Gram's blocks are copied into the real drop's K x K
+// output after (the virtual Grams are already full Hermitian).
+__global__ __launch_bounds__(256) void k_gather_users(const double* __restrict__ pos, const int64_t* __restrict__ map,
+                                                      int64_t n_vusers, double* __restrict__ vpos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_vusers * 3) return;
+  const int64_t u = t / 3;
+  vpos[t] = pos[map[u] * 3 + (t - u * 3)];
+}
+
+// One workgroup per virtual drop; entry (r, c) of its (ka + kb)^2 Gram is
+// copied when it lies in the cross blocks or in a group's own block that the
+// descriptor assigns to this virtual drop.
+__global__ __launch_bounds__(256) void k_scatter_groups(const VDropK* __restrict__ vd,
+                                                        const double2* __restrict__ vgram,
+                                                        double2* __restrict__ gram) {
+  const VDropK v = vd[blockIdx.x];
+  const int kv = v.ka + v.kb;
+  for (int idx = threadIdx.x; idx < kv * kv; idx += blockDim.x) {
+    const int r = idx / kv, c = idx - (idx / kv) * kv;
+    const bool ra = r < v.ka, ca = c < v.ka;
+    if (ra && ca && !(v.flags & kVCopyA)) continue;
+    if (!ra && !ca && !(v.flags & kVCopyB)) continue;
+    const int gr = ra ? v.a0 + r : v.b0 + (r - v.ka);
+    const int gc = ca ? v.a0 + c : v.b0 + (c - v.ka);
+    gram[v.gram_off + (int64_t)gr * v.k + gc] = vgram[v.vgram_off + idx];
+  }
+}
+
+hipError_t launch_gather_users(const double* d_pos, const int64_t* d_map, int64_t n_vusers, double* d_vpos,
+                               hipStream_t s) {
+  if (n_vusers == 0) return hipSuccess;
+  const int64_t n = n_vusers * 3;
+  k_gather_users<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_pos, d_map, n_vusers, d_vpos);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_groups(const VDropK* d_v, int n_v, const double* d_vgram, double* d_gram, hipStream_t s) {
+  if (n_v == 0) return hipSuccess;
+  k_scatter_groups<<<n_v, 256, 0, s>>>(d_v, reinterpret_cast<const double2*>(d_vgram),
+                                       reinterpret_cast<double2*>(d_gram));
+  return hipGetLastError();
+}
+
 template <int NBMAX, typename T, int GEOM, int AMP, bool SPLIT>
 static int occupancy_grid() {
   static int cached = 0;

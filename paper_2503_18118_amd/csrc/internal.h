@@ -41,6 +41,22 @@ struct ItemK {
   int32_t e_end;
 };
 
+// A drop with more users than one work item holds (K > XLMIMO_MAX_USERS) runs
+// as virtual drops: its users fall in groups of at most kGroupUsers, and every
+// pair of groups (a < b) is one virtual drop with group a's users then group
+// b's.  One descriptor per virtual drop tells the scatter which blocks of the
+// virtual Gram land where in the real one.
+constexpr int kGroupUsers = 32;
+enum : int32_t { kVCopyA = 1, kVCopyB = 2 };   // also copy group a's / b's own block
+struct VDropK {
+  int64_t gram_off;   // the real drop's first complex element
+  int64_t vgram_off;  // the virtual drop's first complex element in the virtual Gram
+  int32_t k;          // the real drop's K
+  int32_t a0, ka;     // group a: first user (drop-local) and size
+  int32_t b0, kb;     // group b
+  int32_t flags;      // kVCopyA | kVCopyB; the cross block a-b is always copied
+};
+
 // Values of one partial: per lane, NB(NB+1)/2 symmetric Re blocks and NB^2
 // cross blocks, 4 accumulator registers each.
 __host__ __device__ constexpr int partial_values(int nb) { return (nb * (nb + 1) / 2 + nb * nb) * 4; }
@@ -76,15 +92,21 @@ hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const
                              hipEvent_t ev1 = nullptr, const int32_t* d_mask = nullptr,
                              ItemK* d_items_sel = nullptr, int* d_n_sel = nullptr);
 int gram_exact_grid(int precision, int nb_max, int geom, int amp);
+// Virtual drops: positions gathered by user map, blocks scattered back.
+hipError_t launch_gather_users(const double* d_pos, const int64_t* d_map, int64_t n_vusers, double* d_vpos,
+                               hipStream_t s);
+hipError_t launch_scatter_groups(const VDropK* d_v, int n_v, const double* d_vgram, double* d_gram, hipStream_t s);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
                              const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,
                              int k_max, hipStream_t s, int64_t n_pairs = 0,
                              int32_t* d_route = nullptr);
 
+// k_max > XLMIMO_MAX_USERS runs the workgroup-per-drop kernel, whose matrices
+// live in d_work (complex128, one K x K block per drop at its Gram offset).
 hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
-                        int32_t* d_status, hipStream_t s);
+                        int32_t* d_status, hipStream_t s, double* d_work = nullptr);
 
 hipError_t launch_ergodic(const double* d_rates, int n_drops, int n_vals, double* d_out, hipStream_t s);
 hipError_t launch_y_bounds(const double* d_pos, const DropK* d_drops, int n_drops, int geom, double t_sat,

@@ -574,11 +574,227 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
   }
 }
 
+// ---------------------------------------------------------------------------
+// K > XLMIMO_MAX_USERS: one 256-thread workgroup per drop, each factorisation's
+// matrix in a global workspace as a column-major lower triangle (element
+// (i, j), i >= j, at M[j K + i]).  Right-looking Cholesky one column per step:
+// the scaled column is staged in LDS and every thread updates whole rows of
+// the trailing triangle, so a wave's accesses to one column are contiguous.
+// W = L^-1 is then formed row by row, W_ik = -(1/L_ii) sum_{k <= t < i} L_it W_tk,
+// with W_ik (k < i) kept in the unused upper triangle at M[i K + k], so
+// [M^-1]_kk = sum_i |W_ik|^2.  The SINRs, NaN and status conventions and the
+// column order are those of k_rates; sums over users run in a fixed order.
+constexpr int kLargeThreads = 256;
+
+// Sum over the workgroup in a fixed order (per-thread sums, wave butterfly,
+// then the waves in order); every thread gets the total.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kLargeThreads / 64; ++w) t += red[w];
+  return t;
+}
+
+__device__ bool chol_global(cplx* M, int K, cplx* s_col) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < K; ++j) {
+    __syncthreads();                                   // step j - 1's updates are visible
+    const double djj = M[(int64_t)j * K + j].x;
+    if (!(djj > 0.0) || !isfinite(djj)) return false;  // uniform: every thread read the same pivot
+    const double l = sqrt(djj), il = 1.0 / l;
+    for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
+      const cplx v = M[(int64_t)j * K + i];
+      const cplx w = {v.x * il, v.y * il};
+      M[(int64_t)j * K + i] = w;
+      s_col[i] = w;
+    }
+    __syncthreads();
+    if (tid == 0) M[(int64_t)j * K + j] = {l, 0.0};
+    for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
+      const cplx lij = s_col[i];
+      int c = j + 1;
+      for (; c + 3 <= i; c += 4) {
+        cplx v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = M[(int64_t)(c + u) * K + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const cplx t = cmulc(lij, s_col[c + u]);
+          v[u].x -= t.x;
+          v[u].y -= t.y;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) M[(int64_t)(c + u) * K + i] = v[u];
+      }
+      for (; c <= i; ++c) {
+        const cplx t = cmulc(lij, s_col[c]);
+        cplx v = M[(int64_t)c * K + i];
+        M[(int64_t)c * K + i] = {v.x - t.x, v.y - t.y};
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Diagonal of (L L^H)^-1 for the factor L in M, into s_inv[0, K).
+__device__ void inv_diag_global(cplx* M, int K, cplx* s_row, double* s_inv) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < K; k += kLargeThreads) {
+    const double w = 1.0 / M[(int64_t)k * K + k].x;
+    s_inv[k] = w * w;
+  }
+  for (int i = 1; i < K; ++i) {
+    __syncthreads();                                   // row i - 1 of W is written, s_row is free
+    for (int t = tid; t < i; t += kLargeThreads) s_row[t] = M[(int64_t)t * K + i];   // L_it
+    __syncthreads();
+    const double ili = 1.0 / M[(int64_t)i * K + i].x;
+    for (int k = tid; k < i; k += kLargeThreads) {
+      const double wkk = 1.0 / M[(int64_t)k * K + k].x;
+      cplx acc = {s_row[k].x * wkk, s_row[k].y * wkk};   // t = k: L_ik W_kk
+      // t runs from the wave's first column so that a wave reads one row of W
+      // contiguously; terms with t <= k are multiplied by zero
+      const int t0 = (k & ~63) + 1;
+#pragma unroll 4
+      for (int t = t0; t < i; ++t) {
+        const cplx m = M[(int64_t)t * K + k];
+        const cplx w = t > k ? m : cplx{0.0, 0.0};
+        const cplx p = cmul(s_row[t], w);
+        acc.x += p.x;
+        acc.y += p.y;
+      }
+      const cplx wik = {-acc.x * ili, -acc.y * ili};
+      M[(int64_t)i * K + k] = wik;
+      s_inv[k] += wik.x * wik.x + wik.y * wik.y;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kLargeThreads) void k_rates_large(const DropK* __restrict__ drops,
+                                                               const double* __restrict__ gram, int n_snr,
+                                                               const double* __restrict__ rho, int64_t total_users,
+                                                               int schemes, int n_sch, double* __restrict__ work,
+                                                               double* __restrict__ rates,
+                                                               int32_t* __restrict__ status) {
+  __shared__ cplx s_vec[XLMIMO_MAX_USERS_EXACT];
+  __shared__ double s_inv[XLMIMO_MAX_USERS_EXACT], s_ginv[XLMIMO_MAX_USERS_EXACT];
+  __shared__ double s_red[kLargeThreads / 64];
+  const int tid = threadIdx.x;
+  const DropK dp = drops[blockIdx.x];
+  const int K = dp.k;
+  const int64_t KK = (int64_t)K * K;
+  const cplx* G = reinterpret_cast<const cplx*>(gram) + dp.gram_off;
+  cplx* M = reinterpret_cast<cplx*>(work) + dp.gram_off;
+  const double nan = __builtin_nan("");
+  int st = 0;
+
+  // G itself: ZF's [G^-1]_kk and the correlation gap -(1/K) log2 det R
+  double gap = nan;
+  bool g_ok = false;
+  if (schemes & (XLMIMO_ZF | XLMIMO_CORR_GAP)) {
+    // M_ic = G_ic = conj(G_ci): row c of the row-major Gram is column c of M
+    for (int64_t e = tid; e < KK; e += kLargeThreads) {
+      const int c = (int)(e / K), i = (int)(e - (int64_t)c * K);
+      if (i >= c) M[e] = {G[e].x, -G[e].y};
+    }
+    g_ok = chol_global(M, K, s_vec);
+    if (g_ok) {
+      double t = 0.0;
+      for (int k = tid; k < K; k += kLargeThreads)
+        t += 2.0 * log2(M[(int64_t)k * K + k].x) - log2(G[(int64_t)k * K + k].x);
+      gap = -block_sum(t, s_red) / K;
+      if (schemes & XLMIMO_ZF) {
+        inv_diag_global(M, K, s_vec, s_inv);
+        for (int k = tid; k < K; k += kLargeThreads) s_ginv[k] = s_inv[k];
+      }
+    } else {
+      st |= XLMIMO_ST_G_NOT_PD;
+    }
+  }
+
+  const int64_t rbase = (int64_t)blockIdx.x * n_snr * n_sch;
+  for (int s = 0; s < n_snr; ++s) {
+    const double* rs = rho + (int64_t)s * total_users + dp.user_off;
+    int col = 0;
+    if (schemes & XLMIMO_ZF) {
+      double v = 0.0;
+      for (int k = tid; k < K; k += kLargeThreads) v += g_ok ? log2(1.0 + rs[k] / s_ginv[k]) : nan;
+      const double tot = block_sum(v, s_red);
+      if (tid == 0) rates[rbase + s * n_sch + col] = tot;
+      ++col;
+    }
+    double cap = nan;
+    if (schemes & (XLMIMO_MMSE | XLMIMO_CAP)) {
+      // I + D^1/2 G D^1/2, lower triangle
+      for (int64_t e = tid; e < KK; e += kLargeThreads) {
+        const int c = (int)(e / K), i = (int)(e - (int64_t)c * K);
+        if (i >= c) {
+          const double f = sqrt(rs[i]) * sqrt(rs[c]);
+          M[e] = {(i == c ? 1.0 : 0.0) + f * G[e].x, -f * G[e].y};
+        }
+      }
+      double mmse = nan;
+      if (chol_global(M, K, s_vec)) {
+        double t = 0.0;
+        for (int k = tid; k < K; k += kLargeThreads) t += log2(M[(int64_t)k * K + k].x);
+        cap = 2.0 * block_sum(t, s_red);
+        if (schemes & XLMIMO_MMSE) {
+          inv_diag_global(M, K, s_vec, s_inv);
+          double u = 0.0;
+          for (int k = tid; k < K; k += kLargeThreads) u -= log2(s_inv[k]);   // log2(1 + SINR) = -log2 [M^-1]_kk
+          mmse = block_sum(u, s_red);
+        }
+      } else {
+        st |= XLMIMO_ST_MMSE_NOT_PD;
+      }
+      if (schemes & XLMIMO_MMSE) {
+        if (tid == 0) rates[rbase + s * n_sch + col] = mmse;
+        ++col;
+      }
+    }
+    if (schemes & XLMIMO_MRC) {
+      double v = 0.0;
+      for (int k = tid; k < K; k += kLargeThreads) {
+        const double gkk = G[(int64_t)k * K + k].x;
+        double interf = 0.0;
+        for (int j = 0; j < K; ++j) {
+          if (j == k) continue;
+          const cplx g = G[(int64_t)j * K + k];   // |G_kj| = |G_jk|, contiguous over k
+          interf += rs[j] * (g.x * g.x + g.y * g.y);
+        }
+        v += log2(1.0 + rs[k] * gkk * gkk / (interf + gkk));
+      }
+      const double tot = block_sum(v, s_red);
+      if (tid == 0) rates[rbase + s * n_sch + col] = tot;
+      ++col;
+    }
+    if (schemes & XLMIMO_CAP) {
+      if (tid == 0) rates[rbase + s * n_sch + col] = cap;
+      ++col;
+    }
+    if (schemes & XLMIMO_CORR_GAP) {
+      if (tid == 0) rates[rbase + s * n_sch + col] = gap;
+      ++col;
+    }
+  }
+  if (status != nullptr && tid == 0) status[blockIdx.x] = st;
+}
+
 hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
-                        int32_t* d_status, hipStream_t s) {
+                        int32_t* d_status, hipStream_t s, double* d_work) {
   if (n_drops == 0) return hipSuccess;
   int n_sch = __builtin_popcount(schemes);
+  if (k_max > XLMIMO_MAX_USERS) {
+    if (d_work == nullptr || (schemes & (XLMIMO_MZF | XLMIMO_MZF_MISM))) return hipErrorInvalidValue;
+    k_rates_large<<<n_drops, kLargeThreads, 0, s>>>(d_drops, d_gram, n_snr, d_rho, total_users, schemes, n_sch,
+                                                    d_work, d_rates, d_status);
+    return hipGetLastError();
+  }
   const int ld = k_max + 1;
   const bool mism = schemes & XLMIMO_MZF_MISM;
   const int jobs = ((schemes & (XLMIMO_ZF | XLMIMO_CORR_GAP)) ? 1 : 0) + ((schemes & XLMIMO_MZF) ? 1 : 0) +

@@ -26,7 +26,7 @@ ZF, MMSE, MRC, CAP, MZF, MZF_MISM, CORR_GAP = 1, 2, 4, 8, 16, 32, 64
 ST_G_NOT_PD, ST_MMSE_NOT_PD, ST_FILTER_NOT_PD, ST_BAD_INPUT, ST_CF_DEGENERATE, ST_FELL_BACK = 1, 2, 4, 8, 16, 32
 FORM_EXACT_FP64, FORM_EXACT_FP32C, FORM_CF_PAPER, FORM_CF_GATED, FORM_CF_GATED_MLP, FORM_EXACT_FP32H, FORM_CF_UNIFORM = \
     0, 1, 2, 3, 4, 5, 6
-MAX_USERS = 64
+MAX_USERS, MAX_USERS_EXACT = 64, 1024
 MLP_IN, MLP_OUT, PAIR_FEAT_PITCH, PAIR_AUX_PITCH = 6, 7, 8, 8
 
 EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlmimo_version",

@@ -142,9 +142,12 @@ def test_invalid_arguments_rejected(X, ctx):
         ctx.gram_exact(bad, b, X.FP64)
     with pytest.raises(X.XlmimoError, match="precision"):
         ctx.gram_exact(arr, b, 7)
+    big = W._pack([10], [1025], np.ones((1025, 3)))
+    with pytest.raises(X.XlmimoError, match="K = 1025"):
+        ctx.gram_exact(arr, X.Batch(big), X.FP64)
     big = W._pack([10], [65], np.ones((65, 3)))
     with pytest.raises(X.XlmimoError, match="K = 65"):
-        ctx.gram_exact(arr, X.Batch(big), X.FP64)
+        ctx.gram_closedform(arr, X.Batch(big), X.CF_PAPER)
     zero_n = W._pack([0], [2], np.ones((2, 3)))
     with pytest.raises(X.XlmimoError, match="N = 0"):
         ctx.gram_exact(arr, X.Batch(zero_n), X.FP64)
