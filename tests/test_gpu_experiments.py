@@ -1,4 +1,4 @@
-"""The paper's experiments (Fig. 3, Fig. 4) through the library's capacity sweep, against the oracle.
+"""The paper's experiments (Figs. 3, 4 and 5) through the library's capacity sweep, against the oracle.
 
 Small cases are compared with the FP64 oracle drop by drop through the ergodic means: ZF, MMSE,
 MRC and the capacity on the exact FP64 Gram (1e-8 relative),
@@ -90,10 +90,11 @@ def test_fig4_sweep_matches_oracle(X, E, ctx):
 
 
 def test_fig3_sweep_matches_oracle(X, E, ctx):
-    n_list = [256, 1024]
-    r = E.fig3(ctx, n_drops=4, n_list=n_list, k=64)
+    # K = 100 (the paper's user count: every drop runs as group-pair virtual drops)
+    n_list = [1024, 4096]
+    r = E.fig3(ctx, n_drops=4, n_list=n_list, k=100)
     arr = W.ula(n_list[-1], W.LAMBDA_100GHZ, W.AMP_PNUSW)
-    drops = W.rect_drops(W.rng_for(10), 4, 64, n_list[-1], (1.0, 10.0), (-7.5, 7.5))
+    drops = W.rect_drops(W.rng_for(10), 4, 100, n_list[-1], (1.0, 10.0), (-7.5, 7.5))
     rho = X.rho_for_snr(arr, [0.0, 200.0], 5.5, drops.n_users.sum()).cpu().numpy()
     ref, _ = _oracle_ergodic(arr, drops, n_list, rho, orates.SCHEME_CAP)
     assert np.allclose(np.array(r["capacity"]), ref[:, :, 0], rtol=1e-9)
@@ -121,7 +122,7 @@ def test_fig4_reproduces_the_papers_claims(X, E, ctx):
 
 
 def test_fig3_reproduces_the_papers_claims(X, E, ctx):
-    # Sec. IV-C (K = 64 here, 200 drops): the normalised capacity grows with N and has all but
+    # Sec. IV-C (K = 100, 200 drops): the normalised capacity grows with N and has all but
     # saturated at the analytic saturation point of eqs. (15)-(16); it converges faster at 200 dB.
     r = E.fig3(ctx, n_drops=200)
     n = np.array(r["n_list"], np.float64)
@@ -134,14 +135,19 @@ def test_fig3_reproduces_the_papers_claims(X, E, ctx):
     assert r["empirical_saturation_n"][1] < r["empirical_saturation_n"][0]
 
 
-def test_fig5_matches_oracle_and_the_papers_trend(X, E, ctx):
-    # Appendix A: the normalised bound gap grows with K and stays below the paper's maximum of 0.064
-    # (reached at K = 1000); the small case against the oracle drop by drop
+def test_fig5_matches_oracle_and_the_papers_value(X, E, ctx):
+    # Appendix A: the normalised bound gap grows with K, about linearly, and reaches the paper's
+    # printed 0.064 at K = 1000 (two digits; the paper states neither N nor the drop count: 5 %);
+    # the small case against the oracle drop by drop
     r = E.fig5(ctx, n_drops=100)
+    k = np.array(r["k_list"], np.float64)
     g = np.array(r["negative_mean_log2_eig_R"])
+    assert r["k_list"][-1] == 1000 and sum(r["flagged_drops_by_k"]) == 0
     assert np.all(np.diff(g) > 0) and g[0] > 0
+    assert np.all(np.abs(g[k >= 64] / k[k >= 64] / (g[-1] / 1000.0) - 1) < 0.05)
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
-    assert g[-1] < gold["appendix_a_max_gap"]["value"]
+    assert gold["appendix_a_max_gap"]["K"] == 1000
+    assert abs(g[-1] / gold["appendix_a_max_gap"]["value"] - 1) < 0.05, g[-1]
     small = E.fig5(ctx, n_drops=5, k_list=(2, 8), n=1024)
     arr = W.ula(1024, W.LAMBDA_100GHZ, W.AMP_PNUSW)
     for k, got in zip((2, 8), small["negative_mean_log2_eig_R"]):
