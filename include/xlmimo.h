@@ -189,6 +189,25 @@ int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
 int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                       int32_t precision, double* gram_out, void* stream);
 
+/* Tracking update of the exact Gram (Sec. V-B: user states known from sensing
+ * let the channel be regenerated as users move).  After users of the batch
+ * have moved (their new positions already written to batch->user_pos),
+ * recompute the rows and columns of gram_inout that involve them; every other
+ * entry is left as it is.  Replacing row and column m of G is a Hermitian
+ * rank-2 change.  Each moved user m runs as work items of itself and at most
+ * 63 other users of its drop, so a row costs about K channel evaluations per
+ * element against the full Gram's K (K <= 64) or (ceil(K/32) - 1) K (K > 64).
+ *   precision   XLMIMO_FP64, XLMIMO_FP32C or XLMIMO_FP32H (as xlmimo_gram_exact)
+ *   moved       HOST int64 [n_moved]: global user indices (drops back to back),
+ *               strictly ascending; an entry between two moved users is written
+ *               by the row of the lower index
+ *   gram_inout  DEVICE complex128 Grams (layout above) of the previous positions
+ * K up to XLMIMO_MAX_USERS_EXACT.  A new moved set builds (and caches) a launch
+ * plan synchronously: warm it before graph capture. */
+int xlmimo_gram_update_users(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                             int32_t precision, int64_t n_moved, const int64_t* moved, double* gram_inout,
+                             void* stream);
+
 /* Closed-form Gram of the paper's modified ZF (eqs. (22)-(23)):
  *   G~_ii = eq. (4) / P (PNUSW ULA, general spacing d: beta0/(d x_i) S_i with
  *           half-aperture L = N d / 2); the free-space ULA analogue

@@ -47,6 +47,8 @@ struct Plan {
   int64_t n_vusers = 0;
   VDropK* d_v = nullptr;
   int64_t* d_vmap = nullptr;
+  VRowK* d_vr = nullptr;          // row plans (moved users): one descriptor per virtual drop
+  int n_vr = 0;
 };
 
 }  // namespace
@@ -232,10 +234,12 @@ void drop_plan_buffers(xlmimo_ctx* c, Plan& p) {
   (void)release(c, p.d_items);
   (void)release(c, p.d_v);
   (void)release(c, p.d_vmap);
+  (void)release(c, p.d_vr);
   p.d_drops = nullptr;
   p.d_items = nullptr;
   p.d_v = nullptr;
   p.d_vmap = nullptr;
+  p.d_vr = nullptr;
   if (p.vplan) {
     drop_plan_buffers(c, *p.vplan);
     delete p.vplan;
@@ -459,14 +463,24 @@ int exact_grid(xlmimo_ctx* c, const Plan* p, int precision) {
   return std::min(g, std::max(p->n_items, 1));
 }
 
+int run_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, Plan* p, int32_t precision,
+              double* gram_out, hipStream_t s);
+
 int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override,
                     int32_t precision, double* gram_out, hipStream_t s) {
   Plan* p = nullptr;
   int rc = get_plan(c, a, b, n_override, &p);
   if (rc) return rc;
   if (p->k_max > XLMIMO_MAX_USERS && !p->vplan && (rc = build_groups(c, a, *p))) return rc;
+  return run_exact(c, a, b, p, precision, gram_out, s);
+}
+
+// Launch the exact Gram of a plan: directly, or through its virtual drops
+// (user groups or moved-user rows) and the matching scatter.
+int run_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, Plan* p, int32_t precision,
+              double* gram_out, hipStream_t s) {
   Plan* run = p->vplan ? p->vplan : p;   // the plan whose drops the kernels see
-  rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(run->partial_doubles, 1), s);
+  int rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(run->partial_doubles, 1), s);
   if (rc) return rc;
   const double* pos = b->user_pos;
   double* out = gram_out;
@@ -491,7 +505,107 @@ int gram_exact_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b,
   }
   HIP_TRY(c, launch_gram_exact(precision, run->nb_max, to_kernel(a), run->d_drops, run->n_drops, pos, run->d_items,
                                run->n_items, c->d_counter, (double*)c->partials.p, out, grid, s, ev0, ev1));
-  if (p->vplan) HIP_TRY(c, launch_scatter_groups(p->d_v, p->n_v, (const double*)c->scratch_vgram.p, gram_out, s));
+  if (p->d_vr)
+    HIP_TRY(c, launch_scatter_rows(p->d_vr, p->n_vr, p->d_vmap, (const double*)c->scratch_vgram.p, gram_out, s));
+  else if (p->vplan)
+    HIP_TRY(c, launch_scatter_groups(p->d_v, p->n_v, (const double*)c->scratch_vgram.p, gram_out, s));
+  return XLMIMO_OK;
+}
+
+// Row plan of a set of moved users (global indices, strictly ascending): for
+// each moved user m of drop d, its partners are every other user of d except
+// moved users below m (their rows already hold the entry), in runs of at most
+// XLMIMO_MAX_USERS - 1; each run with m first is one virtual drop.  A user
+// with no partners (K = 1, or every other user moved and below it) is a
+// virtual drop of its own, for G_mm.
+int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int64_t n_moved,
+                 const int64_t* moved, Plan** out) {
+  uint64_t h = plan_key(a, b, nullptr);
+  h = fnv(h ^ 0x726f777375706474ULL, moved, sizeof(int64_t) * n_moved);
+  auto it = c->plans.find(h);
+  if (it != c->plans.end()) {
+    *out = &it->second;
+    return XLMIMO_OK;
+  }
+  if (c->capturing)
+    return set_err(c, XLMIMO_EINVAL, "a new set of moved users needs a launch plan during graph capture: "
+                   "run the same call once before capturing it");
+  if (c->plans.size() >= 64) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    for (auto& kv : c->plans) drop_plan_buffers(c, kv.second);
+    c->plans.clear();
+  }
+  const int n = (int)b->n_drops;
+  std::vector<int64_t> uoff(n + 1, 0), goff(n + 1, 0);
+  for (int d = 0; d < n; ++d) {
+    uoff[d + 1] = uoff[d] + b->n_users[d];
+    goff[d + 1] = goff[d] + (int64_t)b->n_users[d] * b->n_users[d];
+  }
+  std::vector<VRowK> vr;
+  std::vector<int64_t> vmap, vne;
+  std::vector<int32_t> vk;
+  int64_t vgoff = 0;
+  std::vector<char> is_moved;
+  int cur_drop = -1;
+  for (int64_t q = 0; q < n_moved; ++q) {
+    const int64_t u = moved[q];
+    const int d = (int)(std::upper_bound(uoff.begin(), uoff.end(), u) - uoff.begin()) - 1;
+    const int K = b->n_users[d];
+    if (d != cur_drop) {   // moved users of this drop, for the partner rule
+      cur_drop = d;
+      is_moved.assign(K, 0);
+      for (int64_t r = q; r < n_moved && moved[r] < uoff[d + 1]; ++r) is_moved[moved[r] - uoff[d]] = 1;
+    }
+    const int m = (int)(u - uoff[d]);
+    const int64_t ne = a->geometry == XLMIMO_UPA ? a->n_y * a->n_z : (b->n_elems ? b->n_elems[d] : a->n_y);
+    std::vector<int> partners;
+    for (int j = 0; j < K; ++j)
+      if (j != m && !(is_moved[j] && j < m)) partners.push_back(j);
+    const int per = XLMIMO_MAX_USERS - 1;
+    const int runs = std::max<int>(1, ((int)partners.size() + per - 1) / per);
+    for (int r = 0; r < runs; ++r) {
+      const int j0 = r * per, j1 = std::min<int>((int)partners.size(), j0 + per);
+      VRowK v;
+      v.gram_off = goff[d];
+      v.vgram_off = vgoff;
+      v.user_off = uoff[d];
+      v.vu0 = (int64_t)vmap.size();
+      v.k = K;
+      v.kv = 1 + (j1 - j0);
+      v.diag = r == 0;
+      v.pad = 0;
+      vr.push_back(v);
+      vmap.push_back(u);
+      for (int j = j0; j < j1; ++j) vmap.push_back(uoff[d] + partners[j]);
+      vne.push_back(ne);
+      vk.push_back(v.kv);
+      vgoff += (int64_t)v.kv * v.kv;
+    }
+  }
+  if (vr.size() > 2147483647ULL) return set_err(c, XLMIMO_EINVAL, "too many moved-user rows");
+  Plan p;
+  p.n_drops = n;
+  p.key = h;
+  Plan* vp = new Plan();
+  p.vplan = vp;
+  int rc = build_plan(c, a, (int)vr.size(), vne.data(), vk.data(), h ^ 0x9e3779b97f4a7c15ULL, *vp);
+  if (!rc) {
+    p.n_vr = (int)vr.size();
+    p.n_vusers = (int64_t)vmap.size();
+    hipError_t e = hipMalloc(&p.d_vr, sizeof(VRowK) * std::max<size_t>(vr.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&p.d_vmap, sizeof(int64_t) * std::max<size_t>(vmap.size(), 1));
+    if (e == hipSuccess && !vr.empty())
+      e = hipMemcpy(p.d_vr, vr.data(), sizeof(VRowK) * vr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !vmap.empty())
+      e = hipMemcpy(p.d_vmap, vmap.data(), sizeof(int64_t) * vmap.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = set_err(c, XLMIMO_EDEVICE, "row plan upload: %s", hipGetErrorString(e));
+  }
+  if (rc) {
+    drop_plan_buffers(c, p);
+    return rc;
+  }
+  auto ins = c->plans.emplace(h, p);
+  *out = &ins.first->second;
   return XLMIMO_OK;
 }
 
@@ -1044,6 +1158,33 @@ int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* 
   if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
   if ((rc = set_device(c))) return rc;
   return gram_exact_impl(c, a, b, nullptr, precision, gram_out, (hipStream_t)stream);
+}
+
+int xlmimo_gram_update_users(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,
+                             int64_t n_moved, const int64_t* moved, double* gram_inout, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true, XLMIMO_MAX_USERS_EXACT);
+  if (rc) return rc;
+  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C && precision != XLMIMO_FP32H)
+    return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
+  if (n_moved < 0) return set_err(c, XLMIMO_EINVAL, "n_moved must be >= 0");
+  if (n_moved == 0 || b->n_drops == 0) return XLMIMO_OK;
+  if (!moved || !gram_inout) return set_err(c, XLMIMO_EINVAL, "moved and gram_inout are required");
+  int64_t total = 0;
+  for (int64_t d = 0; d < b->n_drops; ++d) total += b->n_users[d];
+  for (int64_t q = 0; q < n_moved; ++q) {
+    if (moved[q] < 0 || moved[q] >= total)
+      return set_err(c, XLMIMO_EINVAL, "moved[%lld] = %lld outside 0..%lld", (long long)q, (long long)moved[q],
+                     (long long)(total - 1));
+    if (q && moved[q] <= moved[q - 1]) return set_err(c, XLMIMO_EINVAL, "moved must be strictly ascending");
+  }
+  if ((rc = set_device(c))) return rc;
+  Plan* p = nullptr;
+  if ((rc = get_row_plan(c, a, b, n_moved, moved, &p))) return rc;
+  return run_exact(c, a, b, p, precision, gram_inout, (hipStream_t)stream);
 }
 
 int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t variant,

@@ -674,6 +674,32 @@ __global__ __launch_bounds__(256) void k_scatter_groups(const VDropK* __restrict
   }
 }
 
+// Row update: one workgroup per virtual drop; row 0 and column 0 of its Gram
+// (the moved user against its partners) land in row m and column m.
+__global__ __launch_bounds__(256) void k_scatter_rows(const VRowK* __restrict__ vr, const int64_t* __restrict__ map,
+                                                      const double2* __restrict__ vgram,
+                                                      double2* __restrict__ gram) {
+  const VRowK v = vr[blockIdx.x];
+  const int m = (int)(map[v.vu0] - v.user_off);
+  for (int c = threadIdx.x; c < v.kv; c += blockDim.x) {
+    if (c == 0) {
+      if (v.diag) gram[v.gram_off + (int64_t)m * v.k + m] = vgram[v.vgram_off];
+      continue;
+    }
+    const int j = (int)(map[v.vu0 + c] - v.user_off);
+    gram[v.gram_off + (int64_t)m * v.k + j] = vgram[v.vgram_off + c];
+    gram[v.gram_off + (int64_t)j * v.k + m] = vgram[v.vgram_off + (int64_t)c * v.kv];
+  }
+}
+
+hipError_t launch_scatter_rows(const VRowK* d_vr, int n_vr, const int64_t* d_map, const double* d_vgram,
+                               double* d_gram, hipStream_t s) {
+  if (n_vr == 0) return hipSuccess;
+  k_scatter_rows<<<n_vr, 256, 0, s>>>(d_vr, d_map, reinterpret_cast<const double2*>(d_vgram),
+                                      reinterpret_cast<double2*>(d_gram));
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_users(const double* d_pos, const int64_t* d_map, int64_t n_vusers, double* d_vpos,
                                hipStream_t s) {
   if (n_vusers == 0) return hipSuccess;

@@ -57,6 +57,20 @@ struct VDropK {
   int32_t flags;      // kVCopyA | kVCopyB; the cross block a-b is always copied
 };
 
+// Row update of moved users: virtual drop = one moved user m (virtual user 0)
+// and up to 63 partner users of its drop; only row 0 and column 0 of its Gram
+// are copied back, into row m and column m of the real drop.
+struct VRowK {
+  int64_t gram_off;   // the real drop's first complex element
+  int64_t vgram_off;  // the virtual drop's first complex element in the virtual Gram
+  int64_t user_off;   // the real drop's first user (global index)
+  int64_t vu0;        // the virtual drop's first virtual user (into the user map)
+  int32_t k;          // the real drop's K
+  int32_t kv;         // users of the virtual drop (1 + partners)
+  int32_t diag;       // also copy G_mm (the first virtual drop of each moved user)
+  int32_t pad;
+};
+
 // Values of one partial: per lane, NB(NB+1)/2 symmetric Re blocks and NB^2
 // cross blocks, 4 accumulator registers each.
 __host__ __device__ constexpr int partial_values(int nb) { return (nb * (nb + 1) / 2 + nb * nb) * 4; }
@@ -96,6 +110,8 @@ int gram_exact_grid(int precision, int nb_max, int geom, int amp);
 hipError_t launch_gather_users(const double* d_pos, const int64_t* d_map, int64_t n_vusers, double* d_vpos,
                                hipStream_t s);
 hipError_t launch_scatter_groups(const VDropK* d_v, int n_v, const double* d_vgram, double* d_gram, hipStream_t s);
+hipError_t launch_scatter_rows(const VRowK* d_vr, int n_vr, const int64_t* d_map, const double* d_vgram,
+                               double* d_gram, hipStream_t s);
 
 hipError_t launch_closedform(const ArrayK& arr, const DropK* d_drops, int n_drops, int variant, const double* d_pos,
                              const double* d_gl, int n_gl, double* d_diag, double* d_gram, int32_t* d_status,

@@ -18,7 +18,12 @@ rates, ergodic means and the saturation point); nothing here computes.
   bounds, -(1/K) log2 det R (eq. (9)), against K in the Sec. IV scene at N = 65536,
   K = 2 ... 1000 as in the paper (which states neither N nor the drop count).
 
-``python -m paper_2503_18118_amd.experiments [fig3|fig4|fig5] [--drops D] [--json PATH]``
+* ``tracking``: the premise of Sec. V-B (user states from sensing, channels regenerated as users
+  move): per frame one user of every drop moves, and the exact Gram is brought up to date by
+  recomputing that user's row and column (xlmimo_gram_update_users) instead of the whole Gram.
+  Times both and checks that they agree.  Not a figure of the paper.
+
+``python -m paper_2503_18118_amd.experiments [fig3|fig4|fig5|tracking] [--drops D] [--json PATH]``
 prints a table and optionally writes the numbers as JSON.
 """
 from __future__ import annotations
@@ -29,6 +34,7 @@ import os
 import sys
 import time
 
+import numpy as np
 import torch
 
 from . import xlmimo as X
@@ -132,6 +138,72 @@ def fig5(ctx, n_drops: int = 100, k_list=FIG5_K, n: int = 65536) -> dict:
             "flagged_drops_by_k": flagged, "gpu_ms": float(sum(ms_k))}
 
 
+def _events():
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def tracking(ctx, n_drops: int = 20, k_list=(16, 256, 1000), n: int = 65536, frames: int = 5,
+             step_m: float = 0.005, precisions=("FP64", "FP32H")) -> dict:
+    """Per frame, the middle user of every drop moves by step_m in y; the Gram is updated by rows
+    and, for comparison, recomputed whole.  Reports the mean time per frame of each and the largest
+    normwise difference between the two Grams over all frames."""
+    arr = W.ula(n, W.LAMBDA_100GHZ, W.AMP_PNUSW)
+    out = {"scene": "Sec. IV: 100 GHz PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m", "n": n, "drops": n_drops,
+           "frames": frames, "step_m": step_m, "k_list": [int(k) for k in k_list], "by_precision": {}}
+    s = torch.cuda.current_stream()
+    for pname in precisions:
+        prec = getattr(X, pname)
+        rows = {"full_ms": [], "update_ms": [], "max_normwise_diff": []}
+        for k in k_list:
+            drops = W.rect_drops(W.rng_for(10), n_drops, int(k), n, (1.0, 10.0), (-7.5, 7.5))
+            b = X.Batch(drops)
+            g = ctx.gram_exact(arr, b, prec)
+            full = torch.empty_like(g)
+            t_full = t_upd = 0.0
+            worst = 0.0
+            moved = (drops.user_off[:-1] + int(k) // 2).astype(np.int64)
+            for f in range(frames + 1):        # frame 0 builds the launch plans and is not timed
+                b.pos[torch.as_tensor(moved, device=b.pos.device), 1] += step_m
+                e0, e1 = _events()
+                e0.record(s)
+                ctx.gram_update_users(arr, b, moved, g, prec)
+                e1.record(s)
+                e2, e3 = _events()
+                e2.record(s)
+                ctx.gram_exact(arr, b, prec, out=full)
+                e3.record(s)
+                e3.synchronize()
+                if f:
+                    t_upd += e0.elapsed_time(e1)
+                    t_full += e2.elapsed_time(e3)
+                gu = g.view(torch.complex128)
+                gf = full.view(torch.complex128)
+                for d in range(n_drops):
+                    lo, hi = int(b.gram_off[d]), int(b.gram_off[d + 1])
+                    a = gu[lo:hi].view(int(k), int(k))
+                    c = gf[lo:hi].view(int(k), int(k))
+                    dg = torch.sqrt(torch.diagonal(c).real)
+                    worst = max(worst, float(((a - c).abs() / torch.outer(dg, dg)).max()))
+            rows["full_ms"].append(t_full / frames)
+            rows["update_ms"].append(t_upd / frames)
+            rows["max_normwise_diff"].append(worst)
+            del b, g, full
+        out["by_precision"][pname] = rows
+    return out
+
+
+def _table_tracking(r):
+    lines = [f"Tracking ({r['scene']}; N = {r['n']}, {r['drops']} drops, one user per drop moves "
+             f"{1e3 * r['step_m']:.0f} mm per frame; mean over {r['frames']} frames)",
+             "| precision | K | full Gram ms | row update ms | speed-up | max normwise difference |",
+             "|---|---|---|---|---|---|"]
+    for p, rows in r["by_precision"].items():
+        for i, k in enumerate(r["k_list"]):
+            fm, um = rows["full_ms"][i], rows["update_ms"][i]
+            lines.append(f"| {p} | {k} | {fm:.3f} | {um:.3f} | {fm / um:.1f} | {rows['max_normwise_diff'][i]:.1e} |")
+    return "\n".join(lines)
+
+
 def _table_fig5(r):
     lines = [f"Fig. 5 ({r['scene']}; N = {r['n']}, {r['drops']} drops): -E[log2 lambda^R] against K",
              "| K | " + " | ".join(str(k) for k in r["k_list"]) + " |", "|---|" + "---|" * len(r["k_list"]),
@@ -170,13 +242,14 @@ def _table_fig4(r):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("figure", choices=["fig3", "fig4", "fig5"])
+    ap.add_argument("figure", choices=["fig3", "fig4", "fig5", "tracking"])
     ap.add_argument("--drops", type=int, default=1000)
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     ctx = X.Context(0)
     t0 = time.perf_counter()
-    run, table = {"fig3": (fig3, _table_fig3), "fig4": (fig4, _table_fig4), "fig5": (fig5, _table_fig5)}[args.figure]
+    run, table = {"fig3": (fig3, _table_fig3), "fig4": (fig4, _table_fig4), "fig5": (fig5, _table_fig5),
+                  "tracking": (tracking, _table_tracking)}[args.figure]
     r = run(ctx, args.drops)
     r["wall_s"] = time.perf_counter() - t0
     print(table(r))

@@ -36,7 +36,7 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_mlp_get_params", "xlmimo_pair_count", "xlmimo_mlp_pair_inputs", "xlmimo_mlp_loss_grad",
             "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
             "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
-            "xlmimo_graph_destroy", "xlmimo_autotune_exact")
+            "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users")
 
 
 class XlArray(C.Structure):
@@ -61,6 +61,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_last_error.restype = C.c_char_p
     lib.xlmimo_version.restype = C.c_char_p
     lib.xlmimo_gram_exact.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp]
+    lib.xlmimo_gram_update_users.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, i64,
+                                             C.POINTER(C.c_int64), vp, vp]
     lib.xlmimo_gram_closedform.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp, vp]
     lib.xlmimo_zf_mmse_sumrate.argtypes = [vp, C.POINTER(XlBatch), vp, vp, i32, vp, i32, vp, vp, vp]
     lib.xlmimo_capacity_sweep.argtypes = [vp, C.POINTER(XlArray), i32, C.POINTER(C.c_int64), C.POINTER(XlBatch),
@@ -213,6 +215,17 @@ class Context:
         self._check(_lib.xlmimo_gram_exact(self.h, C.byref(a), C.byref(batch.struct), precision, _ptr(out),
                                            _stream(stream)), "xlmimo_gram_exact")
         return out
+
+    def gram_update_users(self, arr, batch: Batch, moved, gram: torch.Tensor, precision: int = FP32C,
+                          stream=None) -> torch.Tensor:
+        """Recompute, in place, the rows and columns of `gram` that involve the users `moved`
+        (global indices, strictly ascending) after their positions in batch.pos changed."""
+        mv = np.ascontiguousarray(moved, np.int64)
+        a = make_array(arr)
+        self._check(_lib.xlmimo_gram_update_users(self.h, C.byref(a), C.byref(batch.struct), precision, len(mv),
+                                                  mv.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(gram),
+                                                  _stream(stream)), "xlmimo_gram_update_users")
+        return gram
 
     def gram_closedform(self, arr, batch: Batch, variant: int = CF_PAPER, out: Optional[torch.Tensor] = None,
                         status: Optional[torch.Tensor] = None, stream=None):

@@ -1,0 +1,156 @@
+"""Tracking update of the exact Gram (xlmimo_gram_update_users) against the oracle.
+
+After some users move, the rows and columns that involve them are recomputed
+in place; the result is compared with the oracle's Gram at the new positions
+(normwise, the exact-Gram tolerances: 1e-9 FP64, 1e-5 FP32C/FP32H), every
+other entry must keep its previous bits, and the Gram stays exactly Hermitian.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import channel as och
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"FP64": 1e-9, "FP32C": 1e-5, "FP32H": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2503_18118_amd import xlmimo
+    return xlmimo
+
+
+@pytest.fixture(scope="module")
+def ctx(X):
+    c = X.Context(0)
+    yield c
+    c.close()
+
+
+def _drops(ns, ks, seed, r=(2.0, 40.0), th=(-70.0, 70.0)):
+    rng = np.random.default_rng(seed)
+    pos = []
+    for k in ks:
+        rr = rng.uniform(*r, k)
+        t = np.deg2rad(rng.uniform(*th, k))
+        pos.append(np.stack([rr * np.cos(t), rr * np.sin(t), np.zeros(k)], axis=-1))
+    return W._pack(ns, ks, np.concatenate(pos))
+
+
+def _move(drops, b, moved, seed, step=0.3):
+    """Displace the moved users by up to `step` metres in x and y (host copy and device batch)."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-step, step, (len(moved), 3))
+    d[:, 2] = 0.0
+    drops.pos[moved] += d
+    b.pos[torch.as_tensor(moved, device=b.pos.device)] = torch.as_tensor(drops.pos[moved], device=b.pos.device)
+
+
+def _check(X, arr, drops, b, g_old, g_new, moved, tol, tag):
+    old, new = b.split(g_old), b.split(g_new)
+    mv = set(int(u) for u in moved)
+    for d in range(drops.n_drops):
+        k = int(drops.n_users[d])
+        rows = [u - int(drops.user_off[d]) for u in range(int(drops.user_off[d]), int(drops.user_off[d + 1]))
+                if u in mv]
+        keep = np.ones((k, k), bool)
+        keep[rows, :] = False
+        keep[:, rows] = False
+        assert np.array_equal(new[d][keep], old[d][keep]), (tag, d)
+        assert np.array_equal(new[d], new[d].conj().T), (tag, d)
+        ref = och.gram_exact(arr.with_n(int(drops.n_elems[d])), drops.users_of(d))
+        err = och.normwise_error(new[d], ref)
+        assert err < tol, (tag, d, k, err)
+
+
+@pytest.mark.parametrize("precision", ["FP64", "FP32C", "FP32H"])
+def test_update_users_matches_oracle(X, ctx, precision):
+    # first, last and middle users; two and three moved users in one drop (the lower index writes the
+    # entry they share); K = 1; K > 64 (rows of 63-user runs); a drop with nothing moved
+    ks = [5, 70, 200, 1, 16]
+    ns = [1000, 4097, 3000, 300, 2048]
+    drops = _drops(ns, ks, seed=71)
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    prec = getattr(X, precision)
+    g_old = ctx.gram_exact(arr, b, prec)
+    off = drops.user_off
+    moved = np.array([off[0] + 0, off[0] + 4, off[1] + 3, off[1] + 10, off[1] + 69, off[2] + 150, off[3]], np.int64)
+    _move(drops, b, moved, seed=1)
+    g = ctx.gram_update_users(arr, b, moved, g_old.clone(), prec)
+    torch.cuda.synchronize()
+    _check(X, arr, drops, b, g_old, g, moved, TOL[precision], precision)
+    # the same moved set again (cached plan), after a second move
+    g2_old = g.clone()
+    _move(drops, b, moved, seed=2)
+    g2 = ctx.gram_update_users(arr, b, moved, g.clone(), prec)
+    torch.cuda.synchronize()
+    _check(X, arr, drops, b, g2_old, g2, moved, TOL[precision], precision + " again")
+
+
+def test_update_every_user_of_a_drop(X, ctx):
+    # every user of a K = 70 drop moves: the last user's row has no partners left but its diagonal
+    ks = [70, 3]
+    drops = _drops([2000, 500], ks, seed=73)
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g_old = ctx.gram_exact(arr, b, X.FP64)
+    moved = np.arange(70, dtype=np.int64)
+    _move(drops, b, moved, seed=3)
+    g = ctx.gram_update_users(arr, b, moved, g_old.clone(), X.FP64)
+    torch.cuda.synchronize()
+    _check(X, arr, drops, b, g_old, g, moved, TOL["FP64"], "all")
+    full = b.split(ctx.gram_exact(arr, b, X.FP64))[0]
+    assert och.normwise_error(b.split(g)[0], full) < 1e-12
+
+
+def test_update_users_upa(X, ctx):
+    arr = W.ArraySpec(W.GEOM_UPA, 16, 12, 1.5e-3, 3.0e-3, W.AMP_PNUSW)
+    rng = np.random.default_rng(7)
+    ks = [9, 80]
+    pos = []
+    for k in ks:
+        pos.append(np.stack([rng.uniform(0.5, 3.0, k), rng.uniform(-1, 1, k), rng.uniform(-1, 1, k)], axis=-1))
+    drops = W._pack([arr.n_elems] * 2, ks, np.concatenate(pos))
+    b = X.Batch(drops)
+    g_old = ctx.gram_exact(arr, b, X.FP64)
+    moved = np.array([2, 9 + 40, 9 + 79], np.int64)
+    rngm = np.random.default_rng(4)
+    drops.pos[moved] += rngm.uniform(-0.2, 0.2, (3, 3))
+    b.pos[torch.as_tensor(moved, device="cuda")] = torch.as_tensor(drops.pos[moved], device="cuda")
+    g = ctx.gram_update_users(arr, b, moved, g_old.clone(), X.FP64)
+    torch.cuda.synchronize()
+    new = b.split(g)
+    for d in range(2):
+        assert och.normwise_error(new[d], och.gram_exact(arr, drops.users_of(d))) < TOL["FP64"]
+
+
+def test_update_users_rejects_bad_lists(X, ctx):
+    drops = _drops([300, 300], [4, 6], seed=79)
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    with pytest.raises(X.XlmimoError, match="ascending"):
+        ctx.gram_update_users(arr, b, [3, 1], g, X.FP64)
+    with pytest.raises(X.XlmimoError, match="ascending"):
+        ctx.gram_update_users(arr, b, [2, 2], g, X.FP64)
+    with pytest.raises(X.XlmimoError, match="outside"):
+        ctx.gram_update_users(arr, b, [10], g, X.FP64)
+    with pytest.raises(X.XlmimoError, match="outside"):
+        ctx.gram_update_users(arr, b, [-1], g, X.FP64)
+    before = g.clone()
+    ctx.gram_update_users(arr, b, [], g, X.FP64)   # nothing moved: a no-op
+    torch.cuda.synchronize()
+    assert torch.equal(before, g)
+
+
+def test_tracking_experiment_agrees_with_full_recompute(X, ctx):
+    from paper_2503_18118_amd import experiments as E
+    r = E.tracking(ctx, n_drops=3, k_list=(16, 100), n=4096, frames=2)
+    assert max(r["by_precision"]["FP64"]["max_normwise_diff"]) < 1e-12
+    assert max(r["by_precision"]["FP32H"]["max_normwise_diff"]) < 1e-5
