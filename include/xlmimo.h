@@ -236,7 +236,7 @@ int xlmimo_gram_closedform(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmim
  *   status_out   DEVICE int32 [n_drops] or NULL: OR of XLMIMO_ST_* over the SNR points
  * Batches with K up to XLMIMO_MAX_USERS run one wave per drop with the matrix
  * in LDS (or registers for K <= 16).  A batch with a larger K (up to
- * XLMIMO_MAX_USERS_EXACT) runs one 256-thread workgroup per drop with the
+ * XLMIMO_MAX_USERS_EXACT) runs one 512-thread workgroup per drop with the
  * matrix in a context workspace of the Gram's size (schemes XLMIMO_MZF and
  * XLMIMO_MZF_MISM are rejected there with XLMIMO_EINVAL). */
 int xlmimo_zf_mmse_sumrate(xlmimo_ctx* ctx, const xlmimo_batch* batch,

@@ -575,16 +575,15 @@ __global__ __launch_bounds__(256) void k_rates_small(const DropK* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
-// K > XLMIMO_MAX_USERS: one 256-thread workgroup per drop, each factorisation's
+// K > XLMIMO_MAX_USERS: one 512-thread workgroup per drop, each factorisation's
 // matrix in a global workspace as a column-major lower triangle (element
-// (i, j), i >= j, at M[j K + i]).  Right-looking Cholesky one column per step:
-// the scaled column is staged in LDS and every thread updates whole rows of
-// the trailing triangle, so a wave's accesses to one column are contiguous.
-// W = L^-1 is then formed row by row, W_ik = -(1/L_ii) sum_{k <= t < i} L_it W_tk,
+// (i, j), i >= j, at M[j K + i]).  Blocked right-looking Cholesky (chol_global):
+// every thread updates whole rows, so a wave's accesses to one column are
+// contiguous.  W = L^-1 is then formed row by row, W_ik = -(1/L_ii) sum_{k <= t < i} L_it W_tk,
 // with W_ik (k < i) kept in the unused upper triangle at M[i K + k], so
 // [M^-1]_kk = sum_i |W_ik|^2.  The SINRs, NaN and status conventions and the
 // column order are those of k_rates; sums over users run in a fixed order.
-constexpr int kLargeThreads = 256;
+constexpr int kLargeThreads = 512;
 
 // Sum over the workgroup in a fixed order (per-thread sums, wave butterfly,
 // then the waves in order); every thread gets the total.
@@ -598,41 +597,75 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-__device__ bool chol_global(cplx* M, int K, cplx* s_col) {
+// Blocked right-looking Cholesky in panels of kPanel columns.  A panel is
+// factorised one column at a time (each finished column is staged in LDS and
+// updates only the panel's later columns); then the trailing triangle takes the
+// panel's rank-kPanel update in one pass: thread i holds L_i,panel in registers
+// and walks the columns c <= i, two at a time, reading L_c,panel from LDS (a
+// broadcast) and M[c K + i] once.  The trailing triangle is read and written
+// once per panel instead of once per column.
+constexpr int kPanel = 8;
+
+__device__ bool chol_global(cplx* M, int K, cplx* s_pan) {
   const int tid = threadIdx.x;
-  for (int j = 0; j < K; ++j) {
-    __syncthreads();                                   // step j - 1's updates are visible
-    const double djj = M[(int64_t)j * K + j].x;
-    if (!(djj > 0.0) || !isfinite(djj)) return false;  // uniform: every thread read the same pivot
-    const double l = sqrt(djj), il = 1.0 / l;
-    for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
-      const cplx v = M[(int64_t)j * K + i];
-      const cplx w = {v.x * il, v.y * il};
-      M[(int64_t)j * K + i] = w;
-      s_col[i] = w;
+  for (int j0 = 0; j0 < K; j0 += kPanel) {
+    const int jp = min(kPanel, K - j0);
+    for (int p = 0; p < jp; ++p) {
+      const int j = j0 + p;
+      __syncthreads();                                   // the previous step's updates are visible
+      const double djj = M[(int64_t)j * K + j].x;
+      if (!(djj > 0.0) || !isfinite(djj)) return false;  // uniform: every thread read the same pivot
+      const double l = sqrt(djj), il = 1.0 / l;
+      for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
+        const cplx v = M[(int64_t)j * K + i];
+        const cplx w = {v.x * il, v.y * il};
+        M[(int64_t)j * K + i] = w;
+        s_pan[p * K + i] = w;
+      }
+      __syncthreads();
+      if (tid == 0) M[(int64_t)j * K + j] = {l, 0.0};
+      // the panel's later columns c in (j, j0 + jp), rows i >= c
+      for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
+        const cplx lij = s_pan[p * K + i];
+        const int c1 = min(i, j0 + jp - 1);
+        for (int c = j + 1; c <= c1; ++c) {
+          const cplx t = cmulc(lij, s_pan[p * K + c]);
+          const cplx v = M[(int64_t)c * K + i];
+          M[(int64_t)c * K + i] = {v.x - t.x, v.y - t.y};
+        }
+      }
     }
     __syncthreads();
-    if (tid == 0) M[(int64_t)j * K + j] = {l, 0.0};
-    for (int i = j + 1 + tid; i < K; i += kLargeThreads) {
-      const cplx lij = s_col[i];
-      int c = j + 1;
-      for (; c + 3 <= i; c += 4) {
-        cplx v[4];
+    // trailing update (a panel with a trailing part is always full: jp == kPanel)
+    const int c0 = j0 + jp;
+    for (int i = c0 + tid; i < K; i += kLargeThreads) {
+      cplx li[kPanel];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = M[(int64_t)(c + u) * K + i];
+      for (int p = 0; p < kPanel; ++p) li[p] = s_pan[p * K + i];
+      int c = c0;
+      for (; c < i; c += 2) {
+        cplx a0 = M[(int64_t)c * K + i], a1 = M[(int64_t)(c + 1) * K + i];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const cplx t = cmulc(lij, s_col[c + u]);
-          v[u].x -= t.x;
-          v[u].y -= t.y;
+        for (int p = 0; p < kPanel; ++p) {
+          const cplx t0 = cmulc(li[p], s_pan[p * K + c]);
+          const cplx t1 = cmulc(li[p], s_pan[p * K + c + 1]);
+          a0.x -= t0.x;
+          a0.y -= t0.y;
+          a1.x -= t1.x;
+          a1.y -= t1.y;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) M[(int64_t)(c + u) * K + i] = v[u];
+        M[(int64_t)c * K + i] = a0;
+        M[(int64_t)(c + 1) * K + i] = a1;
       }
-      for (; c <= i; ++c) {
-        const cplx t = cmulc(lij, s_col[c]);
-        cplx v = M[(int64_t)c * K + i];
-        M[(int64_t)c * K + i] = {v.x - t.x, v.y - t.y};
+      if (c == i) {
+        cplx a0 = M[(int64_t)c * K + i];
+#pragma unroll
+        for (int p = 0; p < kPanel; ++p) {
+          const cplx t0 = cmulc(li[p], s_pan[p * K + c]);
+          a0.x -= t0.x;
+          a0.y -= t0.y;
+        }
+        M[(int64_t)c * K + i] = a0;
       }
     }
   }
@@ -680,7 +713,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_rates_large(const DropK* __re
                                                                int schemes, int n_sch, double* __restrict__ work,
                                                                double* __restrict__ rates,
                                                                int32_t* __restrict__ status) {
-  __shared__ cplx s_vec[XLMIMO_MAX_USERS_EXACT];
+  __shared__ cplx s_vec[kPanel * XLMIMO_MAX_USERS_EXACT];   // Cholesky panel; row of L in the inverse
   __shared__ double s_inv[XLMIMO_MAX_USERS_EXACT], s_ginv[XLMIMO_MAX_USERS_EXACT];
   __shared__ double s_red[kLargeThreads / 64];
   const int tid = threadIdx.x;
