@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libxlmimo.so")
 
-SOURCES = ["api.cpp", "gram_exact.hip", "gram_closedform.hip", "rates.hip", "sweep.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "gram_exact.hip", "virtual_drops.hip", "gram_closedform.hip", "rates.hip", "sweep.hip",
+           "mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          # no packed FP32 (v_pk_*_f32) instructions in any kernel
