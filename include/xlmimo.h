@@ -202,8 +202,9 @@ int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_bat
  *               strictly ascending; an entry between two moved users is written
  *               by the row of the lower index
  *   gram_inout  DEVICE complex128 Grams (layout above) of the previous positions
- * K up to XLMIMO_MAX_USERS_EXACT.  A new moved set builds (and caches) a launch
- * plan synchronously: warm it before graph capture. */
+ * K up to XLMIMO_MAX_USERS_EXACT.  A new moved set builds a launch plan
+ * synchronously (warm it before graph capture); the context keeps the plans
+ * of the last 16 moved sets, apart from its other plans. */
 int xlmimo_gram_update_users(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                              int32_t precision, int64_t n_moved, const int64_t* moved, double* gram_inout,
                              void* stream);

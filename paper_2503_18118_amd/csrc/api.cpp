@@ -66,6 +66,7 @@ struct xlmimo_ctx {
   DevBuf scratch_work;     // matrices of the workgroup-per-drop rate kernel (K > XLMIMO_MAX_USERS)
   std::vector<double> nlist_host;  // N list last uploaded to scratch_nlist
   std::unordered_map<uint64_t, Plan> plans;
+  std::unordered_map<uint64_t, Plan> row_plans;   // moved-user row plans, evicted on their own
   // kernel timing (xlmimo_timing_enable / xlmimo_timing_read)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -522,18 +523,18 @@ int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, in
                  const int64_t* moved, Plan** out) {
   uint64_t h = plan_key(a, b, nullptr);
   h = fnv(h ^ 0x726f777375706474ULL, moved, sizeof(int64_t) * n_moved);
-  auto it = c->plans.find(h);
-  if (it != c->plans.end()) {
+  auto it = c->row_plans.find(h);
+  if (it != c->row_plans.end()) {
     *out = &it->second;
     return XLMIMO_OK;
   }
   if (c->capturing)
     return set_err(c, XLMIMO_EINVAL, "a new set of moved users needs a launch plan during graph capture: "
                    "run the same call once before capturing it");
-  if (c->plans.size() >= 64) {
+  if (c->row_plans.size() >= 16) {   // a tracking loop with changing moved sets keeps the batch plans
     HIP_TRY(c, hipDeviceSynchronize());
-    for (auto& kv : c->plans) drop_plan_buffers(c, kv.second);
-    c->plans.clear();
+    for (auto& kv : c->row_plans) drop_plan_buffers(c, kv.second);
+    c->row_plans.clear();
   }
   const int n = (int)b->n_drops;
   std::vector<int64_t> uoff(n + 1, 0), goff(n + 1, 0);
@@ -604,7 +605,7 @@ int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, in
     drop_plan_buffers(c, p);
     return rc;
   }
-  auto ins = c->plans.emplace(h, p);
+  auto ins = c->row_plans.emplace(h, p);
   *out = &ins.first->second;
   return XLMIMO_OK;
 }
@@ -1105,6 +1106,7 @@ int xlmimo_ctx_destroy(xlmimo_ctx* c) {
   (void)hipDeviceSynchronize();
   for (void* p : c->retired) (void)hipFree(p);
   for (auto& kv : c->plans) drop_plan_buffers(c, kv.second);   // no graphs: frees at once
+  for (auto& kv : c->row_plans) drop_plan_buffers(c, kv.second);
   DevBuf* bufs[] = {&c->partials, &c->scratch_gram, &c->scratch_gram2, &c->scratch_rates, &c->scratch_bounds,
                     &c->scratch_nlist, &c->scratch_pairs, &c->scratch_routes, &c->scratch_vpos,
                     &c->scratch_vgram, &c->scratch_work};

@@ -154,3 +154,20 @@ def test_tracking_experiment_agrees_with_full_recompute(X, ctx):
     r = E.tracking(ctx, n_drops=3, k_list=(16, 100), n=4096, frames=2)
     assert max(r["by_precision"]["FP64"]["max_normwise_diff"]) < 1e-12
     assert max(r["by_precision"]["FP32H"]["max_normwise_diff"]) < 1e-5
+
+
+def test_tracking_loop_with_changing_moved_sets(X, ctx):
+    # 20 frames, each moving a different user of every drop: more moved sets than the row-plan cache
+    # holds (16), so plans are evicted and rebuilt while the batch's own plans stay
+    ks = [5, 70]
+    drops = _drops([500, 1000], ks, seed=83)
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    for f in range(20):
+        moved = np.array([drops.user_off[0] + f % 5, drops.user_off[1] + (7 * f) % 70], np.int64)
+        old = g.clone()
+        _move(drops, b, moved, seed=100 + f, step=0.05)
+        ctx.gram_update_users(arr, b, moved, g, X.FP64)
+        torch.cuda.synchronize()
+        _check(X, arr, drops, b, old, g, moved, TOL["FP64"], f"frame {f}")
