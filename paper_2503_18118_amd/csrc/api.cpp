@@ -249,7 +249,8 @@ void drop_plan_buffers(xlmimo_ctx* c, Plan& p) {
 }
 
 // Fill a plan for drops with the given N and K and upload its descriptors.
-int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne, const int32_t* kk, uint64_t h, Plan& p);
+int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne, const int32_t* kk, uint64_t h, Plan& p,
+               const int32_t* cross = nullptr);
 
 // Build (or fetch) the launch plan of a batch shape.  A cache miss uploads the
 // descriptors synchronously; warm the cache before capturing a graph.
@@ -289,7 +290,7 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
 }
 
 int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of, const int32_t* kk, uint64_t h,
-               Plan& p) {
+               Plan& p, const int32_t* cross) {
   p.n_drops = n;
   std::vector<DropK> drops(n);
   int64_t uoff = 0, goff = 0, total_elems = 0, pairs = 0;
@@ -298,6 +299,7 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
     const int64_t ne = ne_of[d];
     dk.n_elems = (int32_t)ne;
     dk.k = kk[d];
+    dk.cross = cross ? cross[d] : 0;
     dk.nb = (dk.k + 15) / 16;
     dk.user_off = uoff;
     dk.gram_off = goff;
@@ -358,10 +360,11 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
 
 // Virtual drops of a batch with K > XLMIMO_MAX_USERS.  A drop with K <=
 // XLMIMO_MAX_USERS is one virtual drop of its own; a larger one has
-// g = ceil(K / kGroupUsers) groups of near-equal size (group i holds users
-// [K i / g, K (i + 1) / g)) and one virtual drop per group pair a < b.  Group
-// a's own block is taken from the pair (a, a + 1), the last group's from
-// (g - 2, g - 1).
+// g = ceil(K / kGroupUsers) groups (group i holds users [32 i, min(32 i + 32, K)),
+// so only the last is short and it is never group a) and one virtual drop per
+// group pair a < b.  The pairs (a, a + 1) compute their whole Gram and give
+// group a's own block (the last group's from (g - 2, g - 1)); every other pair
+// computes only the products between its two groups.
 int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
   if (c->capturing)
     return set_err(c, XLMIMO_EINVAL, "a new batch shape needs a launch plan during graph capture: "
@@ -369,11 +372,11 @@ int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
   const int n = p.n_drops;
   std::vector<VDropK> vd;
   std::vector<int64_t> vmap, vne;
-  std::vector<int32_t> vk;
+  std::vector<int32_t> vk, vcross;
   int64_t uoff = 0, goff = 0, vgoff = 0;
   for (int d = 0; d < n; ++d) {
     const int K = p.k_host[d];
-    auto add = [&](int a0, int ka, int b0, int kb, int flags) {
+    auto add = [&](int a0, int ka, int b0, int kb, int flags, int cross) {
       VDropK v;
       v.gram_off = goff;
       v.vgram_off = vgoff;
@@ -388,19 +391,20 @@ int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
       for (int i = 0; i < kb; ++i) vmap.push_back(uoff + b0 + i);
       vne.push_back(p.ne_host[d]);
       vk.push_back(ka + kb);
+      vcross.push_back(cross);
       vgoff += (int64_t)(ka + kb) * (ka + kb);
     };
     if (K <= XLMIMO_MAX_USERS) {
-      add(0, K, 0, 0, kVCopyA);
+      add(0, K, 0, 0, kVCopyA, 0);
     } else {
       const int g = (K + kGroupUsers - 1) / kGroupUsers;
-      auto first = [&](int i) { return (int)((int64_t)K * i / g); };
+      auto first = [&](int i) { return std::min(K, i * kGroupUsers); };
       for (int ga = 0; ga < g; ++ga)
         for (int gb = ga + 1; gb < g; ++gb) {
           int flags = 0;
           if (gb == ga + 1) flags |= kVCopyA;
           if (ga == g - 2 && gb == g - 1) flags |= kVCopyB;
-          add(first(ga), first(ga + 1) - first(ga), first(gb), first(gb + 1) - first(gb), flags);
+          add(first(ga), first(ga + 1) - first(ga), first(gb), first(gb + 1) - first(gb), flags, flags ? 0 : 1);
         }
     }
     uoff += K;
@@ -408,7 +412,8 @@ int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
   }
   if (vd.size() > 2147483647ULL) return set_err(c, XLMIMO_EINVAL, "too many user-group pairs");
   Plan* vp = new Plan();
-  int rc = build_plan(c, a, (int)vd.size(), vne.data(), vk.data(), p.key ^ 0x9e3779b97f4a7c15ULL, *vp);
+  int rc = build_plan(c, a, (int)vd.size(), vne.data(), vk.data(), p.key ^ 0x9e3779b97f4a7c15ULL, *vp,
+                      vcross.data());
   if (rc) {
     drop_plan_buffers(c, *vp);
     delete vp;

@@ -139,7 +139,11 @@ __device__ __forceinline__ void store_partial(const double* fin, double* s_red, 
   __syncthreads();
 }
 
-template <int NB, typename T, int GEOM, int AMP>
+// CROSS (NB == 4 only): a virtual drop of two 32-user groups of a larger drop,
+// whose own blocks come from other virtual drops: only the products between
+// user blocks {0, 1} and {2, 3} (16 MFMAs per round instead of 36); the other
+// accumulators stay zero.
+template <int NB, typename T, int GEOM, int AMP, bool CROSS = false>
 __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it, const double* __restrict__ pos,
                              double* __restrict__ part_out, double* s_red) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -187,10 +191,27 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   const double cy = 0.5 * (double)(ny - 1) * ds;
   const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
 
+  static_assert(!CROSS || NB == 4, "cross-only items have two 32-user groups");
   auto round = [&](const double* dy, double ez) {
     T hre[NB], him[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP>(dy[b], u[b].uz - ez, u[b].xp2, hre[b], him[b]);
+    if constexpr (CROSS) {
+      {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+          for (int bj = 2; bj < 4; ++bj) {
+            const int t = tri_index(bi, bj, NB);
+            are[t] = Mfma<T>::run(hre[bi], hre[bj], are[t]);
+            are[t] = Mfma<T>::run(him[bi], him[bj], are[t]);
+            ax[bi * NB + bj] = Mfma<T>::run(hre[bi], him[bj], ax[bi * NB + bj]);
+            ax[bj * NB + bi] = Mfma<T>::run(hre[bj], him[bi], ax[bj * NB + bi]);
+          }
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
@@ -520,7 +541,12 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
         case 2: if constexpr (NBMAX >= 2) process_item_split<2, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         // more than 32 users: the split operands do not fit beside the FP64 carries; FP32C products
         case 3: if constexpr (NBMAX >= 3) process_item<3, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 4: if constexpr (NBMAX >= 4) process_item<4, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 4:
+          if constexpr (NBMAX >= 4) {
+            if (dp.cross) process_item<4, float, GEOM, AMP, true>(arr, dp, it, pos, out, s_red);
+            else process_item<4, float, GEOM, AMP>(arr, dp, it, pos, out, s_red);
+          }
+          break;
         default: break;
       }
     } else {
@@ -528,7 +554,12 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const D
         case 1: process_item<1, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         case 2: if constexpr (NBMAX >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         case 3: if constexpr (NBMAX >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 4: if constexpr (NBMAX >= 4) process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 4:
+          if constexpr (NBMAX >= 4) {
+            if (dp.cross) process_item<4, T, GEOM, AMP, true>(arr, dp, it, pos, out, s_red);
+            else process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red);
+          }
+          break;
         default: break;
       }
     }

@@ -31,6 +31,9 @@ struct DropK {
   int32_t k;          // users
   int32_t nb;         // ceil(k / 16) user blocks
   int32_t n_items;    // work items (element chunks) of this drop
+  int32_t cross;      // virtual drop of two 32-user groups whose own blocks come from elsewhere:
+                      // only the products between user blocks {0, 1} and {2, 3}
+  int32_t pad_;
 };
 
 // One work item of the exact Gram: a contiguous element range of one drop.
@@ -42,10 +45,11 @@ struct ItemK {
 };
 
 // A drop with more users than one work item holds (K > XLMIMO_MAX_USERS) runs
-// as virtual drops: its users fall in groups of at most kGroupUsers, and every
-// pair of groups (a < b) is one virtual drop with group a's users then group
-// b's.  One descriptor per virtual drop tells the scatter which blocks of the
-// virtual Gram land where in the real one.
+// as virtual drops: its users fall in groups of kGroupUsers (the last one
+// shorter), and every pair of groups (a < b) is one virtual drop with group a's
+// users (user blocks 0-1) then group b's (blocks 2-3).  One descriptor per
+// virtual drop tells the scatter which blocks of the virtual Gram land where in
+// the real one.
 constexpr int kGroupUsers = 32;
 enum : int32_t { kVCopyA = 1, kVCopyB = 2 };   // also copy group a's / b's own block
 struct VDropK {
