@@ -209,6 +209,42 @@ int xlmimo_gram_update_users(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlm
                              int32_t precision, int64_t n_moved, const int64_t* moved, double* gram_inout,
                              void* stream);
 
+/* Cholesky factors for tracking.  The factored matrix of a drop is its Gram G
+ * (rho == NULL) or I + D^1/2 G D^1/2 with D = diag(rho) for one SNR (the MMSE /
+ * capacity matrix).  The factor L (A = L L^H, real positive diagonal) is FP64
+ * complex in LAPACK column-major order: element (i, j), i >= j, at complex
+ * element gram_off + j K + i of the Gram layout above, the strict upper
+ * triangle zero.  log2 det A = 2 sum_k log2 L_kk gives the capacity
+ * log2 det(I + A) directly (eq. (9)).
+ *   gram        DEVICE complex128 Grams (layout above)
+ *   rho         DEVICE double [total_users] or NULL
+ *   factor_out  DEVICE complex128, the Gram's size
+ *   logdet_out  DEVICE double [n_drops] or NULL: log2 det A (NaN when not PD)
+ *   status_out  DEVICE int32 [n_drops] or NULL: 0, or XLMIMO_ST_G_NOT_PD
+ *               (XLMIMO_ST_MMSE_NOT_PD with rho) with the factor undefined
+ * One 512-thread workgroup per drop, K up to XLMIMO_MAX_USERS_EXACT. */
+int xlmimo_cholesky(xlmimo_ctx* ctx, const xlmimo_batch* batch, const double* gram, const double* rho,
+                    double* factor_out, double* logdet_out, int32_t* status_out, void* stream);
+
+/* Tracking update of the factors: after xlmimo_gram_update_users has replaced
+ * the rows and columns of the moved users in `gram`, bring factors made by
+ * xlmimo_cholesky (same rho) up to date.  Per moved user m the change of A is
+ * Hermitian rank 2, u e_m^H + e_m u^H (u: the new column m minus the old one,
+ * the old one from L L^H, u_m halved) = v1 v1^H - v2 v2^H with
+ * v1,2 = (u / s +- s e_m) / sqrt 2; one pass over the columns applies the
+ * rotation of the rank-1 update with v1 and the hyperbolic rotation of the
+ * downdate with v2: O(K^2) per moved user against O(K^3) for a new
+ * factorisation.  Moved users of a drop are applied in ascending order.
+ *   arr, batch, moved  as in xlmimo_gram_update_users (they share its cached plan)
+ *   logdet_out, status_out  as in xlmimo_cholesky, written only for drops with
+ *               moved users; a downdate that meets a non-positive pivot (A no
+ *               longer positive definite) sets the status bit, and the factor
+ *               is then undefined: factor the matrix anew.
+ * Repeated updates accumulate rounding; refactor from time to time. */
+int xlmimo_cholesky_update_users(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                                 int64_t n_moved, const int64_t* moved, const double* gram, const double* rho,
+                                 double* factor_inout, double* logdet_out, int32_t* status_out, void* stream);
+
 /* Closed-form Gram of the paper's modified ZF (eqs. (22)-(23)):
  *   G~_ii = eq. (4) / P (PNUSW ULA, general spacing d: beta0/(d x_i) S_i with
  *           half-aperture L = N d / 2); the free-space ULA analogue

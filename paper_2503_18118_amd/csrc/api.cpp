@@ -49,6 +49,10 @@ struct Plan {
   int64_t* d_vmap = nullptr;
   VRowK* d_vr = nullptr;          // row plans (moved users): one descriptor per virtual drop
   int n_vr = 0;
+  int32_t* d_mdrop = nullptr;     // row plans: drops with moved users, offsets into the drop-local
+  int32_t* d_moff = nullptr;      // indices of their moved users (ascending)
+  int32_t* d_mloc = nullptr;
+  int n_mdrop = 0;
 };
 
 }  // namespace
@@ -236,6 +240,10 @@ void drop_plan_buffers(xlmimo_ctx* c, Plan& p) {
   (void)release(c, p.d_v);
   (void)release(c, p.d_vmap);
   (void)release(c, p.d_vr);
+  (void)release(c, p.d_mdrop);
+  (void)release(c, p.d_moff);
+  (void)release(c, p.d_mloc);
+  p.d_mdrop = p.d_moff = p.d_mloc = nullptr;
   p.d_drops = nullptr;
   p.d_items = nullptr;
   p.d_v = nullptr;
@@ -549,7 +557,7 @@ int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, in
   }
   std::vector<VRowK> vr;
   std::vector<int64_t> vmap, vne;
-  std::vector<int32_t> vk;
+  std::vector<int32_t> vk, mdrop, moff, mloc;
   int64_t vgoff = 0;
   std::vector<char> is_moved;
   int cur_drop = -1;
@@ -558,11 +566,14 @@ int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, in
     const int d = (int)(std::upper_bound(uoff.begin(), uoff.end(), u) - uoff.begin()) - 1;
     const int K = b->n_users[d];
     if (d != cur_drop) {   // moved users of this drop, for the partner rule
+      mdrop.push_back(d);
+      moff.push_back((int32_t)mloc.size());
       cur_drop = d;
       is_moved.assign(K, 0);
       for (int64_t r = q; r < n_moved && moved[r] < uoff[d + 1]; ++r) is_moved[moved[r] - uoff[d]] = 1;
     }
     const int m = (int)(u - uoff[d]);
+    mloc.push_back(m);
     const int64_t ne = a->geometry == XLMIMO_UPA ? a->n_y * a->n_z : (b->n_elems ? b->n_elems[d] : a->n_y);
     std::vector<int> partners;
     for (int j = 0; j < K; ++j)
@@ -604,6 +615,16 @@ int get_row_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, in
       e = hipMemcpy(p.d_vr, vr.data(), sizeof(VRowK) * vr.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !vmap.empty())
       e = hipMemcpy(p.d_vmap, vmap.data(), sizeof(int64_t) * vmap.size(), hipMemcpyHostToDevice);
+    moff.push_back((int32_t)mloc.size());
+    p.n_mdrop = (int)mdrop.size();
+    if (e == hipSuccess) e = hipMalloc(&p.d_mdrop, sizeof(int32_t) * std::max<size_t>(mdrop.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&p.d_moff, sizeof(int32_t) * moff.size());
+    if (e == hipSuccess) e = hipMalloc(&p.d_mloc, sizeof(int32_t) * std::max<size_t>(mloc.size(), 1));
+    if (e == hipSuccess && !mdrop.empty())
+      e = hipMemcpy(p.d_mdrop, mdrop.data(), sizeof(int32_t) * mdrop.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.d_moff, moff.data(), sizeof(int32_t) * moff.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !mloc.empty())
+      e = hipMemcpy(p.d_mloc, mloc.data(), sizeof(int32_t) * mloc.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = set_err(c, XLMIMO_EDEVICE, "row plan upload: %s", hipGetErrorString(e));
   }
   if (rc) {
@@ -1192,6 +1213,59 @@ int xlmimo_gram_update_users(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_
   Plan* p = nullptr;
   if ((rc = get_row_plan(c, a, b, n_moved, moved, &p))) return rc;
   return run_exact(c, a, b, p, precision, gram_inout, (hipStream_t)stream);
+}
+
+int xlmimo_cholesky(xlmimo_ctx* c, const xlmimo_batch* b, const double* gram, const double* rho,
+                    double* factor_out, double* logdet_out, int32_t* status_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
+  int rc = check_batch(c, b, false, XLMIMO_MAX_USERS_EXACT);
+  if (rc) return rc;
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram || !factor_out) return set_err(c, XLMIMO_EINVAL, "gram and factor_out are required");
+  if ((rc = set_device(c))) return rc;
+  xlmimo_array dummy = {XLMIMO_ULA, XLMIMO_AMP_FREESPACE, 1, 1, 1.0, 1.0, 1.0};
+  xlmimo_batch bb = *b;
+  bb.n_elems = nullptr;
+  Plan* p = nullptr;
+  if ((rc = get_plan(c, &dummy, &bb, nullptr, &p))) return rc;
+  HIP_TRY(c, launch_cholesky(p->d_drops, p->n_drops, gram, rho, factor_out, logdet_out, status_out,
+                             (hipStream_t)stream));
+  return XLMIMO_OK;
+}
+
+int xlmimo_cholesky_update_users(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int64_t n_moved,
+                                 const int64_t* moved, const double* gram, const double* rho, double* factor_inout,
+                                 double* logdet_out, int32_t* status_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = stream_ok(c, stream)) return rc0;
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, false, XLMIMO_MAX_USERS_EXACT);
+  if (rc) return rc;
+  if (n_moved < 0) return set_err(c, XLMIMO_EINVAL, "n_moved must be >= 0");
+  if (n_moved == 0 || b->n_drops == 0) return XLMIMO_OK;
+  if (!moved || !gram || !factor_inout) return set_err(c, XLMIMO_EINVAL, "moved, gram and factor_inout are required");
+  int64_t total = 0;
+  for (int64_t d = 0; d < b->n_drops; ++d) total += b->n_users[d];
+  for (int64_t q = 0; q < n_moved; ++q) {
+    if (moved[q] < 0 || moved[q] >= total)
+      return set_err(c, XLMIMO_EINVAL, "moved[%lld] = %lld outside 0..%lld", (long long)q, (long long)moved[q],
+                     (long long)(total - 1));
+    if (q && moved[q] <= moved[q - 1]) return set_err(c, XLMIMO_EINVAL, "moved must be strictly ascending");
+  }
+  if ((rc = set_device(c))) return rc;
+  Plan* rp = nullptr;
+  if ((rc = get_row_plan(c, a, b, n_moved, moved, &rp))) return rc;
+  xlmimo_array dummy = {XLMIMO_ULA, XLMIMO_AMP_FREESPACE, 1, 1, 1.0, 1.0, 1.0};
+  xlmimo_batch bb = *b;
+  bb.n_elems = nullptr;
+  Plan* p = nullptr;
+  if ((rc = get_plan(c, &dummy, &bb, nullptr, &p))) return rc;
+  HIP_TRY(c, launch_chol_update(p->d_drops, rp->n_mdrop, rp->d_mdrop, rp->d_moff, rp->d_mloc, gram, rho,
+                                factor_inout, logdet_out, status_out, (hipStream_t)stream));
+  return XLMIMO_OK;
 }
 
 int xlmimo_gram_closedform(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t variant,

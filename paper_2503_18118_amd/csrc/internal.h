@@ -128,6 +128,13 @@ hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const doub
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
                         int32_t* d_status, hipStream_t s, double* d_work = nullptr);
 
+// Cholesky factors for tracking (LAPACK column-major L at each drop's Gram offset).
+hipError_t launch_cholesky(const DropK* d_drops, int n_drops, const double* d_gram, const double* d_rho,
+                           double* d_factor, double* d_logdet, int32_t* d_status, hipStream_t s);
+hipError_t launch_chol_update(const DropK* d_drops, int n_mdrops, const int32_t* d_mdrop, const int32_t* d_moff,
+                              const int32_t* d_mloc, const double* d_gram, const double* d_rho, double* d_factor,
+                              double* d_logdet, int32_t* d_status, hipStream_t s);
+
 hipError_t launch_ergodic(const double* d_rates, int n_drops, int n_vals, double* d_out, hipStream_t s);
 hipError_t launch_y_bounds(const double* d_pos, const DropK* d_drops, int n_drops, int geom, double t_sat,
                            double* d_bounds, hipStream_t s);

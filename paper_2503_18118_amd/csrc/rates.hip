@@ -817,6 +817,181 @@ __global__ __launch_bounds__(kLargeThreads) void k_rates_large(const DropK* __re
   if (status != nullptr && tid == 0) status[blockIdx.x] = st;
 }
 
+// ---------------------------------------------------------------------------
+// Cholesky factors for tracking.  The factored matrix is G (rho == nullptr) or
+// I + D^1/2 G D^1/2 with D = diag(rho) for one SNR; its factor L is kept in
+// LAPACK column-major order (element (i, j), i >= j, at [j K + i] of the drop's
+// K x K block at its Gram offset), the strict upper triangle zero.
+
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kLargeThreads / 64; ++w) t = fmax(t, red[w]);
+  return t;
+}
+
+// log2 det of the factored matrix, 2 sum log2 L_kk (fixed order; every thread gets it)
+__device__ double factor_log2det(const cplx* M, int K, double* red) {
+  double t = 0.0;
+  for (int k = threadIdx.x; k < K; k += kLargeThreads) t += log2(M[(int64_t)k * K + k].x);
+  return 2.0 * block_sum(t, red);
+}
+
+__global__ __launch_bounds__(kLargeThreads) void k_cholesky(const DropK* __restrict__ drops,
+                                                            const double* __restrict__ gram,
+                                                            const double* __restrict__ rho,
+                                                            double* __restrict__ factor,
+                                                            double* __restrict__ logdet,
+                                                            int32_t* __restrict__ status) {
+  __shared__ cplx s_pan[kPanel * XLMIMO_MAX_USERS_EXACT];
+  __shared__ double s_red[kLargeThreads / 64];
+  const DropK dp = drops[blockIdx.x];
+  const int K = dp.k;
+  const int64_t KK = (int64_t)K * K;
+  const cplx* G = reinterpret_cast<const cplx*>(gram) + dp.gram_off;
+  cplx* M = reinterpret_cast<cplx*>(factor) + dp.gram_off;
+  const double* rs = rho != nullptr ? rho + dp.user_off : nullptr;
+  // element (i, c) = conj(G_ci): row c of the row-major Gram is column c of M
+  for (int64_t e = threadIdx.x; e < KK; e += kLargeThreads) {
+    const int c = (int)(e / K), i = (int)(e - (int64_t)c * K);
+    if (i < c) {
+      M[e] = {0.0, 0.0};
+    } else if (rs != nullptr) {
+      const double f = sqrt(rs[i]) * sqrt(rs[c]);
+      M[e] = {(i == c ? 1.0 : 0.0) + f * G[e].x, -f * G[e].y};
+    } else {
+      M[e] = {G[e].x, -G[e].y};
+    }
+  }
+  const bool ok = chol_global(M, K, s_pan);
+  double ld = __builtin_nan("");
+  if (ok) ld = factor_log2det(M, K, s_red);
+  if (threadIdx.x == 0) {
+    if (logdet != nullptr) logdet[blockIdx.x] = ld;
+    if (status != nullptr) status[blockIdx.x] = ok ? 0 : (rho != nullptr ? XLMIMO_ST_MMSE_NOT_PD : XLMIMO_ST_G_NOT_PD);
+  }
+}
+
+// Moved users of one drop per workgroup (drop mdrop[b], users mloc[moff[b] .. moff[b + 1]), ascending).
+// Row and column m of the factored matrix A changed: Delta = u e_m^H + e_m u^H with u the new column m
+// minus the old one (the old row from L L^H, u_m halved), = v1 v1^H - v2 v2^H for
+// v1,2 = (u / s +- s e_m) / sqrt 2.  One pass over the columns applies, at column k, the rotation
+// of the update with v1 and then the hyperbolic rotation of the downdate with v2 to column k and
+// to the vectors' later entries.  A downdate pivot <= 0 (A no longer positive definite) stops the
+// drop with the status bit set and log2 det NaN.
+__global__ __launch_bounds__(kLargeThreads) void k_chol_update(const DropK* __restrict__ drops,
+                                                               const int32_t* __restrict__ mdrop,
+                                                               const int32_t* __restrict__ moff,
+                                                               const int32_t* __restrict__ mloc,
+                                                               const double* __restrict__ gram,
+                                                               const double* __restrict__ rho,
+                                                               double* __restrict__ factor,
+                                                               double* __restrict__ logdet,
+                                                               int32_t* __restrict__ status) {
+  __shared__ cplx s_l[XLMIMO_MAX_USERS_EXACT], s_v1[XLMIMO_MAX_USERS_EXACT], s_v2[XLMIMO_MAX_USERS_EXACT];
+  __shared__ double s_red[kLargeThreads / 64];
+  const int tid = threadIdx.x;
+  const int d = mdrop[blockIdx.x];
+  const DropK dp = drops[d];
+  const int K = dp.k;
+  const cplx* G = reinterpret_cast<const cplx*>(gram) + dp.gram_off;
+  cplx* M = reinterpret_cast<cplx*>(factor) + dp.gram_off;
+  const double* rs = rho != nullptr ? rho + dp.user_off : nullptr;
+  bool ok = true;
+  for (int q = moff[blockIdx.x]; q < moff[blockIdx.x + 1] && ok; ++q) {
+    const int m = mloc[q];
+    __syncthreads();                                        // the previous user's pass is complete
+    for (int k = tid; k <= m; k += kLargeThreads) s_l[k] = M[(int64_t)k * K + m];   // row m of L
+    __syncthreads();
+    double umax = 0.0;
+    for (int j = tid; j < K; j += kLargeThreads) {
+      cplx a = {0.0, 0.0};                                  // old (L L^H)_mj = sum_k L_mk conj(L_jk)
+      const int kmax = min(m, j);
+      for (int k = 0; k <= kmax; ++k) {
+        const cplx t = cmulc(s_l[k], M[(int64_t)k * K + j]);
+        a.x += t.x;
+        a.y += t.y;
+      }
+      const cplx g = G[(int64_t)m * K + j];                 // new G_mj
+      cplx an = g;
+      if (rs != nullptr) {
+        const double f = sqrt(rs[m]) * sqrt(rs[j]);
+        an = {(j == m ? 1.0 : 0.0) + f * g.x, f * g.y};
+      }
+      const cplx dl = {an.x - a.x, an.y - a.y};             // Delta_mj
+      const cplx u = j == m ? cplx{0.5 * dl.x, 0.0} : cplx{dl.x, -dl.y};   // Delta_jm, u_m halved
+      s_v1[j] = u;
+      umax = fmax(umax, fmax(fabs(u.x), fabs(u.y)));
+    }
+    umax = block_max(umax, s_red);
+    if (!isfinite(umax)) {
+      ok = false;
+      break;
+    }
+    if (!(umax > 0.0)) continue;                            // row unchanged (uniform)
+    const double sc = sqrt(umax), isc = 1.0 / sc, h = 0.70710678118654752440;
+    for (int j = tid; j < K; j += kLargeThreads) {
+      const cplx u = s_v1[j];
+      const double em = j == m ? sc : 0.0;
+      s_v1[j] = {(u.x * isc + em) * h, u.y * isc * h};
+      s_v2[j] = {(u.x * isc - em) * h, u.y * isc * h};
+    }
+    for (int k = 0; k < K; ++k) {
+      __syncthreads();                                      // column k - 1 and the vectors are written
+      const double lkk = M[(int64_t)k * K + k].x;
+      const cplx x1 = s_v1[k], x2 = s_v2[k];
+      const double ra = sqrt(fma(lkk, lkk, x1.x * x1.x + x1.y * x1.y));
+      const double rb2 = ra * ra - (x2.x * x2.x + x2.y * x2.y);
+      if (!(rb2 > 0.0) || !isfinite(rb2)) {                 // uniform: every thread read the same values
+        ok = false;
+        break;
+      }
+      const double rb = sqrt(rb2), ia = 1.0 / ra, ib = 1.0 / rb;
+      __syncthreads();                                      // every thread has read L_kk, x1_k, x2_k
+      for (int i = k + 1 + tid; i < K; i += kLargeThreads) {
+        const cplx li = M[(int64_t)k * K + i];
+        cplx y1 = s_v1[i], y2 = s_v2[i];
+        const cplx c1 = cconjmul(x1, y1), c2 = cmul(x1, li);
+        const cplx l1 = {(lkk * li.x + c1.x) * ia, (lkk * li.y + c1.y) * ia};
+        y1 = {(lkk * y1.x - c2.x) * ia, (lkk * y1.y - c2.y) * ia};
+        const cplx c3 = cconjmul(x2, y2), c4 = cmul(x2, l1);
+        M[(int64_t)k * K + i] = {(ra * l1.x - c3.x) * ib, (ra * l1.y - c3.y) * ib};
+        y2 = {(ra * y2.x - c4.x) * ib, (ra * y2.y - c4.y) * ib};
+        s_v1[i] = y1;
+        s_v2[i] = y2;
+      }
+      if (tid == 0) M[(int64_t)k * K + k] = {rb, 0.0};
+    }
+  }
+  __syncthreads();
+  double ld = __builtin_nan("");
+  if (ok) ld = factor_log2det(M, K, s_red);
+  if (tid == 0) {
+    if (logdet != nullptr) logdet[d] = ld;
+    if (status != nullptr) status[d] = ok ? 0 : (rho != nullptr ? XLMIMO_ST_MMSE_NOT_PD : XLMIMO_ST_G_NOT_PD);
+  }
+}
+
+hipError_t launch_cholesky(const DropK* d_drops, int n_drops, const double* d_gram, const double* d_rho,
+                           double* d_factor, double* d_logdet, int32_t* d_status, hipStream_t s) {
+  if (n_drops == 0) return hipSuccess;
+  k_cholesky<<<n_drops, kLargeThreads, 0, s>>>(d_drops, d_gram, d_rho, d_factor, d_logdet, d_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_update(const DropK* d_drops, int n_mdrops, const int32_t* d_mdrop, const int32_t* d_moff,
+                              const int32_t* d_mloc, const double* d_gram, const double* d_rho, double* d_factor,
+                              double* d_logdet, int32_t* d_status, hipStream_t s) {
+  if (n_mdrops == 0) return hipSuccess;
+  k_chol_update<<<n_mdrops, kLargeThreads, 0, s>>>(d_drops, d_mdrop, d_moff, d_mloc, d_gram, d_rho, d_factor,
+                                                  d_logdet, d_status);
+  return hipGetLastError();
+}
+
 hipError_t launch_rates(const DropK* d_drops, int n_drops, int k_max, const double* d_gram, const double* d_filter,
                         int n_snr, const double* d_rho, int64_t total_users, int schemes, double* d_rates,
                         int32_t* d_status, hipStream_t s, double* d_work) {

@@ -145,22 +145,26 @@ def _events():
 def tracking(ctx, n_drops: int = 20, k_list=(16, 256, 1000), n: int = 65536, frames: int = 5,
              step_m: float = 0.005, precisions=("FP64", "FP32H")) -> dict:
     """Per frame, the middle user of every drop moves by step_m in y; the Gram is updated by rows
-    and, for comparison, recomputed whole.  Reports the mean time per frame of each and the largest
-    normwise difference between the two Grams over all frames."""
+    and, for comparison, recomputed whole; the Cholesky factor of G is updated (rank 2 per moved
+    user) and, for comparison, computed anew from the recomputed Gram.  Reports the mean time per
+    frame of each, the largest normwise difference between the two Grams and the largest
+    difference of log2 det G over all frames."""
     arr = W.ula(n, W.LAMBDA_100GHZ, W.AMP_PNUSW)
     out = {"scene": "Sec. IV: 100 GHz PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m", "n": n, "drops": n_drops,
            "frames": frames, "step_m": step_m, "k_list": [int(k) for k in k_list], "by_precision": {}}
     s = torch.cuda.current_stream()
     for pname in precisions:
         prec = getattr(X, pname)
-        rows = {"full_ms": [], "update_ms": [], "max_normwise_diff": []}
+        rows = {"full_ms": [], "update_ms": [], "max_normwise_diff": [], "refactor_ms": [], "factor_update_ms": [],
+                "max_log2det_diff": []}
         for k in k_list:
             drops = W.rect_drops(W.rng_for(10), n_drops, int(k), n, (1.0, 10.0), (-7.5, 7.5))
             b = X.Batch(drops)
             g = ctx.gram_exact(arr, b, prec)
             full = torch.empty_like(g)
-            t_full = t_upd = 0.0
-            worst = 0.0
+            factor, _, _ = ctx.cholesky(b, g)
+            t_full = t_upd = t_refac = t_fupd = 0.0
+            worst = worst_ld = 0.0
             moved = (drops.user_off[:-1] + int(k) // 2).astype(np.int64)
             for f in range(frames + 1):        # frame 0 builds the launch plans and is not timed
                 b.pos[torch.as_tensor(moved, device=b.pos.device), 1] += step_m
@@ -172,10 +176,21 @@ def tracking(ctx, n_drops: int = 20, k_list=(16, 256, 1000), n: int = 65536, fra
                 e2.record(s)
                 ctx.gram_exact(arr, b, prec, out=full)
                 e3.record(s)
-                e3.synchronize()
+                e4, e5 = _events()
+                e4.record(s)
+                ld_upd, _ = ctx.cholesky_update_users(arr, b, moved, g, factor)
+                e5.record(s)
+                e6, e7 = _events()
+                e6.record(s)
+                _, ld_new, _ = ctx.cholesky(b, full)
+                e7.record(s)
+                e7.synchronize()
                 if f:
                     t_upd += e0.elapsed_time(e1)
                     t_full += e2.elapsed_time(e3)
+                    t_fupd += e4.elapsed_time(e5)
+                    t_refac += e6.elapsed_time(e7)
+                worst_ld = max(worst_ld, float((ld_upd - ld_new).abs().max()))
                 gu = g.view(torch.complex128)
                 gf = full.view(torch.complex128)
                 for d in range(n_drops):
@@ -187,7 +202,10 @@ def tracking(ctx, n_drops: int = 20, k_list=(16, 256, 1000), n: int = 65536, fra
             rows["full_ms"].append(t_full / frames)
             rows["update_ms"].append(t_upd / frames)
             rows["max_normwise_diff"].append(worst)
-            del b, g, full
+            rows["refactor_ms"].append(t_refac / frames)
+            rows["factor_update_ms"].append(t_fupd / frames)
+            rows["max_log2det_diff"].append(worst_ld)
+            del b, g, full, factor
         out["by_precision"][pname] = rows
     return out
 
@@ -195,12 +213,15 @@ def tracking(ctx, n_drops: int = 20, k_list=(16, 256, 1000), n: int = 65536, fra
 def _table_tracking(r):
     lines = [f"Tracking ({r['scene']}; N = {r['n']}, {r['drops']} drops, one user per drop moves "
              f"{1e3 * r['step_m']:.0f} mm per frame; mean over {r['frames']} frames)",
-             "| precision | K | full Gram ms | row update ms | speed-up | max normwise difference |",
-             "|---|---|---|---|---|---|"]
+             "| Gram precision | K | full Gram ms | row update ms | speed-up | max normwise difference "
+             "| new factor ms | factor update ms | speed-up | max log2 det difference |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     for p, rows in r["by_precision"].items():
         for i, k in enumerate(r["k_list"]):
             fm, um = rows["full_ms"][i], rows["update_ms"][i]
-            lines.append(f"| {p} | {k} | {fm:.3f} | {um:.3f} | {fm / um:.1f} | {rows['max_normwise_diff'][i]:.1e} |")
+            rf, fu = rows["refactor_ms"][i], rows["factor_update_ms"][i]
+            lines.append(f"| {p} | {k} | {fm:.3f} | {um:.3f} | {fm / um:.1f} | {rows['max_normwise_diff'][i]:.1e} "
+                         f"| {rf:.3f} | {fu:.3f} | {rf / fu:.1f} | {rows['max_log2det_diff'][i]:.1e} |")
     return "\n".join(lines)
 
 

@@ -36,7 +36,8 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_mlp_get_params", "xlmimo_pair_count", "xlmimo_mlp_pair_inputs", "xlmimo_mlp_loss_grad",
             "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
             "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
-            "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users")
+            "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users", "xlmimo_cholesky",
+            "xlmimo_cholesky_update_users")
 
 
 class XlArray(C.Structure):
@@ -63,6 +64,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_gram_exact.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp]
     lib.xlmimo_gram_update_users.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, i64,
                                              C.POINTER(C.c_int64), vp, vp]
+    lib.xlmimo_cholesky.argtypes = [vp, C.POINTER(XlBatch), vp, vp, vp, vp, vp, vp]
+    lib.xlmimo_cholesky_update_users.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i64,
+                                                 C.POINTER(C.c_int64), vp, vp, vp, vp, vp, vp]
     lib.xlmimo_gram_closedform.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp, vp]
     lib.xlmimo_zf_mmse_sumrate.argtypes = [vp, C.POINTER(XlBatch), vp, vp, i32, vp, i32, vp, vp, vp]
     lib.xlmimo_capacity_sweep.argtypes = [vp, C.POINTER(XlArray), i32, C.POINTER(C.c_int64), C.POINTER(XlBatch),
@@ -226,6 +230,34 @@ class Context:
                                                   mv.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(gram),
                                                   _stream(stream)), "xlmimo_gram_update_users")
         return gram
+
+    def cholesky(self, batch: Batch, gram: torch.Tensor, rho: Optional[torch.Tensor] = None, stream=None):
+        """Factors L of G (or of I + D^1/2 G D^1/2 for one SNR row rho), LAPACK column-major per drop.
+        Returns (factor, log2 det, status)."""
+        factor = torch.empty_like(gram)
+        logdet = torch.empty(batch.n_drops, dtype=torch.float64, device=gram.device)
+        status = torch.empty(batch.n_drops, dtype=torch.int32, device=gram.device)
+        r = None if rho is None else rho.contiguous()
+        self._check(_lib.xlmimo_cholesky(self.h, C.byref(batch.struct), _ptr(gram), _ptr(r), _ptr(factor),
+                                         _ptr(logdet), _ptr(status), _stream(stream)), "xlmimo_cholesky")
+        return factor, logdet, status
+
+    def cholesky_update_users(self, arr, batch: Batch, moved, gram: torch.Tensor, factor: torch.Tensor,
+                              rho: Optional[torch.Tensor] = None, logdet: Optional[torch.Tensor] = None,
+                              status: Optional[torch.Tensor] = None, stream=None):
+        """Update `factor` in place after the rows of `moved` changed in `gram`; returns (logdet, status)."""
+        mv = np.ascontiguousarray(moved, np.int64)
+        if logdet is None:
+            logdet = torch.full((batch.n_drops,), float("nan"), dtype=torch.float64, device=gram.device)
+        if status is None:
+            status = torch.zeros(batch.n_drops, dtype=torch.int32, device=gram.device)
+        a = make_array(arr)
+        r = None if rho is None else rho.contiguous()
+        self._check(_lib.xlmimo_cholesky_update_users(self.h, C.byref(a), C.byref(batch.struct), len(mv),
+                                                      mv.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(gram), _ptr(r),
+                                                      _ptr(factor), _ptr(logdet), _ptr(status), _stream(stream)),
+                    "xlmimo_cholesky_update_users")
+        return logdet, status
 
     def gram_closedform(self, arr, batch: Batch, variant: int = CF_PAPER, out: Optional[torch.Tensor] = None,
                         status: Optional[torch.Tensor] = None, stream=None):

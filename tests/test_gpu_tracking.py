@@ -171,3 +171,119 @@ def test_tracking_loop_with_changing_moved_sets(X, ctx):
         ctx.gram_update_users(arr, b, moved, g, X.FP64)
         torch.cuda.synchronize()
         _check(X, arr, drops, b, old, g, moved, TOL["FP64"], f"frame {f}")
+
+
+# ---- Cholesky factors and their tracking updates ------------------------------------------------
+
+from oracle import rates as orates   # noqa: E402
+
+
+def _factored(g, rk):
+    """The matrix the factor belongs to: G, or I + D^1/2 G D^1/2 for one SNR row."""
+    if rk is None:
+        return g
+    s = np.sqrt(rk)
+    return np.eye(len(g)) + s[:, None] * g * s[None, :]
+
+
+def _factor_blocks(b, factor):
+    """Per-drop L from the LAPACK column-major blocks."""
+    f = factor.detach().cpu().numpy().view(np.complex128)
+    return [f[b.gram_off[d]:b.gram_off[d + 1]].reshape(b.k[d], b.k[d]).T for d in range(b.n_drops)]
+
+
+def _check_factor(A, L, tol, tag):
+    assert np.array_equal(np.triu(L, 1), np.zeros_like(L)), tag
+    ref = np.linalg.cholesky(A)
+    assert np.abs(L - ref).max() <= tol * np.abs(ref).max(), (tag, np.abs(L - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("with_rho", [False, True])
+def test_cholesky_matches_lapack(X, ctx, with_rho):
+    ks = [5, 70, 200, 1, 16]
+    drops = _drops([4 * k + 300 for k in ks], ks, seed=89, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    gh = b.split(g)
+    rho = None
+    if with_rho:
+        rng = np.random.default_rng(2)
+        rho = torch.as_tensor(rng.uniform(0.5, 2.0, b.total_users) * 1e3 / np.real(gh[0][0, 0]), device="cuda")
+    factor, logdet, status = ctx.cholesky(b, g, rho)
+    torch.cuda.synchronize()
+    assert torch.all(status == 0)
+    Ls = _factor_blocks(b, factor)
+    rh = None if rho is None else rho.cpu().numpy()
+    ld = logdet.cpu().numpy()
+    for d in range(b.n_drops):
+        rk = None if rh is None else rh[drops.user_off[d]:drops.user_off[d + 1]]
+        A = _factored(gh[d], rk)
+        _check_factor(A, Ls[d], 1e-12, (with_rho, d))
+        if rk is None:
+            want = np.linalg.slogdet(A)[1] / np.log(2.0)
+        else:   # the capacity of eq. (9), from the oracle's rates
+            want = orates.rates(gh[d], rk, orates.SCHEME_CAP)[orates.SCHEME_CAP]
+        assert ld[d] == pytest.approx(want, rel=1e-10, abs=1e-10), (with_rho, d)
+
+
+@pytest.mark.parametrize("with_rho", [False, True])
+def test_cholesky_update_users_matches_refactor(X, ctx, with_rho):
+    # three frames of moves (two and three moved users in one drop, K > 64, K = 1); after each, the
+    # updated factor against LAPACK's factor of the updated matrix and log2 det against a new one
+    ks = [5, 70, 200, 1, 16]
+    drops = _drops([4 * k + 300 for k in ks], ks, seed=97, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    rho = None
+    if with_rho:
+        rng = np.random.default_rng(3)
+        rho = torch.as_tensor(rng.uniform(0.5, 2.0, b.total_users) * 1e3 / float(g[0]), device="cuda")
+    factor, _, status = ctx.cholesky(b, g, rho)
+    off = drops.user_off
+    moved = np.array([off[0] + 1, off[0] + 4, off[1] + 0, off[1] + 33, off[1] + 69, off[2] + 100, off[3]], np.int64)
+    rh = None if rho is None else rho.cpu().numpy()
+    for frame in range(3):
+        _move(drops, b, moved, seed=200 + frame, step=0.1)
+        ctx.gram_update_users(arr, b, moved, g, X.FP64)
+        logdet, status = ctx.cholesky_update_users(arr, b, moved, g, factor, rho)
+        torch.cuda.synchronize()
+        st = status.cpu().numpy()
+        assert np.all(st == 0), (frame, st)
+        gh = b.split(g)
+        Ls = _factor_blocks(b, factor)
+        ld = logdet.cpu().numpy()
+        for d in range(b.n_drops):
+            rk = None if rh is None else rh[off[d]:off[d + 1]]
+            A = _factored(gh[d], rk)
+            _check_factor(A, Ls[d], 1e-10, (with_rho, frame, d))
+            if d != 4:   # drop 4 has no moved user: its log det is not written
+                assert ld[d] == pytest.approx(np.linalg.slogdet(A)[1] / np.log(2.0), rel=1e-10, abs=1e-9)
+        assert np.isnan(ld[4])
+
+
+def test_cholesky_update_flags_an_indefinite_matrix(X, ctx):
+    ks = [40, 70]
+    drops = _drops([600, 800], ks, seed=101, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    g = ctx.gram_exact(arr, b, X.FP64)
+    factor, _, _ = ctx.cholesky(b, g)
+    moved = np.array([7, 40 + 12], np.int64)
+    gh = b.split(g)
+    gh[0][7, 7] = -np.real(gh[0][7, 7])        # the new matrix of drop 0 is indefinite
+    g_new = torch.as_tensor(np.concatenate([m.ravel() for m in gh]).view(np.float64), device="cuda")
+    logdet, status = ctx.cholesky_update_users(arr, b, moved, g_new, factor)
+    torch.cuda.synchronize()
+    st, ld = status.cpu().numpy(), logdet.cpu().numpy()
+    assert st[0] == X.ST_G_NOT_PD and np.isnan(ld[0])
+    assert st[1] == 0 and ld[1] == pytest.approx(np.linalg.slogdet(gh[1])[1] / np.log(2.0), rel=1e-10)
+    with pytest.raises(X.XlmimoError, match="ascending"):
+        ctx.cholesky_update_users(arr, b, [5, 3], g_new, factor)
+
+
+def test_tracking_experiment_factor_updates_agree(X, ctx):
+    from paper_2503_18118_amd import experiments as E
+    r = E.tracking(ctx, n_drops=3, k_list=(16, 100), n=4096, frames=2, precisions=("FP64",))
+    assert max(r["by_precision"]["FP64"]["max_log2det_diff"]) < 1e-9
