@@ -22,6 +22,9 @@ ZF SINR equals the projection form rho ||P_perp h_k||^2 and MMSE SINR the
 whitened-interference form, both computed from H itself; ZF <= MMSE <= CAP
 <= Hadamard bound (Appendix A) and CAP >= the Schur-Horn lower bound;
 the mismatched rate with G~ = G equals ZF; MMSE -> ZF as SNR grows.
+The tracked Cholesky factor: the 2 x 2 closed form, L L^H = A with L lower
+and a real positive diagonal, log2 det against the Leibniz expansion of the
+determinant (3 x 3) and against the capacity.
 """
 from __future__ import annotations
 
@@ -84,6 +87,27 @@ def corr_gap(g):
     r = g / np.outer(d, d)
     sign, logdet = np.linalg.slogdet(r)
     return float(-logdet / np.log(2.0) / g.shape[0]) if sign > 0 else float("nan")
+
+
+def factored_matrix(g, rho=None):
+    """The matrix whose Cholesky factor the tracking path keeps: G itself (rho None) or the
+    capacity matrix I + D^{1/2} G D^{1/2} of eq. (9) for one SNR row rho."""
+    if rho is None:
+        return np.array(g, dtype=np.complex128)
+    s = np.sqrt(np.asarray(rho, dtype=np.float64))
+    return np.eye(g.shape[0]) + s[:, None] * g * s[None, :]
+
+
+def cholesky_factor(g, rho=None):
+    """The Cholesky factor of factored_matrix(g, rho): the unique lower-triangular L with a real
+    positive diagonal and L L^H = A (LAPACK).  A tracking update must reach it for the updated A."""
+    return np.linalg.cholesky(factored_matrix(g, rho))
+
+
+def log2det(g, rho=None):
+    """log2 det of factored_matrix(g, rho) from its factor, 2 sum log2 L_kk; with rho it is the
+    capacity of eq. (9)."""
+    return float(2.0 * np.sum(np.log2(np.real(np.diag(cholesky_factor(g, rho))))))
 
 
 def rates(g_true, rho, schemes=SCHEME_ZF | SCHEME_MMSE, g_filter=None):

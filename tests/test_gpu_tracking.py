@@ -178,23 +178,15 @@ def test_tracking_loop_with_changing_moved_sets(X, ctx):
 from oracle import rates as orates   # noqa: E402
 
 
-def _factored(g, rk):
-    """The matrix the factor belongs to: G, or I + D^1/2 G D^1/2 for one SNR row."""
-    if rk is None:
-        return g
-    s = np.sqrt(rk)
-    return np.eye(len(g)) + s[:, None] * g * s[None, :]
-
-
 def _factor_blocks(b, factor):
     """Per-drop L from the LAPACK column-major blocks."""
     f = factor.detach().cpu().numpy().view(np.complex128)
     return [f[b.gram_off[d]:b.gram_off[d + 1]].reshape(b.k[d], b.k[d]).T for d in range(b.n_drops)]
 
 
-def _check_factor(A, L, tol, tag):
+def _check_factor(g, rk, L, tol, tag):
     assert np.array_equal(np.triu(L, 1), np.zeros_like(L)), tag
-    ref = np.linalg.cholesky(A)
+    ref = orates.cholesky_factor(g, rk)
     assert np.abs(L - ref).max() <= tol * np.abs(ref).max(), (tag, np.abs(L - ref).max() / np.abs(ref).max())
 
 
@@ -218,10 +210,9 @@ def test_cholesky_matches_lapack(X, ctx, with_rho):
     ld = logdet.cpu().numpy()
     for d in range(b.n_drops):
         rk = None if rh is None else rh[drops.user_off[d]:drops.user_off[d + 1]]
-        A = _factored(gh[d], rk)
-        _check_factor(A, Ls[d], 1e-12, (with_rho, d))
+        _check_factor(gh[d], rk, Ls[d], 1e-12, (with_rho, d))
         if rk is None:
-            want = np.linalg.slogdet(A)[1] / np.log(2.0)
+            want = orates.log2det(gh[d])
         else:   # the capacity of eq. (9), from the oracle's rates
             want = orates.rates(gh[d], rk, orates.SCHEME_CAP)[orates.SCHEME_CAP]
         assert ld[d] == pytest.approx(want, rel=1e-10, abs=1e-10), (with_rho, d)
@@ -256,10 +247,9 @@ def test_cholesky_update_users_matches_refactor(X, ctx, with_rho):
         ld = logdet.cpu().numpy()
         for d in range(b.n_drops):
             rk = None if rh is None else rh[off[d]:off[d + 1]]
-            A = _factored(gh[d], rk)
-            _check_factor(A, Ls[d], 1e-10, (with_rho, frame, d))
+            _check_factor(gh[d], rk, Ls[d], 1e-10, (with_rho, frame, d))
             if d != 4:   # drop 4 has no moved user: its log det is not written
-                assert ld[d] == pytest.approx(np.linalg.slogdet(A)[1] / np.log(2.0), rel=1e-10, abs=1e-9)
+                assert ld[d] == pytest.approx(orates.log2det(gh[d], rk), rel=1e-10, abs=1e-9)
         assert np.isnan(ld[4])
 
 
@@ -278,7 +268,7 @@ def test_cholesky_update_flags_an_indefinite_matrix(X, ctx):
     torch.cuda.synchronize()
     st, ld = status.cpu().numpy(), logdet.cpu().numpy()
     assert st[0] == X.ST_G_NOT_PD and np.isnan(ld[0])
-    assert st[1] == 0 and ld[1] == pytest.approx(np.linalg.slogdet(gh[1])[1] / np.log(2.0), rel=1e-10)
+    assert st[1] == 0 and ld[1] == pytest.approx(orates.log2det(gh[1]), rel=1e-10)
     with pytest.raises(X.XlmimoError, match="ascending"):
         ctx.cholesky_update_users(arr, b, [5, 3], g_new, factor)
 

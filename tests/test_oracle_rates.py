@@ -118,3 +118,36 @@ def test_corr_gap_appendix_a():
         unit = 1.0 / np.real(np.diag(g))                      # a_i = rho_i G_ii = 1
         u, lo = R.hadamard_bound(g, unit), R.schur_horn_bound(g, unit)
         assert R.corr_gap(g) == pytest.approx((u - lo) / u, rel=1e-10)
+
+
+def test_cholesky_factor_two_by_two_closed_form():
+    # A = [[a, b], [conj b, c]]: L = [[sqrt a, 0], [conj(b) / sqrt a, sqrt(c - |b|^2 / a)]]
+    a, b, c = 2.5, 0.7 - 1.1j, 3.0
+    L = R.cholesky_factor(np.array([[a, b], [np.conj(b), c]]))
+    want = np.array([[math.sqrt(a), 0.0], [np.conj(b) / math.sqrt(a), math.sqrt(c - abs(b) ** 2 / a)]])
+    assert np.allclose(L, want, rtol=0, atol=1e-15)
+
+
+def test_cholesky_factor_properties_and_log2det():
+    h, g, rho = _drop(n=40, k=6, seed=4)
+    for r in (None, rho):
+        A = R.factored_matrix(g, r)
+        L = R.cholesky_factor(g, r)
+        assert np.array_equal(np.triu(L, 1), np.zeros_like(L))
+        d = np.diag(L)
+        assert np.all(np.abs(d.imag) == 0) and np.all(d.real > 0)
+        assert np.abs(L @ L.conj().T - A).max() <= 1e-14 * np.abs(A).max()
+    # with rho, log2 det is the capacity of eq. (9)
+    assert R.log2det(g, rho) == pytest.approx(R.capacity(g, rho), rel=1e-13)
+
+
+def test_log2det_against_leibniz_expansion():
+    # 3 x 3 determinant by its permutation expansion, independent of any factorisation
+    import itertools
+    h, g, rho = _drop(n=30, k=3, seed=6)
+    det = 0.0
+    for perm in itertools.permutations(range(3)):
+        sign = (-1) ** sum(perm[i] > perm[j] for i in range(3) for j in range(i + 1, 3))   # inversions
+        det += sign * g[0, perm[0]] * g[1, perm[1]] * g[2, perm[2]]
+    assert abs(det.imag) < 1e-12 * abs(det.real)
+    assert R.log2det(g) == pytest.approx(math.log2(det.real), rel=1e-12)
