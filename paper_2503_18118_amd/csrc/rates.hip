@@ -673,35 +673,74 @@ __device__ bool chol_global(cplx* M, int K, cplx* s_pan) {
   return true;
 }
 
-// Diagonal of (L L^H)^-1 for the factor L in M, into s_inv[0, K).
-__device__ void inv_diag_global(cplx* M, int K, cplx* s_row, double* s_inv) {
+// Diagonal of (L L^H)^-1 for the factor L in M, into s_inv[0, K).  W = L^-1 is
+// formed kPanel rows at a time: those rows of L are staged in LDS (s_rows,
+// kPanel x K), and thread k, for its columns k, sums the earlier rows'
+// contributions sum_{t < i0} L_it W_tk for all kPanel rows from one read of
+// each W_tk, then runs the rows' own recurrence in registers.  W_ik (k < i) is
+// kept in the unused upper triangle at M[i K + k].
+__device__ void inv_diag_global(cplx* M, int K, cplx* s_rows, double* s_inv) {
   const int tid = threadIdx.x;
   for (int k = tid; k < K; k += kLargeThreads) {
     const double w = 1.0 / M[(int64_t)k * K + k].x;
     s_inv[k] = w * w;
   }
-  for (int i = 1; i < K; ++i) {
-    __syncthreads();                                   // row i - 1 of W is written, s_row is free
-    for (int t = tid; t < i; t += kLargeThreads) s_row[t] = M[(int64_t)t * K + i];   // L_it
+  for (int i0 = 0; i0 < K; i0 += kPanel) {
+    const int nr = min(kPanel, K - i0);
+    __syncthreads();                                   // earlier rows of W are written, s_rows is free
+    for (int r = 0; r < nr; ++r)
+      for (int t = tid; t <= i0 + r; t += kLargeThreads) s_rows[r * K + t] = M[(int64_t)t * K + i0 + r];   // L_{i0+r,t}
     __syncthreads();
-    const double ili = 1.0 / M[(int64_t)i * K + i].x;
-    for (int k = tid; k < i; k += kLargeThreads) {
+    for (int k = tid; k < i0 + nr; k += kLargeThreads) {
       const double wkk = 1.0 / M[(int64_t)k * K + k].x;
-      cplx acc = {s_row[k].x * wkk, s_row[k].y * wkk};   // t = k: L_ik W_kk
-      // t runs from the wave's first column so that a wave reads one row of W
-      // contiguously; terms with t <= k are multiplied by zero
-      const int t0 = (k & ~63) + 1;
-#pragma unroll 4
-      for (int t = t0; t < i; ++t) {
-        const cplx m = M[(int64_t)t * K + k];
-        const cplx w = t > k ? m : cplx{0.0, 0.0};
-        const cplx p = cmul(s_row[t], w);
-        acc.x += p.x;
-        acc.y += p.y;
+      cplx acc[kPanel];
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r) acc[r] = {0.0, 0.0};
+      if (k < i0) {
+        // earlier rows: t = k (W_kk), then t in (k, i0) from the wave's first column on, so that a
+        // wave reads one row of W contiguously; terms with t <= k are multiplied by zero
+#pragma unroll
+        for (int r = 0; r < kPanel; ++r)
+          if (r < nr) acc[r] = {s_rows[r * K + k].x * wkk, s_rows[r * K + k].y * wkk};
+        const int t0 = (k & ~63) + 1;
+        for (int t = t0; t < i0; ++t) {
+          const cplx m = M[(int64_t)t * K + k];
+          const cplx w = t > k ? m : cplx{0.0, 0.0};
+#pragma unroll
+          for (int r = 0; r < kPanel; ++r) {
+            if (r < nr) {
+              const cplx p = cmul(s_rows[r * K + t], w);
+              acc[r].x += p.x;
+              acc[r].y += p.y;
+            }
+          }
+        }
       }
-      const cplx wik = {-acc.x * ili, -acc.y * ili};
-      M[(int64_t)i * K + k] = wik;
-      s_inv[k] += wik.x * wik.x + wik.y * wik.y;
+      // this block's rows in order: W_ik = -(1/L_ii)(acc + sum_{t in [max(k, i0), i)} L_it W_tk)
+      cplx wb[kPanel];
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r) {
+        const int i = i0 + r;
+        wb[r] = {0.0, 0.0};
+        if (r >= nr || i < k) continue;
+        if (i == k) {
+          wb[r] = {wkk, 0.0};
+          continue;
+        }
+        cplx a = acc[r];
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) {
+          if (q < r && i0 + q >= k) {
+            const cplx p = cmul(s_rows[r * K + i0 + q], wb[q]);
+            a.x += p.x;
+            a.y += p.y;
+          }
+        }
+        const double ili = 1.0 / s_rows[r * K + i].x;
+        wb[r] = {-a.x * ili, -a.y * ili};
+        M[(int64_t)i * K + k] = wb[r];
+        s_inv[k] += wb[r].x * wb[r].x + wb[r].y * wb[r].y;
+      }
     }
   }
   __syncthreads();
