@@ -277,3 +277,67 @@ def test_tracking_experiment_factor_updates_agree(X, ctx):
     from paper_2503_18118_amd import experiments as E
     r = E.tracking(ctx, n_drops=3, k_list=(16, 100), n=4096, frames=2, precisions=("FP64",))
     assert max(r["by_precision"]["FP64"]["max_log2det_diff"]) < 1e-9
+
+
+def test_large_k_and_tracking_replay_in_a_graph(X, ctx):
+    # the K > 64 path (gather, virtual drops, scatter), the workgroup-per-drop rates and a tracking
+    # frame (Gram rows, factor update) captured into one graph; every replay against the eager run,
+    # bit for bit, with the tracked state reset and unrelated eager work between the replays
+    ks = [70, 5, 130]
+    drops = _drops([2000, 700, 1500], ks, seed=107, r=(1.0, 6.0))
+    arr = W.ula(1, W.LAMBDA_28GHZ)
+    b = X.Batch(drops)
+    dev = b.pos.device
+    s = torch.cuda.Stream()
+    gram = torch.empty(2 * b.gram_elems, dtype=torch.float64, device=dev)
+    ctx.gram_exact(arr, b, X.FP64, out=gram, stream=s)
+    s.synchronize()
+    factor0, _, _ = ctx.cholesky(b, gram)
+    torch.cuda.synchronize()
+    gram0 = gram.clone()
+    moved = np.array([drops.user_off[0] + 7, drops.user_off[2] + 64, drops.user_off[2] + 129], np.int64)
+    _move(drops, b, moved, seed=11, step=0.05)
+    rho = torch.full((1, b.total_users), 1e3 / float(gram0[0]), dtype=torch.float64, device=dev)
+    g_full = torch.empty_like(gram)
+    rates = torch.empty((b.n_drops, 1, 3), dtype=torch.float64, device=dev)
+    st = torch.empty(b.n_drops, dtype=torch.int32, device=dev)
+    g_trk, f_trk = torch.empty_like(gram), torch.empty_like(gram)
+    ld = torch.empty(b.n_drops, dtype=torch.float64, device=dev)
+    st2 = torch.empty(b.n_drops, dtype=torch.int32, device=dev)
+
+    def reset():
+        g_trk.copy_(gram0)
+        f_trk.copy_(factor0)
+        for t in (g_full, rates, ld):
+            t.fill_(-1)
+        st.fill_(-1)
+        st2.fill_(-1)
+        torch.cuda.synchronize()
+
+    def run():
+        ctx.gram_exact(arr, b, X.FP64, out=g_full, stream=s)
+        ctx.sumrate(b, g_full, rho, X.ZF | X.CAP | X.CORR_GAP, out=rates, status=st, stream=s)
+        ctx.gram_update_users(arr, b, moved, g_trk, X.FP64, stream=s)
+        ctx.cholesky_update_users(arr, b, moved, g_trk, f_trk, logdet=ld, status=st2, stream=s)
+
+    reset()
+    run()   # eager, and warm
+    s.synchronize()
+    want = [t.clone() for t in (g_full, rates, st, g_trk, f_trk, ld, st2)]
+    assert torch.all(want[2] == 0)
+    assert want[6].tolist() == [0, -1, 0]   # drop 1 has no moved user: its status is not written
+    assert och.normwise_error(b.split(want[3])[2], b.split(want[0])[2]) < 1e-12
+    ctx.graph_begin(s)
+    run()
+    g = ctx.graph_end(s)
+    other = X.Batch(_drops([300, 300], [3, 90], seed=109))
+    for r in range(3):
+        reset()
+        ctx.gram_exact(arr, other, X.FP32H)
+        torch.ones(128, 128, device=dev).sum().item()
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        for w, t in zip(want, (g_full, rates, st, g_trk, f_trk, ld, st2)):
+            assert torch.equal(w, t), r
+    g.close()
