@@ -1,6 +1,7 @@
 /*
  * xlmimo.h - C ABI of the MI355X (gfx950) library for near-field XL-MIMO
- * multiuser Gram matrices, linear-receiver sum-rates and capacity saturation.
+ * multiuser Gram matrices, linear-receiver sum-rates and capacity saturation,
+ * and their updates as users move (tracking).
  *
  * Method: Cui, Park, Alouini, "Channel Capacity Saturation Point and
  * Beamforming Acceleration for Near-Field XL-MIMO Multiuser Communications".
