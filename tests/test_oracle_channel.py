@@ -125,8 +125,8 @@ def test_diagonal_matches_eq4_integral(n):
 
 def test_large_m_converges_to_eq6():
     # eq. (6) is the stationary-phase value of rho; with the stationary point well
-    # inside a long PNUSW array the exact correlation approaches it (survey check:
-    # normwise 2.6e-6 at M = 262144, lambda = 3 mm).  The phase part pins the
+    # inside a long PNUSW array the exact correlation approaches it (normwise about
+    # 2.6e-6 at M = 262144, lambda = 3 mm).  The phase part pins the
     # conjugation convention G = H^H H with h ~ exp(-j k r).
     lam = W.LAMBDA_100GHZ
     arr = W.ula(262144, lam, W.AMP_PNUSW)
