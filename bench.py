@@ -114,7 +114,8 @@ def cpu_baseline(arr, drops, n_list, rho_host, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU (drops shard across GPUs without "
+                                   "communication); runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

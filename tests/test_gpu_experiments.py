@@ -103,7 +103,7 @@ def test_fig3_sweep_matches_oracle(X, E, ctx):
 def test_fig4_reproduces_the_papers_claims(X, E, ctx):
     # Sec. V-C, over 300 drops of the Sec. V scene: ZF beats MRC and reaches the capacity; the modified
     # ZF (the closed-form filter on the true channel) is worse before the saturation point and equal
-    # after it; the saturation point is around 10^4 antennas.  Beside it, the uniform closed form's
+    # after it; the saturation point is of the order of 10^4 antennas.  Beside it, the uniform closed form's
     # modified ZF matches ZF already at small N.
     r = E.fig4(ctx, n_drops=300)
     n = np.array(r["n_list"])

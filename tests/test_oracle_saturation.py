@@ -71,7 +71,7 @@ def test_paper_printed_values():
     e_up = S.expected_y_up_eq17(1.0, 2.0, -7.5, 7.5, 0.9, 10)
     e_dn = S.expected_y_down_eq18(1.0, 2.0, -7.5, 7.5, 0.9, 10)
     m = S.saturation_m(e_up, e_dn, W.LAMBDA_100GHZ / 2)
-    # "around 10^4 antennas": same order of magnitude
+    # the paper gives the saturation scale as about ten thousand antennas: same order of magnitude
     assert sec5["value"] / 2 < m < sec5["value"] * 2
     dens = gold["hexagonal_density_per_m2"]
     d = dens["spacing_m"]
