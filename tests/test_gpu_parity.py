@@ -588,3 +588,22 @@ def test_uneven_batch_samples(X, ctx):
         ref = _exact_ref(arr, drops, d)
         assert och.normwise_error(g[d], ref) < TOL_FP32C
         assert och.normwise_error(gh[d], ref) < TOL_FP32C
+
+
+def test_every_entry_point_accepts_an_empty_batch(X, ctx):
+    # n_drops = 0: every call is a no-op that returns OK and writes nothing
+    arr, drops, _ = W.plain_fp64(4)
+    empty = X.Batch(drops.subset([]))
+    sentinel = torch.full((2,), 7.0, dtype=torch.float64, device="cuda")
+    ctx.gram_exact(arr, empty, X.FP64, out=sentinel)
+    ctx.gram_closedform(arr, empty, X.CF_PAPER, out=sentinel)
+    rho = torch.ones((1, 1), dtype=torch.float64, device="cuda")
+    ctx.sumrate(empty, sentinel, rho, X.ZF | X.MMSE | X.CORR_GAP)
+    erg = torch.full((2, 1, 1), 7.0, dtype=torch.float64, device="cuda")
+    sat = torch.full((4,), 7.0, dtype=torch.float64, device="cuda")
+    ctx.capacity_sweep(arr, [64, 256], empty, X.FORM_EXACT_FP64, rho, X.ZF, ergodic=erg, sat=sat)
+    ctx.gram_update_users(arr, empty, [], sentinel, X.FP64)
+    ctx.cholesky(empty, sentinel)
+    ctx.cholesky_update_users(arr, empty, [], sentinel, sentinel)
+    torch.cuda.synchronize()
+    assert torch.all(sentinel == 7.0) and torch.all(erg == 7.0) and torch.all(sat == 7.0)
