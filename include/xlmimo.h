@@ -182,11 +182,12 @@ int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
  * Drops with a non-finite position or a user at distance 0 from an element
  * get NaN entries (no status array here; xlmimo_zf_mmse_sumrate flags them).
  * K up to XLMIMO_MAX_USERS_EXACT.  A drop with K > XLMIMO_MAX_USERS is split
- * into groups of at most 32 users and every pair of groups runs as one
- * work item of at most 64 users; the group-pair blocks are then copied into
- * the drop's K x K output (a group's own block from its pair with the next
- * group).  Workspace grows with the sum over such drops of (groups choose 2)
- * x 64^2 complex values plus the per-item partial sums. */
+ * into groups of 32 users (the last one shorter) and every pair of groups
+ * runs as one work item of at most 64 users: pairs of neighbouring groups
+ * compute their whole Gram (and give each group its own block), the others
+ * only the products between their two groups; the blocks are then copied
+ * into the drop's K x K output.  Workspace grows with the sum over such drops
+ * of (groups choose 2) x 64^2 complex values plus the per-item partial sums. */
 int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                       int32_t precision, double* gram_out, void* stream);
 
