@@ -3,6 +3,9 @@
 Both run through the library's capacity sweep (exact Gram, closed forms, FP64
 rates, ergodic means and the saturation point); nothing here computes.
 
+* ``fig2``: the power saturation point of Sec. IV-A (Fig. 2): a user's received power reaches the
+  fraction t of its limit (eq. (5)) once the centred array covers [y_down, y_up] of eqs. (13)-(16)
+  (at y = 0, M >= 4 x t / (lambda sqrt(1 - t^2)), eq. (12)); the exact Gram's diagonal at that M.
 * ``fig3``: normalised capacity C(N) / C(N_max) of the Sec. IV scene (100 GHz
   PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m, t = 0.9) at 0 dB and 200 dB,
   beside the analytic saturation span E[y_up] - E[y_down] of eqs. (15)-(16),
@@ -23,13 +26,14 @@ rates, ergodic means and the saturation point); nothing here computes.
   recomputing that user's row and column (xlmimo_gram_update_users) instead of the whole Gram.
   Times both and checks that they agree.  Not a figure of the paper.
 
-``python -m paper_2503_18118_amd.experiments [fig3|fig4|fig5|tracking] [--drops D] [--json PATH]``
+``python -m paper_2503_18118_amd.experiments [fig2|fig3|fig4|fig5|tracking] [--drops D] [--json PATH]``
 prints a table and optionally writes the numbers as JSON.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -49,6 +53,42 @@ import workloads as W  # noqa: E402  (seeded input generators)
 FIG_N = [2 ** e for e in range(6, 18)]
 FIG3_N = [2 ** e for e in range(9, 18)]          # 512 ... 131072 (4 K and up, K = 100)
 FIG5_K = (2, 4, 8, 16, 32, 64, 128, 256, 512, 1000)
+
+
+FIG2_USERS = ((1.0, 0.0), (2.0, 0.0), (5.0, 0.0), (10.0, 0.0), (2.0, 3.0), (5.0, -4.0), (10.0, 7.5))
+
+
+def fig2(ctx, n_drops: int = 0, users=FIG2_USERS, t: float = 0.9) -> dict:
+    """Sec. IV-A power saturation (Fig. 2): for each user (x, y) in metres, the array size M at which
+    the centred 100 GHz PNUSW ULA covers [y_down, y_up] = [y - x tau, y + x tau], tau = t / sqrt(1 - t^2)
+    (eqs. (13)-(16); eq. (12) at y = 0), and the ratio of the exact received power (the Gram's
+    diagonal, FP64) at that M to its limit 4 beta0 / (lambda x) (eq. (5)).  Each user is a drop of its
+    own with its own M (n_drops is unused)."""
+    lam, beta0 = W.LAMBDA_100GHZ, 1.0
+    d = lam / 2.0
+    tau = t / math.sqrt(1.0 - t * t)
+    ms = [int(math.ceil(2.0 * max(abs(y + x * tau), abs(y - x * tau)) / d)) for x, y in users]
+    drops = W._pack(ms, [1] * len(users), [[x, y, 0.0] for x, y in users])
+    b = X.Batch(drops)
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    e0.record(s)
+    g = ctx.gram_exact(W.ula(1, lam, W.AMP_PNUSW), b, X.FP64)
+    e1.record(s)
+    e1.synchronize()
+    power = g.view(torch.complex128).real.cpu().numpy()          # one entry per single-user drop
+    ratio = [float(power[i] / (4.0 * beta0 / (lam * x))) for i, (x, _) in enumerate(users)]
+    return {"scene": "Sec. IV-A: 100 GHz PNUSW ULA, half-wavelength spacing", "t": t,
+            "users": [list(u) for u in users], "saturation_m": ms, "power_ratio": ratio,
+            "gpu_ms": e0.elapsed_time(e1)}
+
+
+def _table_fig2(r):
+    lines = [f"Fig. 2 ({r['scene']}; t = {r['t']}): received power at the saturation size M against its limit",
+             "| user (x, y) m | M | P / P_lim |", "|---|---|---|"]
+    for u, m, q in zip(r["users"], r["saturation_m"], r["power_ratio"]):
+        lines.append(f"| ({u[0]:g}, {u[1]:g}) | {m} | {q:.6f} |")
+    return "\n".join(lines)
 
 
 def _timed_sweep(ctx, arr, n_list, batch, form, rho, schemes, t_sat=0.9, eps_sat=0.05):
@@ -263,13 +303,14 @@ def _table_fig4(r):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("figure", choices=["fig3", "fig4", "fig5", "tracking"])
+    ap.add_argument("figure", choices=["fig2", "fig3", "fig4", "fig5", "tracking"])
     ap.add_argument("--drops", type=int, default=1000)
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     ctx = X.Context(0)
     t0 = time.perf_counter()
-    run, table = {"fig3": (fig3, _table_fig3), "fig4": (fig4, _table_fig4), "fig5": (fig5, _table_fig5),
+    run, table = {"fig2": (fig2, _table_fig2), "fig3": (fig3, _table_fig3), "fig4": (fig4, _table_fig4),
+                  "fig5": (fig5, _table_fig5),
                   "tracking": (tracking, _table_tracking)}[args.figure]
     r = run(ctx, args.drops)
     r["wall_s"] = time.perf_counter() - t0

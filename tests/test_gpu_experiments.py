@@ -154,3 +154,17 @@ def test_fig5_matches_oracle_and_the_papers_value(X, E, ctx):
         drops = W.rect_drops(W.rng_for(10), 5, k, 1024, (1.0, 10.0), (-7.5, 7.5))
         want = np.mean([orates.corr_gap(och.gram_exact(arr, drops.users_of(d))) for d in range(5)])
         assert got == pytest.approx(want, rel=1e-10)
+
+
+def test_fig2_power_saturation_point(X, E, ctx):
+    # Sec. IV-A: at the array size of eqs. (12)-(16) the exact received power reaches the fraction t of
+    # its limit: t itself (to the rounding of M up to whole antennas) for users at y = 0, at least t
+    # otherwise; the GPU ratio against the oracle's eq. (4) / eq. (5) at the same M
+    r = E.fig2(ctx)
+    t = r["t"]
+    for (x, y), m, q in zip(r["users"], r["saturation_m"], r["power_ratio"]):
+        want = ocf.power_eq4(x, y, m, W.LAMBDA_100GHZ) / ocf.power_limit_eq5(x, W.LAMBDA_100GHZ)
+        assert q == pytest.approx(want, rel=1e-5), (x, y, m)
+        assert q >= t - 1e-6, (x, y, m, q)
+        if y == 0.0:
+            assert q == pytest.approx(t, abs=2e-4), (x, m, q)
