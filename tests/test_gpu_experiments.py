@@ -168,3 +168,26 @@ def test_fig2_power_saturation_point(X, E, ctx):
         assert q >= t - 1e-6, (x, y, m, q)
         if y == 0.0:
             assert q == pytest.approx(t, abs=2e-4), (x, m, q)
+
+
+def test_sweep_saturation_converges_to_eqs_17_18(X, ctx):
+    # Sec. IV-B: for users uniform on a rectangle the expected saturation bounds E[y_up], E[y_down]
+    # have the closed forms of eqs. (17)-(18); the sweep's mean over 2e5 drops of the Sec. V scene
+    # (K = 10) converges to them within five Monte Carlo standard errors (from the same drops' bounds)
+    from oracle import saturation as osat
+    t, k, n_drops = 0.9, 10, 200_000
+    drops = W.rect_drops(W.rng_for(12), n_drops, k, 64, (1.0, 2.0), (-7.5, 7.5))
+    b = X.Batch(drops)
+    rho = torch.ones((1, b.total_users), dtype=torch.float64, device="cuda")
+    erg, sat, st = ctx.capacity_sweep(W.ula(64, W.LAMBDA_100GHZ, W.AMP_PNUSW), [64], b, X.FORM_CF_PAPER,
+                                      rho, X.MRC, t_sat=t)
+    sat = sat.cpu().numpy()
+    u = drops.pos.reshape(n_drops, k, 3)
+    tau = t / np.sqrt(1.0 - t * t)
+    up = (tau * u[:, :, 0] + u[:, :, 1]).max(axis=1)
+    dn = (-tau * u[:, :, 0] + u[:, :, 1]).min(axis=1)
+    for got, per_drop, want in ((sat[0], up, osat.expected_y_up_eq17(1.0, 2.0, -7.5, 7.5, t, k)),
+                                (sat[1], dn, osat.expected_y_down_eq18(1.0, 2.0, -7.5, 7.5, t, k))):
+        se = per_drop.std() / np.sqrt(n_drops)
+        assert got == pytest.approx(per_drop.mean(), rel=1e-12)
+        assert abs(got - want) < 5 * se, (got, want, se)
