@@ -352,7 +352,8 @@ int xlmimo_mlp_loss_grad(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void
 int xlmimo_mlp_train_step(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
                           const float* target, float lr, double* loss_out, void* stream);
 /* Network outputs, DEVICE float [n][XLMIMO_MLP_OUT].  Widths 64, 128 and 256 run
- * one fused kernel (64 pairs per workgroup, activations kept in LDS). */
+ * one fused kernel (128 pairs per workgroup at width 256, 64 otherwise;
+ * activations kept in LDS). */
 int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, float* out,
                        void* stream);
 
