@@ -62,15 +62,17 @@ __device__ __forceinline__ GeluParts gelu_parts(float z) {
 // FP32, about the rounding of the result, 1.6e-7 relative for |z| < 0.01, and
 // x Q(x) < 1e-8 |z| / 6 past the clamp.  Ten instructions, one of them an exp2,
 // against thirteen with a reciprocal and an exp2 for the form above.
+// Clamp and max(z, 0) as v_med3_f32: with IEEE min/max the compiler would first quiet
+// the inputs (a v_max each) when z comes straight from the matrix core.
 __device__ __forceinline__ float gelu(float z) {
-  const float x = fminf(fabsf(z), 6.0f);
+  const float x = __builtin_amdgcn_fmed3f(fabsf(z), 0.0f, 6.0f);
   float p = fmaf(x, 2.992528485e-05f, -7.398832138e-04f);
   p = fmaf(p, x, 7.977489636e-03f);
   p = fmaf(p, x, -5.323822283e-02f);
   p = fmaf(p, x, -4.589156649e-01f);
   p = fmaf(p, x, -1.151147087e+00f);
   p = fmaf(p, x, -1.000000000e+00f);
-  return fmaf(-fabsf(z), __builtin_amdgcn_exp2f(p), fmaxf(z, 0.0f));
+  return fmaf(-fabsf(z), __builtin_amdgcn_exp2f(p), __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
   const GeluParts g = gelu_parts(z);
@@ -524,11 +526,15 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
   for (int l = 0; l < depth; ++l) {  // hidden layers
     const int K = (l == 0) ? 32 : W;
     const float* bl = master + offs[2 * l + 1];
+    // the sums start at the bias: the products accumulate onto it, with no add in the epilogue
     floatx4 acc[FB][NB];
 #pragma unroll
-    for (int i = 0; i < FB; ++i)
+    for (int i = 0; i < FB; ++i) {
+      const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
+      const floatx4 bv = {bl[f0], bl[f0 + 1], bl[f0 + 2], bl[f0 + 3]};
 #pragma unroll
-      for (int j = 0; j < NB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NB; ++j) acc[i][j] = bv;
+    }
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kk = k0 + 8 * kg;
       if (k0 + 64 < K) load_w(l, kk + 64, wn2);
@@ -549,18 +555,16 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
       load_w(l + 1, 8 * kg, wcur);
       load_w(l + 1, 32 + 8 * kg, wn1);
     }
-    // bias + GELU into packed BF16 before the barrier; only the stores wait for the other waves
+    // GELU into packed BF16 before the barrier; only the stores wait for the other waves
     bf16x4 outv[FB][NB];
 #pragma unroll
     for (int i = 0; i < FB; ++i) {
-      const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
-      const float b0 = bl[f0], b1 = bl[f0 + 1], b2 = bl[f0 + 2], b3 = bl[f0 + 3];
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        outv[i][j][0] = (__bf16)gelu(acc[i][j][0] + b0);
-        outv[i][j][1] = (__bf16)gelu(acc[i][j][1] + b1);
-        outv[i][j][2] = (__bf16)gelu(acc[i][j][2] + b2);
-        outv[i][j][3] = (__bf16)gelu(acc[i][j][3] + b3);
+        outv[i][j][0] = (__bf16)gelu(acc[i][j][0]);
+        outv[i][j][1] = (__bf16)gelu(acc[i][j][1]);
+        outv[i][j][2] = (__bf16)gelu(acc[i][j][2]);
+        outv[i][j][3] = (__bf16)gelu(acc[i][j][3]);
       }
     }
     __syncthreads();   // every wave has read this layer's input
