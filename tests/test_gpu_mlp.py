@@ -167,6 +167,30 @@ def test_fused_forward_other_shapes(X, ctx, width, depth, n_drops):
     mlp.close()
 
 
+@pytest.mark.parametrize("width,depth", [(256, 4), (128, 3), (64, 2)])
+def test_fused_forward_at_kernel_precision(X, ctx, width, depth):
+    # The fused forward against the oracle's network evaluated at the kernel's precision:
+    # BF16 weights and inputs, FP32 biases, FP64 sums, each hidden activation rounded to
+    # BF16 after the GELU.  What is left is the FP32 accumulation and the rare BF16
+    # rounding it flips, so an error in the activation (its polynomial, clamp or max)
+    # at the 1e-3 level fails here, where the plain FP64 comparison allows 2e-2.
+    rng = np.random.default_rng(29 + width)
+    mlp = X.MLP(ctx, width, depth)
+    params = OM.init_params(rng, width, depth)
+    mlp.set_params(params.astype(np.float32))
+    arr, drops, pi, *_ = _pairs(X, ctx, mlp, n_drops=20, k=16, stream=31 + width)   # 2400 pairs, ragged tile
+    out = mlp.forward(pi).cpu().numpy().astype(np.float64)
+    layers = OM.unpack(params, width, depth)
+    a = pi.feat.float().cpu().numpy()[:, :6].astype(np.float64)
+    for li, (w, b) in enumerate(layers):
+        z = a @ bf16_round(w).T + np.asarray(b, np.float32).astype(np.float64)
+        a = bf16_round(OM.gelu(z)) if li + 1 < len(layers) else z
+    err = np.linalg.norm(out - a) / np.linalg.norm(a)
+    print(f"fused forward, width {width}, depth {depth}: {err:.2e} against the BF16-activation network")
+    assert err < 1e-3, (width, depth, err)
+    mlp.close()
+
+
 def test_fallback_recomputes_flagged_drops_exactly(X, ctx):
     # Drops where the predicted log-variance exceeds log_var_max for some pair are recomputed by the
     # exact FP32H kernel over their own work items only (selected on the device); the other drops keep
