@@ -67,9 +67,7 @@ Variant UNIFORM (ULA; an extension beyond the paper's formulas, not one of them)
     plus the same discrete end corrections; or the direct sum over the N
     elements (the definition itself) when the array has at most DIRECT_MAX_N
     elements or the sum costs no more than the quadrature.
-  The diagonal is the closed form above.  end_term() (the regularised
-  geometric-series end term) is the learned correction's basis, not part of
-  this variant.
+  The diagonal is the closed form above.
 """
 from __future__ import annotations
 
@@ -192,18 +190,6 @@ def _amp_product(arr: ArraySpec, xp_i, xp_j, ri, rj):
     if arr.amp_model == AMP_PNUSW:
         return arr.beta0 * np.sqrt(xp_i * xp_j) / (ri * rj) ** 1.5
     return (arr.wavelength / (4.0 * np.pi)) ** 2 / (ri * rj)
-
-
-def end_term(arr: ArraySpec, xp_i, y_i, xp_j, y_j, y_e, side):
-    """End-element term of sum_n conj(h_i) h_j at the array end y_e (side +1 top, -1 bottom), regularised."""
-    k = 2.0 * np.pi / arr.wavelength
-    d = arr.spacing
-    ri, rj = np.hypot(xp_i, y_e - y_i), np.hypot(xp_j, y_e - y_j)
-    d1 = k * ((y_e - y_i) / ri - (y_e - y_j) / rj)
-    d2 = k * (xp_i ** 2 / ri ** 3 - xp_j ** 2 / rj ** 3)
-    den = 1.0 - np.exp(-1j * side * d1 * d)
-    eps2 = d * d * abs(d2) / (2.0 * np.pi)
-    return _amp_product(arr, xp_i, xp_j, ri, rj) * np.exp(1j * k * (ri - rj)) * np.conj(den) / (abs(den) ** 2 + eps2)
 
 
 def quad_panels(spacing, lam, xp_i, y_i, xp_j, y_j, n):

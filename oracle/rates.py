@@ -142,11 +142,3 @@ def schur_horn_bound(g, rho):
     r = g / np.outer(dg, dg)
     sign, logdet = np.linalg.slogdet(r)
     return float(logdet / np.log(2.0) + hadamard_bound(g, rho))
-
-
-def normalised_bound_gap(g):
-    """Appendix A: -(1/K) sum_i log2 lambda_i(R), the normalised gap at a_i = 1."""
-    dg = np.sqrt(np.real(np.diag(g)))
-    r = g / np.outer(dg, dg)
-    ev = np.linalg.eigvalsh(r)
-    return float(-np.mean(np.log2(ev)))
