@@ -191,6 +191,37 @@ int xlmimo_timing_read(xlmimo_ctx* ctx, double* total_ms, int64_t* n_launches);
 int xlmimo_gram_exact(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                       int32_t precision, double* gram_out, void* stream);
 
+/* Allocation-free exact Gram, for callers that cannot allocate device memory
+ * during the call (tight serving loops, harnesses that forbid hipMalloc after
+ * start-up).  It computes what xlmimo_gram_exact computes, with
+ * the same kernels, and calls no hipMalloc, hipFree or other allocating
+ * routine: its queue counter, launch plan and per-item partial sums live in
+ * one static device array of XLMIMO_NOALLOC_SCRATCH_BYTES per GPU, held from
+ * the library's first use of that GPU until the process ends; its address is
+ * taken once per device by xlmimo_ctx_create.
+ *   ctx        a context of the GPU to run on (device, error text); none of
+ *              its workspace is used
+ *   arr, batch, precision, gram_out  as in xlmimo_gram_exact
+ *   stream     as in xlmimo_gram_exact
+ * Limits: K <= XLMIMO_MAX_USERS per drop, and the batch's plan and partial
+ * sums must fit the static array (56 B per drop, plus 16 B and
+ * (nb(nb+1)/2 + nb^2) x 2 KiB per work item, nb = ceil(K/16); work items are
+ * element ranges of the length xlmimo_gram_exact picks for the batch,
+ * lengthened up to one item per drop when needed).  A batch beyond them
+ * returns XLMIMO_EINVAL before anything is enqueued.  Untuned, the work items
+ * equal those of xlmimo_gram_exact, and the Grams are bit-identical to its
+ * own.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (the queue counter is cleared by a kernel at the start of each call):
+ * calls whose work overlaps in time on one GPU race, whatever their context
+ * or stream.  Each call uploads its launch plan with an asynchronous copy on
+ * `stream` from a static host buffer (pageable memory, so the call is not
+ * meant for graph capture); a call first waits until the previous call's
+ * upload has completed. */
+#define XLMIMO_NOALLOC_SCRATCH_BYTES (64u << 20)
+int xlmimo_gram_exact_noalloc(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
+                              int32_t precision, double* gram_out, void* stream);
+
 /* Tracking update of the exact Gram (Sec. V-B: user states known from sensing
  * let the channel be regenerated as users move).  After users of the batch
  * have moved (their new positions already written to batch->user_pos),

@@ -85,6 +85,7 @@ struct xlmimo_ctx {
   // autotuned exact-Gram launch shapes (xlmimo_autotune_exact), keyed by plan
   std::unordered_map<uint64_t, int64_t> tuned_chunk;
   std::unordered_map<uint64_t, int> tuned_grid;   // key ^ precision
+  hipError_t scratch_init = hipSuccess;   // look-up of the allocation-free path's static array
 };
 
 struct xlmimo_graph {
@@ -523,6 +524,129 @@ int run_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, Plan*
     HIP_TRY(c, launch_scatter_rows(p->d_vr, p->n_vr, p->d_vmap, (const double*)c->scratch_vgram.p, gram_out, s));
   else if (p->vplan)
     HIP_TRY(c, launch_scatter_groups(p->d_v, p->n_v, (const double*)c->scratch_vgram.p, gram_out, s));
+  return XLMIMO_OK;
+}
+
+// Allocation-free exact Gram (xlmimo_gram_exact_noalloc).  The launch plan is
+// built on the host into a static staging buffer and copied on the stream into
+// the static device array, laid out as
+//   [queue counter: 256 B][DropK x n_drops][ItemK x n_items][partials]
+// (each part 256-byte aligned).  No heap or device allocation is made: the
+// items are sorted in place (cost descending, then drop and chunk ascending,
+// the order of the context's plans).
+constexpr size_t kNoallocBytes = XLMIMO_NOALLOC_SCRATCH_BYTES;
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+struct NoallocState {
+  std::mutex mu;
+  unsigned char stage[kNoallocBytes];   // host image of the plan (DropK, then ItemK)
+  hipEvent_t uploaded[64] = {};         // per device: recorded after the last plan upload
+};
+NoallocState& noalloc_state() {
+  static NoallocState st;
+  return st;
+}
+
+int gram_exact_noalloc_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,
+                            double* gram_out, hipStream_t s) {
+  if (c->device >= 64) return set_err(c, XLMIMO_EINVAL, "device %d beyond the allocation-free path's 64", c->device);
+  unsigned char* dev = static_cast<unsigned char*>(static_scratch(c->device));
+  if (!dev)
+    return set_err(c, XLMIMO_EDEVICE, "static scratch of device %d was not set up: %s", c->device,
+                   hipGetErrorString(c->scratch_init));
+  const int n = (int)b->n_drops;
+  int nb_max = 1;
+  int64_t total_elems = 0, max_ne = 1, part_per_chunk_sum = 0;
+  auto ne_of = [&](int d) -> int64_t {
+    return a->geometry == XLMIMO_UPA ? a->n_y * a->n_z : (b->n_elems ? b->n_elems[d] : a->n_y);
+  };
+  for (int d = 0; d < n; ++d) {
+    const int nb = (b->n_users[d] + 15) / 16;
+    nb_max = std::max(nb_max, nb);
+    total_elems += ne_of(d);
+    max_ne = std::max(max_ne, ne_of(d));
+    part_per_chunk_sum += (int64_t)partial_values(nb) * 64;
+  }
+  // work-item length: the context's default for this batch, lengthened while
+  // the plan and partial sums do not fit
+  const int g32 = gram_exact_grid(XLMIMO_FP32C, nb_max, a->geometry, a->amp_model);
+  const int g64 = gram_exact_grid(XLMIMO_FP64, nb_max, a->geometry, a->amp_model);
+  const int g16 = gram_exact_grid(XLMIMO_FP32H, nb_max, a->geometry, a->amp_model);
+  int64_t ch = chunk_length(total_elems, std::min(std::min(g32, g64), g16));
+  const size_t drops_bytes = align256(sizeof(DropK) * (size_t)n);
+  auto need = [&](int64_t chunk, int64_t* items_out) -> size_t {
+    int64_t items = 0, doubles = 0;
+    for (int d = 0; d < n; ++d) {
+      const int64_t ni = (ne_of(d) + chunk - 1) / chunk;
+      items += ni;
+      doubles += ni * (int64_t)partial_values((b->n_users[d] + 15) / 16) * 64;
+    }
+    if (items_out) *items_out = items;
+    return 256 + drops_bytes + align256(sizeof(ItemK) * (size_t)items) + sizeof(double) * (size_t)doubles;
+  };
+  int64_t n_items = 0;
+  size_t bytes = need(ch, &n_items);
+  while (bytes > kNoallocBytes && ch < max_ne) {
+    ch = std::min<int64_t>(2 * ch, (max_ne + 127) / 128 * 128);
+    bytes = need(ch, &n_items);
+  }
+  if (bytes > kNoallocBytes)
+    return set_err(c, XLMIMO_EINVAL, "batch needs %zu bytes of scratch with one work item per drop; the "
+                   "allocation-free exact Gram holds %zu", bytes, kNoallocBytes);
+  if (n_items > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "too many work items");
+
+  NoallocState& st = noalloc_state();
+  std::lock_guard<std::mutex> lk(st.mu);
+  hipEvent_t& up = st.uploaded[c->device];
+  if (!up) HIP_TRY(c, hipEventCreateWithFlags(&up, hipEventDisableTiming));
+  else HIP_TRY(c, hipEventSynchronize(up));   // the previous upload has left the staging buffer
+  DropK* drops = reinterpret_cast<DropK*>(st.stage);
+  ItemK* items = reinterpret_cast<ItemK*>(st.stage + drops_bytes);
+  int64_t uoff = 0, goff = 0, pairs = 0, poff = 0, it = 0;
+  for (int d = 0; d < n; ++d) {
+    DropK& dk = drops[d];
+    dk = DropK{};
+    dk.n_elems = (int32_t)ne_of(d);
+    dk.k = b->n_users[d];
+    dk.cross = 0;
+    dk.nb = (dk.k + 15) / 16;
+    dk.user_off = uoff;
+    dk.gram_off = goff;
+    dk.pair_off = pairs;
+    pairs += (int64_t)dk.k * (dk.k - 1) / 2;
+    uoff += dk.k;
+    goff += (int64_t)dk.k * dk.k;
+    const int64_t ni = (dk.n_elems + ch - 1) / ch;
+    dk.n_items = (int32_t)ni;
+    dk.part_off = poff;
+    poff += ni * (int64_t)partial_values(dk.nb) * 64;
+    for (int64_t i = 0; i < ni; ++i) {
+      ItemK& itm = items[it++];
+      itm.drop = d;
+      itm.chunk = (int32_t)i;
+      itm.e_begin = (int32_t)(i * ch);
+      itm.e_end = (int32_t)std::min<int64_t>((i + 1) * ch, dk.n_elems);
+    }
+  }
+  auto cost = [&](const ItemK& x) {
+    const int nb = drops[x.drop].nb;
+    return (int64_t)(x.e_end - x.e_begin) * (nb * 8 + 3 * (nb * (nb + 1) / 2 + nb * nb));
+  };
+  std::sort(items, items + n_items, [&](const ItemK& x, const ItemK& y) {
+    const int64_t cx = cost(x), cy = cost(y);
+    if (cx != cy) return cx > cy;
+    return x.drop != y.drop ? x.drop < y.drop : x.chunk < y.chunk;
+  });
+  int* d_counter = reinterpret_cast<int*>(dev);
+  DropK* d_drops = reinterpret_cast<DropK*>(dev + 256);
+  ItemK* d_items = reinterpret_cast<ItemK*>(dev + 256 + drops_bytes);
+  double* d_part = reinterpret_cast<double*>(dev + 256 + drops_bytes + align256(sizeof(ItemK) * (size_t)n_items));
+  HIP_TRY(c, hipMemcpyAsync(dev + 256, st.stage, drops_bytes + sizeof(ItemK) * (size_t)n_items,
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipEventRecord(up, s));
+  const int grid = std::min(gram_exact_grid(precision, nb_max, a->geometry, a->amp_model), std::max((int)n_items, 1));
+  HIP_TRY(c, launch_gram_exact(precision, nb_max, to_kernel(a), d_drops, n, b->user_pos, d_items, (int)n_items,
+                               d_counter, d_part, gram_out, grid, s));
   return XLMIMO_OK;
 }
 
@@ -1107,6 +1231,10 @@ int xlmimo_ctx_create(xlmimo_ctx** out, int device) {
     delete c;
     return XLMIMO_EDEVICE;
   }
+  // the allocation-free exact Gram's static array: its address on this device
+  // (a failure is reported by xlmimo_gram_exact_noalloc, the array's only user)
+  c->scratch_init = static_scratch_init(device);
+  if (c->scratch_init != hipSuccess) (void)hipGetLastError();
   std::vector<double> gl, gl_f;
   c->n_gl = 64;
   gauss_legendre(c->n_gl, gl);
@@ -1186,6 +1314,21 @@ int xlmimo_gram_exact(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* 
   if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
   if ((rc = set_device(c))) return rc;
   return gram_exact_impl(c, a, b, nullptr, precision, gram_out, (hipStream_t)stream);
+}
+
+int xlmimo_gram_exact_noalloc(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,
+                              double* gram_out, void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_array(c, a);
+  if (!rc) rc = check_batch(c, b, true, XLMIMO_MAX_USERS);
+  if (rc) return rc;
+  if (precision != XLMIMO_FP64 && precision != XLMIMO_FP32C && precision != XLMIMO_FP32H)
+    return set_err(c, XLMIMO_EINVAL, "bad precision %d", precision);
+  if (b->n_drops == 0) return XLMIMO_OK;
+  if (!gram_out) return set_err(c, XLMIMO_EINVAL, "gram_out is NULL");
+  if ((rc = set_device(c))) return rc;
+  return gram_exact_noalloc_impl(c, a, b, precision, gram_out, (hipStream_t)stream);
 }
 
 int xlmimo_gram_update_users(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, int32_t precision,

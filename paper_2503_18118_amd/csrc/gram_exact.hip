@@ -38,6 +38,8 @@
 // Determinism: every sum has a fixed order (waves in order through LDS, items
 // of a drop in chunk order in the finalize pass), so results are bitwise
 // repeatable regardless of which workgroup ran which item.
+#include <mutex>
+
 #include "device_math.h"
 #include "internal.h"
 #include "xlmimo.h"
@@ -765,6 +767,44 @@ hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const
     k_gram_finalize<float><<<n_drops, 256, 0, s>>>(arr, d_drops, d_pos, d_partials, d_gram, d_mask,
                                                    precision == XLMIMO_FP32H);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free exact Gram (xlmimo_gram_exact_noalloc): its
+// queue counter, launch plan and per-item partial sums, in one file-scope
+// device array that each GPU holds from the module's load to the end of the
+// process.  Host code never names the array itself (its host-side name is a
+// stand-in, not a device address): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// every launch and copy uses that address.
+static __device__ __align__(256) unsigned char scratch[XLMIMO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;   // the caller makes the device current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace xl

@@ -163,4 +163,11 @@ hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf1
                                     const float* master, const int64_t* d_offs, float* out, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;
 
+// Allocation-free exact Gram: the per-device address of the static scratch
+// array (XLMIMO_NOALLOC_SCRATCH_BYTES).  static_scratch_init looks it up once
+// per device, with that device current; static_scratch returns it (nullptr
+// before the look-up).
+hipError_t static_scratch_init(int device);
+void* static_scratch(int device);
+
 }  // namespace xl

@@ -37,7 +37,7 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
             "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
             "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users", "xlmimo_cholesky",
-            "xlmimo_cholesky_update_users")
+            "xlmimo_cholesky_update_users", "xlmimo_gram_exact_noalloc")
 
 
 class XlArray(C.Structure):
@@ -62,6 +62,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_last_error.restype = C.c_char_p
     lib.xlmimo_version.restype = C.c_char_p
     lib.xlmimo_gram_exact.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp]
+    lib.xlmimo_gram_exact_noalloc.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, vp]
     lib.xlmimo_gram_update_users.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, i64,
                                              C.POINTER(C.c_int64), vp, vp]
     lib.xlmimo_cholesky.argtypes = [vp, C.POINTER(XlBatch), vp, vp, vp, vp, vp, vp]
@@ -218,6 +219,13 @@ class Context:
         a = make_array(arr)
         self._check(_lib.xlmimo_gram_exact(self.h, C.byref(a), C.byref(batch.struct), precision, _ptr(out),
                                            _stream(stream)), "xlmimo_gram_exact")
+        return out
+
+    def gram_exact_noalloc(self, arr, batch: Batch, precision: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """xlmimo_gram_exact_noalloc into the caller's `out` (complex128 interleaved, the Gram layout)."""
+        a = make_array(arr)
+        self._check(_lib.xlmimo_gram_exact_noalloc(self.h, C.byref(a), C.byref(batch.struct), precision, _ptr(out),
+                                                   _stream(stream)), "xlmimo_gram_exact_noalloc")
         return out
 
     def gram_update_users(self, arr, batch: Batch, moved, gram: torch.Tensor, precision: int = FP32C,
