@@ -123,6 +123,7 @@ def main():
 
     import workloads as W
     from paper_2503_18118_amd import learned as Lr
+    from paper_2503_18118_amd import snr
     from paper_2503_18118_amd import xlmimo as X
 
     if not torch.cuda.is_available():
@@ -136,7 +137,7 @@ def main():
     n_list = list(meta["n_list"])
     ctx = X.Context(0)
     batch = X.Batch(drops)
-    rho = X.rho_for_snr(arr, meta["snr_db"], meta["ref_distance"], batch.total_users)
+    rho = snr.rho_for_snr(arr, meta["snr_db"], meta["ref_distance"], batch.total_users)
     schemes = X.ZF | X.MMSE
     k = int(drops.n_users[0])
     n_drops = drops.n_drops

@@ -348,9 +348,12 @@ int xlmimo_capacity_sweep(xlmimo_ctx* ctx, const xlmimo_array* arr, int32_t n_N,
  *   (r_i/50, theta_i/(pi/3), r_j/50, theta_j/(pi/3), log4 N - 6, d/lambda - 1/2)
  * (r, theta: polar coordinates of the user about the array centre, theta from
  * broadside, with x the distance from the array line) and predicts
- *   delta_rho = sum_m c_m e^{j phi_m},  phi(y) = (2 pi / lambda)(r_i(y) - r_j(y)),
- * at y = the two end elements and the stationary point (phasors computed in
- * FP64), plus s = log sigma^2.  Network: XLMIMO_MLP_IN -> [Linear(width) +
+ *   delta_rho = sum_m c_m b_m,  c_m = c0_m + (network output m),  c0 = (1, 1, 0),
+ * over three basis phasors b_m: the discrete sum's end-element terms at the two
+ * array ends and e^{j phi(y*)} at the stationary point y*, with
+ * phi(y) = (2 pi / lambda)(r_i(y) - r_j(y)) (phases computed in FP64), plus
+ * s = log sigma^2.  An all-zero output is thus the analytic end correction,
+ * and the network learns the deviation from it.  Network: XLMIMO_MLP_IN -> [Linear(width) +
  * GELU] x depth -> Linear(XLMIMO_MLP_OUT); BF16 weights and activations on the
  * matrix cores, FP32 accumulation; FP32 master weights and Adam state.
  * Parameters, flat FP32: per layer W (out x in, row-major) then b (out). */
@@ -361,6 +364,19 @@ int64_t xlmimo_mlp_param_count(const xlmimo_mlp* mlp);
 /* HOST float [param_count]; set also resets the Adam state.  Both synchronise the device. */
 int     xlmimo_mlp_set_params(xlmimo_mlp* mlp, const float* host_params);
 int     xlmimo_mlp_get_params(xlmimo_mlp* mlp, float* host_params);
+/* Fallback gate by antenna count.  A drop of N antennas falls back to the exact
+ * Gram when any of its pairs has a predicted log-variance above
+ * min(log_var_max of the call, log_var_max[b]), b the first bin with
+ * N <= n_upper[b]; N above the last bound uses the call's value alone.  A
+ * threshold of -inf sends every drop of its bin to the exact Gram (a batch that
+ * falls back whole skips the network).  The thresholds are meant to be
+ * calibrated on held-out drops with the exact Gram as the judge.
+ *   n_bins       0 .. 16 (0 clears the table)
+ *   n_upper      HOST int64 [n_bins], strictly ascending, >= 1
+ *   log_var_max  HOST double [n_bins], not NaN (-inf allowed)
+ * Takes effect for calls enqueued afterwards (a captured graph keeps the
+ * table it was captured with). */
+int     xlmimo_mlp_set_gate(xlmimo_mlp* mlp, int32_t n_bins, const int64_t* n_upper, const double* log_var_max);
 /* Number of pairs i < j over the batch (host arithmetic, -1 on bad input). */
 int64_t xlmimo_pair_count(const xlmimo_batch* batch);
 
@@ -390,7 +406,8 @@ int xlmimo_mlp_forward(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* 
 
 /* Closed form (variant as in xlmimo_gram_closedform) + learned residual:
  * G_ij = G~_ij + delta_rho sqrt(G~_ii G~_jj) for every pair.  A drop with any
- * pair whose predicted log-variance exceeds log_var_max is recomputed with the
+ * pair whose predicted log-variance exceeds log_var_max (or the threshold of its
+ * N set by xlmimo_mlp_set_gate, whichever is lower) is recomputed with the
  * exact FP32H Gram and gets XLMIMO_ST_FELL_BACK in status_out (ULA only). */
 int xlmimo_gram_closedform_mlp(xlmimo_ctx* ctx, const xlmimo_array* arr, const xlmimo_batch* batch,
                                int32_t variant, xlmimo_mlp* mlp, double log_var_max, double* gram_out,

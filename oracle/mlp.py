@@ -27,8 +27,10 @@ Pair inputs (user i, user j of one drop; x = perpendicular distance, y along the
             (closedform.numeric_route: slow-phase pairs and broad stationary zones).
   target    delta = rho_exact_ij - rho~_ij (complex)
 Network: 6 -> [Linear(w) + GELU] x depth -> Linear(7); GELU(z) = z (1 + erf(z / sqrt 2)) / 2.
-Output o: coefficients c_m = o[2m] + j o[2m+1] (m = top, bot, star) and s = o[6] = log sigma^2;
-  prediction  p = sum_m c_m b_m   (c_top = c_bot = 1, c_spm = 0 is the analytic end correction)
+Output o: coefficients c_m = C0_m + o[2m] + j o[2m+1] (m = top, bot, star) and s = o[6] = log sigma^2,
+  with C0 = (1, 1, 0): an all-zero output is the analytic end correction (both end terms of the
+  discrete sum added to the closed form), and the network predicts how far the coefficients lie from it;
+  prediction  p = sum_m c_m b_m
   loss        mean over pairs of |delta - p|^2 e^{-s} + s        (Gaussian negative log-likelihood)
 Parameters, flat, layer by layer: W (out x in, row-major) then b (out).
 Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
@@ -143,9 +145,12 @@ def forward(params, x, width=256, depth=4):
     return a, cache
 
 
+C0 = np.array([1.0, 1.0, 0.0])   # basis coefficients of the analytic end correction
+
+
 def predict(out, phasors):
     """Complex prediction p [n] and log-variance s [n] from the network output."""
-    c = out[:, 0:6:2] + 1j * out[:, 1:6:2]
+    c = C0 + out[:, 0:6:2] + 1j * out[:, 1:6:2]
     return np.sum(c * phasors, axis=1), out[:, 6]
 
 

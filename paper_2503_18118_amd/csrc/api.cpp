@@ -796,6 +796,9 @@ struct xlmimo_mlp {
   int64_t* d_offs = nullptr;  // per layer: weight offset, bias offset (fused inference)
   int64_t t = 0;
   DevBuf act, partial, split;
+  // fallback gate by antenna count (xlmimo_mlp_set_gate)
+  std::vector<int64_t> gate_n;
+  std::vector<double> gate_thr;
 };
 
 namespace {
@@ -979,8 +982,29 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   int rc = get_plan(c, a, b, n_override, &p);
   if (rc) return rc;
   if ((rc = ensure(c, c->scratch_routes, sizeof(int32_t) * std::max<int64_t>(p->n_pairs, 1), s))) return rc;
-  HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
-                               gram_out, status, p->k_max, s, p->n_pairs, (int32_t*)c->scratch_routes.p));
+  GateK gate{};
+  gate.cap = (float)log_var_max;
+  gate.n_bins = (int32_t)M->gate_n.size();
+  for (int i = 0; i < gate.n_bins; ++i) {
+    gate.n_upper[i] = M->gate_n[i];
+    gate.thr[i] = (float)M->gate_thr[i];
+  }
+  // a batch whose every drop falls in a bin (or under a cap) of -inf falls back whole: the
+  // network and its inputs are skipped
+  bool all_fall_back = !(gate.cap > -INFINITY);
+  if (!all_fall_back && gate.n_bins > 0) {
+    all_fall_back = true;
+    for (int d = 0; d < (int)b->n_drops && all_fall_back; ++d) {
+      const int64_t ne = n_override ? *n_override : (b->n_elems ? b->n_elems[d] : a->n_y);
+      float thr = gate.cap;
+      for (int i = 0; i < gate.n_bins; ++i)
+        if (ne <= gate.n_upper[i]) {
+          thr = std::min(thr, gate.thr[i]);
+          break;
+        }
+      all_fall_back = !(thr > -INFINITY);
+    }
+  }
   const int64_t np = p->n_pairs;
   const size_t fb = (sizeof(__bf16) * kFeatPitch * np + 255) / 256 * 256;
   const size_t ab = (sizeof(float) * kAuxPitch * np + 255) / 256 * 256;
@@ -997,11 +1021,22 @@ int closedform_mlp_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch
   float* net_out = (float*)(base + fb + ab + pb + flb);
   ItemK* items_sel = (ItemK*)(base + fb + ab + pb + flb + ob);
   int* n_sel = (int*)(base + fb + ab + pb + flb + ob + ib - 256);
-  HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 0, s));
-  HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_out, nullptr, feat, aux,
-                                nullptr, pmap, s));
-  if ((rc = mlp_infer(c, M, np, feat, net_out, s))) return rc;
-  HIP_TRY(c, launch_mlp_apply(np, net_out, aux, pmap, p->d_drops, gram_out, flags, (float)log_var_max, s));
+  if (all_fall_back) {
+    // the exact Gram overwrites every drop; the status words still get the closed form's bits
+    if (status)
+      HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl,
+                                   nullptr, gram_out, status, p->k_max, s, p->n_pairs,
+                                   (int32_t*)c->scratch_routes.p));
+    HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 1, s));
+  } else {
+    HIP_TRY(c, launch_closedform(to_kernel(a), p->d_drops, p->n_drops, variant, b->user_pos, c->d_gl, c->n_gl, nullptr,
+                                 gram_out, status, p->k_max, s, p->n_pairs, (int32_t*)c->scratch_routes.p));
+    HIP_TRY(c, launch_fill_i32(flags, p->n_drops, 0, s));
+    HIP_TRY(c, launch_pair_inputs(to_kernel(a), p->d_drops, p->n_drops, b->user_pos, gram_out, nullptr, feat, aux,
+                                  nullptr, pmap, s));
+    if ((rc = mlp_infer(c, M, np, feat, net_out, s))) return rc;
+    HIP_TRY(c, launch_mlp_apply(np, net_out, aux, pmap, p->d_drops, gram_out, flags, gate, s));
+  }
   if ((rc = ensure(c, c->partials, sizeof(double) * std::max<int64_t>(p->partial_doubles, 1), s))) return rc;
   const int grid = exact_grid(c, p, XLMIMO_FP32H);
   HIP_TRY(c, launch_gram_exact(XLMIMO_FP32H, p->nb_max, to_kernel(a), p->d_drops, p->n_drops, b->user_pos, p->d_items,
@@ -1113,6 +1148,23 @@ int xlmimo_mlp_get_params(xlmimo_mlp* M, float* host) {
   if (rc) return rc;
   HIP_TRY(c, hipDeviceSynchronize());
   HIP_TRY(c, hipMemcpy(host, M->master, sizeof(float) * M->n_params, hipMemcpyDeviceToHost));
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_set_gate(xlmimo_mlp* M, int32_t n_bins, const int64_t* n_upper, const double* log_var_max) {
+  if (!M) return XLMIMO_EINVAL;
+  xlmimo_ctx* c = M->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (n_bins < 0 || n_bins > kGateBins)
+    return set_err(c, XLMIMO_EINVAL, "gate bins %d outside 0..%d", n_bins, kGateBins);
+  if (n_bins > 0 && (!n_upper || !log_var_max)) return set_err(c, XLMIMO_EINVAL, "gate arrays are NULL");
+  for (int i = 0; i < n_bins; ++i) {
+    if (n_upper[i] < 1 || (i > 0 && n_upper[i] <= n_upper[i - 1]))
+      return set_err(c, XLMIMO_EINVAL, "gate bounds must be >= 1 and strictly ascending");
+    if (std::isnan(log_var_max[i])) return set_err(c, XLMIMO_EINVAL, "gate threshold %d is NaN", i);
+  }
+  M->gate_n.assign(n_upper, n_upper + n_bins);
+  M->gate_thr.assign(log_var_max, log_var_max + n_bins);
   return XLMIMO_OK;
 }
 

@@ -157,8 +157,18 @@ hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, 
 hipError_t launch_to_bf16(int64_t n, const float* w, __bf16* wbf, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit, hipStream_t s);
+// Fallback gate of the learned correction: a drop falls back to the exact Gram
+// when a pair's predicted log-variance exceeds min(cap, thr[b]), b the first bin
+// with N <= n_upper[b] (no bin: cap alone).
+constexpr int kGateBins = 16;
+struct GateK {
+  int32_t n_bins;
+  float cap;
+  int64_t n_upper[kGateBins];
+  float thr[kGateBins];
+};
 hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const int32_t* pmap, const DropK* d_drops,
-                            double* gram, int32_t* flags, float log_var_max, hipStream_t s);
+                            double* gram, int32_t* flags, const GateK& gate, hipStream_t s);
 hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                     const float* master, const int64_t* d_offs, float* out, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;

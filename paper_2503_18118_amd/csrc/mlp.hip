@@ -197,6 +197,13 @@ __device__ __forceinline__ void phasor_turns(double u, float& re, float& im) {
   im = (float)(-sg * ns);
 }
 
+// The residual is predicted on top of the analytic end correction: the
+// coefficients of the basis phasors (top end, bottom end, stationary point) are
+// basis_c0 + the network's outputs, so an all-zero output is the discrete sum's
+// two end terms added to the closed form, and the network only learns how far
+// the best coefficients lie from them.
+__device__ __forceinline__ float basis_c0(int m) { return m < 2 ? 1.0f : 0.0f; }
+
 __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __restrict__ drops,
                                                       const double* __restrict__ pos,
                                                       const double* __restrict__ gram_cf,
@@ -313,8 +320,9 @@ __global__ __launch_bounds__(256) void k_mlp_head(int64_t n, const float* __rest
     float prr = 0.f, pii = 0.f;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      prr += o[2 * m] * a[2 * m] - o[2 * m + 1] * a[2 * m + 1];
-      pii += o[2 * m] * a[2 * m + 1] + o[2 * m + 1] * a[2 * m];
+      const float cr = o[2 * m] + basis_c0(m);
+      prr += cr * a[2 * m] - o[2 * m + 1] * a[2 * m + 1];
+      pii += cr * a[2 * m + 1] + o[2 * m + 1] * a[2 * m];
     }
     const float s = o[6];
     const float er = target[2 * p] - prr, ei = target[2 * p + 1] - pii;
@@ -438,7 +446,7 @@ hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int
 // predicted log-variance exceeds the threshold (they are recomputed exactly).
 __global__ void k_mlp_apply(int64_t n, const float* __restrict__ out, const float* __restrict__ aux,
                             const int32_t* __restrict__ pmap, const DropK* __restrict__ drops,
-                            double* __restrict__ gram, int32_t* __restrict__ flags, float log_var_max) {
+                            double* __restrict__ gram, int32_t* __restrict__ flags, GateK gate) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float* o = out + p * 7;
@@ -446,8 +454,9 @@ __global__ void k_mlp_apply(int64_t n, const float* __restrict__ out, const floa
   double pr = 0.0, pi = 0.0;
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    pr += (double)o[2 * m] * a[2 * m] - (double)o[2 * m + 1] * a[2 * m + 1];
-    pi += (double)o[2 * m] * a[2 * m + 1] + (double)o[2 * m + 1] * a[2 * m];
+    const double cr = (double)o[2 * m] + (double)basis_c0(m);
+    pr += cr * a[2 * m] - (double)o[2 * m + 1] * a[2 * m + 1];
+    pi += cr * a[2 * m + 1] + (double)o[2 * m + 1] * a[2 * m];
   }
   const int d = pmap[2 * p];
   const int i = pmap[2 * p + 1] / XLMIMO_MAX_USERS, j = pmap[2 * p + 1] % XLMIMO_MAX_USERS;
@@ -459,12 +468,19 @@ __global__ void k_mlp_apply(int64_t n, const float* __restrict__ out, const floa
   gij[1] += pi * sc;
   gji[0] += pr * sc;
   gji[1] -= pi * sc;
-  if (!(o[6] <= log_var_max)) atomicOr(&flags[d], 1);
+  float thr = gate.cap;
+  for (int b = 0; b < gate.n_bins; ++b) {
+    if ((int64_t)dp.n_elems <= gate.n_upper[b]) {
+      thr = fminf(thr, gate.thr[b]);
+      break;
+    }
+  }
+  if (!(o[6] <= thr)) atomicOr(&flags[d], 1);
 }
 
 hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const int32_t* pmap, const DropK* d_drops,
-                            double* gram, int32_t* flags, float log_var_max, hipStream_t s) {
-  if (n > 0) k_mlp_apply<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, out, aux, pmap, d_drops, gram, flags, log_var_max);
+                            double* gram, int32_t* flags, const GateK& gate, hipStream_t s) {
+  if (n > 0) k_mlp_apply<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, out, aux, pmap, d_drops, gram, flags, gate);
   return hipGetLastError();
 }
 

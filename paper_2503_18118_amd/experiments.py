@@ -41,6 +41,7 @@ import time
 import numpy as np
 import torch
 
+from . import snr
 from . import xlmimo as X
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -111,7 +112,7 @@ def fig3(ctx, n_drops: int = 200, n_list=FIG3_N, k: int = 100, snr_db=(0.0, 200.
     arr = W.ula(int(n_list[-1]), W.LAMBDA_100GHZ, W.AMP_PNUSW)
     drops = W.rect_drops(W.rng_for(10), n_drops, k, int(n_list[-1]), (1.0, 10.0), (-7.5, 7.5))
     b = X.Batch(drops)
-    rho = X.rho_for_snr(arr, snr_db, 5.5, b.total_users)       # reference user at the mean x
+    rho = snr.rho_for_snr(arr, snr_db, 5.5, b.total_users)       # reference user at the mean x
     erg, sat, st, ms = _timed_sweep(ctx, arr, n_list, b, X.FORM_EXACT_FP64, rho, X.CAP, t, eps)
     cap = erg[:, :, 0]
     return {"scene": "Sec. IV: 100 GHz PNUSW ULA, x ~ U[1,10] m, y ~ U[-7.5,7.5] m, t = 0.9",
@@ -135,7 +136,7 @@ def fig4(ctx, n_drops: int = 200, n_list=FIG_N, rx_snr_db: float = 33.0, forms=(
     arr = W.ula(int(n_list[-1]), W.LAMBDA_100GHZ, W.AMP_PNUSW)
     drops = W.rect_drops(W.rng_for(11), n_drops, 10, int(n_list[-1]), (1.0, 2.0), (-7.5, 7.5))
     b = X.Batch(drops)
-    rho = X.rho_for_snr(arr, [rx_snr_db], 1.5, b.total_users)  # SNR limit of one user at (1.5 m, 0)
+    rho = snr.rho_for_snr(arr, [rx_snr_db], 1.5, b.total_users)  # SNR limit of one user at (1.5 m, 0)
     exact_schemes = (("ZF", X.ZF), ("MMSE", X.MMSE), ("MRC", X.MRC), ("CAP", X.CAP))
     cf_schemes = (("MZF", X.MZF), ("MZF_MISM", X.MZF_MISM))
     erg, sat, st, ms = _timed_sweep(ctx, arr, n_list, b, X.FORM_EXACT_FP64, rho,

@@ -19,9 +19,9 @@ from . import xlmimo as X
 
 
 def init_params(width: int, depth: int, rng: np.random.Generator, log_var0: float) -> np.ndarray:
-    """He-normal weights, zero biases; the output layer is scaled by 1e-2, its end-term
-    coefficients start at 1 (the analytic end correction) and its log-variance bias at
-    log_var0."""
+    """He-normal weights, zero biases; the output layer is scaled by 1e-2 and its
+    log-variance bias starts at log_var0.  Zero coefficient outputs are the analytic end
+    correction (the kernels add its coefficients to the network's)."""
     dims = [X.MLP_IN] + [width] * depth + [X.MLP_OUT]
     parts = []
     for li in range(len(dims) - 1):
@@ -30,8 +30,6 @@ def init_params(width: int, depth: int, rng: np.random.Generator, log_var0: floa
         b = np.zeros(fan_out)
         if li == len(dims) - 2:
             w *= 1e-2
-            b[0] = 1.0   # c_top = 1
-            b[2] = 1.0   # c_bot = 1
             b[6] = log_var0
         parts += [w.ravel(), b]
     return np.concatenate(parts).astype(np.float32)
@@ -61,3 +59,55 @@ def train(mlp: X.MLP, data: X.PairInputs, steps: int, batch: int = 8192, lr_max:
             history.append((s + 1, float(loss.item())))
     torch.cuda.synchronize()
     return history, time.perf_counter() - t0
+
+
+def constant_network(ctx: X.Context, width: int, depth: int, coeffs, log_var: float = -100.0) -> X.MLP:
+    """A network whose output is the constant (coeffs, log_var) (zero weights, output bias
+    only): coefficient outputs (0, 0, 0, 0, 0, 0) give the analytic end correction,
+    (-1, 0, -1, 0, 0, 0) the base closed form alone."""
+    m = X.MLP(ctx, width, depth)
+    p = np.zeros(m.n_params, np.float32)
+    p[-X.MLP_OUT:] = list(coeffs) + [log_var]
+    m.set_params(p)
+    return m
+
+
+def drop_log_var(mlp: X.MLP, pi: X.PairInputs, n_drops: int) -> torch.Tensor:
+    """Largest predicted log-variance over each drop's pairs (the quantity the fallback gate tests)."""
+    out = mlp.forward(pi)
+    lv = torch.full((n_drops,), -float("inf"), dtype=torch.float32, device=out.device)
+    return lv.scatter_reduce(0, pi.pmap[:, 0].long(), out[:, 6], reduce="amax")
+
+
+def calibrate_gate(ctx: X.Context, mlp: X.MLP, arr, drops, n_list, rho: torch.Tensor, target: float = 2.5e-4,
+                   schemes: int = X.ZF | X.MMSE):
+    """Fallback thresholds per antenna count, judged by the exact FP64 Gram on held-out drops.
+
+    For each N the drops are ordered by their largest predicted log-variance; the threshold
+    is the largest one whose kept drops all have a sum-rate error (relative, worst over the
+    SNRs and schemes) of at most ``target`` with the network applied, or -inf when even
+    the most certain drop misses it.  Returns (thresholds, per-N statistics)."""
+    b = X.Batch(drops)
+    thr, stats = [], []
+    for n in n_list:
+        a = arr.with_n(n)
+        bn = X.Batch(drops.with_n(n), pos=b.pos)
+        g64 = ctx.gram_exact(a, bn, X.FP64)
+        gcf, _ = ctx.gram_closedform(a, bn, X.CF_GATED_QUAD)
+        lv = drop_log_var(mlp, mlp.pair_inputs(a, bn, gcf), bn.n_drops)
+        gml, _ = ctx.gram_closedform_mlp(a, bn, mlp, X.CF_GATED_QUAD, log_var_max=float("inf"))
+        r64, _ = ctx.sumrate(bn, g64, rho, schemes)
+        rml, _ = ctx.sumrate(bn, gml, rho, schemes)
+        err = torch.nan_to_num(torch.abs(rml / r64 - 1), nan=float("inf")).amax(dim=(1, 2))
+        lv_s, order = torch.sort(lv.double())
+        ok = torch.cummax(err[order], dim=0).values <= target
+        k = int(ok.long().cumprod(0).sum())          # longest prefix within the target
+        while 0 < k < len(lv_s) and lv_s[k] == lv_s[k - 1]:
+            k -= 1                                   # a threshold cannot split equal log-variances
+        t = float(lv_s[k - 1]) if k > 0 else -float("inf")
+        thr.append(t)
+        stats.append({"n": int(n), "log_var_max": t, "kept_fraction": k / len(lv_s),
+                      "kept_err_max": float(err[order[:k]].max()) if k > 0 else 0.0,
+                      "err_max_all": float(err.max())})
+    mlp.set_gate(list(n_list), thr)
+    return thr, stats

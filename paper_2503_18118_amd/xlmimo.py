@@ -37,7 +37,7 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
             "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
             "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users", "xlmimo_cholesky",
-            "xlmimo_cholesky_update_users", "xlmimo_gram_exact_noalloc")
+            "xlmimo_cholesky_update_users", "xlmimo_gram_exact_noalloc", "xlmimo_mlp_set_gate")
 
 
 class XlArray(C.Structure):
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_mlp_param_count.restype = i64
     lib.xlmimo_mlp_set_params.argtypes = [vp, vp]
     lib.xlmimo_mlp_get_params.argtypes = [vp, vp]
+    lib.xlmimo_mlp_set_gate.argtypes = [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.xlmimo_pair_count.argtypes = [C.POINTER(XlBatch)]
     lib.xlmimo_pair_count.restype = i64
     lib.xlmimo_mlp_pair_inputs.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), vp, vp, vp, vp, vp, vp, vp]
@@ -403,6 +404,14 @@ class MLP:
         self.ctx._check(_lib.xlmimo_mlp_get_params(self.h, p.ctypes.data_as(C.c_void_p)), "xlmimo_mlp_get_params")
         return p
 
+    def set_gate(self, n_upper: Sequence[int], log_var_max: Sequence[float]):
+        """Fallback thresholds by antenna count (xlmimo_mlp_set_gate); empty lists clear the table."""
+        nu = np.ascontiguousarray(n_upper, np.int64)
+        th = np.ascontiguousarray(log_var_max, np.float64)
+        assert nu.size == th.size
+        self.ctx._check(_lib.xlmimo_mlp_set_gate(self.h, int(nu.size), nu.ctypes.data_as(C.POINTER(C.c_int64)),
+                                                 th.ctypes.data_as(C.POINTER(C.c_double))), "xlmimo_mlp_set_gate")
+
     def pair_inputs(self, arr, batch: Batch, gram_cf: torch.Tensor, gram_exact: Optional[torch.Tensor] = None,
                     stream=None) -> PairInputs:
         n = int(_lib.xlmimo_pair_count(C.byref(batch.struct)))
@@ -442,32 +451,3 @@ class MLP:
 
 def version() -> str:
     return _lib.xlmimo_version().decode()
-
-
-# -- harness helper: SNR calibration -----------------------------------------
-
-def reference_gain(arr, ref_distance: float) -> float:
-    """Array gain of a broadside reference user at ``ref_distance``.
-
-    ULA: the N -> infinity limit of the diagonal (free space: lambda / (8 pi x)
-    at half-wavelength spacing, i.e. (lambda/4pi)^2 pi / (d x); PNUSW: eq. (5),
-    2 beta0 / (d x)).  UPA (no finite limit): the panel's own diagonal, taken
-    as the far-field value N (lambda / (4 pi x))^2 (free space) or N beta0 / x^2.
-    """
-    lam, d, x = arr.wavelength, arr.spacing, float(ref_distance)
-    if arr.geometry == ULA:
-        if arr.amp_model == AMP_FREESPACE:
-            return (lam / (4 * np.pi)) ** 2 * np.pi / (d * x)
-        return 2.0 * arr.beta0 / (d * x)
-    n = arr.n_y * arr.n_z
-    if arr.amp_model == AMP_FREESPACE:
-        return n * (lam / (4 * np.pi * x)) ** 2
-    return n * arr.beta0 / (x * x)
-
-
-def rho_for_snr(arr, snr_db: Sequence[float], ref_distance: float, total_users: int, device=0) -> torch.Tensor:
-    """Per-user P/sigma^2 so that the reference user's gain gives the stated SNR (common power)."""
-    g = reference_gain(arr, ref_distance)
-    vals = [10.0 ** (s / 10.0) / g for s in snr_db]
-    return torch.tensor(vals, dtype=torch.float64, device=f"cuda:{device}")[:, None].expand(
-        len(vals), max(total_users, 1)).contiguous()

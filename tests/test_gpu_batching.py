@@ -34,7 +34,8 @@ def _sweep_setup(X):
     arr = W.ula(4096, W.LAMBDA_28GHZ)
     drops = W.polar_drops(W.rng_for(7), 48, 8, 4096, (5.0, 50.0), (-60.0, 60.0))
     b = X.Batch(drops)
-    rho = X.rho_for_snr(arr, (0.0, 20.0), 27.5, b.total_users)
+    from paper_2503_18118_amd import snr
+    rho = snr.rho_for_snr(arr, (0.0, 20.0), 27.5, b.total_users)
     return arr, drops, b, rho
 
 

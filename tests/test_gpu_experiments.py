@@ -77,7 +77,8 @@ def test_fig4_sweep_matches_oracle(X, E, ctx):
     r = E.fig4(ctx, n_drops=10, n_list=n_list, forms=("PAPER", "UNIFORM"))
     arr = W.ula(n_list[-1], W.LAMBDA_100GHZ, W.AMP_PNUSW)
     drops = W.rect_drops(W.rng_for(11), 10, 10, n_list[-1], (1.0, 2.0), (-7.5, 7.5))
-    rho = X.rho_for_snr(arr, [33.0], 1.5, drops.n_users.sum()).cpu().numpy()
+    from paper_2503_18118_amd import snr
+    rho = snr.rho_for_snr(arr, [33.0], 1.5, drops.n_users.sum()).cpu().numpy()
     exact = orates.SCHEME_ZF | orates.SCHEME_MMSE | orates.SCHEME_MRC | orates.SCHEME_CAP
     ref, keys = _oracle_ergodic(arr, drops, n_list, rho, exact)
     for c, name in enumerate(("ZF", "MMSE", "MRC", "CAP")):
@@ -95,7 +96,8 @@ def test_fig3_sweep_matches_oracle(X, E, ctx):
     r = E.fig3(ctx, n_drops=4, n_list=n_list, k=100)
     arr = W.ula(n_list[-1], W.LAMBDA_100GHZ, W.AMP_PNUSW)
     drops = W.rect_drops(W.rng_for(10), 4, 100, n_list[-1], (1.0, 10.0), (-7.5, 7.5))
-    rho = X.rho_for_snr(arr, [0.0, 200.0], 5.5, drops.n_users.sum()).cpu().numpy()
+    from paper_2503_18118_amd import snr
+    rho = snr.rho_for_snr(arr, [0.0, 200.0], 5.5, drops.n_users.sum()).cpu().numpy()
     ref, _ = _oracle_ergodic(arr, drops, n_list, rho, orates.SCHEME_CAP)
     assert np.allclose(np.array(r["capacity"]), ref[:, :, 0], rtol=1e-9)
 

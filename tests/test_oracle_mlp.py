@@ -133,9 +133,11 @@ def test_loss_is_minimised_by_the_target():
     rng = np.random.default_rng(3)
     x, ph, t = _batch(rng, 50)
     out = np.zeros((50, 7))
-    # choose c_top so that p = t exactly, and s = log mean |e|^2 -> e = 0 gives loss = s
-    out[:, 0] = (t * ph[:, 0].conj()).real
+    # choose c_top so that p = t exactly (c_bot = 0: its output cancels the analytic C0 = 1);
+    # s = 0 and e = 0 give loss = 0
+    out[:, 0] = (t * ph[:, 0].conj()).real - 1.0
     out[:, 1] = (t * ph[:, 0].conj()).imag
+    out[:, 2] = -1.0
     p, s = M.predict(out, ph)
     assert np.allclose(p, t)
     loss, dout = M.loss_and_dout(out, ph, t)

@@ -217,6 +217,15 @@ def paper_sec5(n_drops: int = 100, n: int = 16384):
     return arr, drops, dict(t=0.9, rx_snr_limit_db=33.0, ref_point=(1.5, 0.0))
 
 
+def learned_calibration(n_drops: int = 4000, n_list=SWEEP_N):
+    """Held-out drops of the sweep's law (K=16, the same positions at every N) on which the
+    learned correction's fallback thresholds are calibrated; disjoint from the training
+    drops and from the sweep workload's drops."""
+    arr = ula(n_list[-1], LAMBDA_28GHZ)
+    drops = polar_drops(rng_for(4, 7), n_drops, 16, n_list[-1], (5.0, 50.0), (-60.0, 60.0))
+    return arr, drops, dict(snr_db=(0.0, 10.0, 20.0), ref_distance=27.5, n_list=tuple(n_list))
+
+
 def learned_drops(n_drops: int, stream: int = 0, k: int = 16, n_list=SWEEP_N):
     """Drops of K users over the sweep's user law, N drawn per drop from the sweep's N set
     (training and evaluation pairs of the learned correction: K(K-1)/2 pairs per drop)."""
