@@ -394,12 +394,13 @@ def sweep_leg(args, ctx, X, Lr, W, snr, stream):
 
     # the rate kernel alone on one resident Gram (10^4 drops, N = 4096): ZF + MMSE at every SNR
     log("sum-rate kernel throughput")
-    g_rates = ctx.gram_exact(arr.with_n(4096), batch, X.FP32H, stream=stream)
+    b4096 = X.Batch(drops.with_n(4096), pos=batch.pos)
+    g_rates = ctx.gram_exact(arr.with_n(4096), b4096, X.FP32H, stream=stream)
     times = []
     for r in range(23):
         a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a0.record(stream)
-        ctx.sumrate(batch, g_rates, rho, schemes, stream=stream)
+        ctx.sumrate(b4096, g_rates, rho, schemes, stream=stream)
         a1.record(stream)
         a1.synchronize()
         if r >= 3:

@@ -374,19 +374,99 @@ __device__ __forceinline__ void split_pair(const float* a, const float* c, const
   }
 }
 
+// Expansion of the channel along a lane's 8 consecutive elements (FP32H).
+// The distance is exact in FP64 at the centre of the run (element m = 3.5, offset
+// t = 0), its phase reduced there: c0 = fract(r_c).  Along the run the element
+// offset is t = m' d, m' = m - 3.5, d the spacing in wavelengths, and with
+// dy_c the centre's offset along the line, mu = dy_c / r_c:
+//   r(t) - r_c = r_c sum_k C_k^(-1/2)(mu) (t / r_c)^k       (Gegenbauer generating function of
+//   r(t)^-p    = r_c^-p sum_k C_k^(p/2)(mu) (t / r_c)^k      r_c^2 - 2 dy_c t + t^2)
+// evaluated in FP32 by Horner's rule in m' (the coefficients carry d^k), to t^4 for the
+// phase and t^3 for the amplitude.  With the half-run |t| <= 3.5 d and every user at a
+// distance x >= kExpandXmin d from the array line (plane), the truncated terms stay below
+// 1e-8 turns and 2e-8 relative; the FP32 evaluation leaves |phase error| <= 3e-7 turns
+// at d = 1/2 (the phase is carried to |theta| < 3, so its rounding dominates) and
+// 1.2e-7 relative in the amplitude.  Items whose users come closer take the
+// per-element FP64 path.
+constexpr double kExpandXmin = 368.0;
+
+template <int AMP>
+struct Expansion {
+  float th[5];   // phase in turns: c0, then the coefficients of m', m'^2, m'^3, m'^4
+  float am[4];   // amplitude (times the user scale): coefficients of 1, m', m'^2, m'^3
+};
+
+template <int AMP>
+__device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double ds, float us) {
+  Expansion<AMP> x;
+  const double r2 = fma(dyc, dyc, xp2);
+  const float yf = __builtin_amdgcn_rsqf((float)r2);
+  const double y0 = (double)yf;
+  const double r0 = r2 * y0;
+  const double rc = fma(0.5 * y0, fma(-r0, r0, r2), r0);      // r_c to ~1e-14 relative
+  const double y1 = fma(y0, fma(-rc, y0, 1.0), y0);           // 1 / r_c to ~1e-14 relative
+  const double mu64 = dyc * y1;
+  x.th[0] = (float)__builtin_amdgcn_fract(rc);
+  x.th[1] = (float)(-mu64 * ds);
+  const float mu = (float)mu64;
+  const float dsf = (float)ds;
+  const float q = yf * dsf;                                   // d / r_c
+  const float w = __builtin_fmaf(-mu, mu, 1.0f);              // 1 - mu^2
+  const float q2 = q * q;
+  x.th[2] = (w * q) * (0.5f * dsf);                           // (1 - mu^2) d^2 / (2 r_c)
+  x.th[3] = (mu * x.th[2]) * q;                               // mu (1 - mu^2) d^3 / (2 r_c^2)
+  x.th[4] = (x.th[2] * q2) * __builtin_fmaf(1.25f, mu * mu, -0.25f);   // (1 - mu^2)(5 mu^2 - 1) d^4 / (8 r_c^3)
+  float b0 = yf;
+  if constexpr (AMP == XLMIMO_AMP_PNUSW) b0 = b0 * __builtin_amdgcn_sqrtf(b0);
+  b0 = b0 * us;
+  const float mu2 = mu * mu;
+  x.am[0] = b0;
+  if constexpr (AMP == XLMIMO_AMP_FREESPACE) {          // Legendre polynomials P_k(mu)
+    x.am[1] = (b0 * mu) * q;
+    x.am[2] = (b0 * q2) * __builtin_fmaf(1.5f, mu2, -0.5f);
+    x.am[3] = (b0 * q2) * ((q * mu) * __builtin_fmaf(2.5f, mu2, -1.5f));
+  } else {                                              // C_k^(3/4)(mu)
+    x.am[1] = (b0 * mu) * (1.5f * q);
+    x.am[2] = (b0 * q2) * __builtin_fmaf(2.625f, mu2, -0.75f);
+    x.am[3] = (b0 * q2) * ((q * mu) * __builtin_fmaf(4.8125f, mu2, -2.625f));
+  }
+  return x;
+}
+
+// The two elements at m' = -p and +p from the even and odd parts of both series:
+// theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (9 FMAs per pair).
+template <int AMP>
+__device__ __forceinline__ void expansion_pair(const Expansion<AMP>& x, float p, float (&a)[2], float (&c)[2],
+                                               float (&sn)[2]) {
+  const float p2 = p * p;
+  const float ev = __builtin_fmaf(__builtin_fmaf(x.th[4], p2, x.th[2]), p2, x.th[0]);
+  const float od = __builtin_fmaf(x.th[3], p2, x.th[1]);
+  const float ae = __builtin_fmaf(x.am[2], p2, x.am[0]);
+  const float ao = __builtin_fmaf(x.am[3], p2, x.am[1]);
+  const float th0 = __builtin_fmaf(-p, od, ev), th1 = __builtin_fmaf(p, od, ev);
+  a[0] = __builtin_fmaf(-p, ao, ae);
+  a[1] = __builtin_fmaf(p, ao, ae);
+  c[0] = __builtin_amdgcn_cosf(th0);
+  sn[0] = __builtin_amdgcn_sinf(th0);
+  c[1] = __builtin_amdgcn_cosf(th1);
+  sn[1] = __builtin_amdgcn_sinf(th1);
+}
+
+template <int NB, int GEOM, int AMP, bool EXPAND>
+__device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, const UserLane (&u)[NB],
+                           const float (&us)[NB], double* __restrict__ part_out, double* s_red);
+
 template <int NB, int GEOM, int AMP>
 __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const ItemK& it,
                                    const double* __restrict__ pos, double* __restrict__ part_out, double* s_red) {
-  constexpr int NRE = NB * (NB + 1) / 2;
-  constexpr int NX = NB * NB;
-  constexpr int NV = (NRE + NX) * 4;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const double sc = arr.inv_lambda;  // wavelengths: r counts turns
   constexpr double kFar = 1e30;
-
   UserLane u[NB];
   float us[NB];
+  const double ds = arr.spacing * sc;
+  const double xmin = kExpandXmin * ds;
+  bool near = false;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int k = 16 * b + (lane & 15);
@@ -401,7 +481,24 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
     u[b].uy = y;
     u[b].uz = z;
     us[b] = k < dp.k ? __builtin_ldexpf(1.0f, split_exp(u[b].xp2, AMP)) : 1.0f;
+    near |= !(u[b].xp2 >= xmin * xmin);
   }
+  // every wave of the workgroup holds the same users, so they all take the same path
+  const bool expand = (GEOM == XLMIMO_ULA || arr.n_z % 8 == 0) && !__any(near);
+  if (expand) split_body<NB, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red);
+  else split_body<NB, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red);
+}
+
+template <int NB, int GEOM, int AMP, bool EXPAND>
+__device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, const UserLane (&u)[NB],
+                           const float (&us)[NB], double* __restrict__ part_out, double* s_red) {
+  constexpr int NRE = NB * (NB + 1) / 2;
+  constexpr int NX = NB * NB;
+  constexpr int NV = (NRE + NX) * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const double sc = arr.inv_lambda;  // wavelengths: r counts turns
+  constexpr double kFar = 1e30;
 
   floatx4 are[NRE], ax[NX];
 #pragma unroll
@@ -426,7 +523,39 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
   auto round = [&](int e, auto tail_tag) {
     constexpr bool TAIL = decltype(tail_tag)::value;
     halfx8 rh[NB], rl[NB], ih[NB], il[NB];
-    if constexpr (GEOM == XLMIMO_ULA) {
+    if constexpr (EXPAND) {
+      // the run's centre, element e + 3.5, and the expansion of each user about it
+      double ey = 0.0, ez = 0.0;
+      if constexpr (GEOM == XLMIMO_ULA) {
+        ey = fma((double)e + 3.5, ds, -cy);
+      } else {
+        const int ea = e / arr.n_z;
+        ey = fma((double)ea, ds, -cy);
+        ez = fma((double)(e - ea * arr.n_z) + 3.5, ds, -cz);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        Expansion<AMP> x;
+        if constexpr (GEOM == XLMIMO_ULA) {
+          x = expand<AMP>(u[b].uy - ey, u[b].xp2, ds, us[b]);
+        } else {
+          const double dy = u[b].uy - ey;
+          x = expand<AMP>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
+        }
+        // operand slots 2j, 2j + 1 hold elements 3 - j and 4 + j (the sums over the 32
+        // elements of a round are order-free, and every user uses the same order)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float a[2], c[2], sn[2];
+          expansion_pair<AMP>(x, 0.5f + (float)j, a, c, sn);
+          if constexpr (TAIL) {
+            a[0] = e + 3 - j < it.e_end ? a[0] : 0.0f;
+            a[1] = e + 4 + j < it.e_end ? a[1] : 0.0f;
+          }
+          split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], 2 * j);
+        }
+      }
+    } else if constexpr (GEOM == XLMIMO_ULA) {
       const double ey = fma((double)e, ds, -cy);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {

@@ -1,0 +1,99 @@
+"""The FP32H exact Gram's two channel paths against the FP64 oracle.
+
+Items whose users are all at least 368 element spacings from the array line
+(plane) evaluate each lane's run of 8 consecutive elements from an FP64 distance
+and phase at the run's centre plus FP32 expansions of the phase and amplitude
+along the run; other items evaluate every element in FP64.  Each case below is
+built so that one path or the other must run (users all far, or one user near),
+for the ULA and the UPA, both amplitude models and three spacings, and each is
+held to the exact form's tolerance (1e-5 normwise) against the oracle, with
+ragged element counts so that the last run of an item is partial."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import channel as och
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+XMIN = 368.0   # element spacings
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2503_18118_amd import xlmimo
+    return xlmimo
+
+
+@pytest.fixture(scope="module")
+def ctx(X):
+    c = X.Context(0)
+    yield c
+    c.close()
+
+
+def _users(rng, k, x_lo, x_hi, y_span, z_span=0.0):
+    x = rng.uniform(x_lo, x_hi, k)
+    y = rng.uniform(-y_span, y_span, k)
+    z = rng.uniform(-z_span, z_span, k) if z_span else np.zeros(k)
+    return np.stack([x, y, z], axis=-1)
+
+
+def _check(X, ctx, arr, drops, what):
+    b = X.Batch(drops)
+    print(f"{what}: {drops.n_drops} drops, N up to {int(drops.n_elems.max())}", flush=True)
+    g = b.split(ctx.gram_exact(arr, b, X.FP32H))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for d in range(drops.n_drops):
+        a = arr.with_n(int(drops.n_elems[d])) if arr.geometry == W.GEOM_ULA else arr
+        ref = och.gram_exact(a, drops.users_of(d))
+        err = och.normwise_error(g[d], ref)
+        worst = max(worst, err)
+        assert err < TOL, (what, d, err)
+        assert np.array_equal(g[d], g[d].conj().T)
+    return worst
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+@pytest.mark.parametrize("spacing_lam", [0.5, 1.0, 0.25])
+def test_ula_far_and_near_users(X, ctx, amp, spacing_lam):
+    lam = W.LAMBDA_28GHZ
+    d = spacing_lam * lam
+    x_far = XMIN * d * 1.001
+    rng = np.random.default_rng(int(spacing_lam * 100) + amp)
+    ns = [1000, 4099, 70001, 129, 16384]
+    ks = [16, 9, 16, 32, 5]
+    far = [_users(rng, k, x_far, x_far + 40.0, 30.0) for k in ks]          # expansion path
+    near = [u.copy() for u in far]
+    for u in near:
+        u[-1, 0] = x_far * 0.5                                               # one user near: FP64 path
+    arr = W.ula(1, lam, amp, spacing=d)
+    w_far = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(far)), "far users")
+    w_near = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(near)), "one near user")
+    print(f"worst normwise error: far {w_far:.2e}, near {w_near:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("ny,nz", [(40, 64), (33, 24), (16, 21)])
+def test_upa_runs_along_columns(X, ctx, ny, nz):
+    # n_z a multiple of 8: every run of 8 elements stays in one column (expansion path);
+    # otherwise the FP64 path
+    lam = W.LAMBDA_100GHZ_UPA
+    d = lam / 2
+    rng = np.random.default_rng(ny * 100 + nz)
+    k = 12
+    users = [_users(rng, k, XMIN * d * 1.01, 20.0, 5.0, 5.0) for _ in range(3)]
+    arr = W.ArraySpec(W.GEOM_UPA, ny, nz, d, lam, W.AMP_FREESPACE)
+    drops = W._pack([ny * nz] * 3, [k] * 3, np.concatenate(users))
+    _check(X, ctx, arr, drops, f"UPA {ny}x{nz}")
+
+
+def test_sweep_drops_at_the_largest_aperture(X, ctx):
+    # the sweep's user law (x >= 2.5 m, far above 368 d = 1.97 m) at N = 262144
+    arr, drops, _ = W.sweep(n_drops=6, n_list=(262144,))
+    w = _check(X, ctx, arr, drops, "sweep drops, N = 262144")
+    print(f"worst normwise error {w:.2e}", flush=True)
