@@ -80,13 +80,16 @@ def drop_log_var(mlp: X.MLP, pi: X.PairInputs, n_drops: int) -> torch.Tensor:
 
 
 def calibrate_gate(ctx: X.Context, mlp: X.MLP, arr, drops, n_list, rho: torch.Tensor, target: float = 2.5e-4,
-                   schemes: int = X.ZF | X.MMSE):
+                   schemes: int = X.ZF | X.MMSE, min_keep: float = 0.25):
     """Fallback thresholds per antenna count, judged by the exact FP64 Gram on held-out drops.
 
     For each N the drops are ordered by their largest predicted log-variance; the threshold
     is the largest one whose kept drops all have a sum-rate error (relative, worst over the
     SNRs and schemes) of at most ``target`` with the network applied, or -inf when even
-    the most certain drop misses it.  Returns (thresholds, per-N statistics)."""
+    the most certain drop misses it.  A threshold that keeps fewer than ``min_keep`` of the
+    drops is set to -inf as well: the closed form and the network would then cost more than
+    the exact kernel they spare (a batch whose every drop falls back skips them).
+    Returns (thresholds, per-N statistics)."""
     b = X.Batch(drops)
     thr, stats = [], []
     for n in n_list:
@@ -104,9 +107,13 @@ def calibrate_gate(ctx: X.Context, mlp: X.MLP, arr, drops, n_list, rho: torch.Te
         k = int(ok.long().cumprod(0).sum())          # longest prefix within the target
         while 0 < k < len(lv_s) and lv_s[k] == lv_s[k - 1]:
             k -= 1                                   # a threshold cannot split equal log-variances
+        within = k / len(lv_s)
+        if within < min_keep:
+            k = 0
         t = float(lv_s[k - 1]) if k > 0 else -float("inf")
         thr.append(t)
         stats.append({"n": int(n), "log_var_max": t, "kept_fraction": k / len(lv_s),
+                      "within_target_fraction": within,
                       "kept_err_max": float(err[order[:k]].max()) if k > 0 else 0.0,
                       "err_max_all": float(err.max())})
     mlp.set_gate(list(n_list), thr)

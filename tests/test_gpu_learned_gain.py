@@ -10,10 +10,14 @@ Gram, in three forms that differ only in the basis coefficients:
   (iii) GATED_QUAD + the trained network.
 Per drop: the Gram's normwise error (worst pair) and the sum-rate error
 (relative, worst over ZF/MMSE at 0, 10, 20 dB).  Gains asserted:
-  * (iii) below (i) in median Gram error at every N;
-  * (iii) below (ii) in median Gram error and median sum-rate error for
-    N >= 1024 (at N = 256 the end terms alone are the more accurate in the
-    median, and the network is not claimed to help there).
+  * (iii) below (i) in median Gram error and median sum-rate error at every N;
+  * (iii) below (ii) in median Gram error for N >= 1024, by at least 1.5x;
+  * (iii) below (ii) in median sum-rate error at N = 1024 and 4096.
+At N = 256 the end terms alone are the more accurate in the median, and the
+network is not claimed to help there.  From N = 16384 on, both corrected forms
+stay within ~3e-6 median sum-rate error and the network's edge there is within
+what retraining on slightly different targets moves (measured either side of
+the end terms), so only its Gram error is claimed.
 Then the fallback gate is calibrated on a second held-out set and a third one
 checks that the drops the network keeps meet the 1e-3 sum-rate target."""
 import math
@@ -81,8 +85,10 @@ def test_network_gains_over_its_base_and_the_end_terms(env):
               f"ends {med['ends'][0]:.2e} / {med['ends'][1]:.2e}  net {med['net'][0]:.2e} / {med['net'][1]:.2e}",
               flush=True)
         assert med["net"][0] < med["base"][0], n
+        assert med["net"][1] < med["base"][1], n
         if n >= 1024:
-            assert med["net"][0] < med["ends"][0], n
+            assert med["net"][0] * 1.5 < med["ends"][0], n
+        if n in (1024, 4096):
             assert med["net"][1] < med["ends"][1], n
 
 
