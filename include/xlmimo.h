@@ -398,6 +398,14 @@ int xlmimo_mlp_loss_grad(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void
 /* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the loss above. */
 int xlmimo_mlp_train_step(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
                           const float* target, float lr, double* loss_out, void* stream);
+/* n_steps Adam steps as xlmimo_mlp_train_step, enqueued in one call: step i
+ * trains on the pairs [(i mod (n / batch)) batch, + batch) of the pair arrays,
+ * with learning rate lr[i].
+ *   lr        HOST float [n_steps], finite, >= 0
+ *   loss_out  DEVICE double [n_steps] (each step's loss) or NULL */
+int xlmimo_mlp_train(xlmimo_ctx* ctx, xlmimo_mlp* mlp, int64_t n, const void* features, const float* aux,
+                     const float* target, int64_t batch, int64_t n_steps, const float* lr, double* loss_out,
+                     void* stream);
 /* Network outputs, DEVICE float [n][XLMIMO_MLP_OUT].  Widths 64, 128 and 256 run
  * one fused kernel (128 pairs per workgroup at width 256, 64 otherwise;
  * activations kept in LDS). */
@@ -425,7 +433,7 @@ int xlmimo_gram_closedform_mlp(xlmimo_ctx* ctx, const xlmimo_array* arr, const x
  *     them, so that their launch plans exist and the workspace is large enough.
  *     A call that would need a new plan, a larger workspace or a new N list,
  *     and the synchronising calls (xlmimo_mlp_create, xlmimo_mlp_set_params,
- *     xlmimo_mlp_get_params, xlmimo_mlp_train_step, xlmimo_timing_read,
+ *     xlmimo_mlp_get_params, xlmimo_mlp_train_step, xlmimo_mlp_train, xlmimo_timing_read,
  *     xlmimo_autotune_exact), fail with XLMIMO_EINVAL; xlmimo_graph_end then
  *     fails as well and no graph is made.
  *   - A graph reads and writes the same device buffers at every launch (the

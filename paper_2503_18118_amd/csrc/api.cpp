@@ -795,7 +795,7 @@ struct xlmimo_mlp {
   __bf16* wbf = nullptr;
   int64_t* d_offs = nullptr;  // per layer: weight offset, bias offset (fused inference)
   int64_t t = 0;
-  DevBuf act, partial, split;
+  DevBuf act, partial, split, loss_scratch;
   // fallback gate by antenna count (xlmimo_mlp_set_gate)
   std::vector<int64_t> gate_n;
   std::vector<double> gate_thr;
@@ -822,7 +822,7 @@ int mlp_acts(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, bool train, Acts& a, hipSt
   size_t bytes = 0;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t xb = al(sizeof(__bf16) * n * H), zb = al(sizeof(float) * n * H);
-  const size_t ob = al(sizeof(float) * n * kOut), dob = al(sizeof(__bf16) * n * kOut);
+  const size_t ob = al(sizeof(float) * n * kOut), dob = al(sizeof(__bf16) * n * kDoutPitch);
   bytes = (train ? (L - 1) * (xb + zb) + 2 * xb + dob : 2 * xb) + ob;
   int rc = ensure(c, M->act, bytes, s);
   if (rc) return rc;
@@ -875,6 +875,7 @@ int mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, con
 
 // Split of the batch dimension for the weight-gradient GEMMs (dZ^T X reduces over pairs).
 constexpr int kGradSplits = 32;
+constexpr int64_t kGradSplitK = 512;   // pairs per split of the weight-gradient GEMMs
 
 // Inference outputs [n][XLMIMO_MLP_OUT] into `out`: fused single-kernel path for
 // widths 64/128/256, layer-by-layer GEMMs otherwise.
@@ -896,11 +897,12 @@ int mlp_infer(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, float
 }
 
 int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, hipStream_t s) {
-  int rc = ensure(c, M->split, sizeof(float) * (size_t)kGradSplits * M->width * std::max(M->width, XLMIMO_MLP_IN), s);
+  int rc = ensure(c, M->split,
+                  sizeof(float) * (size_t)kGradSplits * M->width * (std::max(M->width, XLMIMO_MLP_IN) + 1), s);
   if (rc) return rc;
   float* part = (float*)M->split.p;
   const __bf16* dz = a.dout;
-  int64_t ldz = kOut;
+  int64_t ldz = kDoutPitch;
   __bf16* bufs[2] = {a.da, a.db};
   int flip = 0;
   for (int l = M->n_layers - 1; l >= 0; --l) {
@@ -918,9 +920,9 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
     gw.b_k = ldx;
     gw.b_n = 1;
     gw.ldo = in;
-    HIP_TRY(c, launch_gemm_splitk(gw, kGradSplits, part, M->grad + M->w_off[l], s));
-    const int max_splits = (int)std::min<int64_t>(4096, (int64_t)kGradSplits * M->width * std::max(M->width, XLMIMO_MLP_IN) / o);
-    HIP_TRY(c, launch_colsum(dz, n, o, M->grad + M->b_off[l], part, max_splits, s));
+    gw.row_sums = 1;   // the bias gradient sum_pairs dZ follows W's gradient (b_off = w_off + o in)
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(kGradSplits, n / kGradSplitK));
+    HIP_TRY(c, launch_gemm_splitk(gw, splits, part, M->grad + M->w_off[l], s));
     if (l > 0) {
       GemmArgs gx{};
       gx.M = (int)n;
@@ -1114,6 +1116,7 @@ int xlmimo_mlp_destroy(xlmimo_mlp* M) {
   if (M->act.p) (void)hipFree(M->act.p);
   if (M->partial.p) (void)hipFree(M->partial.p);
   if (M->split.p) (void)hipFree(M->split.p);
+  if (M->loss_scratch.p) (void)hipFree(M->loss_scratch.p);
   (void)hipFree(M->d_offs);
   delete M;
   return XLMIMO_OK;
@@ -1227,6 +1230,37 @@ int xlmimo_mlp_train_step(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* f
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
   HIP_TRY(c, launch_adam(M->n_params, M->master, M->m, M->v, M->grad, lr, b1, b2, 1e-8f, bc1, bc2, M->wbf, s));
+  return XLMIMO_OK;
+}
+
+int xlmimo_mlp_train(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, const float* aux,
+                     const float* target, int64_t batch, int64_t n_steps, const float* lr, double* loss_out,
+                     void* stream) {
+  if (!c) return XLMIMO_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc0 = no_capture(c, "xlmimo_mlp_train (its Adam step count lives on the host)")) return rc0;
+  int rc = check_mlp_args(c, M, n, features, aux);
+  if (rc) return rc;
+  if (!target || !lr) return set_err(c, XLMIMO_EINVAL, "targets and learning rates are needed");
+  if (batch < 1 || batch > n || n_steps < 0) return set_err(c, XLMIMO_EINVAL, "need 1 <= batch <= n and n_steps >= 0");
+  for (int64_t i = 0; i < n_steps; ++i)
+    if (!(lr[i] >= 0.0f) || !std::isfinite(lr[i])) return set_err(c, XLMIMO_EINVAL, "bad learning rate at step %lld",
+                                                                (long long)i);
+  if ((rc = set_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (!loss_out && (rc = ensure(c, M->loss_scratch, sizeof(double), s))) return rc;
+  const int64_t n_batches = n / batch;
+  const __bf16* feat = (const __bf16*)features;
+  const float b1 = 0.9f, b2 = 0.999f;
+  for (int64_t i = 0; i < n_steps; ++i) {
+    const int64_t off = (i % n_batches) * batch;
+    double* lo = loss_out ? loss_out + i : (double*)M->loss_scratch.p;
+    if ((rc = mlp_loss_grad_impl(c, M, batch, feat + off * kFeatPitch, aux + off * kAuxPitch, target + off * 2, lo, s)))
+      return rc;
+    M->t += 1;
+    const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
+    HIP_TRY(c, launch_adam(M->n_params, M->master, M->m, M->v, M->grad, lr[i], b1, b2, 1e-8f, bc1, bc2, M->wbf, s));
+  }
   return XLMIMO_OK;
 }
 

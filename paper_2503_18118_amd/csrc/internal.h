@@ -101,6 +101,7 @@ struct GemmArgs {
   float* out_f;       // FWD_OUT, STORE_F32 (split-K: [splits][M][ldo] partials)
   int64_t ldo;
   int k_chunk;        // STORE_F32 split-K: K range per grid.z slice (0 = whole K)
+  int row_sums;       // STORE_F32: also write sum_k A(m, k) after the M x ldo block of each slice
 };
 
 // Launchers (stream-ordered, no host synchronisation).
@@ -147,10 +148,8 @@ hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_dro
                               int32_t* pmap, hipStream_t s);
 hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
                            double* partial, double* loss, hipStream_t s);
-// Column sums of dz [rows x cols] into db [cols], in a fixed order over at most
-// max_splits row blocks (partial holds max_splits * cols floats).
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int max_splits,
-                         hipStream_t s);
+// Split-K GEMM into out[M x ldo] (fixed-order sum over the slices); with row_sums, also
+// out[M * ldo + m] = sum_k A(m, k) (the bias gradient of a weight-gradient GEMM).
 hipError_t launch_gemm_splitk(const GemmArgs& g, int splits, float* partial, float* out, hipStream_t s);
 hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s);
@@ -172,6 +171,7 @@ hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const
 hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                     const float* master, const int64_t* d_offs, float* out, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;
+constexpr int kDoutPitch = 8;   // bf16 per pair of the output-layer gradient (7 used; 16-byte rows)
 
 // Allocation-free exact Gram: the per-device address of the static scratch
 // array (XLMIMO_NOALLOC_SCRATCH_BYTES).  static_scratch_init looks it up once

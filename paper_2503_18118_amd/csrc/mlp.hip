@@ -80,55 +80,145 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return fmaf(z * 0.3989422804014327f, g.e, phi);   // Phi(z) + z phi(z)
 }
 
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 sA[TM * LDS_K];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[TN * LDS_K];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  floatx4 acc[2][2];
+// Operand tiles: 64 rows (m of A, n of B) x TK = 32 k-values, staged in LDS with k
+// contiguous (the MFMA operand layout).  Three ways to fetch a tile, chosen per operand
+// on the host from its strides and alignment:
+//   LOAD_K   k-contiguous rows, 16-byte aligned: thread t loads row t/4, k-values 8 (t%4) .. + 7
+//            as one 16-byte vector (one 16-byte LDS store);
+//   LOAD_R   row-contiguous (k strided), aligned: thread t loads rows 8 (t%8) .. + 7 at k = t/8
+//            as one vector and stores them transposed (8 two-byte LDS stores);
+//   LOAD_S   anything else: the LOAD_K pattern with element loads.
+// Out-of-range elements load as zero (vector loads only where the whole vector is in range).
+enum { LOAD_S = 0, LOAD_K = 1, LOAD_R = 2 };
+
+template <int MODE>
+__device__ __forceinline__ bf16x8 tile_fetch(const __bf16* __restrict__ P, int64_t p_r, int64_t p_k, int rows, int r0,
+                                             int k0, int ke, int tid) {
+  bf16x8 v;
+  if constexpr (MODE == LOAD_R) {
+    const int k = k0 + (tid >> 3), rc = r0 + 8 * (tid & 7);
+    if (k < ke && rc + 8 <= rows) {
+      v = *reinterpret_cast<const bf16x8*>(P + (int64_t)k * p_k + rc);
+    } else {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int q = 0; q < 8; ++q) v[q] = (k < ke && rc + q < rows) ? P[(int64_t)k * p_k + rc + q] : (__bf16)0.0f;
+    }
+  } else {
+    const int r = r0 + (tid >> 2), kc = k0 + 8 * (tid & 3);
+    if (MODE == LOAD_K && r < rows && kc + 8 <= ke) {
+      v = *reinterpret_cast<const bf16x8*>(P + (int64_t)r * p_r + kc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        v[q] = (r < rows && kc + q < ke) ? P[(int64_t)r * p_r + (int64_t)(kc + q) * p_k] : (__bf16)0.0f;
+    }
+  }
+  return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void tile_store(__bf16* s, const bf16x8& v, int tid) {
+  if constexpr (MODE == LOAD_R) {
+    const int k = tid >> 3, rc = 8 * (tid & 7);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[(rc + q) * LDS_K + k] = v[q];
+  } else {
+    *reinterpret_cast<bf16x8*>(&s[(tid >> 2) * LDS_K + 8 * (tid & 3)]) = v;
+  }
+}
+
+// Double-buffered main loop: the next k-step's tiles are fetched into registers while the
+// matrix cores work on the current one from LDS; one barrier per k-step.  A workgroup
+// computes a (64 MT) x 64 tile; each of its 4 waves a (32 MT) x 32 block of 16x16 MFMA tiles.
+template <int EPI, int AM, int BM, int MT>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int TMM = TM * MT;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][TMM * LDS_K];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][TN * LDS_K];
+  constexpr bool RS = EPI == EPI_STORE_F32 && AM == LOAD_R;
+  static_assert(!RS || MT == 1, "row sums with single row tiles");
+  __shared__ float s_rs[RS ? 32 * TM : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * TMM, n0 = blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32 * MT, wn = (wave & 1) * 32;
+  floatx4 acc[2 * MT][2];
+#pragma unroll
+  for (int i = 0; i < 2 * MT; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8 k-values
   int kb = 0, ke = g.K;
   if (EPI == EPI_STORE_F32 && g.k_chunk > 0) {
     kb = blockIdx.z * g.k_chunk;
     ke = min(g.K, kb + g.k_chunk);
   }
+  // row sums of A over this slice (bias gradients), accumulated from the fetched tiles
+  const bool row_sums = RS && g.row_sums && blockIdx.x == 0;
+  float rs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+  bf16x8 va[MT], vb;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) va[t] = tile_fetch<AM>(g.A, g.a_m, g.a_k, g.M, m0 + TM * t, kb, ke, tid);
+  vb = tile_fetch<BM>(g.B, g.b_n, g.b_k, g.N, n0, kb, ke, tid);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) tile_store<AM>(sA[0] + TM * t * LDS_K, va[t], tid);
+  tile_store<BM>(sB[0], vb, tid);
+  if constexpr (RS) {
+    if (row_sums) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rs[q] += (float)va[0][q];
+    }
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += TK) {
-    {
-      const int m = m0 + lr;
+    const bool more = k0 + TK < ke;
+    if (more) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + lk + q;
-        sA[lr * LDS_K + lk + q] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.a_m + (int64_t)k * g.a_k] : (__bf16)0.0f;
-      }
-      const int n = n0 + lr;
+      for (int t = 0; t < MT; ++t) va[t] = tile_fetch<AM>(g.A, g.a_m, g.a_k, g.M, m0 + TM * t, k0 + TK, ke, tid);
+      vb = tile_fetch<BM>(g.B, g.b_n, g.b_k, g.N, n0, k0 + TK, ke, tid);
+    }
+    const int kk = 8 * (lane >> 4);
+    bf16x8 af[2 * MT], bfr[2];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + lk + q;
-        sB[lr * LDS_K + lk + q] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (__bf16)0.0f;
+    for (int i = 0; i < 2 * MT; ++i)
+      af[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][(wm + i * 16 + (lane & 15)) * LDS_K + kk]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      bfr[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][(wn + j * 16 + (lane & 15)) * LDS_K + kk]);
+#pragma unroll
+    for (int i = 0; i < 2 * MT; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) tile_store<AM>(sA[buf ^ 1] + TM * t * LDS_K, va[t], tid);
+      tile_store<BM>(sB[buf ^ 1], vb, tid);
+      if constexpr (RS) {
+        if (row_sums) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) rs[q] += (float)va[0][q];
+        }
       }
     }
     __syncthreads();
-    const int kk = 8 * (lane >> 4);
-    bf16x8 af[2], bfr[2];
+    buf ^= 1;
+  }
+  if constexpr (RS) {
+    if (row_sums) {
+      // thread t holds rows 8 (t%8) .. + 7 summed over k = t/8 (mod 32): fixed-order sum over t/8
 #pragma unroll
-    for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDS_K + kk]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDS_K + kk]);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+      for (int q = 0; q < 8; ++q) s_rs[(tid >> 3) * TM + 8 * (tid & 7) + q] = rs[q];
+      __syncthreads();
+      if (tid < TM && m0 + tid < g.M) {
+        float t = 0.f;
+        for (int j = 0; j < 32; ++j) t += s_rs[j * TM + tid];
+        g.out_f[(int64_t)blockIdx.z * ((int64_t)g.M * g.ldo + g.M) + (int64_t)g.M * g.ldo + m0 + tid] = t;
+      }
+    }
   }
   // C layout of 16x16 blocks: lane l, register r -> row 4 (l / 16) + r, column l % 16
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 2 * MT; ++i) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn + j * 16 + (lane & 15);
@@ -147,7 +237,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         } else if constexpr (EPI == EPI_BWD_DX) {
           g.out_bf[o] = (__bf16)(v * gelu_grad(g.Z[o]));
         } else {
-          g.out_f[(int64_t)blockIdx.z * g.M * g.ldo + o] = v;
+          const int64_t slice = g.row_sums ? (int64_t)g.M * g.ldo + g.M : (int64_t)g.M * g.ldo;
+          g.out_f[(int64_t)blockIdx.z * slice + o] = v;
         }
       }
     }
@@ -163,14 +254,45 @@ __global__ void k_reduce_splits(const float* __restrict__ partial, int splits, i
   out[i] = acc;
 }
 
+// Fetch mode of an operand with row stride p_r and k stride p_k.
+static int load_mode(const __bf16* P, int64_t p_r, int64_t p_k) {
+  const bool aligned = ((uintptr_t)P & 15) == 0;
+  if (p_k == 1 && p_r % 8 == 0 && aligned) return LOAD_K;
+  if (p_r == 1 && p_k % 8 == 0 && aligned) return LOAD_R;
+  return LOAD_S;
+}
+
+template <int EPI, int MT>
+static void launch_modes_mt(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  const int am = load_mode(g.A, g.a_m, g.a_k), bm = load_mode(g.B, g.b_n, g.b_k);
+#define XL_GEMM_CASE(A_, B_) \
+  if (am == A_ && bm == B_) { k_gemm_bf16<EPI, A_, B_, MT><<<grid, 256, 0, s>>>(g); return; }
+  XL_GEMM_CASE(LOAD_K, LOAD_K)
+  XL_GEMM_CASE(LOAD_K, LOAD_R)
+  XL_GEMM_CASE(LOAD_R, LOAD_R)
+  XL_GEMM_CASE(LOAD_K, LOAD_S)
+  XL_GEMM_CASE(LOAD_R, LOAD_S)
+  XL_GEMM_CASE(LOAD_S, LOAD_K)
+  XL_GEMM_CASE(LOAD_S, LOAD_R)
+#undef XL_GEMM_CASE
+  k_gemm_bf16<EPI, LOAD_S, LOAD_S, MT><<<grid, 256, 0, s>>>(g);
+}
+
+template <int EPI>
+static void launch_modes(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  // (row tiles of 128, half the workgroups at batch 8192, measured 13 % slower per training step)
+  launch_modes_mt<EPI, 1>(g, grid, s);
+}
+
 hipError_t launch_gemm_splitk(const GemmArgs& g0, int splits, float* partial, float* out, hipStream_t s) {
   GemmArgs g = g0;
   g.k_chunk = ((g.K + splits - 1) / splits + TK - 1) / TK * TK;
   splits = (g.K + g.k_chunk - 1) / g.k_chunk;
   g.out_f = partial;
   dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
-  k_gemm_bf16<EPI_STORE_F32><<<grid, 256, 0, s>>>(g);
-  const int64_t n = (int64_t)g.M * g.ldo;
+  if (g.row_sums && load_mode(g.A, g.a_m, g.a_k) != LOAD_R) return hipErrorInvalidValue;
+  launch_modes<EPI_STORE_F32>(g, grid, s);
+  const int64_t n = (int64_t)g.M * g.ldo + (g.row_sums ? g.M : 0);
   k_reduce_splits<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, splits, n, out);
   return hipGetLastError();
 }
@@ -178,10 +300,10 @@ hipError_t launch_gemm_splitk(const GemmArgs& g0, int splits, float* partial, fl
 hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s) {
   dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
   switch (epi) {
-    case EPI_FWD_HIDDEN: k_gemm_bf16<EPI_FWD_HIDDEN><<<grid, 256, 0, s>>>(g); break;
-    case EPI_FWD_OUT: k_gemm_bf16<EPI_FWD_OUT><<<grid, 256, 0, s>>>(g); break;
-    case EPI_BWD_DX: k_gemm_bf16<EPI_BWD_DX><<<grid, 256, 0, s>>>(g); break;
-    default: k_gemm_bf16<EPI_STORE_F32><<<grid, 256, 0, s>>>(g); break;
+    case EPI_FWD_HIDDEN: launch_modes<EPI_FWD_HIDDEN>(g, grid, s); break;
+    case EPI_FWD_OUT: launch_modes<EPI_FWD_OUT>(g, grid, s); break;
+    case EPI_BWD_DX: launch_modes<EPI_BWD_DX>(g, grid, s); break;
+    default: launch_modes<EPI_STORE_F32>(g, grid, s); break;
   }
   return hipGetLastError();
 }
@@ -330,13 +452,14 @@ __global__ __launch_bounds__(256) void k_mlp_head(int64_t n, const float* __rest
     const float e2 = er * er + ei * ei;
     acc += (double)(e2 * w + s);
     const float gpr = -2.0f * er * w * inv_n, gpi = -2.0f * ei * w * inv_n;
-    __bf16* d = dout + p * 7;
+    __bf16* d = dout + p * kDoutPitch;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       d[2 * m] = (__bf16)(gpr * a[2 * m] + gpi * a[2 * m + 1]);
       d[2 * m + 1] = (__bf16)(-gpr * a[2 * m + 1] + gpi * a[2 * m]);
     }
     d[6] = (__bf16)((1.0f - e2 * w) * inv_n);
+    d[7] = (__bf16)0.0f;
   }
   s_sum[threadIdx.x] = acc;
   __syncthreads();
@@ -365,29 +488,6 @@ hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const 
                            double* partial, double* loss, hipStream_t s) {
   k_mlp_head<<<kMlpHeadBlocks, 256, 0, s>>>(n, out, aux, target, dout, partial);
   k_sum_partials<<<1, 256, 0, s>>>(partial, kMlpHeadBlocks, n, loss);
-  return hipGetLastError();
-}
-
-// db[c] = sum over rows of dZ[row][c]: row slices in parallel, then the slices
-// in fixed order.
-__global__ void k_colsum_part(const __bf16* __restrict__ dz, int64_t rows, int cols, int64_t rows_per,
-                              float* __restrict__ partial) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  const int64_t r0 = blockIdx.y * rows_per, r1 = min(rows, r0 + rows_per);
-  float acc = 0.0f;
-  for (int64_t r = r0; r < r1; ++r) acc += (float)dz[r * cols + c];
-  partial[(int64_t)blockIdx.y * cols + c] = acc;
-}
-
-hipError_t launch_colsum(const __bf16* dz, int64_t rows, int cols, float* db, float* partial, int max_splits,
-                         hipStream_t s) {
-  // about 32 rows per thread: enough workgroups to fill the chip at a few thousand rows
-  const int64_t rows_per = std::max<int64_t>(32, (rows + max_splits - 1) / max_splits);
-  const int splits = (int)((rows + rows_per - 1) / rows_per);
-  dim3 grid((cols + 255) / 256, splits);
-  k_colsum_part<<<grid, 256, 0, s>>>(dz, rows, cols, rows_per, partial);
-  k_reduce_splits<<<(cols + 255) / 256, 256, 0, s>>>(partial, splits, cols, db);
   return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ EXPORTED = ("xlmimo_ctx_create", "xlmimo_ctx_destroy", "xlmimo_last_error", "xlm
             "xlmimo_mlp_train_step", "xlmimo_mlp_forward", "xlmimo_gram_closedform_mlp",
             "xlmimo_graph_begin", "xlmimo_graph_end", "xlmimo_graph_launch", "xlmimo_graph_node_count",
             "xlmimo_graph_destroy", "xlmimo_autotune_exact", "xlmimo_gram_update_users", "xlmimo_cholesky",
-            "xlmimo_cholesky_update_users", "xlmimo_gram_exact_noalloc", "xlmimo_mlp_set_gate")
+            "xlmimo_cholesky_update_users", "xlmimo_gram_exact_noalloc", "xlmimo_mlp_set_gate",
+            "xlmimo_mlp_train")
 
 
 class XlArray(C.Structure):
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.xlmimo_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     lib.xlmimo_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp]
     lib.xlmimo_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.xlmimo_mlp_train.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, vp, vp, vp]
     lib.xlmimo_gram_closedform_mlp.argtypes = [vp, C.POINTER(XlArray), C.POINTER(XlBatch), i32, vp, C.c_double, vp,
                                                vp, vp]
     lib.xlmimo_timing_enable.argtypes = [vp, C.c_int]
@@ -440,6 +442,15 @@ class MLP:
         self.ctx._check(_lib.xlmimo_mlp_train_step(self.ctx.h, self.h, pi.n, _ptr(pi.feat), _ptr(pi.aux),
                                                    _ptr(pi.target), float(lr), _ptr(loss), _stream(stream)),
                         "xlmimo_mlp_train_step")
+        return loss
+
+    def train(self, pi: PairInputs, batch: int, lr: np.ndarray, loss: Optional[torch.Tensor] = None, stream=None):
+        """len(lr) Adam steps over consecutive batch slices of pi (xlmimo_mlp_train); loss: CUDA float64
+        [len(lr)] or None."""
+        lr = np.ascontiguousarray(lr, np.float32)
+        self.ctx._check(_lib.xlmimo_mlp_train(self.ctx.h, self.h, pi.n, _ptr(pi.feat), _ptr(pi.aux), _ptr(pi.target),
+                                              int(batch), int(lr.size), lr.ctypes.data_as(C.c_void_p), _ptr(loss),
+                                              _stream(stream)), "xlmimo_mlp_train")
         return loss
 
     def forward(self, pi: PairInputs, stream=None) -> torch.Tensor:

@@ -145,6 +145,29 @@ def test_training_reduces_loss_and_adam_matches(X, ctx):
     assert losses[-1] < losses[0] - 1.0, losses
 
 
+def test_multi_step_training_equals_single_steps(X, ctx):
+    # xlmimo_mlp_train enqueues the same kernels as repeated xlmimo_mlp_train_step calls on
+    # consecutive batch slices (wrapping around): bit-identical parameters and losses
+    rng = np.random.default_rng(15)
+    params = OM.init_params(rng, 256, 4).astype(np.float32)
+    arr, drops, pi, *_ = _pairs(X, ctx, X.MLP(ctx, 256, 4), n_drops=40, k=16, stream=16)   # 4800 pairs
+    batch, steps = 1000, 11
+    lr = np.linspace(3e-3, 1e-4, steps).astype(np.float32)
+    a, b = X.MLP(ctx, 256, 4), X.MLP(ctx, 256, 4)
+    a.set_params(params)
+    b.set_params(params)
+    la = []
+    nb = pi.n // batch
+    for s_ in range(steps):
+        o = (s_ % nb) * batch
+        la.append(a.train_step(pi.slice(o, o + batch), float(lr[s_])).item())
+    lb = torch.empty(steps, dtype=torch.float64, device=pi.aux.device)
+    b.train(pi, batch, lr, lb)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert np.array_equal(np.array(la), lb.cpu().numpy())
+
+
 @pytest.mark.parametrize("width,depth,n_drops", [(64, 2, 3), (128, 3, 5), (256, 1, 2)])
 def test_fused_forward_other_shapes(X, ctx, width, depth, n_drops):
     # the fused inference kernel at every width it supports, with a ragged last tile
