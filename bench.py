@@ -334,6 +334,10 @@ def sweep_leg(args, ctx, X, Lr, W, snr, stream):
                        "sumrate_evals_per_s_all_n": evals_per_sweep / (ms * 1e-3)}
     forms["learned"]["fallback_fraction_by_n"] = [
         float(x) for x in (bufs["learned"][2] & X.ST_FELL_BACK).ne(0).float().mean(dim=1).cpu()]
+    # the ergodic means average the drops whose rates are finite: how many were left out, per N
+    for name in order:
+        bad = (bufs[name][2] & (X.ST_G_NOT_PD | X.ST_MMSE_NOT_PD | X.ST_BAD_INPUT)).ne(0)
+        forms[name]["drops_left_out_of_ergodic_by_n"] = [int(x) for x in bad.sum(dim=1).cpu()]
 
     # roofline of the exact kernel: vector-ALU work per launch over the live-timed launch time
     evals = n_drops * sum(n_list) * k
