@@ -218,7 +218,7 @@ int64_t chunk_length(int64_t total_elems, int grid) {
   int64_t target = total_elems / (8LL * std::max(grid, 1));
   target = std::max<int64_t>(target, 2048);
   target = std::min<int64_t>(target, 65536);
-  return (target + 127) / 128 * 128;  // whole rounds of both FP32 kernels (16 and 128 elements)
+  return (target + 255) / 256 * 256;  // whole rounds of every FP32 kernel (16, 128 and 256 elements)
 }
 
 uint64_t plan_key(const xlmimo_array* a, const xlmimo_batch* b, const int64_t* n_override) {

@@ -74,7 +74,8 @@ struct Mfma<double> {
 // gfx950: |error| <= 1.3e-7 over a full turn).  Lanes with nothing to contribute
 // (users beyond K, elements past the end) carry a coordinate of 1e30:
 // rsq(inf) = 0 makes their entry exactly zero.
-// Amplitude a (times us, a power of two: exact) and cos / sin of the phase in turns.
+// Amplitude a (times us, a power of two: exact), c = cos(2 pi t) and sn = -sin(2 pi t),
+// so that h = a (c + j sn).
 template <int GEOM, int AMP>
 __device__ __forceinline__ void channel_parts(double dy, double dz, double xp2, float us, float& a, float& c,
                                               float& sn) {
@@ -89,7 +90,7 @@ __device__ __forceinline__ void channel_parts(double dy, double dz, double xp2, 
   if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * __builtin_amdgcn_sqrtf(a);
   a = a * us;
   c = __builtin_amdgcn_cosf(t);
-  sn = __builtin_amdgcn_sinf(t);
+  sn = __builtin_amdgcn_sinf(-t);
 }
 
 template <int GEOM, int AMP>
@@ -97,7 +98,7 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
   float a, c, sn;
   channel_parts<GEOM, AMP>(dy, dz, xp2, 1.0f, a, c, sn);
   re = a * c;
-  im = -a * sn;
+  im = a * sn;
 }
 
 // FP64: distances in units of lambda / 2 (r counts half turns),
@@ -331,13 +332,16 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
 // with |dropped| + rounding of lo <= ~2^-22 |x_i x_j| (or 2^-25 absolute where
 // lo is subnormal), i.e. FP32-level products.  Three 16x16x32 FP16 MFMA per
 // product stream cover 32 elements where FP32 MFMA needs eight.
-// Work layout: a round covers 128 elements; wave w takes 32 of them and lane l
-// evaluates user 16b + (l % 16) at the 8 consecutive elements 8 (l / 16) + m,
-// m = 0..7 (the 16x16x32 operand layout: lane l holds row l % 16, k-block l / 16).
-// Products accumulate in FP32 over 8 rounds (256 elements per wave), then in FP64.
+// Work layout: a lane evaluates one user per 16-user block at a run of R
+// consecutive elements, and 32 elements of each wave (one k-block of 8 per
+// 16-lane group) feed one set of MFMAs: lane l holds row l % 16 and k-block l / 16
+// of the 16x16x32 operands.  The per-element path takes R = 8 (one MFMA set per
+// round, 128 elements per workgroup round); the expansion path takes R = 16 (its
+// run feeds two MFMA sets, 256 elements per workgroup round).  Which element sits
+// in which k slot does not matter as long as every user uses the same slots.
+// Products accumulate in FP32 over 256 elements per wave, then in FP64.
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
-constexpr int kSplitRound = 128;
-constexpr int kSplitFlush = 8;
+constexpr int kSplitFlushElems = 256;   // elements per wave between FP64 carries
 constexpr int kSplitMaxNb = 2;  // user blocks of 16 handled by the split kernel
 
 __device__ __forceinline__ floatx4 mfma_h(halfx8 a, halfx8 b, floatx4 c) {
@@ -353,47 +357,64 @@ __device__ __forceinline__ int split_exp(double xp2, int amp) {
   return min(max(q, -100), 100);
 }
 
-// Entries m, m + 1 of the hi and lo operands from amplitudes a and cos / sin:
-// hi = f16(a c) (two at a time), lo = f16(a c - hi) with the product exact inside
-// the FMA, so hi + lo = a c to ~2^-22 relative.
+// Entries m, m + 1 of the hi and lo operands from amplitudes a and c, sn (h = a (c + j sn)):
+// hi = f16(a c) (two at a time: FP32 products, one packed conversion) and
+// lo = f16(a c - hi) with a c exact inside the fused multiply-add, so
+// hi + lo = a c to ~2^-22 relative.  lo is formed in FP32 (v_fma_mix_f32 reads
+// hi straight from its FP16 half) and converted two at a time: on gfx950 the
+// packed conversion and v_fma_mix_f32 issue like an FP32 FMA, while
+// v_fma_mixlo_f16 / v_fma_mixhi_f16 (FP16 results into half registers) take
+// over twice as long, so the empty asm statements keep the compiler from fusing
+// the conversions into them (and make lo use these very hi values).
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void split_pair(const float* a, const float* c, const float* sn, halfx8& rh, halfx8& rl,
                                            halfx8& ih, halfx8& il, int m) {
-  halfx2 hr = __builtin_convertvector((floatx2){a[0] * c[0], a[1] * c[1]}, halfx2);
-  halfx2 hi = __builtin_convertvector((floatx2){-a[0] * sn[0], -a[1] * sn[1]}, halfx2);
-  // opaque from here: lo must be formed from these very hi values (the
-  // compiler would otherwise re-derive hi from the product for the FMA)
-  asm volatile("" : "+v"(hr), "+v"(hi));
+  floatx2 pr = {a[0] * c[0], a[1] * c[1]};
+  floatx2 pi = {a[0] * sn[0], a[1] * sn[1]};
+  asm("" : "+v"(pr));
+  asm("" : "+v"(pi));
+  halfx2 hr = __builtin_convertvector(pr, halfx2);
+  halfx2 hi = __builtin_convertvector(pi, halfx2);
+  asm("" : "+v"(hr));
+  asm("" : "+v"(hi));
+  floatx2 lr = {__builtin_fmaf(a[0], c[0], -(float)hr[0]), __builtin_fmaf(a[1], c[1], -(float)hr[1])};
+  floatx2 li = {__builtin_fmaf(a[0], sn[0], -(float)hi[0]), __builtin_fmaf(a[1], sn[1], -(float)hi[1])};
+  asm("" : "+v"(lr));
+  asm("" : "+v"(li));
+  const halfx2 lrh = __builtin_convertvector(lr, halfx2);
+  const halfx2 lih = __builtin_convertvector(li, halfx2);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     rh[m + q] = hr[q];
     ih[m + q] = hi[q];
-    rl[m + q] = (_Float16)__builtin_fmaf(a[q], c[q], -(float)hr[q]);
-    il[m + q] = (_Float16)__builtin_fmaf(-a[q], sn[q], -(float)hi[q]);
+    rl[m + q] = lrh[q];
+    il[m + q] = lih[q];
   }
 }
 
-// Expansion of the channel along a lane's 8 consecutive elements (FP32H).
-// The distance is exact in FP64 at the centre of the run (element m = 3.5, offset
+// Expansion of the channel along a lane's run of 16 consecutive elements (FP32H).
+// The distance is exact in FP64 at the centre of the run (element m = 7.5, offset
 // t = 0), its phase reduced there: c0 = fract(r_c).  Along the run the element
-// offset is t = m' d, m' = m - 3.5, d the spacing in wavelengths, and with
+// offset is t = m' d, m' = m - 7.5, d the spacing in wavelengths, and with
 // dy_c the centre's offset along the line, mu = dy_c / r_c:
 //   r(t) - r_c = r_c sum_k C_k^(-1/2)(mu) (t / r_c)^k       (Gegenbauer generating function of
 //   r(t)^-p    = r_c^-p sum_k C_k^(p/2)(mu) (t / r_c)^k      r_c^2 - 2 dy_c t + t^2)
-// evaluated in FP32 by Horner's rule in m' (the coefficients carry d^k), to t^4 for the
-// phase and t^3 for the amplitude.  With the half-run |t| <= 3.5 d and every user at a
-// distance x >= kExpandXmin d from the array line (plane), the truncated terms stay below
-// 1e-8 turns and 2e-8 relative; the FP32 evaluation leaves |phase error| <= 3e-7 turns
-// at d = 1/2 (the phase is carried to |theta| < 3, so its rounding dominates) and
-// 1.2e-7 relative in the amplitude.  Items whose users come closer take the
+// evaluated in FP32 by Horner's rule in m'^2 on the even and odd parts (the
+// coefficients carry d^k), to t^4 for both.  With the half-run |t| <= 7.5 d and
+// every user at a distance x >= kExpandXmin d from the array line (plane), the
+// truncated terms stay below 1e-7 turns (d <= 1) and 2e-9 relative; the FP32
+// evaluation leaves |phase error| <= 5e-7 turns at d = 1/2 (9e-7 at d = 1: the
+// phase is carried to |theta| < 4.3 turns, so its rounding dominates) and 3e-7
+// relative in the amplitude.  Items whose users come closer take the
 // per-element FP64 path.
 constexpr double kExpandXmin = 368.0;
+constexpr int kExpandRun = 16;
 
 template <int AMP>
 struct Expansion {
-  float th[5];   // phase in turns: c0, then the coefficients of m', m'^2, m'^3, m'^4
-  float am[4];   // amplitude (times the user scale): coefficients of 1, m', m'^2, m'^3
+  float th[5];   // minus the phase in turns: -c0, then the coefficients of m', ..., m'^4 (all negated)
+  float am[5];   // amplitude (times the user scale): coefficients of 1, m', ..., m'^4
 };
 
 template <int AMP>
@@ -406,42 +427,46 @@ __device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double 
   const double rc = fma(0.5 * y0, fma(-r0, r0, r2), r0);      // r_c to ~1e-14 relative
   const double y1 = fma(y0, fma(-rc, y0, 1.0), y0);           // 1 / r_c to ~1e-14 relative
   const double mu64 = dyc * y1;
-  x.th[0] = (float)__builtin_amdgcn_fract(rc);
-  x.th[1] = (float)(-mu64 * ds);
+  x.th[0] = -(float)__builtin_amdgcn_fract(rc);
+  x.th[1] = (float)(mu64 * ds);
   const float mu = (float)mu64;
   const float dsf = (float)ds;
   const float q = yf * dsf;                                   // d / r_c
   const float w = __builtin_fmaf(-mu, mu, 1.0f);              // 1 - mu^2
   const float q2 = q * q;
-  x.th[2] = (w * q) * (0.5f * dsf);                           // (1 - mu^2) d^2 / (2 r_c)
-  x.th[3] = (mu * x.th[2]) * q;                               // mu (1 - mu^2) d^3 / (2 r_c^2)
-  x.th[4] = (x.th[2] * q2) * __builtin_fmaf(1.25f, mu * mu, -0.25f);   // (1 - mu^2)(5 mu^2 - 1) d^4 / (8 r_c^3)
+  const float mu2 = mu * mu;
+  x.th[2] = (w * q) * (-0.5f * dsf);                          // -(1 - mu^2) d^2 / (2 r_c)
+  x.th[3] = (mu * x.th[2]) * q;                               // -mu (1 - mu^2) d^3 / (2 r_c^2)
+  x.th[4] = (x.th[2] * q2) * __builtin_fmaf(1.25f, mu2, -0.25f);   // -(1 - mu^2)(5 mu^2 - 1) d^4 / (8 r_c^3)
   float b0 = yf;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) b0 = b0 * __builtin_amdgcn_sqrtf(b0);
   b0 = b0 * us;
-  const float mu2 = mu * mu;
+  const float bq2 = b0 * q2;
   x.am[0] = b0;
   if constexpr (AMP == XLMIMO_AMP_FREESPACE) {          // Legendre polynomials P_k(mu)
     x.am[1] = (b0 * mu) * q;
-    x.am[2] = (b0 * q2) * __builtin_fmaf(1.5f, mu2, -0.5f);
-    x.am[3] = (b0 * q2) * ((q * mu) * __builtin_fmaf(2.5f, mu2, -1.5f));
+    x.am[2] = bq2 * __builtin_fmaf(1.5f, mu2, -0.5f);
+    x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(2.5f, mu2, -1.5f));
+    x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(4.375f, mu2, -3.75f), mu2, 0.375f);
   } else {                                              // C_k^(3/4)(mu)
     x.am[1] = (b0 * mu) * (1.5f * q);
-    x.am[2] = (b0 * q2) * __builtin_fmaf(2.625f, mu2, -0.75f);
-    x.am[3] = (b0 * q2) * ((q * mu) * __builtin_fmaf(4.8125f, mu2, -2.625f));
+    x.am[2] = bq2 * __builtin_fmaf(2.625f, mu2, -0.75f);
+    x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(4.8125f, mu2, -2.625f));
+    x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(9.0234375f, mu2, -7.21875f), mu2, 0.65625f);
   }
   return x;
 }
 
-// The two elements at m' = -p and +p from the even and odd parts of both series:
-// theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (9 FMAs per pair).
+// The two elements at m' = -p and +p from the even and odd parts of both series,
+// with the phase carried negated (so that sn = sin(-theta) needs no sign flip):
+// -theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (10 FMAs per pair).
 template <int AMP>
 __device__ __forceinline__ void expansion_pair(const Expansion<AMP>& x, float p, float (&a)[2], float (&c)[2],
                                                float (&sn)[2]) {
   const float p2 = p * p;
   const float ev = __builtin_fmaf(__builtin_fmaf(x.th[4], p2, x.th[2]), p2, x.th[0]);
   const float od = __builtin_fmaf(x.th[3], p2, x.th[1]);
-  const float ae = __builtin_fmaf(x.am[2], p2, x.am[0]);
+  const float ae = __builtin_fmaf(__builtin_fmaf(x.am[4], p2, x.am[2]), p2, x.am[0]);
   const float ao = __builtin_fmaf(x.am[3], p2, x.am[1]);
   const float th0 = __builtin_fmaf(-p, od, ev), th1 = __builtin_fmaf(p, od, ev);
   a[0] = __builtin_fmaf(-p, ao, ae);
@@ -484,7 +509,7 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
     near |= !(u[b].xp2 >= xmin * xmin);
   }
   // every wave of the workgroup holds the same users, so they all take the same path
-  const bool expand = (GEOM == XLMIMO_ULA || arr.n_z % 8 == 0) && !__any(near);
+  const bool expand = (GEOM == XLMIMO_ULA || arr.n_z % kExpandRun == 0) && !__any(near);
   if (expand) split_body<NB, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red);
   else split_body<NB, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red);
 }
@@ -509,93 +534,21 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
 #pragma unroll
   for (int i = 0; i < NV; ++i) carry[i] = 0.0;
 
+  constexpr int RUN = EXPAND ? kExpandRun : 8;   // consecutive elements per lane and round
+  constexpr int ROUND = 16 * RUN;                  // elements per workgroup round (4 waves x 4 groups)
+  constexpr int FLUSH = kSplitFlushElems * 8 / (RUN * 32);   // rounds between FP64 carries
   const int len = it.e_end - it.e_begin;
-  const int n_full = len / kSplitRound;
-  const int n_rounds = (len + kSplitRound - 1) / kSplitRound;
-  const int sub = 32 * wave + 8 * (lane >> 4);  // lane's first element within a round
+  const int n_full = len / ROUND;
+  const int n_rounds = (len + ROUND - 1) / ROUND;
+  const int sub = RUN * (4 * wave + (lane >> 4));  // lane's first element within a round
   const int ny = (GEOM == XLMIMO_ULA) ? dp.n_elems : arr.n_y;
   const double ds = arr.spacing * sc;
   const double cy = 0.5 * (double)(ny - 1) * ds;
   const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
 
-  // One round: the lane's 8 elements start at element index e; elements at or
-  // past e_end (only in the last round, TAIL) take the far coordinate.
-  auto round = [&](int e, auto tail_tag) {
-    constexpr bool TAIL = decltype(tail_tag)::value;
-    halfx8 rh[NB], rl[NB], ih[NB], il[NB];
-    if constexpr (EXPAND) {
-      // the run's centre, element e + 3.5, and the expansion of each user about it
-      double ey = 0.0, ez = 0.0;
-      if constexpr (GEOM == XLMIMO_ULA) {
-        ey = fma((double)e + 3.5, ds, -cy);
-      } else {
-        const int ea = e / arr.n_z;
-        ey = fma((double)ea, ds, -cy);
-        ez = fma((double)(e - ea * arr.n_z) + 3.5, ds, -cz);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        Expansion<AMP> x;
-        if constexpr (GEOM == XLMIMO_ULA) {
-          x = expand<AMP>(u[b].uy - ey, u[b].xp2, ds, us[b]);
-        } else {
-          const double dy = u[b].uy - ey;
-          x = expand<AMP>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
-        }
-        // operand slots 2j, 2j + 1 hold elements 3 - j and 4 + j (the sums over the 32
-        // elements of a round are order-free, and every user uses the same order)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float a[2], c[2], sn[2];
-          expansion_pair<AMP>(x, 0.5f + (float)j, a, c, sn);
-          if constexpr (TAIL) {
-            a[0] = e + 3 - j < it.e_end ? a[0] : 0.0f;
-            a[1] = e + 4 + j < it.e_end ? a[1] : 0.0f;
-          }
-          split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], 2 * j);
-        }
-      }
-    } else if constexpr (GEOM == XLMIMO_ULA) {
-      const double ey = fma((double)e, ds, -cy);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        double dy = u[b].uy - ey;
-#pragma unroll
-        for (int m = 0; m < 8; m += 2) {
-          float a[2], c[2], sn[2];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            double d = dy;
-            dy -= ds;
-            if constexpr (TAIL) d = e + m + q < it.e_end ? d : kFar;
-            channel_parts<GEOM, AMP>(d, 0.0, u[b].xp2, us[b], a[q], c[q], sn[q]);
-          }
-          split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], m);
-        }
-      }
-    } else {
-      int ea = e / arr.n_z;
-      int eb = e - ea * arr.n_z;
-      float a[NB][2], c[NB][2], sn[NB][2];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        double ey = fma((double)ea, ds, -cy);
-        const double ez = fma((double)eb, ds, -cz);
-        if constexpr (TAIL) ey = e + m < it.e_end ? ey : kFar;
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-          channel_parts<GEOM, AMP>(u[b].uy - ey, u[b].uz - ez, u[b].xp2, us[b], a[b][m & 1], c[b][m & 1],
-                                   sn[b][m & 1]);
-        if (m & 1) {
-#pragma unroll
-          for (int b = 0; b < NB; ++b) split_pair(a[b], c[b], sn[b], rh[b], rl[b], ih[b], il[b], m - 1);
-        }
-        if (++eb == arr.n_z) {
-          eb = 0;
-          ++ea;
-        }
-      }
-    }
+  // One MFMA set: the 32 elements of each wave held as hi / lo operands.
+  auto accumulate = [&](const halfx8 (&rh)[NB], const halfx8 (&rl)[NB], const halfx8 (&ih)[NB],
+                        const halfx8 (&il)[NB]) {
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
@@ -620,6 +573,98 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
       }
     }
   };
+
+  // One round: the lane's RUN elements start at element index e; elements at or
+  // past e_end (only in the last round, TAIL) contribute nothing.
+  auto round = [&](int e, auto tail_tag) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
+    if constexpr (EXPAND) {
+      // the run's centre, element e + 7.5, and the expansion of each user about it
+      double ey = 0.0, ez = 0.0;
+      if constexpr (GEOM == XLMIMO_ULA) {
+        ey = fma((double)e + 0.5 * (RUN - 1), ds, -cy);
+      } else {
+        const int ea = e / arr.n_z;
+        ey = fma((double)ea, ds, -cy);
+        ez = fma((double)(e - ea * arr.n_z) + 0.5 * (RUN - 1), ds, -cz);
+      }
+      Expansion<AMP> x[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if constexpr (GEOM == XLMIMO_ULA) {
+          x[b] = expand<AMP>(u[b].uy - ey, u[b].xp2, ds, us[b]);
+        } else {
+          const double dy = u[b].uy - ey;
+          x[b] = expand<AMP>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
+        }
+      }
+      // set s takes the pairs m' = +-(4 s + j + 1/2), j = 0..3: operand slots 2j, 2j + 1
+      // hold elements 7 - (4 s + j) and 8 + (4 s + j) of the run
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        halfx8 rh[NB], rl[NB], ih[NB], il[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int k = 4 * s + j;
+            float a[2], c[2], sn[2];
+            expansion_pair<AMP>(x[b], 0.5f + (float)k, a, c, sn);
+            if constexpr (TAIL) {
+              a[0] = e + 7 - k < it.e_end ? a[0] : 0.0f;
+              a[1] = e + 8 + k < it.e_end ? a[1] : 0.0f;
+            }
+            split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], 2 * j);
+          }
+        }
+        accumulate(rh, rl, ih, il);
+      }
+    } else if constexpr (GEOM == XLMIMO_ULA) {
+      halfx8 rh[NB], rl[NB], ih[NB], il[NB];
+      const double ey = fma((double)e, ds, -cy);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        double dy = u[b].uy - ey;
+#pragma unroll
+        for (int m = 0; m < 8; m += 2) {
+          float a[2], c[2], sn[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            double d = dy;
+            dy -= ds;
+            if constexpr (TAIL) d = e + m + q < it.e_end ? d : kFar;
+            channel_parts<GEOM, AMP>(d, 0.0, u[b].xp2, us[b], a[q], c[q], sn[q]);
+          }
+          split_pair(a, c, sn, rh[b], rl[b], ih[b], il[b], m);
+        }
+      }
+      accumulate(rh, rl, ih, il);
+    } else {
+      halfx8 rh[NB], rl[NB], ih[NB], il[NB];
+      int ea = e / arr.n_z;
+      int eb = e - ea * arr.n_z;
+      float a[NB][2], c[NB][2], sn[NB][2];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        double ey = fma((double)ea, ds, -cy);
+        const double ez = fma((double)eb, ds, -cz);
+        if constexpr (TAIL) ey = e + m < it.e_end ? ey : kFar;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          channel_parts<GEOM, AMP>(u[b].uy - ey, u[b].uz - ez, u[b].xp2, us[b], a[b][m & 1], c[b][m & 1],
+                                   sn[b][m & 1]);
+        if (m & 1) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) split_pair(a[b], c[b], sn[b], rh[b], rl[b], ih[b], il[b], m - 1);
+        }
+        if (++eb == arr.n_z) {
+          eb = 0;
+          ++ea;
+        }
+      }
+      accumulate(rh, rl, ih, il);
+    }
+  };
   auto flush = [&]() {
 #pragma unroll
     for (int i = 0; i < NRE; ++i) {
@@ -636,17 +681,20 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
   };
 
   const int e0 = it.e_begin + sub;
-  for (int r0 = 0; r0 < n_rounds; r0 += kSplitFlush) {
-    const int r1 = min(r0 + kSplitFlush, n_full);
-    for (int r = r0; r < r1; ++r) round(e0 + kSplitRound * r, std::false_type{});
-    if (r0 + kSplitFlush >= n_rounds && n_rounds > n_full) round(e0 + kSplitRound * n_full, std::true_type{});
+  for (int r0 = 0; r0 < n_full; r0 += FLUSH) {
+    const int r1 = min(r0 + FLUSH, n_full);
+    for (int r = r0; r < r1; ++r) round(e0 + ROUND * r, std::false_type{});
+    flush();
+  }
+  if (n_rounds > n_full) {   // the partial last round, carried on its own
+    round(e0 + ROUND * n_full, std::true_type{});
     flush();
   }
   store_partial<NV>(carry, s_red, part_out);
 }
 
 template <int NBMAX, typename T, int GEOM, int AMP, bool SPLIT>
-__global__ __launch_bounds__(kGramThreads) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
+__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SPLIT && NBMAX <= 2 ? 4 / NBMAX : 1))) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
                                                                const double* __restrict__ pos,
                                                                const ItemK* __restrict__ items, int n_items,
                                                                int* __restrict__ counter,
