@@ -793,6 +793,8 @@ struct xlmimo_mlp {
   int64_t n_params = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
   __bf16* wbf = nullptr;
+  __bf16* wbf_t = nullptr;    // per layer, the weights transposed ([in][out] BF16; input gradients)
+  xl::SplitLayers dims{};     // layer table (start = weight offset, in_dim) for the per-parameter kernels
   int64_t* d_offs = nullptr;  // per layer: weight offset, bias offset (fused inference)
   int64_t t = 0;
   DevBuf act, partial, split, loss_scratch;
@@ -813,6 +815,7 @@ constexpr int kOut = 7;
 struct Acts {
   std::vector<__bf16*> x;   // x[l] = input of layer l for l >= 1
   std::vector<float*> z;    // z[l] = pre-activation of hidden layer l
+  std::vector<__bf16*> dz;  // dz[l] = gradient at the pre-activation of hidden layer l (training)
   float* out = nullptr;
   __bf16 *da = nullptr, *db = nullptr, *dout = nullptr;
 };
@@ -823,7 +826,8 @@ int mlp_acts(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, bool train, Acts& a, hipSt
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t xb = al(sizeof(__bf16) * n * H), zb = al(sizeof(float) * n * H);
   const size_t ob = al(sizeof(float) * n * kOut), dob = al(sizeof(__bf16) * n * kDoutPitch);
-  bytes = (train ? (L - 1) * (xb + zb) + 2 * xb + dob : 2 * xb) + ob;
+  const int n_dz = std::max(2, L - 1);
+  bytes = (train ? (L - 1) * (xb + zb) + n_dz * xb + dob : 2 * xb) + ob;
   int rc = ensure(c, M->act, bytes, s);
   if (rc) return rc;
   char* p = (char*)M->act.p;
@@ -832,8 +836,10 @@ int mlp_acts(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, bool train, Acts& a, hipSt
   if (train) {
     for (int l = 1; l < L; ++l) { a.x[l] = (__bf16*)p; p += xb; }
     for (int l = 0; l < L - 1; ++l) { a.z[l] = (float*)p; p += zb; }
-    a.da = (__bf16*)p; p += xb;
-    a.db = (__bf16*)p; p += xb;
+    a.dz.assign(n_dz, nullptr);
+    for (int l = 0; l < n_dz; ++l) { a.dz[l] = (__bf16*)p; p += xb; }
+    a.da = a.dz[0];
+    a.db = a.dz[1];
     a.dout = (__bf16*)p; p += dob;
   } else {
     // inference ping-pongs two activation buffers
@@ -896,11 +902,91 @@ int mlp_infer(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, float
   return XLMIMO_OK;
 }
 
-int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, hipStream_t s) {
-  int rc = ensure(c, M->split,
-                  sizeof(float) * (size_t)kGradSplits * M->width * (std::max(M->width, XLMIMO_MLP_IN) + 1), s);
+// The weight-gradient GEMMs' split-K slices of all layers stay unreduced (to be summed by the
+// Adam kernel, or by one reduction over all layers) when they fit this budget; larger networks
+// reduce each layer's slices right after its GEMM.
+constexpr size_t kKeepSliceBytes = size_t(256) << 20;
+
+int grad_splits(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kGradSplits, n / kGradSplitK)); }
+
+bool keep_slices(const xlmimo_mlp* M, int64_t n) {
+  size_t all = 0;
+  for (int l = 0; l < M->n_layers; ++l) all += (size_t)grad_splits(n) * M->out_dim[l] * (M->in_dim[l] + 1);
+  return all * sizeof(float) <= kKeepSliceBytes;
+}
+
+// Backward pass. With keep, the weight gradients are left as split-K slices described by *L
+// (L->n = 0 otherwise: M->grad holds the reduced gradients).
+int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, bool keep,
+                 SplitLayers* L, hipStream_t s) {
+  const int splits_req = grad_splits(n);
+  size_t need = 0;
+  for (int l = 0; l < M->n_layers; ++l) {
+    const size_t nl = (size_t)splits_req * M->out_dim[l] * (M->in_dim[l] + 1);
+    need = keep ? need + nl : std::max(need, nl);
+  }
+  int rc = ensure(c, M->split, sizeof(float) * need, s);
   if (rc) return rc;
   float* part = (float*)M->split.p;
+  L->n = keep ? M->n_layers : 0;
+  if (keep) {
+    // the input gradients layer by layer (each hidden layer's own buffer), then every layer's
+    // weight and bias gradients in one grouped launch
+    const int NL = M->n_layers;
+    std::vector<const __bf16*> dzs(NL);
+    std::vector<int64_t> ldzs(NL);
+    dzs[NL - 1] = a.dout;
+    ldzs[NL - 1] = kDoutPitch;
+    for (int l = NL - 1; l >= 1; --l) {
+      GemmArgs gx{};
+      gx.M = (int)n;
+      gx.N = M->in_dim[l];
+      gx.K = M->out_dim[l];
+      gx.A = dzs[l];
+      gx.a_m = ldzs[l];
+      gx.a_k = 1;
+      gx.B = M->wbf_t + M->w_off[l];   // B(k = output, n = input) with k contiguous
+      gx.b_k = 1;
+      gx.b_n = M->out_dim[l];
+      gx.Z = a.z[l - 1];
+      gx.out_bf = a.dz[l - 1];
+      gx.ldo = M->in_dim[l];
+      HIP_TRY(c, launch_gemm(EPI_BWD_DX, gx, s));
+      dzs[l - 1] = a.dz[l - 1];
+      ldzs[l - 1] = M->in_dim[l];
+    }
+    std::vector<GemmArgs> gs(NL);
+    std::vector<int> req(NL, splits_req), slices(NL, 0);
+    std::vector<float*> parts(NL);
+    int64_t off = 0;
+    for (int l = 0; l < NL; ++l) {
+      const int in = M->in_dim[l], o = M->out_dim[l];
+      GemmArgs& gw = gs[l];
+      gw = GemmArgs{};
+      gw.M = o;
+      gw.N = in;
+      gw.K = (int)n;
+      gw.A = dzs[l];
+      gw.a_m = 1;
+      gw.a_k = ldzs[l];
+      gw.B = l == 0 ? feat : a.x[l];
+      gw.b_k = l == 0 ? kFeatPitch : M->width;
+      gw.b_n = 1;
+      gw.ldo = in;
+      gw.row_sums = 1;   // the bias gradient sum_pairs dZ follows W's gradient (b_off = w_off + o in)
+      parts[l] = part + off;
+      L->part_off[l] = off;
+      off += (int64_t)splits_req * o * (in + 1);
+    }
+    HIP_TRY(c, launch_gemm_grouped_partials(gs.data(), req.data(), parts.data(), NL, slices.data(), s));
+    for (int l = 0; l < NL; ++l) {
+      L->splits[l] = slices[l];
+      L->in_dim[l] = M->in_dim[l];
+      L->start[l] = M->w_off[l];
+    }
+    L->start[NL] = M->n_params;
+    return XLMIMO_OK;
+  }
   const __bf16* dz = a.dout;
   int64_t ldz = kDoutPitch;
   __bf16* bufs[2] = {a.da, a.db};
@@ -921,8 +1007,7 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
     gw.b_n = 1;
     gw.ldo = in;
     gw.row_sums = 1;   // the bias gradient sum_pairs dZ follows W's gradient (b_off = w_off + o in)
-    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(kGradSplits, n / kGradSplitK));
-    HIP_TRY(c, launch_gemm_splitk(gw, splits, part, M->grad + M->w_off[l], s));
+    HIP_TRY(c, launch_gemm_splitk(gw, splits_req, part, M->grad + M->w_off[l], s));
     if (l > 0) {
       GemmArgs gx{};
       gx.M = (int)n;
@@ -946,15 +1031,45 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
   return XLMIMO_OK;
 }
 
+// Loss and gradients of one batch.  With fused != nullptr and slices that fit, the gradients
+// and the loss are left for launch_adam_layers (*fused describes the slices; the loss head's
+// block partials are in M->partial); otherwise (fused->n = 0) M->grad and *loss_out are final.
 int mlp_loss_grad_impl(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const float* aux,
-                       const float* target, double* loss_out, hipStream_t s) {
+                       const float* target, double* loss_out, hipStream_t s, SplitLayers* fused = nullptr) {
   Acts a;
   int rc = mlp_acts(c, M, n, true, a, s);
   if (rc) return rc;
   if ((rc = ensure(c, M->partial, sizeof(double) * kMlpHeadBlocks, s))) return rc;
   if ((rc = mlp_forward(c, M, n, feat, a, true, s))) return rc;
-  HIP_TRY(c, launch_mlp_head(n, a.out, aux, target, a.dout, (double*)M->partial.p, loss_out, s));
-  return mlp_backward(c, M, n, feat, a, s);
+  const bool keep = keep_slices(M, n);
+  const bool fuse = fused != nullptr && keep;
+  HIP_TRY(c, launch_mlp_head(n, a.out, aux, target, a.dout, (double*)M->partial.p, fuse ? nullptr : loss_out, s));
+  SplitLayers L{};
+  if ((rc = mlp_backward(c, M, n, feat, a, keep, &L, s))) return rc;
+  if (keep && !fuse) HIP_TRY(c, launch_reduce_layers(L, (const float*)M->split.p, M->grad, s));
+  if (fused != nullptr) {
+    *fused = L;
+    if (!fuse) fused->n = 0;
+  }
+  return XLMIMO_OK;
+}
+
+// One Adam step after mlp_loss_grad_impl(..., &L): fused with the gradient reduction and the
+// loss sum when L.n > 0.
+int mlp_adam(xlmimo_ctx* c, xlmimo_mlp* M, const SplitLayers& L, int64_t n, float lr, double* loss_out,
+             hipStream_t s) {
+  M->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
+  if (L.n > 0) {
+    HIP_TRY(c, launch_adam_layers(L, (const float*)M->split.p, nullptr, M->n_params, M->master, M->m, M->v, lr, b1, b2,
+                                  1e-8f, bc1, bc2, M->wbf, M->wbf_t, (const double*)M->partial.p, kMlpHeadBlocks, n,
+                                  loss_out, s));
+  } else {
+    HIP_TRY(c, launch_adam_layers(M->dims, nullptr, M->grad, M->n_params, M->master, M->m, M->v, lr, b1, b2, 1e-8f,
+                                  bc1, bc2, M->wbf, M->wbf_t, nullptr, 0, n, nullptr, s));
+  }
+  return XLMIMO_OK;
 }
 
 int check_mlp_args(xlmimo_ctx* c, const xlmimo_mlp* M, int64_t n, const void* feat, const void* aux) {
@@ -1078,12 +1193,21 @@ int xlmimo_mlp_create(xlmimo_ctx* c, int32_t width, int32_t depth, xlmimo_mlp** 
     off += o;
   }
   M->n_params = off;
+  M->dims.n = M->n_layers;
+  for (int l = 0; l < M->n_layers; ++l) {
+    M->dims.start[l] = M->w_off[l];
+    M->dims.in_dim[l] = M->in_dim[l];
+  }
+  M->dims.start[M->n_layers] = off;
   const size_t fb = sizeof(float) * off;
   if (hipMalloc(&M->master, fb) || hipMalloc(&M->m, fb) || hipMalloc(&M->v, fb) || hipMalloc(&M->grad, fb) ||
-      hipMalloc(&M->wbf, sizeof(__bf16) * off) || hipMemset(M->master, 0, fb) || hipMemset(M->m, 0, fb) ||
-      hipMemset(M->v, 0, fb) || hipMemset(M->grad, 0, fb) || hipMemset(M->wbf, 0, sizeof(__bf16) * off)) {
+      hipMalloc(&M->wbf, sizeof(__bf16) * off) || hipMalloc(&M->wbf_t, sizeof(__bf16) * off) ||
+      hipMemset(M->master, 0, fb) || hipMemset(M->m, 0, fb) || hipMemset(M->v, 0, fb) ||
+      hipMemset(M->grad, 0, fb) || hipMemset(M->wbf, 0, sizeof(__bf16) * off) ||
+      hipMemset(M->wbf_t, 0, sizeof(__bf16) * off)) {
     (void)hipGetLastError();
     (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
+    (void)hipFree(M->wbf_t);
     delete M;
     return set_err(c, XLMIMO_ENOMEM, "MLP parameter allocation failed");
   }
@@ -1096,7 +1220,7 @@ int xlmimo_mlp_create(xlmimo_ctx* c, int32_t width, int32_t depth, xlmimo_mlp** 
       hipMemcpy(M->d_offs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice)) {
     (void)hipGetLastError();
     (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
-    (void)hipFree(M->d_offs);
+    (void)hipFree(M->wbf_t); (void)hipFree(M->d_offs);
     delete M;
     return set_err(c, XLMIMO_ENOMEM, "MLP offset table allocation failed");
   }
@@ -1113,6 +1237,7 @@ int xlmimo_mlp_destroy(xlmimo_mlp* M) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(M->master); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad); (void)hipFree(M->wbf);
+  (void)hipFree(M->wbf_t);
   if (M->act.p) (void)hipFree(M->act.p);
   if (M->partial.p) (void)hipFree(M->partial.p);
   if (M->split.p) (void)hipFree(M->split.p);
@@ -1137,6 +1262,7 @@ int xlmimo_mlp_set_params(xlmimo_mlp* M, const float* host) {
   HIP_TRY(c, hipMemset(M->m, 0, fb));
   HIP_TRY(c, hipMemset(M->v, 0, fb));
   HIP_TRY(c, launch_to_bf16(M->n_params, M->master, M->wbf, nullptr));
+  HIP_TRY(c, launch_weights_t(M->dims, M->master, M->wbf_t, nullptr));
   HIP_TRY(c, hipDeviceSynchronize());
   M->t = 0;
   return XLMIMO_OK;
@@ -1225,12 +1351,9 @@ int xlmimo_mlp_train_step(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* f
   if (!(lr >= 0.0f) || !std::isfinite(lr)) return set_err(c, XLMIMO_EINVAL, "bad learning rate");
   if ((rc = set_device(c))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = mlp_loss_grad_impl(c, M, n, (const __bf16*)features, aux, target, loss_out, s))) return rc;
-  M->t += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
-  HIP_TRY(c, launch_adam(M->n_params, M->master, M->m, M->v, M->grad, lr, b1, b2, 1e-8f, bc1, bc2, M->wbf, s));
-  return XLMIMO_OK;
+  SplitLayers L{};
+  if ((rc = mlp_loss_grad_impl(c, M, n, (const __bf16*)features, aux, target, loss_out, s, &L))) return rc;
+  return mlp_adam(c, M, L, n, lr, loss_out, s);
 }
 
 int xlmimo_mlp_train(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* features, const float* aux,
@@ -1251,15 +1374,14 @@ int xlmimo_mlp_train(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const void* featur
   if (!loss_out && (rc = ensure(c, M->loss_scratch, sizeof(double), s))) return rc;
   const int64_t n_batches = n / batch;
   const __bf16* feat = (const __bf16*)features;
-  const float b1 = 0.9f, b2 = 0.999f;
   for (int64_t i = 0; i < n_steps; ++i) {
     const int64_t off = (i % n_batches) * batch;
     double* lo = loss_out ? loss_out + i : (double*)M->loss_scratch.p;
-    if ((rc = mlp_loss_grad_impl(c, M, batch, feat + off * kFeatPitch, aux + off * kAuxPitch, target + off * 2, lo, s)))
+    SplitLayers L{};
+    if ((rc = mlp_loss_grad_impl(c, M, batch, feat + off * kFeatPitch, aux + off * kAuxPitch, target + off * 2, lo, s,
+                                 &L)))
       return rc;
-    M->t += 1;
-    const float bc1 = 1.0f - std::pow(b1, (float)M->t), bc2 = 1.0f - std::pow(b2, (float)M->t);
-    HIP_TRY(c, launch_adam(M->n_params, M->master, M->m, M->v, M->grad, lr[i], b1, b2, 1e-8f, bc1, bc2, M->wbf, s));
+    if ((rc = mlp_adam(c, M, L, batch, lr[i], lo, s))) return rc;
   }
   return XLMIMO_OK;
 }

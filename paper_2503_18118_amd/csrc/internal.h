@@ -146,13 +146,49 @@ hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_inputs(const ArrayK& arr, const DropK* d_drops, int n_drops, const double* d_pos,
                               const double* d_cf, const double* d_exact, __bf16* feat, float* aux, float* target,
                               int32_t* pmap, hipStream_t s);
+// loss == nullptr: the per-block partial sums are left for launch_adam_layers.
 hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
                            double* partial, double* loss, hipStream_t s);
 // Split-K GEMM into out[M x ldo] (fixed-order sum over the slices); with row_sums, also
 // out[M * ldo + m] = sum_k A(m, k) (the bias gradient of a weight-gradient GEMM).
 hipError_t launch_gemm_splitk(const GemmArgs& g, int splits, float* partial, float* out, hipStream_t s);
-hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s);
+// Split-K weight-gradient GEMM that leaves its slices unreduced: partial[z][M * ldo (+ M)];
+// returns the number of slices actually used through *slices.
+hipError_t launch_gemm_splitk_partials(const GemmArgs& g, int splits, float* partial, int* slices, hipStream_t s);
+// The unreduced slices of every layer's weight and bias gradients: layer l owns parameters
+// [start[l], start[l + 1]) and its slices sit at part + part_off[l] + z (start[l + 1] - start[l]).
+constexpr int kMaxLayers = 17;
+struct SplitLayers {
+  int32_t n;
+  int32_t splits[kMaxLayers];
+  int32_t in_dim[kMaxLayers];   // layer l: in_dim[l] inputs, (start[l + 1] - start[l]) / (in_dim[l] + 1) outputs
+  int64_t start[kMaxLayers + 1];
+  int64_t part_off[kMaxLayers];
+};
+// Split-K GEMMs (EPI_STORE_F32, unreduced slices into partials[p]) of up to kMaxLayers
+// problems in one launch; all problems must share the operands' fetch modes (else
+// hipErrorInvalidValue).  slices[p] returns the slices used by problem p.
+struct GemmGroup {
+  int32_t n;
+  int32_t first[kMaxLayers + 1];
+  int32_t gx[kMaxLayers], gy[kMaxLayers];
+  GemmArgs g[kMaxLayers];
+};
+hipError_t launch_gemm_grouped_partials(const GemmArgs* gs, const int* splits, float* const* partials, int n,
+                                       int* slices, hipStream_t s);
+// grad[i] = sum over slices (in slice order) of parameter i's partials.
+hipError_t launch_reduce_layers(const SplitLayers& L, const float* part, float* grad, hipStream_t s);
+// Adam on every parameter, with the gradient summed from the slices as launch_reduce_layers does
+// (bitwise the same gradient), or read from grad when part == nullptr; the BF16 copy wbf and
+// its per-layer transpose wbf_t (layer l's weights as [in][out] at start[l]) follow.  With
+// loss != nullptr, block 0 also sums the loss head's per-block partials into
+// *loss = sum / n_pairs (the order of launch_mlp_head's sum).
+hipError_t launch_adam_layers(const SplitLayers& L, const float* part, const float* grad, int64_t n, float* w,
+                              float* m, float* v, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                              __bf16* wbf, __bf16* wbf_t, const double* loss_part, int n_loss_part, int64_t n_pairs,
+                              double* loss, hipStream_t s);
+// wbf_t = per-layer transpose of the weights in w (BF16), layers as in L (start, in_dim).
+hipError_t launch_weights_t(const SplitLayers& L, const float* w, __bf16* wbf_t, hipStream_t s);
 hipError_t launch_to_bf16(int64_t n, const float* w, __bf16* wbf, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_or_flags(int32_t* status, const int32_t* flags, int64_t n, int32_t bit, hipStream_t s);

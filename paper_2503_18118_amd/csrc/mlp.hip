@@ -127,11 +127,78 @@ __device__ __forceinline__ void tile_store(__bf16* s, const bf16x8& v, int tid) 
   }
 }
 
+// Epilogue of a (64 MT) x 64 tile.  The MFMAs take B's fragment as their first operand, so a
+// 16x16 block comes out transposed: lane l, register r -> row l % 16, column 4 (l / 16) + r,
+// i.e. each lane holds four consecutive columns of one row and writes them as one vector
+// (16 bytes of FP32, 8 of BF16) wherever they are in range and aligned.
+__device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+__device__ __forceinline__ bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
+
+template <int EPI, int MT>
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, const floatx4 (&acc)[2 * MT][2], int m0, int n0, int wm,
+                                           int wn, int lane, int bz) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int64_t slice = g.row_sums ? (int64_t)g.M * g.ldo + g.M : (int64_t)g.M * g.ldo;
+#pragma unroll
+  for (int i = 0; i < 2 * MT; ++i) {
+    const int row = m0 + wm + i * 16 + (lane & 15);
+    if (row >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + 4 * (lane >> 4);
+      const int64_t o = (int64_t)row * g.ldo + col;
+      const floatx4 v = acc[i][j];
+      const bool whole = col + 4 <= g.N;
+      if constexpr (EPI == EPI_FWD_HIDDEN) {
+        if (whole && aligned16(&g.bias[col]) && aligned8(&g.out_bf[o]) && (!g.Z || aligned16(&g.Z[o]))) {
+          const floatx4 b = *reinterpret_cast<const floatx4*>(&g.bias[col]);
+          const floatx4 z = v + b;
+          if (g.Z) *reinterpret_cast<floatx4*>(&g.Z[o]) = z;
+          const bf16x4 y = {(__bf16)gelu(z[0]), (__bf16)gelu(z[1]), (__bf16)gelu(z[2]), (__bf16)gelu(z[3])};
+          *reinterpret_cast<bf16x4*>(&g.out_bf[o]) = y;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (col + r >= g.N) continue;
+            const float z = v[r] + g.bias[col + r];
+            if (g.Z) g.Z[o + r] = z;
+            g.out_bf[o + r] = (__bf16)gelu(z);
+          }
+        }
+      } else if constexpr (EPI == EPI_FWD_OUT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (col + r < g.N) g.out_f[o + r] = v[r] + g.bias[col + r];
+      } else if constexpr (EPI == EPI_BWD_DX) {
+        if (whole && aligned16(&g.Z[o]) && aligned8(&g.out_bf[o])) {
+          const floatx4 z = *reinterpret_cast<const floatx4*>(&g.Z[o]);
+          const bf16x4 d = {(__bf16)(v[0] * gelu_grad(z[0])), (__bf16)(v[1] * gelu_grad(z[1])),
+                            (__bf16)(v[2] * gelu_grad(z[2])), (__bf16)(v[3] * gelu_grad(z[3]))};
+          *reinterpret_cast<bf16x4*>(&g.out_bf[o]) = d;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (col + r < g.N) g.out_bf[o + r] = (__bf16)(v[r] * gelu_grad(g.Z[o + r]));
+        }
+      } else {
+        float* dst = g.out_f + (int64_t)bz * slice + o;
+        if (whole && aligned16(dst)) {
+          *reinterpret_cast<floatx4*>(dst) = v;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (col + r < g.N) dst[r] = v[r];
+        }
+      }
+    }
+  }
+}
+
 // Double-buffered main loop: the next k-step's tiles are fetched into registers while the
 // matrix cores work on the current one from LDS; one barrier per k-step.  A workgroup
 // computes a (64 MT) x 64 tile; each of its 4 waves a (32 MT) x 32 block of 16x16 MFMA tiles.
 template <int EPI, int AM, int BM, int MT>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+__device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, int bz) {
   constexpr int TMM = TM * MT;
   __shared__ __attribute__((aligned(16))) __bf16 sA[2][TMM * LDS_K];
   __shared__ __attribute__((aligned(16))) __bf16 sB[2][TN * LDS_K];
@@ -139,7 +206,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   static_assert(!RS || MT == 1, "row sums with single row tiles");
   __shared__ float s_rs[RS ? 32 * TM : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * TMM, n0 = blockIdx.x * TN;
+  const int m0 = by * TMM, n0 = bx * TN;
   const int wm = (wave >> 1) * 32 * MT, wn = (wave & 1) * 32;
   floatx4 acc[2 * MT][2];
 #pragma unroll
@@ -148,11 +215,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   int kb = 0, ke = g.K;
   if (EPI == EPI_STORE_F32 && g.k_chunk > 0) {
-    kb = blockIdx.z * g.k_chunk;
+    kb = bz * g.k_chunk;
     ke = min(g.K, kb + g.k_chunk);
   }
   // row sums of A over this slice (bias gradients), accumulated from the fetched tiles
-  const bool row_sums = RS && g.row_sums && blockIdx.x == 0;
+  const bool row_sums = RS && g.row_sums && bx == 0;
   float rs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
   bf16x8 va[MT], vb;
@@ -188,7 +255,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int i = 0; i < 2 * MT; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
     if (more) {
 #pragma unroll
       for (int t = 0; t < MT; ++t) tile_store<AM>(sA[buf ^ 1] + TM * t * LDS_K, va[t], tid);
@@ -212,37 +279,82 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       if (tid < TM && m0 + tid < g.M) {
         float t = 0.f;
         for (int j = 0; j < 32; ++j) t += s_rs[j * TM + tid];
-        g.out_f[(int64_t)blockIdx.z * ((int64_t)g.M * g.ldo + g.M) + (int64_t)g.M * g.ldo + m0 + tid] = t;
+        g.out_f[(int64_t)bz * ((int64_t)g.M * g.ldo + g.M) + (int64_t)g.M * g.ldo + m0 + tid] = t;
       }
     }
   }
-  // C layout of 16x16 blocks: lane l, register r -> row 4 (l / 16) + r, column l % 16
+  gemm_store<EPI, MT>(g, acc, m0, n0, wm, wn, lane, bz);
+}
+
+template <int EPI, int AM, int BM, int MT>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  gemm_block<EPI, AM, BM, MT>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Whole-K variant for K <= kKallMax (the layers' own GEMMs: forward and input gradients):
+// every k-step's A and B tiles are fetched at once (one memory latency per tile instead of
+// one per k-step, which dominates a 256-deep contraction), staged in LDS with k contiguous,
+// then contracted.  K-contiguous operands only (LOAD_K), 16-byte aligned rows.
+constexpr int kKallMax = 256;
+constexpr int KALL_P = kKallMax + 8;   // LDS row pitch (bf16)
+constexpr int64_t kKallMaxBlocks = 512;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_kall(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 sA[TM * KALL_P];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[TN * KALL_P];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int K = g.K;
+  constexpr int NKS = kKallMax / TK;
+  bf16x8 va[NKS], vb[NKS];
 #pragma unroll
-  for (int i = 0; i < 2 * MT; ++i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn + j * 16 + (lane & 15);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        if (row >= g.M || col >= g.N) continue;
-        const int64_t o = (int64_t)row * g.ldo + col;
-        const float v = acc[i][j][r];
-        if constexpr (EPI == EPI_FWD_HIDDEN) {
-          const float z = v + g.bias[col];
-          if (g.Z) g.Z[o] = z;
-          g.out_bf[o] = (__bf16)gelu(z);
-        } else if constexpr (EPI == EPI_FWD_OUT) {
-          g.out_f[o] = v + g.bias[col];
-        } else if constexpr (EPI == EPI_BWD_DX) {
-          g.out_bf[o] = (__bf16)(v * gelu_grad(g.Z[o]));
-        } else {
-          const int64_t slice = g.row_sums ? (int64_t)g.M * g.ldo + g.M : (int64_t)g.M * g.ldo;
-          g.out_f[(int64_t)blockIdx.z * slice + o] = v;
-        }
-      }
+  for (int ks = 0; ks < NKS; ++ks) {
+    if (ks * TK < K) {
+      va[ks] = tile_fetch<LOAD_K>(g.A, g.a_m, g.a_k, g.M, m0, ks * TK, K, tid);
+      vb[ks] = tile_fetch<LOAD_K>(g.B, g.b_n, g.b_k, g.N, n0, ks * TK, K, tid);
     }
   }
+  const int r = tid >> 2, kc = 8 * (tid & 3);
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
+    if (ks * TK < K) {
+      *reinterpret_cast<bf16x8*>(&sA[r * KALL_P + ks * TK + kc]) = va[ks];
+      *reinterpret_cast<bf16x8*>(&sB[r * KALL_P + ks * TK + kc]) = vb[ks];
+    }
+  }
+  __syncthreads();
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int kk = 8 * (lane >> 4);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * KALL_P + k0 + kk]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * KALL_P + k0 + kk]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+  }
+  gemm_store<EPI, 1>(g, acc, m0, n0, wm, wn, lane, 0);
+}
+
+// Several split-K weight-gradient GEMMs in one launch: problem p owns the flat block range
+// [first[p], first[p + 1]), laid out as its own (gx, gy, slices) grid.
+template <int AM, int BM>
+__global__ __launch_bounds__(256) void k_gemm_grouped(GemmGroup G) {
+  const int b = blockIdx.x;
+  int p = 0;
+  while (p + 1 < G.n && b >= G.first[p + 1]) ++p;
+  const int local = b - G.first[p];
+  const int gx = G.gx[p], gy = G.gy[p];
+  gemm_block<EPI_STORE_F32, AM, BM, 1>(G.g[p], local % gx, (local / gx) % gy, local / (gx * gy));
 }
 
 // out[i] = sum over splits of partial[split][i], in split order.
@@ -284,7 +396,7 @@ static void launch_modes(const GemmArgs& g, dim3 grid, hipStream_t s) {
   launch_modes_mt<EPI, 1>(g, grid, s);
 }
 
-hipError_t launch_gemm_splitk(const GemmArgs& g0, int splits, float* partial, float* out, hipStream_t s) {
+hipError_t launch_gemm_splitk_partials(const GemmArgs& g0, int splits, float* partial, int* slices, hipStream_t s) {
   GemmArgs g = g0;
   g.k_chunk = ((g.K + splits - 1) / splits + TK - 1) / TK * TK;
   splits = (g.K + g.k_chunk - 1) / g.k_chunk;
@@ -292,13 +404,87 @@ hipError_t launch_gemm_splitk(const GemmArgs& g0, int splits, float* partial, fl
   dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
   if (g.row_sums && load_mode(g.A, g.a_m, g.a_k) != LOAD_R) return hipErrorInvalidValue;
   launch_modes<EPI_STORE_F32>(g, grid, s);
+  *slices = splits;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_grouped_partials(const GemmArgs* gs, const int* splits, float* const* partials, int n,
+                                       int* slices, hipStream_t s) {
+  if (n < 1 || n > kMaxLayers) return hipErrorInvalidValue;
+  GemmGroup G{};
+  G.n = n;
+  int total = 0;
+  int am = -1, bm = -1;
+  for (int p = 0; p < n; ++p) {
+    GemmArgs g = gs[p];
+    g.k_chunk = ((g.K + splits[p] - 1) / splits[p] + TK - 1) / TK * TK;
+    slices[p] = (g.K + g.k_chunk - 1) / g.k_chunk;
+    g.out_f = partials[p];
+    const int a = load_mode(g.A, g.a_m, g.a_k), b = load_mode(g.B, g.b_n, g.b_k);
+    if ((am >= 0 && a != am) || (bm >= 0 && b != bm)) return hipErrorInvalidValue;   // one fetch mode per launch
+    am = a;
+    bm = b;
+    if (g.row_sums && a != LOAD_R) return hipErrorInvalidValue;
+    G.g[p] = g;
+    G.gx[p] = (g.N + TN - 1) / TN;
+    G.gy[p] = (g.M + TM - 1) / TM;
+    G.first[p] = total;
+    total += G.gx[p] * G.gy[p] * slices[p];
+  }
+  G.first[n] = total;
+  if (total == 0) return hipSuccess;
+  if (am == LOAD_R && bm == LOAD_R) k_gemm_grouped<LOAD_R, LOAD_R><<<total, 256, 0, s>>>(G);
+  else if (am == LOAD_R && bm == LOAD_K) k_gemm_grouped<LOAD_R, LOAD_K><<<total, 256, 0, s>>>(G);
+  else if (am == LOAD_R) k_gemm_grouped<LOAD_R, LOAD_S><<<total, 256, 0, s>>>(G);
+  else k_gemm_grouped<LOAD_S, LOAD_S><<<total, 256, 0, s>>>(G);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_splitk(const GemmArgs& g, int splits, float* partial, float* out, hipStream_t s) {
+  int slices = 0;
+  hipError_t e = launch_gemm_splitk_partials(g, splits, partial, &slices, s);
+  if (e != hipSuccess) return e;
   const int64_t n = (int64_t)g.M * g.ldo + (g.row_sums ? g.M : 0);
-  k_reduce_splits<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, splits, n, out);
+  k_reduce_splits<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, slices, n, out);
+  return hipGetLastError();
+}
+
+// Gradient of parameter i from its layer's unreduced slices, summed in slice order
+// (the order of k_reduce_splits).
+__device__ __forceinline__ float layer_grad(const SplitLayers& L, const float* __restrict__ part, int64_t i) {
+  int l = 0;
+  while (l + 1 < L.n && i >= L.start[l + 1]) ++l;
+  const int64_t nl = L.start[l + 1] - L.start[l];
+  const float* p = part + L.part_off[l] + (i - L.start[l]);
+  float acc = 0.0f;
+  for (int z = 0; z < L.splits[l]; ++z) acc += p[(int64_t)z * nl];
+  return acc;
+}
+
+__global__ void k_reduce_layers(SplitLayers L, const float* __restrict__ part, float* __restrict__ grad) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < L.start[L.n]) grad[i] = layer_grad(L, part, i);
+}
+
+hipError_t launch_reduce_layers(const SplitLayers& L, const float* part, float* grad, hipStream_t s) {
+  const int64_t n = L.start[L.n];
+  if (n > 0) k_reduce_layers<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L, part, grad);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm(int epi, const GemmArgs& g, hipStream_t s) {
   dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+  // whole-K staging while the grid fits the chip in one round (two 68 KB workgroups per CU);
+  // larger grids hide the fetch latency better with more, smaller workgroups per CU
+  if (epi != EPI_STORE_F32 && g.K <= kKallMax && (int64_t)grid.x * grid.y <= kKallMaxBlocks &&
+      load_mode(g.A, g.a_m, g.a_k) == LOAD_K && load_mode(g.B, g.b_n, g.b_k) == LOAD_K) {
+    switch (epi) {
+      case EPI_FWD_HIDDEN: k_gemm_kall<EPI_FWD_HIDDEN><<<grid, 256, 0, s>>>(g); break;
+      case EPI_FWD_OUT: k_gemm_kall<EPI_FWD_OUT><<<grid, 256, 0, s>>>(g); break;
+      default: k_gemm_kall<EPI_BWD_DX><<<grid, 256, 0, s>>>(g); break;
+    }
+    return hipGetLastError();
+  }
   switch (epi) {
     case EPI_FWD_HIDDEN: launch_modes<EPI_FWD_HIDDEN>(g, grid, s); break;
     case EPI_FWD_OUT: launch_modes<EPI_FWD_OUT>(g, grid, s); break;
@@ -487,16 +673,51 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 hipError_t launch_mlp_head(int64_t n, const float* out, const float* aux, const float* target, __bf16* dout,
                            double* partial, double* loss, hipStream_t s) {
   k_mlp_head<<<kMlpHeadBlocks, 256, 0, s>>>(n, out, aux, target, dout, partial);
-  k_sum_partials<<<1, 256, 0, s>>>(partial, kMlpHeadBlocks, n, loss);
+  if (loss != nullptr) k_sum_partials<<<1, 256, 0, s>>>(partial, kMlpHeadBlocks, n, loss);
   return hipGetLastError();
 }
 
-__global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float bc1, float bc2,
-                       __bf16* __restrict__ wbf) {
+// Layer of parameter i and, for a weight, its index in the layer's transposed [in][out] copy
+// (-1 for a bias).
+__device__ __forceinline__ int layer_of(const SplitLayers& L, int64_t i) {
+  int l = 0;
+  while (l + 1 < L.n && i >= L.start[l + 1]) ++l;
+  return l;
+}
+__device__ __forceinline__ int64_t transposed_index(const SplitLayers& L, int l, int64_t i) {
+  const int64_t j = i - L.start[l];
+  const int in = L.in_dim[l];
+  const int64_t o = (L.start[l + 1] - L.start[l]) / (in + 1);
+  if (j >= o * in) return -1;
+  const int64_t oi = j / in, ii = j - oi * in;
+  return L.start[l] + ii * o + oi;
+}
+
+// Adam with the gradient summed from the layers' split-K slices (the reduction and the
+// update in one pass over the parameters), or taken from grad; block 0 also finishes the
+// loss (k_sum_partials).
+__global__ __launch_bounds__(256) void k_adam_layers(SplitLayers L, const float* __restrict__ part,
+                                                     const float* __restrict__ grad, int64_t n, float* __restrict__ w,
+                                                     float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                     float b2, float eps, float bc1, float bc2,
+                                                     __bf16* __restrict__ wbf, __bf16* __restrict__ wbf_t,
+                                                     const double* __restrict__ loss_part, int n_loss_part,
+                                                     int64_t n_pairs, double* __restrict__ loss) {
+  if (blockIdx.x == 0 && loss != nullptr) {
+    __shared__ double s_sum[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_loss_part; i += 256) acc += loss_part[i];
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = s_sum[0] / (double)n_pairs;
+  }
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
+  const float gi = part != nullptr ? layer_grad(L, part, i) : grad[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
@@ -504,11 +725,30 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, 
   const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   w[i] = wi;
   wbf[i] = (__bf16)wi;
+  const int64_t t = transposed_index(L, layer_of(L, i), i);
+  if (t >= 0) wbf_t[t] = (__bf16)wi;
 }
 
-hipError_t launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2, __bf16* wbf, hipStream_t s) {
-  k_adam<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, w, m, v, g, lr, b1, b2, eps, bc1, bc2, wbf);
+hipError_t launch_adam_layers(const SplitLayers& L, const float* part, const float* grad, int64_t n, float* w,
+                              float* m, float* v, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                              __bf16* wbf, __bf16* wbf_t, const double* loss_part, int n_loss_part, int64_t n_pairs,
+                              double* loss, hipStream_t s) {
+  if (n > 0 || loss != nullptr)
+    k_adam_layers<<<(unsigned)std::max<int64_t>(1, (n + 255) / 256), 256, 0, s>>>(
+        L, part, grad, n, w, m, v, lr, b1, b2, eps, bc1, bc2, wbf, wbf_t, loss_part, n_loss_part, n_pairs, loss);
+  return hipGetLastError();
+}
+
+__global__ void k_weights_t(SplitLayers L, const float* __restrict__ w, __bf16* __restrict__ wbf_t) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= L.start[L.n]) return;
+  const int64_t t = transposed_index(L, layer_of(L, i), i);
+  if (t >= 0) wbf_t[t] = (__bf16)w[i];
+}
+
+hipError_t launch_weights_t(const SplitLayers& L, const float* w, __bf16* wbf_t, hipStream_t s) {
+  const int64_t n = L.start[L.n];
+  if (n > 0) k_weights_t<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L, w, wbf_t);
   return hipGetLastError();
 }
 
