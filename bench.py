@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--mlp-train-drops", type=int, default=83334)   # 120 pairs per drop: 1.0e7 training pairs
     ap.add_argument("--mlp-train-steps", type=int, default=12000)
     ap.add_argument("--mlp-lr", type=float, default=3e-3)
+    ap.add_argument("--mlp-batch", type=int, default=16384)
     ap.add_argument("--mlp-calibration-drops", type=int, default=4000)
     ap.add_argument("--mlp-gate-target", type=float, default=5e-4,
                     help="worst sum-rate error allowed on the calibration drops the network keeps")
@@ -173,7 +174,7 @@ def train_mlp(ctx, X, Lr, W, snr, args):
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
     mlp.set_params(Lr.init_params(256, 4, np.random.default_rng(0), math.log(var0)))
-    batch = 8192
+    batch = args.mlp_batch
     hist, secs = Lr.train(mlp, data, args.mlp_train_steps, batch=batch, lr_max=args.mlp_lr, lr_min=1e-5,
                           log_every=max(args.mlp_train_steps // 6, 1))
     del data
