@@ -882,16 +882,29 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
   for (int l = 0; l < depth; ++l) {  // hidden layers
     const int K = (l == 0) ? 32 : W;
     const float* bl = master + offs[2 * l + 1];
-    // the sums start at the bias: the products accumulate onto it, with no add in the epilogue
+    // the sums start at the bias: the first k-step's products accumulate onto it (the bias is
+    // that MFMA's addend), with no copies and no add in the epilogue
     floatx4 acc[FB][NB];
+    {
+      const int kk = 8 * kg;
+      if (64 < K) load_w(l, kk + 64, wn2);
+      bf16x8 af[NB];
 #pragma unroll
-    for (int i = 0; i < FB; ++i) {
-      const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
-      const floatx4 bv = {bl[f0], bl[f0 + 1], bl[f0 + 2], bl[f0 + 3]};
+      for (int j = 0; j < NB; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) acc[i][j] = bv;
+      for (int i = 0; i < FB; ++i) {
+        const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
+        const floatx4 bv = {bl[f0], bl[f0 + 1], bl[f0 + 2], bl[f0 + 3]};
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], bv, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < FB; ++i) {
+        wcur[i] = wn1[i];
+        wn1[i] = wn2[i];
+      }
     }
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = 32; k0 < K; k0 += 32) {
       const int kk = k0 + 8 * kg;
       if (k0 + 64 < K) load_w(l, kk + 64, wn2);
       bf16x8 af[NB];
