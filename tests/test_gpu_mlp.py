@@ -168,6 +168,40 @@ def test_multi_step_training_equals_single_steps(X, ctx):
     assert np.array_equal(np.array(la), lb.cpu().numpy())
 
 
+def test_gradient_paths_agree(X, ctx):
+    # Two implementations of the backward pass: a network whose split-K weight-gradient slices fit
+    # the library's budget runs the grouped weight-gradient launch on a transposed weight copy
+    # (every sub-batch of 512 pairs here); one whose slices do not (2.1 M parameters x 32 slices at
+    # 16384 pairs) reduces each layer right after its GEMM.  The gradient of the mean loss over
+    # 16384 pairs is the mean of the 32 sub-batch gradients: the 1/n scalings are powers of two,
+    # so every BF16 rounding scales exactly and only the FP32 summation orders differ.
+    rng = np.random.default_rng(37)
+    width, depth = 512, 9
+    mlp = X.MLP(ctx, width, depth)
+    params = OM.init_params(rng, width, depth)
+    params[-OM.N_OUT:] = rng.normal(size=OM.N_OUT) * 0.1
+    mlp.set_params(params.astype(np.float32))
+    arr, drops, pi, *_ = _pairs(X, ctx, mlp, n_drops=137, k=16, stream=37)   # 16440 pairs
+    n, sub = 16384, 512
+    loss_full, grad_full = mlp.loss_grad(pi.slice(0, n))
+    grads, losses = [], []
+    for a in range(0, n, sub):
+        l_, g_ = mlp.loss_grad(pi.slice(a, a + sub))
+        grads.append(g_.double().cpu().numpy())
+        losses.append(l_.item())
+    g_mean = np.mean(grads, axis=0)
+    g_full = grad_full.double().cpu().numpy()
+    assert abs(loss_full.item() - np.mean(losses)) <= 1e-9 * abs(loss_full.item())
+    off = 0
+    for li, (o, i) in enumerate(OM.layer_shapes(width, depth)):
+        for name, m in (("W", o * i), ("b", o)):
+            a_, b_ = g_full[off:off + m], g_mean[off:off + m]
+            err = np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-30)
+            assert err < 1e-5, (li, name, err)
+            off += m
+    mlp.close()
+
+
 @pytest.mark.parametrize("width,depth,n_drops", [(64, 2, 3), (128, 3, 5), (256, 1, 2)])
 def test_fused_forward_other_shapes(X, ctx, width, depth, n_drops):
     # the fused inference kernel at every width it supports, with a ragged last tile
