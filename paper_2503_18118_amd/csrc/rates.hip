@@ -408,18 +408,18 @@ __device__ __forceinline__ bool chol_rows(cplx (&a)[kSmallK], int li, double& di
     const double djj = bcast16(a[j].x, j);
     ok = ok && (djj > 0.0) && isfinite(djj);
     const double l = sqrt(djj), il = 1.0 / l;
-    if (li > j) a[j] = {a[j].x * il, a[j].y * il};
+    a[j] = {a[j].x * il, a[j].y * il};
     if (li == j) {
       a[j] = {l, 0.0};
       diag = l;
     }
+    // every lane updates; rows above c (li < c) only churn their unused upper triangle, which
+    // nothing reads (the inverse below selects L_{li,m} for li > m only), so no lane masks
 #pragma unroll
     for (int c = j + 1; c < kSmallK; ++c) {
       const cplx lcj = shfl16(a[j], c);
-      if (li >= c) {
-        const cplx t = cmulc(a[j], lcj);
-        a[c] = {a[c].x - t.x, a[c].y - t.y};
-      }
+      const cplx t = cmulc(a[j], lcj);
+      a[c] = {a[c].x - t.x, a[c].y - t.y};
     }
   }
   return ok;
