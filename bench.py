@@ -564,6 +564,10 @@ def upa_leg(ctx, X, W, snr, stream):
     out = {"workload": "UPA 512 x 512 (N = 262144) half-wavelength at 100 GHz (lambda = 3.0 mm), K = 64 users "
                        "in a cone (r [3,30] m, azimuth and elevation [-60,60] deg), 2000 drops, MMSE at 10 dB",
            "entries": entries, "evals": evals, "pair_macs": pair_macs}
+    g16 = ctx.gram_exact(arr, b, X.FP32H)
+    ms16 = _timed(lambda: ctx.gram_exact(arr, b, X.FP32H, out=g16, stream=stream), stream, reps=2)
+    k16_ms, k16_n = _kernel_ms(ctx, lambda: ctx.gram_exact(arr, b, X.FP32H, out=g16, stream=stream), reps=2)
+    r16, _ = ctx.sumrate(b, g16, rho, X.MMSE)
     g32 = ctx.gram_exact(arr, b, X.FP32C)
     ms32 = _timed(lambda: ctx.gram_exact(arr, b, X.FP32C, out=g32, stream=stream), stream, reps=2)
     k_ms, k_n = _kernel_ms(ctx, lambda: ctx.gram_exact(arr, b, X.FP32C, out=g32, stream=stream), reps=2)
@@ -582,6 +586,23 @@ def upa_leg(ctx, X, W, snr, stream):
     valu_tf = FLOP_PER_ENTRY_EVAL * evals / t / 1e12
     mfma_tf = FLOP_PER_PAIR_MAC * pair_macs / t / 1e12
     e32 = _gram_err(g32, g64, k)
+    e16 = _gram_err(g16, g64, k)
+    t16 = k16_ms * 1e-3
+    valu16 = FLOP_PER_ENTRY_EVAL * evals / t16 / 1e12
+    mfma16 = FLOP_PER_PAIR_MAC * pair_macs / t16 / 1e12
+    # FP32H: the channel entries on the vector ALU, the products as FP16 hi/lo halves on the
+    # matrix cores (each wave evaluates one 16-user block; the blocks meet through LDS)
+    out["exact_fp32h"] = {"ms": ms16, "entries_per_s": entries / (ms16 * 1e-3), "kernel_ms": k16_ms,
+                          "launches_per_call": k16_n,
+                          "roofline": {"bound": "alu", "achieved": valu16, "peak": PEAK_VALU_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": valu16 / PEAK_VALU_TFLOPS,
+                                       "mfma_achieved": mfma16, "mfma_peak_fp16": PEAK_FP16_MFMA_TFLOPS,
+                                       "mfma_frac": mfma16 / PEAK_FP16_MFMA_TFLOPS,
+                                       "entry_evals_per_s": evals / t16},
+                          "gram_normwise_max_vs_fp64": float(e16.max()),
+                          "gram_normwise_median_vs_fp64": float(e16.median()),
+                          "drops_compared": drops.n_drops,
+                          "mmse_sumrate_rel_max": float(_rate_err(r16, r64).max())}
     out["exact_fp32c"] = {"ms": ms32, "entries_per_s": entries / (ms32 * 1e-3), "kernel_ms": k_ms,
                           "launches_per_call": k_n,
                           "roofline": {"bound": "alu", "achieved": valu_tf, "peak": PEAK_VALU_TFLOPS,

@@ -303,6 +303,7 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
   p.n_drops = n;
   std::vector<DropK> drops(n);
   int64_t uoff = 0, goff = 0, total_elems = 0, pairs = 0;
+  bool has3_or_cross = false;
   for (int d = 0; d < n; ++d) {
     DropK& dk = drops[d];
     const int64_t ne = ne_of[d];
@@ -319,7 +320,9 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
     total_elems += ne;
     p.nb_max = std::max(p.nb_max, dk.nb);
     p.k_max = std::max(p.k_max, dk.k);
+    has3_or_cross = has3_or_cross || dk.nb == 3 || dk.cross;
   }
+  if (p.nb_max == 4 && !has3_or_cross) p.nb_max = kNbWide;
   p.total_users = uoff;
   p.gram_elems = goff;
   p.n_pairs = pairs;
@@ -560,13 +563,16 @@ int gram_exact_noalloc_impl(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_b
   auto ne_of = [&](int d) -> int64_t {
     return a->geometry == XLMIMO_UPA ? a->n_y * a->n_z : (b->n_elems ? b->n_elems[d] : a->n_y);
   };
+  bool has3 = false;
   for (int d = 0; d < n; ++d) {
     const int nb = (b->n_users[d] + 15) / 16;
     nb_max = std::max(nb_max, nb);
+    has3 = has3 || nb == 3;
     total_elems += ne_of(d);
     max_ne = std::max(max_ne, ne_of(d));
     part_per_chunk_sum += (int64_t)partial_values(nb) * 64;
   }
+  if (nb_max == 4 && !has3) nb_max = kNbWide;   // no cross-group drops here (K <= XLMIMO_MAX_USERS)
   // work-item length: the context's default for this batch, lengthened while
   // the plan and partial sums do not fit
   const int g32 = gram_exact_grid(XLMIMO_FP32C, nb_max, a->geometry, a->amp_model);

@@ -693,15 +693,278 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
   store_partial<NV>(carry, s_red, part_out);
 }
 
+// ---------------------------------------------------------------------------
+// FP32H for 64-user drops (four 16-user blocks).  The split operands of four blocks do not fit
+// one lane beside the FP64 carries of all 26 accumulator blocks, so the work is divided by user
+// block instead of by element: in every round all four waves take the same elements, wave w
+// evaluates block w's users there (one user per lane, exactly as in the 16-user kernel), and
+// publishes its hi / lo operands in LDS; after a barrier each wave forms its own share of the
+// products — the cross blocks X[w, *] and two or three of the ten Re blocks — reading the other
+// blocks' operands from LDS.  A lane then holds at most 7 accumulator blocks (and their
+// carries), and each accumulator block lives in exactly one wave, which writes it to the
+// partial image directly (the image layout of the other kernels, so the finalize pass is
+// shared).  Re blocks per wave (bi <= bj), chosen so that every wave issues 24-30 MFMAs per set:
+//   wave 0: (0,0) (0,1)   wave 1: (1,1) (1,2)   wave 2: (2,2) (2,3) (0,2)   wave 3: (3,3) (1,3) (0,3)
+constexpr int kWideReN[4] = {2, 2, 3, 3};
+constexpr int kWideRe[4][3][2] = {{{0, 0}, {0, 1}, {0, 0}},
+                                  {{1, 1}, {1, 2}, {0, 0}},
+                                  {{2, 2}, {2, 3}, {0, 2}},
+                                  {{3, 3}, {1, 3}, {0, 3}}};
+
+struct WideOps {
+  halfx8 rh, rl, ih, il;
+};
+
+template <int W, int GEOM, int AMP, bool EXPAND>
+__device__ void wide_body(const ArrayK& arr, const DropK& dp, const ItemK& it, const UserLane& u, float us,
+                          double* __restrict__ part_out, double* s_red) {
+  constexpr int NB = 4, NRE = 10;
+  constexpr int NR = kWideReN[W];
+  const int lane = threadIdx.x & 63;
+  const double sc = arr.inv_lambda;
+  constexpr double kFar = 1e30;
+  constexpr int RUN = EXPAND ? kExpandRun : 8;   // consecutive elements per lane and round
+  constexpr int SETS = RUN / 8;                  // 32-element MFMA sets per round
+  constexpr int ROUND = 4 * RUN;                 // elements per round (all waves take the same ones)
+  constexpr int FLUSH = kSplitFlushElems / (32 * SETS);   // rounds between FP64 carries
+  // LDS operand exchange: [set][block][hi/lo array][lane], 16 bytes each
+  halfx8* s_ops = reinterpret_cast<halfx8*>(s_red);
+  auto ops_at = [&](int set, int b, int a) -> halfx8& { return s_ops[((set * NB + b) * 4 + a) * 64 + lane]; };
+
+  floatx4 are[NR], ax[NB];
+  double carry[(NR + NB) * 4];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) are[i] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < NB; ++i) ax[i] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < (NR + NB) * 4; ++i) carry[i] = 0.0;
+
+  const int len = it.e_end - it.e_begin;
+  const int n_full = len / ROUND;
+  const int n_rounds = (len + ROUND - 1) / ROUND;
+  const int sub = RUN * (lane >> 4);
+  const int ny = (GEOM == XLMIMO_ULA) ? dp.n_elems : arr.n_y;
+  const double ds = arr.spacing * sc;
+  const double cy = 0.5 * (double)(ny - 1) * ds;
+  const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
+
+  // own block's operands of one round (SETS sets), published to LDS
+  auto evaluate = [&](int e, auto tail_tag) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
+    if constexpr (EXPAND) {
+      double ey = 0.0, ez = 0.0;
+      if constexpr (GEOM == XLMIMO_ULA) {
+        ey = fma((double)e + 0.5 * (RUN - 1), ds, -cy);
+      } else {
+        const int ea = e / arr.n_z;
+        ey = fma((double)ea, ds, -cy);
+        ez = fma((double)(e - ea * arr.n_z) + 0.5 * (RUN - 1), ds, -cz);
+      }
+      Expansion<AMP> x;
+      if constexpr (GEOM == XLMIMO_ULA) {
+        x = expand<AMP>(u.uy - ey, u.xp2, ds, us);
+      } else {
+        const double dy = u.uy - ey;
+        x = expand<AMP>(u.uz - ez, fma(dy, dy, u.xp2), ds, us);
+      }
+#pragma unroll
+      for (int s = 0; s < SETS; ++s) {
+        WideOps o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = 4 * s + j;
+          float a[2], c[2], sn[2];
+          expansion_pair<AMP>(x, 0.5f + (float)k, a, c, sn);
+          if constexpr (TAIL) {
+            a[0] = e + 7 - k < it.e_end ? a[0] : 0.0f;
+            a[1] = e + 8 + k < it.e_end ? a[1] : 0.0f;
+          }
+          split_pair(a, c, sn, o.rh, o.rl, o.ih, o.il, 2 * j);
+        }
+        ops_at(s, W, 0) = o.rh;
+        ops_at(s, W, 1) = o.rl;
+        ops_at(s, W, 2) = o.ih;
+        ops_at(s, W, 3) = o.il;
+      }
+    } else if constexpr (GEOM == XLMIMO_ULA) {
+      WideOps o;
+      const double ey = fma((double)e, ds, -cy);
+      double dy = u.uy - ey;
+#pragma unroll
+      for (int m = 0; m < 8; m += 2) {
+        float a[2], c[2], sn[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          double d = dy;
+          dy -= ds;
+          if constexpr (TAIL) d = e + m + q < it.e_end ? d : kFar;
+          channel_parts<GEOM, AMP>(d, 0.0, u.xp2, us, a[q], c[q], sn[q]);
+        }
+        split_pair(a, c, sn, o.rh, o.rl, o.ih, o.il, m);
+      }
+      ops_at(0, W, 0) = o.rh;
+      ops_at(0, W, 1) = o.rl;
+      ops_at(0, W, 2) = o.ih;
+      ops_at(0, W, 3) = o.il;
+    } else {
+      WideOps o;
+      int ea = e / arr.n_z;
+      int eb = e - ea * arr.n_z;
+      float a[2], c[2], sn[2];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        double ey = fma((double)ea, ds, -cy);
+        const double ez = fma((double)eb, ds, -cz);
+        if constexpr (TAIL) ey = e + m < it.e_end ? ey : kFar;
+        channel_parts<GEOM, AMP>(u.uy - ey, u.uz - ez, u.xp2, us, a[m & 1], c[m & 1], sn[m & 1]);
+        if (m & 1) split_pair(a, c, sn, o.rh, o.rl, o.ih, o.il, m - 1);
+        if (++eb == arr.n_z) {
+          eb = 0;
+          ++ea;
+        }
+      }
+      ops_at(0, W, 0) = o.rh;
+      ops_at(0, W, 1) = o.rl;
+      ops_at(0, W, 2) = o.ih;
+      ops_at(0, W, 3) = o.il;
+    }
+  };
+
+  // this wave's products of one round, from the four blocks' operands in LDS
+  auto contract = [&]() {
+#pragma unroll
+    for (int s = 0; s < SETS; ++s) {
+      WideOps b[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        b[k].rh = ops_at(s, k, 0);
+        b[k].rl = ops_at(s, k, 1);
+        b[k].ih = ops_at(s, k, 2);
+        b[k].il = ops_at(s, k, 3);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int bi = kWideRe[W][r][0], bj = kWideRe[W][r][1];
+        floatx4& c = are[r];
+        c = mfma_h(b[bi].rh, b[bj].rh, c);
+        c = mfma_h(b[bi].ih, b[bj].ih, c);
+        c = mfma_h(b[bi].rh, b[bj].rl, c);
+        c = mfma_h(b[bi].ih, b[bj].il, c);
+        c = mfma_h(b[bi].rl, b[bj].rh, c);
+        c = mfma_h(b[bi].il, b[bj].ih, c);
+      }
+#pragma unroll
+      for (int bj = 0; bj < NB; ++bj) {
+        floatx4& c = ax[bj];
+        c = mfma_h(b[W].rh, b[bj].ih, c);
+        c = mfma_h(b[W].rh, b[bj].il, c);
+        c = mfma_h(b[W].rl, b[bj].ih, c);
+      }
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) carry[i * 4 + c] += (double)are[i][c];
+      are[i] = floatx4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) carry[(NR + i) * 4 + c] += (double)ax[i][c];
+      ax[i] = floatx4{0, 0, 0, 0};
+    }
+  };
+
+  const int e0 = it.e_begin + sub;
+  for (int r0 = 0; r0 < n_full; r0 += FLUSH) {
+    const int r1 = min(r0 + FLUSH, n_full);
+    for (int r = r0; r < r1; ++r) {
+      evaluate(e0 + ROUND * r, std::false_type{});
+      __syncthreads();   // every block's operands of this round are in LDS
+      contract();
+      __syncthreads();   // every wave has read them before the next round overwrites them
+    }
+    flush();
+  }
+  if (n_rounds > n_full) {   // the partial last round, carried on its own
+    evaluate(e0 + ROUND * n_full, std::true_type{});
+    __syncthreads();
+    contract();
+    __syncthreads();
+    flush();
+  }
+  // each accumulator block lives in this wave alone: straight into the partial image
+  // (value v = block * 4 + register at v * 64 + lane; Re blocks by tri_index, then X blocks)
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int blk = tri_index(kWideRe[W][r][0], kWideRe[W][r][1], NB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part_out[(blk * 4 + c) * 64 + lane] = carry[r * 4 + c];
+  }
+#pragma unroll
+  for (int bj = 0; bj < NB; ++bj) {
+    const int blk = NRE + W * NB + bj;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part_out[(blk * 4 + c) * 64 + lane] = carry[(NR + bj) * 4 + c];
+  }
+  __syncthreads();   // the LDS exchange buffer is free again for the next item
+}
+
+template <int GEOM, int AMP>
+__device__ void process_item_wide(const ArrayK& arr, const DropK& dp, const ItemK& it,
+                                  const double* __restrict__ pos, double* __restrict__ part_out, double* s_red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double sc = arr.inv_lambda;
+  constexpr double kFar = 1e30;
+  const double ds = arr.spacing * sc;
+  const double xmin = kExpandXmin * ds;
+  // this wave's user: block `wave`
+  const int k = 16 * wave + (lane & 15);
+  double x = kFar, y = 0.0, z = 0.0;
+  if (k < dp.k) {
+    const double* p = pos + (dp.user_off + k) * 3;
+    x = p[0] * sc;
+    y = p[1] * sc;
+    z = p[2] * sc;
+  }
+  UserLane u;
+  u.xp2 = perp2(GEOM, x, z);
+  u.uy = y;
+  u.uz = z;
+  const float us = k < dp.k ? __builtin_ldexpf(1.0f, split_exp(u.xp2, AMP)) : 1.0f;
+  // the expansion's condition over all 64 users of the workgroup (the waves hold different ones)
+  __shared__ int s_near;
+  if (threadIdx.x == 0) s_near = 0;
+  __syncthreads();
+  if (__any(!(u.xp2 >= xmin * xmin)) && lane == 0) atomicOr(&s_near, 1);
+  __syncthreads();
+  const bool expand = (GEOM == XLMIMO_ULA || arr.n_z % kExpandRun == 0) && s_near == 0;
+  switch (wave) {
+    case 0: expand ? wide_body<0, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red)
+                   : wide_body<0, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red); break;
+    case 1: expand ? wide_body<1, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red)
+                   : wide_body<1, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red); break;
+    case 2: expand ? wide_body<2, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red)
+                   : wide_body<2, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red); break;
+    default: expand ? wide_body<3, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red)
+                    : wide_body<3, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red); break;
+  }
+}
+
 template <int NBMAX, typename T, int GEOM, int AMP, bool SPLIT>
-__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SPLIT && NBMAX <= 2 ? 4 / NBMAX : 1))) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
+__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SPLIT && NBMAX <= 2 ? 4 / NBMAX : (NBMAX == kNbWide ? 2 : 1)))) void k_gram_exact(ArrayK arr, const DropK* __restrict__ drops,
                                                                const double* __restrict__ pos,
                                                                const ItemK* __restrict__ items, int n_items,
                                                                int* __restrict__ counter,
                                                                double* __restrict__ partials,
                                                                const int32_t* __restrict__ mask,
                                                                const int* __restrict__ n_items_dev) {
-  __shared__ double s_red[partial_values(NBMAX) * 64];
+  constexpr bool WIDE_ONLY = NBMAX == kNbWide;   // no 3-block or cross-group drop in the batch
+  constexpr int NBM = WIDE_ONLY ? 4 : NBMAX;
+  __shared__ double s_red[partial_values(NBM) * 64];
   __shared__ int s_item;
   if (n_items_dev != nullptr) n_items = *n_items_dev;   // a compacted item list: its length is on the device
   for (;;) {
@@ -717,13 +980,15 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SP
     if constexpr (SPLIT) {
       switch (dp.nb) {
         case 1: process_item_split<1, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 2: if constexpr (NBMAX >= 2) process_item_split<2, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        // more than 32 users: the split operands do not fit beside the FP64 carries; FP32C products
-        case 3: if constexpr (NBMAX >= 3) process_item<3, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 2: if constexpr (NBM >= 2) process_item_split<2, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        // 33-48 users, and the cross blocks of virtual drops (more than 64 users): FP32C products
+        case 3: if constexpr (NBM >= 3 && !WIDE_ONLY) process_item<3, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         case 4:
-          if constexpr (NBMAX >= 4) {
+          if constexpr (WIDE_ONLY) {
+            process_item_wide<GEOM, AMP>(arr, dp, it, pos, out, s_red);
+          } else if constexpr (NBM >= 4) {
             if (dp.cross) process_item<4, float, GEOM, AMP, true>(arr, dp, it, pos, out, s_red);
-            else process_item<4, float, GEOM, AMP>(arr, dp, it, pos, out, s_red);
+            else process_item_wide<GEOM, AMP>(arr, dp, it, pos, out, s_red);
           }
           break;
         default: break;
@@ -731,10 +996,10 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SP
     } else {
       switch (dp.nb) {
         case 1: process_item<1, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 2: if constexpr (NBMAX >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 3: if constexpr (NBMAX >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 2: if constexpr (NBM >= 2) process_item<2, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 3: if constexpr (NBM >= 3) process_item<3, T, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         case 4:
-          if constexpr (NBMAX >= 4) {
+          if constexpr (NBM >= 4) {
             if (dp.cross) process_item<4, T, GEOM, AMP, true>(arr, dp, it, pos, out, s_red);
             else process_item<4, T, GEOM, AMP>(arr, dp, it, pos, out, s_red);
           }
@@ -838,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_gram_finalize(ArrayK arr, const DropK* 
       const double xq = (arr.geom == XLMIMO_ULA) ? sqrt(fma(uq[0], uq[0], uq[2] * uq[2])) : fabs(uq[0]);
       scale = arr.beta0 * sqrt(xp * xq) * su * su * su;
     }
-    if (split && NB <= kSplitMaxNb) {
+    if (split && (NB <= kSplitMaxNb || (NB == 4 && !dp.cross))) {
       // undo the per-user scales 2^q of the split-half entries (exact powers of two)
       const double* up = pos + (dp.user_off + p) * 3;
       const double* uq = pos + (dp.user_off + q) * 3;
@@ -867,6 +1132,9 @@ static int occupancy_grid() {
 
 template <typename T, int GEOM, int AMP, bool SPLIT>
 static int grid_nb(int nb_max) {
+  if constexpr (SPLIT) {
+    if (nb_max == kNbWide) return occupancy_grid<kNbWide, T, GEOM, AMP, SPLIT>();
+  }
   return nb_max <= 1 ? occupancy_grid<1, T, GEOM, AMP, SPLIT>()
                      : (nb_max <= 2 ? occupancy_grid<2, T, GEOM, AMP, SPLIT>() : occupancy_grid<4, T, GEOM, AMP, SPLIT>());
 }
@@ -900,6 +1168,12 @@ struct MainArgs {
 
 template <typename T, int GEOM, int AMP, bool SPLIT>
 static void launch_main(int nb_max, int grid, hipStream_t s, const MainArgs& a) {
+  if constexpr (SPLIT) {
+    if (nb_max == kNbWide) {
+      k_gram_exact<kNbWide, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask, a.n_items_dev);
+      return;
+    }
+  }
   if (nb_max <= 1)
     k_gram_exact<1, T, GEOM, AMP, SPLIT><<<grid, kGramThreads, 0, s>>>(a.arr, a.drops, a.pos, a.items, a.n_items, a.counter, a.partials, a.mask, a.n_items_dev);
   else if (nb_max <= 2)

@@ -84,6 +84,11 @@ __host__ __device__ constexpr int tri_index(int bi, int bj, int nb) {
 }
 
 constexpr int kGramThreads = 256;     // 4 waves per work item
+// Plan-level user-block bound of the exact Gram's launch: 1, 2 or 4 (the largest drop's
+// 16-user blocks), or kNbWide for batches whose largest drops have four blocks while no drop
+// has three and none is a cross-group virtual drop (the FP32H launch then runs a kernel without
+// the FP32C paths those need, at half the registers).
+constexpr int kNbWide = 5;
 constexpr int kFlushRounds = 64;      // FP32 MFMA partial sums are carried to FP64 every 64 rounds (256 elements per wave)
 
 // BF16 GEMM for the learned correction (mlp.hip): C[M x N] = sum_k A(m,k) B(k,n),

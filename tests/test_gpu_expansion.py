@@ -80,8 +80,8 @@ def test_ula_far_and_near_users(X, ctx, amp, spacing_lam):
 
 @pytest.mark.parametrize("ny,nz", [(40, 64), (33, 24), (16, 21)])
 def test_upa_runs_along_columns(X, ctx, ny, nz):
-    # n_z a multiple of 8: every run of 8 elements stays in one column (expansion path);
-    # otherwise the FP64 path
+    # n_z a multiple of 16: every run of 16 elements stays in one column (expansion path);
+    # otherwise the per-element FP64 distance
     lam = W.LAMBDA_100GHZ_UPA
     d = lam / 2
     rng = np.random.default_rng(ny * 100 + nz)
@@ -97,3 +97,44 @@ def test_sweep_drops_at_the_largest_aperture(X, ctx):
     arr, drops, _ = W.sweep(n_drops=6, n_list=(262144,))
     w = _check(X, ctx, arr, drops, "sweep drops, N = 262144")
     print(f"worst normwise error {w:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+def test_64_user_drops(X, ctx, amp):
+    # Drops of 49-64 users (four 16-user blocks) run the block-per-wave kernel: each wave evaluates
+    # one block and the products are shared out through LDS.  A batch of such drops alone (no
+    # 33-48-user drop) takes the kernel without FP32C paths; far users (expansion) and one near
+    # user (per-element distance), ragged N.
+    lam = W.LAMBDA_28GHZ
+    d = 0.5 * lam
+    x_far = XMIN * d * 1.001
+    rng = np.random.default_rng(64 + amp)
+    ns = [4099, 1000, 20000]
+    ks = [64, 49, 64]
+    far = [_users(rng, k, x_far, x_far + 30.0, 20.0) for k in ks]
+    near = [u.copy() for u in far]
+    for u in near:
+        u[5, 0] = x_far * 0.4
+    arr = W.ula(1, lam, amp)
+    w_far = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(far)), "64 users, far")
+    w_near = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(near)), "64 users, one near")
+    # beside 16- and 33-user drops: the general kernel, whose 4-block drops take the same path
+    mixed = W._pack(ns + [777, 3000], ks + [16, 33],
+                    np.concatenate(far + [_users(rng, 16, x_far, x_far + 30.0, 20.0),
+                                          _users(rng, 33, x_far, x_far + 30.0, 20.0)]))
+    w_mixed = _check(X, ctx, arr, mixed, "64 users beside 16 and 33")
+    print(f"worst normwise error: far {w_far:.2e}, near {w_near:.2e}, mixed {w_mixed:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("ny,nz", [(24, 32), (20, 40)])
+def test_upa_64_users(X, ctx, ny, nz):
+    # the block-per-wave kernel on a UPA: runs of 16 along the columns (n_z = 32) or the
+    # per-element distance (n_z = 40)
+    lam = W.LAMBDA_100GHZ_UPA
+    d = lam / 2
+    rng = np.random.default_rng(ny * 1000 + nz)
+    k = 64
+    users = [_users(rng, k, XMIN * d * 1.01, 3.0, 1.5, 1.5) for _ in range(2)]
+    arr = W.ArraySpec(W.GEOM_UPA, ny, nz, d, lam, W.AMP_FREESPACE)
+    drops = W._pack([ny * nz] * 2, [k] * 2, np.concatenate(users))
+    _check(X, ctx, arr, drops, f"UPA {ny}x{nz}, K = 64")

@@ -574,9 +574,11 @@ def test_full_size_upa_samples(X, ctx):
     arr, drops, meta = W.upa(n_drops=64)
     b = X.Batch(drops)
     g = b.split(ctx.gram_exact(arr, b, X.FP32C))
+    gh = b.split(ctx.gram_exact(arr, b, X.FP32H))
     for d in (0, 63):
         ref = och.gram_exact(arr, drops.users_of(d), chunk=1 << 15)
         assert och.normwise_error(g[d], ref) < TOL_FP32C
+        assert och.normwise_error(gh[d], ref) < TOL_FP32C
 
 
 @pytest.mark.slow
