@@ -48,7 +48,7 @@ METRIC = "Gram entries/s exact vs closed-form vs MLP-corrected at ≤1e-3 sum-ra
 # 2 flops (FMA) x 2.4 GHz; FP32 and FP64 FMAs issue at this rate.
 PEAK_VALU_TFLOPS = 78.6
 PEAK_FP16_MFMA_TFLOPS = 2500.0    # dense FP16 matrix peak (the FP32H products)
-PEAK_FP32_MFMA_TFLOPS = 157.3     # FP32 matrix peak (the FP32C products of K > 32 drops)
+PEAK_FP32_MFMA_TFLOPS = 157.3     # FP32 matrix peak (the FP32C products, reported beside FP32H)
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # dense BF16 matrix peak (the network)
 # Algorithmic work of the exact Gram, counted from the plain formula:
 #   per channel entry (element, user), vector ALU: dy (1), dy^2 + x^2 (2), sqrt (1), r/lambda (1),
