@@ -339,9 +339,9 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
 // round, 128 elements per workgroup round); the expansion path takes R = 16 (its
 // run feeds two MFMA sets, 256 elements per workgroup round).  Which element sits
 // in which k slot does not matter as long as every user uses the same slots.
-// Products accumulate in FP32 over 256 elements per wave, then in FP64.
+// Products accumulate in FP32 over 512 elements per wave, then in FP64.
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
-constexpr int kSplitFlushElems = 256;   // elements per wave between FP64 carries
+constexpr int kSplitFlushElems = 512;   // elements per wave between FP64 carries
 constexpr int kSplitMaxNb = 2;  // user blocks of 16 handled by the split kernel
 
 __device__ __forceinline__ floatx4 mfma_h(halfx8 a, halfx8 b, floatx4 c) {
@@ -401,20 +401,22 @@ __device__ __forceinline__ void split_pair(const float* a, const float* c, const
 //   r(t) - r_c = r_c sum_k C_k^(-1/2)(mu) (t / r_c)^k       (Gegenbauer generating function of
 //   r(t)^-p    = r_c^-p sum_k C_k^(p/2)(mu) (t / r_c)^k      r_c^2 - 2 dy_c t + t^2)
 // evaluated in FP32 by Horner's rule in m'^2 on the even and odd parts (the
-// coefficients carry d^k), to t^4 for both.  With the half-run |t| <= 7.5 d and
-// every user at a distance x >= kExpandXmin d from the array line (plane), the
-// truncated terms stay below 1e-7 turns (d <= 1) and 2e-9 relative; the FP32
-// evaluation leaves |phase error| <= 5e-7 turns at d = 1/2 (9e-7 at d = 1: the
-// phase is carried to |theta| < 4.3 turns, so its rounding dominates) and 3e-7
-// relative in the amplitude.  Items whose users come closer take the
-// per-element FP64 path.
+// coefficients carry d^k), the phase to t^4 and the amplitude to t^3.  With the
+// half-run |t| <= 7.5 d and every user at a distance x >= kExpandXmin d from the
+// array line (plane), the truncated phase terms stay below 1e-7 turns (d <= 1);
+// the first dropped amplitude term is at most C_4(1) (7.5 / 368)^4, 1.7e-7
+// relative for free space and 4.3e-7 for the projected aperture (it peaks at the
+// run's ends, where |m'| = 7.5).  The FP32 evaluation leaves |phase error| <=
+// 5e-7 turns at d = 1/2 (9e-7 at d = 1: the phase is carried to |theta| < 4.3
+// turns, so its rounding dominates) and 3e-7 relative in the amplitude.  Items
+// whose users come closer take the per-element FP64 path.
 constexpr double kExpandXmin = 368.0;
 constexpr int kExpandRun = 16;
 
 template <int AMP>
 struct Expansion {
   float th[5];   // minus the phase in turns: -c0, then the coefficients of m', ..., m'^4 (all negated)
-  float am[5];   // amplitude (times the user scale): coefficients of 1, m', ..., m'^4
+  float am[4];   // amplitude (times the user scale): coefficients of 1, m', m'^2, m'^3
 };
 
 template <int AMP>
@@ -447,26 +449,24 @@ __device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double 
     x.am[1] = (b0 * mu) * q;
     x.am[2] = bq2 * __builtin_fmaf(1.5f, mu2, -0.5f);
     x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(2.5f, mu2, -1.5f));
-    x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(4.375f, mu2, -3.75f), mu2, 0.375f);
   } else {                                              // C_k^(3/4)(mu)
     x.am[1] = (b0 * mu) * (1.5f * q);
     x.am[2] = bq2 * __builtin_fmaf(2.625f, mu2, -0.75f);
     x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(4.8125f, mu2, -2.625f));
-    x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(9.0234375f, mu2, -7.21875f), mu2, 0.65625f);
   }
   return x;
 }
 
 // The two elements at m' = -p and +p from the even and odd parts of both series,
 // with the phase carried negated (so that sn = sin(-theta) needs no sign flip):
-// -theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (10 FMAs per pair).
+// -theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (9 FMAs per pair).
 template <int AMP>
 __device__ __forceinline__ void expansion_pair(const Expansion<AMP>& x, float p, float (&a)[2], float (&c)[2],
                                                float (&sn)[2]) {
   const float p2 = p * p;
   const float ev = __builtin_fmaf(__builtin_fmaf(x.th[4], p2, x.th[2]), p2, x.th[0]);
   const float od = __builtin_fmaf(x.th[3], p2, x.th[1]);
-  const float ae = __builtin_fmaf(__builtin_fmaf(x.am[4], p2, x.am[2]), p2, x.am[0]);
+  const float ae = __builtin_fmaf(x.am[2], p2, x.am[0]);
   const float ao = __builtin_fmaf(x.am[3], p2, x.am[1]);
   const float th0 = __builtin_fmaf(-p, od, ev), th1 = __builtin_fmaf(p, od, ev);
   a[0] = __builtin_fmaf(-p, ao, ae);
@@ -545,6 +545,24 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
   const double ds = arr.spacing * sc;
   const double cy = 0.5 * (double)(ny - 1) * ds;
   const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
+  const int e0 = it.e_begin + sub;
+  // The expansion path's run cursor, advanced by one round per call: on a line, every
+  // user's offset from the run's centre (FP64, less one round's length per round); on a
+  // plane, the column and row of the run's first element (runs never straddle a column).
+  double dyc[NB];
+  int ca = 0, cb = 0, qa = 0, qb = 0;
+  if constexpr (EXPAND) {
+    if constexpr (GEOM == XLMIMO_ULA) {
+      const double ey0 = fma((double)e0 + 0.5 * (RUN - 1), ds, -cy);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) dyc[b] = u[b].uy - ey0;
+    } else {
+      ca = e0 / arr.n_z;
+      cb = e0 - ca * arr.n_z;
+      qa = ROUND / arr.n_z;
+      qb = ROUND - qa * arr.n_z;
+    }
+  }
 
   // One MFMA set: the 32 elements of each wave held as hi / lo operands.
   auto accumulate = [&](const halfx8 (&rh)[NB], const halfx8 (&rl)[NB], const halfx8 (&ih)[NB],
@@ -580,22 +598,26 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
     constexpr bool TAIL = decltype(tail_tag)::value;
     if constexpr (EXPAND) {
       // the run's centre, element e + 7.5, and the expansion of each user about it
-      double ey = 0.0, ez = 0.0;
-      if constexpr (GEOM == XLMIMO_ULA) {
-        ey = fma((double)e + 0.5 * (RUN - 1), ds, -cy);
-      } else {
-        const int ea = e / arr.n_z;
-        ey = fma((double)ea, ds, -cy);
-        ez = fma((double)(e - ea * arr.n_z) + 0.5 * (RUN - 1), ds, -cz);
-      }
       Expansion<AMP> x[NB];
+      if constexpr (GEOM == XLMIMO_ULA) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        if constexpr (GEOM == XLMIMO_ULA) {
-          x[b] = expand<AMP>(u[b].uy - ey, u[b].xp2, ds, us[b]);
-        } else {
+        for (int b = 0; b < NB; ++b) {
+          x[b] = expand<AMP>(dyc[b], u[b].xp2, ds, us[b]);
+          dyc[b] -= ROUND * ds;
+        }
+      } else {
+        const double ey = fma((double)ca, ds, -cy);
+        const double ez = fma((double)cb + 0.5 * (RUN - 1), ds, -cz);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
           const double dy = u[b].uy - ey;
           x[b] = expand<AMP>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
+        }
+        ca += qa;
+        cb += qb;
+        if (cb >= arr.n_z) {
+          cb -= arr.n_z;
+          ++ca;
         }
       }
       // set s takes the pairs m' = +-(4 s + j + 1/2), j = 0..3: operand slots 2j, 2j + 1
@@ -680,7 +702,6 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
     }
   };
 
-  const int e0 = it.e_begin + sub;
   for (int r0 = 0; r0 < n_full; r0 += FLUSH) {
     const int r1 = min(r0 + FLUSH, n_full);
     for (int r = r0; r < r1; ++r) round(e0 + ROUND * r, std::false_type{});
@@ -748,25 +769,40 @@ __device__ void wide_body(const ArrayK& arr, const DropK& dp, const ItemK& it, c
   const double ds = arr.spacing * sc;
   const double cy = 0.5 * (double)(ny - 1) * ds;
   const double cz = 0.5 * (double)(arr.n_z - 1) * ds;
+  const int e0 = it.e_begin + sub;
+  // the expansion path's run cursor, advanced by one round per call (as in the 16-user kernel)
+  double dyc = 0.0;
+  int ca = 0, cb = 0, qa = 0, qb = 0;
+  if constexpr (EXPAND) {
+    if constexpr (GEOM == XLMIMO_ULA) {
+      dyc = u.uy - fma((double)e0 + 0.5 * (RUN - 1), ds, -cy);
+    } else {
+      ca = e0 / arr.n_z;
+      cb = e0 - ca * arr.n_z;
+      qa = ROUND / arr.n_z;
+      qb = ROUND - qa * arr.n_z;
+    }
+  }
 
   // own block's operands of one round (SETS sets), published to LDS
   auto evaluate = [&](int e, auto tail_tag) {
     constexpr bool TAIL = decltype(tail_tag)::value;
     if constexpr (EXPAND) {
-      double ey = 0.0, ez = 0.0;
-      if constexpr (GEOM == XLMIMO_ULA) {
-        ey = fma((double)e + 0.5 * (RUN - 1), ds, -cy);
-      } else {
-        const int ea = e / arr.n_z;
-        ey = fma((double)ea, ds, -cy);
-        ez = fma((double)(e - ea * arr.n_z) + 0.5 * (RUN - 1), ds, -cz);
-      }
       Expansion<AMP> x;
       if constexpr (GEOM == XLMIMO_ULA) {
-        x = expand<AMP>(u.uy - ey, u.xp2, ds, us);
+        x = expand<AMP>(dyc, u.xp2, ds, us);
+        dyc -= ROUND * ds;
       } else {
+        const double ey = fma((double)ca, ds, -cy);
+        const double ez = fma((double)cb + 0.5 * (RUN - 1), ds, -cz);
         const double dy = u.uy - ey;
         x = expand<AMP>(u.uz - ez, fma(dy, dy, u.xp2), ds, us);
+        ca += qa;
+        cb += qb;
+        if (cb >= arr.n_z) {
+          cb -= arr.n_z;
+          ++ca;
+        }
       }
 #pragma unroll
       for (int s = 0; s < SETS; ++s) {
@@ -878,7 +914,6 @@ __device__ void wide_body(const ArrayK& arr, const DropK& dp, const ItemK& it, c
     }
   };
 
-  const int e0 = it.e_begin + sub;
   for (int r0 = 0; r0 < n_full; r0 += FLUSH) {
     const int r1 = min(r0 + FLUSH, n_full);
     for (int r = r0; r < r1; ++r) {
