@@ -44,6 +44,16 @@ constexpr double taylor_coef(int n) { return taylor_coef_w(n, kTwoPi); }
 constexpr double quarter_coef(int n) { return taylor_coef_w(n, kHalfPi); }
 constexpr double half_coef(int n) { return taylor_coef_w(n, 2.0 * kHalfPi); }
 
+// a * b + c in FP64 with the coefficient c in scalar registers.  The Horner steps of the
+// series below otherwise become the two-operand v_fmac_f64, which needs the addend in the
+// destination: with the coefficients held in vector registers across a loop, every step
+// then costs a 64-bit copy on top of the multiply-add.
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 __device__ __forceinline__ double rsqrt_nr1(double r2) {
   double y = (double)__builtin_amdgcn_rsqf((float)r2);
   double e = fma(-r2 * y, y, 1.0);  // 1 - r2 y^2
@@ -83,11 +93,11 @@ __device__ __forceinline__ void sincos_rev(double t, double& s, double& c) {
   const double t2 = t * t;
   double ps = taylor_coef(17);
 #pragma unroll
-  for (int n = 15; n >= 1; n -= 2) ps = fma(ps, t2, taylor_coef(n));
+  for (int n = 15; n >= 1; n -= 2) ps = fma_sc(ps, t2, taylor_coef(n));
   s = ps * t;
   double pc = taylor_coef(18);
 #pragma unroll
-  for (int n = 16; n >= 2; n -= 2) pc = fma(pc, t2, taylor_coef(n));
+  for (int n = 16; n >= 2; n -= 2) pc = fma_sc(pc, t2, taylor_coef(n));
   c = fma(pc, t2, 1.0);
 }
 
@@ -111,11 +121,11 @@ __device__ __forceinline__ void sincos_quarter(double t, double& s, double& c) {
   const double t2 = t * t;
   double ps = quarter_coef(17);
 #pragma unroll
-  for (int n = 15; n >= 1; n -= 2) ps = fma(ps, t2, quarter_coef(n));
+  for (int n = 15; n >= 1; n -= 2) ps = fma_sc(ps, t2, quarter_coef(n));
   s = ps * t;
   double pc = quarter_coef(18);
 #pragma unroll
-  for (int n = 16; n >= 2; n -= 2) pc = fma(pc, t2, quarter_coef(n));
+  for (int n = 16; n >= 2; n -= 2) pc = fma_sc(pc, t2, quarter_coef(n));
   c = fma(pc, t2, 1.0);
 }
 
@@ -136,11 +146,11 @@ __device__ __forceinline__ void sincos_half(double t, double& ns, double& c) {
   const double t2 = t * t;
   double ps = -half_coef(21);
 #pragma unroll
-  for (int n = 19; n >= 1; n -= 2) ps = fma(ps, t2, -half_coef(n));
+  for (int n = 19; n >= 1; n -= 2) ps = fma_sc(ps, t2, -half_coef(n));
   ns = ps * t;
   double pc = half_coef(22);
 #pragma unroll
-  for (int n = 20; n >= 2; n -= 2) pc = fma(pc, t2, half_coef(n));
+  for (int n = 20; n >= 2; n -= 2) pc = fma_sc(pc, t2, half_coef(n));
   c = fma(pc, t2, 1.0);
 }
 

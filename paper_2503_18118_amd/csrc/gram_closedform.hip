@@ -146,7 +146,7 @@ __device__ __forceinline__ Cplx gated_ula(const ArrayK& arr, const UlaUser& up, 
 // whole batch (the drop found by bisection of the pairs' offsets).  Writes the entry and its
 // conjugate for analytic pairs and NaN for pairs with a bad user; records every pair's route
 // for k_closedform, which evaluates the numeric ones.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_cf_pairs(ArrayK arr, const DropK* __restrict__ drops, int n_drops,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_cf_pairs(ArrayK arr, const DropK* __restrict__ drops, int n_drops,
                                                   int64_t n_pairs, int variant, const double* __restrict__ pos,
                                                   const double* __restrict__ gl, int n_gl,
                                                   double* __restrict__ gram, int32_t* __restrict__ route_out) {
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
 }
 
-__global__ __launch_bounds__(256) void k_closedform(ArrayK arr, const DropK* __restrict__ drops, int variant,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_closedform(ArrayK arr, const DropK* __restrict__ drops, int variant,
                                                      const double* __restrict__ pos,
                                                      const double* __restrict__ gl, int n_gl,
                                                      double* __restrict__ gram, int32_t* __restrict__ status,
