@@ -353,32 +353,34 @@ __global__ __launch_bounds__(64) void k_rates(const DropK* __restrict__ drops, c
 // parallel; rows and pivots move by DPP row broadcasts, with no LDS or barrier.
 // Matrices with K < 16 are padded with an identity block: the Cholesky factor
 // and the inverse's diagonal of the leading K x K block are unchanged, operation
-// by operation.  The arithmetic is the generic kernel's in the same order.
+// by operation.  The factorisation's arithmetic is the generic kernel's in the
+// same order; the inverse's diagonal sums its squared entries in another order.
 //
 // Jobs of a drop, in order: [G (ZF)] [G~ (MZF)] then one per SNR when MMSE, CAP
 // or MRC is asked for (MRC needs no factorisation and rides on that job).
 constexpr int kSmallK = 16;
 
 // Lane `src` of each 16-lane row to the whole row: a DPP row broadcast (a VALU
-// move, no LDS round trip).  src is a constant once the callers' loops unroll.
+// move, no LDS round trip, and no initial value: every lane of the row is written).
+// src is a constant once the callers' loops unroll.
 __device__ __forceinline__ int row_bcast(int v, int src) {
   switch (src) {
-    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xF, 0xF, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x151, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x152, 0xF, 0xF, false);
-    case 3: return __builtin_amdgcn_update_dpp(0, v, 0x153, 0xF, 0xF, false);
-    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x154, 0xF, 0xF, false);
-    case 5: return __builtin_amdgcn_update_dpp(0, v, 0x155, 0xF, 0xF, false);
-    case 6: return __builtin_amdgcn_update_dpp(0, v, 0x156, 0xF, 0xF, false);
-    case 7: return __builtin_amdgcn_update_dpp(0, v, 0x157, 0xF, 0xF, false);
-    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x158, 0xF, 0xF, false);
-    case 9: return __builtin_amdgcn_update_dpp(0, v, 0x159, 0xF, 0xF, false);
-    case 10: return __builtin_amdgcn_update_dpp(0, v, 0x15A, 0xF, 0xF, false);
-    case 11: return __builtin_amdgcn_update_dpp(0, v, 0x15B, 0xF, 0xF, false);
-    case 12: return __builtin_amdgcn_update_dpp(0, v, 0x15C, 0xF, 0xF, false);
-    case 13: return __builtin_amdgcn_update_dpp(0, v, 0x15D, 0xF, 0xF, false);
-    case 14: return __builtin_amdgcn_update_dpp(0, v, 0x15E, 0xF, 0xF, false);
-    default: return __builtin_amdgcn_update_dpp(0, v, 0x15F, 0xF, 0xF, false);
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_mov_dpp(v, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_mov_dpp(v, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_mov_dpp(v, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_mov_dpp(v, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_mov_dpp(v, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_mov_dpp(v, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_mov_dpp(v, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_mov_dpp(v, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_mov_dpp(v, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15F, 0xF, 0xF, false);
   }
 }
 
@@ -390,6 +392,33 @@ __device__ __forceinline__ double bcast16(double v, int src) {
 }
 
 __device__ __forceinline__ cplx shfl16(cplx v, int src) { return {bcast16(v.x, src), bcast16(v.y, src)}; }
+
+// A DPP move of a double within each 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One halving step of a reduce-scatter over the row: of the 2H values each lane holds
+// (ordered by index, the halves split by index bit MASK), the lane keeps the half its
+// own bit MASK selects (the upper half when set) and adds the partner's copy of that
+// half.  The partner (DPP control CTRL) agrees with the lane in every index bit above
+// MASK, so both hold the same index set, and differs in bit MASK: lane 15 - i (row
+// mirror) for bit 3, i ^ 7 (half-row mirror) for bit 2, i ^ 2 and i ^ 1 (quad
+// permutations) for bits 1 and 0.
+template <int H, int MASK, int CTRL>
+__device__ __forceinline__ void halve16(double (&v)[kSmallK], int li) {
+  const bool up = li & MASK;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double keep = up ? v[H + j] : v[j];
+    const double send = up ? v[j] : v[H + j];
+    v[j] = keep + dpp64<CTRL>(send);
+  }
+}
 
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
@@ -426,38 +455,47 @@ __device__ __forceinline__ bool chol_rows(cplx (&a)[kSmallK], int li, double& di
 }
 
 // [ (L L^H)^-1 ]_{li,li} = sum_i |W_{i,li}|^2 with W = L^-1, built row by row
-// in place of L: at step m lane m completes row m of W (W_mm = 1 / L_mm, the
-// rest scaled by -1 / L_mm), the row is broadcast, and every later row i adds
-// L_{i,m} W_{m,k} to its running W_{i,k}.  L_{i,m} is read for the last time at
-// step m, where slot m of row i starts to accumulate W_{i,m}, so one array of
-// 16 values per lane holds both.
+// in place of L: at step m lane m's row of W is complete up to the scale -1 / L_mm
+// (W_mm = 1 / L_mm), the row is broadcast, and every later row i adds
+// L_{i,m} W_{m,k} to its running sum for W_{i,k}.  L_{i,m} is read for the last
+// time at step m, where slot m of row i starts to accumulate, so one array of 16
+// values per lane holds both.  At the end lane i holds -L_ii W_{i,k} for k < i
+// and zeros from slot i on; the squared column norms are summed across the rows
+// by a reduce-scatter (four halving steps), which leaves column li in lane li.
 __device__ __forceinline__ double inv_diag_inplace(cplx (&a)[kSmallK], int li) {
-  double s = 0.0;
+  double guard = 0.0, w = 0.0;   // w: the lane's own 1 / L_{li,li}, kept from step li
 #pragma unroll
   for (int m = 0; m < kSmallK; ++m) {
-    // a[m] is untouched by the earlier steps; tying it to the running sum keeps
-    // the compiler from evaluating every step's pivot up front (16 live
-    // reciprocals and multipliers would push the kernel to one wave per SIMD)
+    // a[m] is untouched by the earlier steps; tying it to the previous step's
+    // result keeps the compiler from evaluating every step's pivot up front (16
+    // live reciprocals and multipliers would push the kernel to one wave per SIMD)
     cplx am = a[m];
-    asm volatile("" : "+v"(am.x), "+v"(am.y) : "v"(s));
+    asm volatile("" : "+v"(am.x), "+v"(am.y) : "v"(guard));
     const double w0 = 1.0 / bcast16(am.x, m);             // 1 / L_mm
+    if (li == m) w = w0;
     // L_{li,m} for the rows below m, zero elsewhere: adding t * W_{m,k} = 0
     // leaves the other rows unchanged
     const cplx t = li > m ? am : cplx{0.0, 0.0};
     a[m] = {0.0, 0.0};
-    cplx own = {0.0, 0.0};                                 // W_{m,li}
 #pragma unroll
     for (int k = 0; k <= m; ++k) {
       // W_{m,k}: lane m holds the unscaled sum, every lane applies -1 / L_mm
       const cplx raw = shfl16(a[k], m);
       const cplx wmk = k == m ? cplx{w0, 0.0} : cplx{raw.x * -w0, raw.y * -w0};
-      if (li == k) own = wmk;
       const cplx u = cmul(t, wmk);
       a[k] = {a[k].x + u.x, a[k].y + u.y};
     }
-    if (li <= m) s += own.x * own.x + own.y * own.y;
+    guard = a[m].x;   // the step's last update
   }
-  return s;
+  const double w2 = w * w;
+  double v[kSmallK];
+#pragma unroll
+  for (int k = 0; k < kSmallK; ++k) v[k] = k == li ? w2 : (a[k].x * a[k].x + a[k].y * a[k].y) * w2;
+  halve16<8, 8, 0x140>(v, li);   // row_mirror
+  halve16<4, 4, 0x141>(v, li);   // row_half_mirror
+  halve16<2, 2, 0x4E>(v, li);    // quad_perm [2, 3, 0, 1]
+  halve16<1, 1, 0xB1>(v, li);    // quad_perm [1, 0, 3, 2]
+  return v[0];
 }
 
 __device__ __forceinline__ void load_row(cplx (&a)[kSmallK], const double* g, int64_t off, int K, int li) {
