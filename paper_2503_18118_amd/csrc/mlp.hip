@@ -904,20 +904,26 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
         wn1[i] = wn2[i];
       }
     }
-    for (int k0 = 32; k0 < K; k0 += 32) {
-      const int kk = k0 + 8 * kg;
-      if (k0 + 64 < K) load_w(l, kk + 64, wn2);
-      bf16x8 af[NB];
+    // the remaining k-steps (K = W past layer 0), unrolled so that the three weight
+    // stages rotate by renaming rather than by register copies
+    if (K > 32) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
+      for (int k0 = 32; k0 < W; k0 += 32) {
+        const int kk = k0 + 8 * kg;
+        if (k0 + 64 < W) load_w(l, kk + 64, wn2);
+        bf16x8 af[NB];
 #pragma unroll
-      for (int i = 0; i < FB; ++i)
+        for (int j = 0; j < NB; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&act[(j * 16 + li) * P + kk]);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < FB; ++i)
 #pragma unroll
-      for (int i = 0; i < FB; ++i) {
-        wcur[i] = wn1[i];
-        wn1[i] = wn2[i];
+          for (int j = 0; j < NB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+          wcur[i] = wn1[i];
+          wn1[i] = wn2[i];
+        }
       }
     }
     if (l + 1 < depth) {   // the next layer's first two k-steps, in flight during this epilogue

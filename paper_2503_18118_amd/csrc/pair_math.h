@@ -85,11 +85,12 @@ __device__ __forceinline__ double amp_product(const PairGeom& g, double ri, doub
   return g.c_fs / (ri * rj);
 }
 
-// r = sqrt(r2) and 1/r, both to FP64 accuracy, without a division: the
-// reciprocal square root from the FP32 estimate and two Newton steps, then one
-// correction of r = r2 / sqrt(r2).
+// r = sqrt(r2) and 1/r without a division: the reciprocal square root from the
+// FP32 estimate and one Newton step (relative error below 4e-14), then one
+// correction of r = r2 / sqrt(r2), which squares that error away: r to FP64
+// rounding (it feeds the phase), 1/r to 4e-14 (it feeds amplitudes only).
 __device__ __forceinline__ void dist_inv(double r2, double& r, double& inv) {
-  inv = rsqrt_nr2(r2);
+  inv = rsqrt_nr1(r2);
   r = r2 * inv;
   r = fma(0.5 * inv, fma(-r, r, r2), r);
 }
