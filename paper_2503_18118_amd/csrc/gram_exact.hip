@@ -339,9 +339,9 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
 // round, 128 elements per workgroup round); the expansion path takes R = 16 (its
 // run feeds two MFMA sets, 256 elements per workgroup round).  Which element sits
 // in which k slot does not matter as long as every user uses the same slots.
-// Products accumulate in FP32 over 512 elements per wave, then in FP64.
+// Products accumulate in FP32 over 1024 elements per wave, then in FP64.
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
-constexpr int kSplitFlushElems = 512;   // elements per wave between FP64 carries
+constexpr int kSplitFlushElems = 1024;   // elements per wave between FP64 carries
 constexpr int kSplitMaxNb = 2;  // user blocks of 16 handled by the split kernel
 
 __device__ __forceinline__ floatx4 mfma_h(halfx8 a, halfx8 b, floatx4 c) {
