@@ -145,49 +145,57 @@ __device__ __forceinline__ Cplx gated_ula(const ArrayK& arr, const UlaUser& up, 
 // Analytic pairs of the ULA variants UNIFORM and GATED_QUAD, one thread per pair over the
 // whole batch (the drop found by bisection of the pairs' offsets).  Writes the entry and its
 // conjugate for analytic pairs and NaN for pairs with a bad user; records every pair's route
-// for k_closedform, which evaluates the numeric ones.
+// for k_closedform, which evaluates the numeric ones.  Lanes past the last pair stay in the
+// wave (idle) until the Fresnel integrals of the uniform form have been completed together.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_cf_pairs(ArrayK arr, const DropK* __restrict__ drops, int n_drops,
                                                   int64_t n_pairs, int variant, const double* __restrict__ pos,
                                                   const double* __restrict__ gl, int n_gl,
                                                   double* __restrict__ gram, int32_t* __restrict__ route_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_pairs) return;
-  int lo = 0, hi = n_drops - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (drops[mid].pair_off <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  const DropK dp = drops[lo];
-  const int K = dp.k;
-  int p, q;
-  pair_of(K, (int)(t - dp.pair_off), p, q);
-  const double d = arr.spacing, lam = arr.lambda;
-  const double c_fs = (lam / (4.0 * kPi)) * (lam / (4.0 * kPi));
-  const double Ly = 0.5 * (double)dp.n_elems * d;
-  const UlaUser up = ula_user(arr, pos + (dp.user_off + p) * 3, Ly, c_fs);
-  const UlaUser uq = ula_user(arr, pos + (dp.user_off + q) * 3, Ly, c_fs);
-  double* out = gram + 2 * dp.gram_off;
-  int word = ROUTE_NONE;
-  bool write = true;
+  const bool valid = t < n_pairs;
+  FresnelReq fr;
+  fr.need[0] = fr.need[1] = false;
   Cplx v = {0.0, 0.0};
-  if (!(up.ok && uq.ok && isfinite(up.diag) && isfinite(uq.diag))) {
-    v = Cplx{__builtin_nan(""), __builtin_nan("")};
-  } else {
-    const PairGeom g{up.x, up.y, uq.x, uq.y, 2.0 * kPi * arr.inv_lambda, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
-    int panels = 0;
-    const int route = numeric_route(g, dp.n_elems, d, n_gl, panels);
-    if (route != ROUTE_NONE) {
-      word = route | (panels << 3);
-      write = false;   // k_closedform evaluates it
-    } else if (variant == XLMIMO_CF_UNIFORM) {
-      v = uniform_pair(g, dp.n_elems, d, gl + 2 * n_gl);   // the Fresnel rule follows the n_gl-node one
+  bool write = false;
+  int K = 0, p = 0, q = 0, word = ROUTE_NONE;
+  double* out = gram;
+  if (valid) {
+    int lo = 0, hi = n_drops - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (drops[mid].pair_off <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const DropK dp = drops[lo];
+    K = dp.k;
+    pair_of(K, (int)(t - dp.pair_off), p, q);
+    const double d = arr.spacing, lam = arr.lambda;
+    const double c_fs = (lam / (4.0 * kPi)) * (lam / (4.0 * kPi));
+    const double Ly = 0.5 * (double)dp.n_elems * d;
+    const UlaUser up = ula_user(arr, pos + (dp.user_off + p) * 3, Ly, c_fs);
+    const UlaUser uq = ula_user(arr, pos + (dp.user_off + q) * 3, Ly, c_fs);
+    out = gram + 2 * dp.gram_off;
+    write = true;
+    if (!(up.ok && uq.ok && isfinite(up.diag) && isfinite(uq.diag))) {
+      v = Cplx{__builtin_nan(""), __builtin_nan("")};
     } else {
-      bool degenerate;
-      v = gated_ula(arr, up, uq, Ly, c_fs, degenerate);
-      if (degenerate) word |= kPairDegenerate;
+      const PairGeom g{up.x, up.y, uq.x, uq.y, 2.0 * kPi * arr.inv_lambda, arr.inv_lambda, arr.amp, arr.beta0, c_fs};
+      int panels = 0;
+      const int route = numeric_route(g, dp.n_elems, d, n_gl, panels);
+      if (route != ROUTE_NONE) {
+        word = route | (panels << 3);
+        write = false;   // k_closedform evaluates it
+      } else if (variant == XLMIMO_CF_UNIFORM) {
+        v = uniform_pair(g, dp.n_elems, d, fr);
+      } else {
+        bool degenerate;
+        v = gated_ula(arr, up, uq, Ly, c_fs, degenerate);
+        if (degenerate) word |= kPairDegenerate;
+      }
     }
   }
+  fresnel_complete(fr, v, gl + 2 * n_gl);   // the Fresnel rule follows the n_gl-node one
+  if (!valid) return;
   route_out[t] = word;
   if (write) {
     out[2 * (p * K + q)] = v.re;

@@ -158,24 +158,22 @@ __device__ Cplx discrete_end_corrections(const PairGeom& g, int n, double d) {
   return total;
 }
 
-// F(s) = int_0^s e^{j sigma t^2 / 2} dt for |s| <= kFresnelSplit (Gauss-Legendre on [0, s]).
-__device__ Cplx fresnel_small(double s, double sigma, const double* __restrict__ gl, int n_gl) {
-  const double half = 0.5 * s;
-  Cplx acc = {0.0, 0.0};
-  for (int q = 0; q < n_gl; ++q) {
-    const double t = half * (1.0 + gl[2 * q]);
-    // e^{j sigma t^2/2}: t^2 / (4 pi) turns
-    const Cplx e = phasor_turns_d(sigma * t * t / (4.0 * kPiPair));
-    acc = cadd(acc, cscale(e, gl[2 * q + 1]));
-  }
-  return cscale(acc, half);
-}
+// The Fresnel integrals F(s_e), |s_e| <= kFresnelSplit, that uniform_pair leaves to its
+// caller: the entry still takes coef[e] F(s_e) for each end e with need[e] set.  A few
+// pairs of a wave need one (about one end in twenty on the sweep's drops), so evaluating
+// them in place would hold every lane of the wave for the whole node loop.
+struct FresnelReq {
+  bool need[2];
+  double s[2], sigma[2];
+  Cplx coef[2];
+};
 
-// Uniform stationary-phase entry of a fast-phase pair (see the file notes).
-// gl_f: the kFresnelNodes-node Gauss-Legendre rule ((node, weight) pairs)
-__device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* __restrict__ gl_f) {
+// Uniform stationary-phase entry of a fast-phase pair (see the file notes), less the
+// Fresnel integrals recorded in fr (fresnel_complete adds them).
+__device__ Cplx uniform_pair(const PairGeom& g, int n, double d, FresnelReq& fr) {
   const double L = 0.5 * (double)n * d;
   Cplx integral = {0.0, 0.0};
+  fr.need[0] = fr.need[1] = false;
   if (g.xi == g.xj) {
     for (int e = 0; e < 2; ++e) {
       const double se = e == 0 ? 1.0 : -1.0;
@@ -237,8 +235,12 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
         endt = cadd(endt, Cplx{qq.im * f, -qq.re * f});
         part = cadd(part, endt);
       } else {
-        const Cplx F = fresnel_small(s, sigma, gl_f, kFresnelNodes);
-        part = cmul(cscale(eph, g0), F);
+        // G0 e^{j phi*} F(s), scaled as the integral below: left to the caller
+        fr.need[e] = true;
+        fr.s[e] = s;
+        fr.sigma[e] = sigma;
+        fr.coef[e] = cscale(eph, se * g0 / d);
+        part = {0.0, 0.0};
         Cplx br;
         if (fabs(s) < kSGuard) {
           const double hh = kSGuard / sq;
@@ -254,6 +256,48 @@ __device__ Cplx uniform_pair(const PairGeom& g, int n, double d, const double* _
     }
   }
   return cadd(cscale(integral, 1.0 / d), discrete_end_corrections(g, n, d));
+}
+
+// Completes the Fresnel integrals F(s) = int_0^s e^{j sigma t^2 / 2} dt that uniform_pair
+// recorded in the wave's lanes (Gauss-Legendre with kFresnelNodes = 32 nodes on [0, s]): the
+// requests go two at a time to the wave's halves, lane q of a half taking node q; the nodes'
+// terms are summed across the half (butterfly) and the requesting lane adds coef F to v.
+// Every lane of the wave calls it (the loop trip count is the wave's, from a ballot).
+// gl_f: the 32-node rule ((node, weight) pairs).
+__device__ void fresnel_complete(const FresnelReq& fr, Cplx& v, const double* __restrict__ gl_f) {
+  static_assert(kFresnelNodes == 32, "one node per lane of a half-wave");
+  const int lane = threadIdx.x & 63, q = lane & 31, upper = lane >> 5;
+  const double xq = gl_f[2 * q], wq = gl_f[2 * q + 1];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    unsigned long long pending = __ballot(fr.need[e]);
+    while (pending != 0) {
+      const int a = __ffsll((long long)pending) - 1;
+      pending &= pending - 1;
+      const int b = pending != 0 ? __ffsll((long long)pending) - 1 : -1;
+      if (b >= 0) pending &= pending - 1;
+      const int src = upper ? b : a;
+      const double s = __shfl(fr.s[e], src < 0 ? a : src);
+      const double sigma = __shfl(fr.sigma[e], src < 0 ? a : src);
+      Cplx term = {0.0, 0.0};
+      if (src >= 0) {
+        const double t = 0.5 * s * (1.0 + xq);
+        // e^{j sigma t^2/2}: t^2 / (4 pi) turns
+        term = cscale(phasor_turns_d(sigma * t * t / (4.0 * kPiPair)), wq);
+      }
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) {
+        term.re += __shfl_xor(term.re, o);
+        term.im += __shfl_xor(term.im, o);
+      }
+      const Cplx sa = {__shfl(term.re, 0), __shfl(term.im, 0)};
+      const Cplx sb = {__shfl(term.re, 32), __shfl(term.im, 32)};
+      if (lane == a || lane == b) {
+        const Cplx F = cscale(lane == a ? sa : sb, 0.5 * fr.s[e]);
+        v = cadd(v, cmul(fr.coef[e], F));
+      }
+    }
+  }
 }
 
 // ---- numeric routes -----------------------------------------------------------
