@@ -437,8 +437,9 @@ __device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double 
   const float w = __builtin_fmaf(-mu, mu, 1.0f);              // 1 - mu^2
   const float q2 = q * q;
   const float mu2 = mu * mu;
+  const float qmu = q * mu;                                   // mu d / r_c, shared by three terms
   x.th[2] = (w * q) * (-0.5f * dsf);                          // -(1 - mu^2) d^2 / (2 r_c)
-  x.th[3] = (mu * x.th[2]) * q;                               // -mu (1 - mu^2) d^3 / (2 r_c^2)
+  x.th[3] = x.th[2] * qmu;                                    // -mu (1 - mu^2) d^3 / (2 r_c^2)
   x.th[4] = (x.th[2] * q2) * __builtin_fmaf(1.25f, mu2, -0.25f);   // -(1 - mu^2)(5 mu^2 - 1) d^4 / (8 r_c^3)
   float b0 = yf;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) b0 = b0 * __builtin_amdgcn_sqrtf(b0);
@@ -446,13 +447,13 @@ __device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double 
   const float bq2 = b0 * q2;
   x.am[0] = b0;
   if constexpr (AMP == XLMIMO_AMP_FREESPACE) {          // Legendre polynomials P_k(mu)
-    x.am[1] = (b0 * mu) * q;
+    x.am[1] = b0 * qmu;
     x.am[2] = bq2 * __builtin_fmaf(1.5f, mu2, -0.5f);
-    x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(2.5f, mu2, -1.5f));
+    x.am[3] = bq2 * (qmu * __builtin_fmaf(2.5f, mu2, -1.5f));
   } else {                                              // C_k^(3/4)(mu)
-    x.am[1] = (b0 * mu) * (1.5f * q);
+    x.am[1] = b0 * (1.5f * qmu);
     x.am[2] = bq2 * __builtin_fmaf(2.625f, mu2, -0.75f);
-    x.am[3] = bq2 * ((q * mu) * __builtin_fmaf(4.8125f, mu2, -2.625f));
+    x.am[3] = bq2 * (qmu * __builtin_fmaf(4.8125f, mu2, -2.625f));
   }
   return x;
 }
