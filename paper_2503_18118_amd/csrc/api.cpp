@@ -859,6 +859,16 @@ int mlp_acts(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, bool train, Acts& a, hipSt
 
 int mlp_forward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, const Acts& a, bool keep_z,
                 hipStream_t s) {
+  if (keep_z && (M->width == 64 || M->width == 128 || M->width == 256)) {
+    // one fused pass through every layer (activations in LDS), storing what the backward reads
+    FwdKeep keep{};
+    for (int l = 0; l + 1 < M->n_layers; ++l) {
+      keep.z[l] = a.z[l];
+      keep.x[l + 1] = a.x[l + 1];
+    }
+    HIP_TRY(c, launch_mlp_fused_train_forward(M->width, M->depth, n, feat, M->wbf, M->master, M->d_offs, keep, a.out, s));
+    return XLMIMO_OK;
+  }
   for (int l = 0; l < M->n_layers; ++l) {
     GemmArgs g{};
     g.M = (int)n;

@@ -211,6 +211,18 @@ hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const
                             double* gram, int32_t* flags, const GateK& gate, hipStream_t s);
 hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                     const float* master, const int64_t* d_offs, float* out, hipStream_t s);
+// What the training forward keeps for the backward pass: hidden layer l's pre-activation
+// z[l] (FP32, n x width) and its GELU output x[l + 1] (BF16, n x width, the next layer's input).
+struct FwdKeep {
+  float* z[kMaxLayers];
+  __bf16* x[kMaxLayers];
+};
+// The fused forward of the training step (widths 64, 128, 256): the inference kernel's pass,
+// storing keep.z / keep.x of every hidden layer besides the output.  Returns
+// hipErrorInvalidValue for other widths (the caller runs the layer GEMMs instead).
+hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
+                                          const float* master, const int64_t* d_offs, const FwdKeep& keep,
+                                          float* out, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;
 constexpr int kDoutPitch = 8;   // bf16 per pair of the output-layer gradient (7 used; 16-byte rows)
 

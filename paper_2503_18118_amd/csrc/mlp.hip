@@ -832,11 +832,15 @@ hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const
 // 128-pair tiles, 0.86 against 0.99 ms per 10^6 pairs with 64-pair tiles).  Wave w
 // owns output columns [w W/NW, (w+1) W/NW) of the hidden layers and row blocks
 // w, w + NW, ... of the output layer.
-template <int W, int NB, int NW>
+// TRAIN: also store each hidden layer's pre-activation (FP32) and GELU output (BF16) for the
+// backward pass (keep); the stores leave from the registers the epilogue already holds (four
+// consecutive features of one pair per lane: one 16-byte and one 8-byte store).
+template <int W, int NB, int NW, bool TRAIN = false>
 __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int depth, const __bf16* __restrict__ feat,
                                                            const __bf16* __restrict__ wbf,
                                                            const float* __restrict__ master,
-                                                           const int64_t* __restrict__ offs, float* __restrict__ out) {
+                                                           const int64_t* __restrict__ offs, float* __restrict__ out,
+                                                           FwdKeep keep) {
   // Activations resident in one LDS buffer (pair-major, features contiguous).  Hidden layers run as
   // out^T = W act^T: the weights are the MFMA's A operand (16 features x 32 k), the activations its B
   // operand (32 k x 16 pairs), so each lane's four results are four consecutive features of one pair
@@ -942,6 +946,20 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
         outv[i][j][3] = (__bf16)gelu(acc[i][j][3]);
       }
     }
+    if constexpr (TRAIN) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int64_t row = row0 + j * 16 + li;
+        if (row < n) {
+#pragma unroll
+          for (int i = 0; i < FB; ++i) {
+            const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
+            *reinterpret_cast<floatx4*>(&keep.z[l][row * W + f0]) = acc[i][j];
+            *reinterpret_cast<bf16x4*>(&keep.x[l + 1][row * W + f0]) = outv[i][j];
+          }
+        }
+      }
+    }
     __syncthreads();   // every wave has read this layer's input
 #pragma unroll
     for (int i = 0; i < FB; ++i) {
@@ -980,9 +998,25 @@ hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf1
   if (n <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((n + 63) / 64);
   const unsigned grid2 = (unsigned)((n + 127) / 128);
-  if (width == 256) k_mlp_fused_forward<256, 8, 4><<<grid2, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
-  else if (width == 128) k_mlp_fused_forward<128, 4, 4><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
-  else if (width == 64) k_mlp_fused_forward<64, 4, 4><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out);
+  const FwdKeep none{};
+  if (width == 256) k_mlp_fused_forward<256, 8, 4><<<grid2, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, none);
+  else if (width == 128) k_mlp_fused_forward<128, 4, 4><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, none);
+  else if (width == 64) k_mlp_fused_forward<64, 4, 4><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, none);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Training batches are 10^3-10^5 pairs: 64-pair tiles at every width, so that a batch of 16384
+// still spreads over 256 workgroups (one per CU).
+hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
+                                          const float* master, const int64_t* d_offs, const FwdKeep& keep,
+                                          float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (depth < 1 || depth >= kMaxLayers) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((n + 63) / 64);
+  if (width == 256) k_mlp_fused_forward<256, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  else if (width == 128) k_mlp_fused_forward<128, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  else if (width == 64) k_mlp_fused_forward<64, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
