@@ -953,7 +953,19 @@ int mlp_backward(xlmimo_ctx* c, xlmimo_mlp* M, int64_t n, const __bf16* feat, co
     std::vector<int64_t> ldzs(NL);
     dzs[NL - 1] = a.dout;
     ldzs[NL - 1] = kDoutPitch;
-    for (int l = NL - 1; l >= 1; --l) {
+    const bool fused_dx = M->width == 64 || M->width == 128 || M->width == 256;
+    if (fused_dx) {
+      // the whole chain in one pass (gradients in LDS), storing every hidden layer's dZ
+      BwdKeep bk{};
+      for (int l = 0; l + 1 < NL; ++l) {
+        bk.z[l] = a.z[l];
+        bk.dz[l] = a.dz[l];
+        dzs[l] = a.dz[l];
+        ldzs[l] = M->in_dim[l + 1];
+      }
+      HIP_TRY(c, launch_mlp_fused_train_backward(M->width, M->depth, n, a.dout, M->wbf_t, M->d_offs, bk, s));
+    }
+    for (int l = NL - 1; l >= 1 && !fused_dx; --l) {
       GemmArgs gx{};
       gx.M = (int)n;
       gx.N = M->in_dim[l];

@@ -223,6 +223,15 @@ struct FwdKeep {
 hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                           const float* master, const int64_t* d_offs, const FwdKeep& keep,
                                           float* out, hipStream_t s);
+// The input-gradient chain of the training step in one fused pass (widths 64, 128, 256): from the
+// output gradient dout (BF16, n x 8) down through every layer, dZ[l - 1] = (dZ[l] W[l]) * GELU'(z[l - 1]),
+// stored to dz[l - 1] (BF16, n x width) for the weight gradients; W[l]^T is read from wbf_t.
+struct BwdKeep {
+  const float* z[kMaxLayers];
+  __bf16* dz[kMaxLayers];
+};
+hipError_t launch_mlp_fused_train_backward(int width, int depth, int64_t n, const __bf16* dout, const __bf16* wbf_t,
+                                           const int64_t* d_offs, const BwdKeep& keep, hipStream_t s);
 constexpr int kMlpHeadBlocks = 256;
 constexpr int kDoutPitch = 8;   // bf16 per pair of the output-layer gradient (7 used; 16-byte rows)
 

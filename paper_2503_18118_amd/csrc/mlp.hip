@@ -993,6 +993,106 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_fused_forward(int64_t n, int de
   }
 }
 
+// The training step's input-gradient chain, fused like the forward: one workgroup of NW waves
+// carries a tile of 16 NB pairs from the output gradient down to layer 1, the current gradient at
+// the pre-activation (BF16, as the layer GEMMs round it) in one LDS buffer.  Layer l's product
+// dA = dZ[l] W[l] runs as dA^T = W[l]^T dZ[l]^T: the transposed weights (k = output index
+// contiguous) are the MFMA's A operand, the LDS gradient its B operand, so each lane's four results
+// are four consecutive input features of one pair, multiplied by GELU'(z) of the same four features
+// (one 16-byte load of the stored pre-activation) and stored as four BF16.  Wave w owns input
+// features [w W/NW, (w+1) W/NW); the output layer's 7 rows enter as K = 32 with zeros beyond.
+template <int W, int NB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mlp_fused_train_backward(int64_t n, int depth,
+                                                                  const __bf16* __restrict__ dout,
+                                                                  const __bf16* __restrict__ wbf_t,
+                                                                  const int64_t* __restrict__ offs, BwdKeep keep) {
+  constexpr int P = W + 8;
+  constexpr int FB = W / (16 * NW);
+  __shared__ __attribute__((aligned(16))) __bf16 grad[16 * NB * P];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * (16 * NB);
+  const int kg = lane >> 4, li = lane & 15;
+  const bf16x8 zero8 = {};
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+  // the output gradient: 7 values per pair (pitch kDoutPitch), zero up to K = 32
+  for (int i = tid; i < 16 * NB * 32; i += 64 * NW) {
+    const int r = i >> 5, k = i & 31;
+    grad[r * P + k] = (k < XLMIMO_MLP_OUT && row0 + r < n) ? dout[(row0 + r) * kDoutPitch + k] : (__bf16)0.0f;
+  }
+  __syncthreads();
+
+  // W[l]^T fragment: input feature f, output indices kk .. kk + 7
+  auto load_wt = [&](int l, int kk, bf16x8 (&wf)[FB]) {
+    const __bf16* Wt = wbf_t + offs[2 * l];
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+      const int f = wave * (W / NW) + i * 16 + li;
+      if (l == depth) {   // the output layer: W^T is W x 7
+        bf16x8 v = zero8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (kk + q < XLMIMO_MLP_OUT) v[q] = Wt[f * XLMIMO_MLP_OUT + kk + q];
+        wf[i] = v;
+      } else {
+        wf[i] = *reinterpret_cast<const bf16x8*>(&Wt[(int64_t)f * W + kk]);
+      }
+    }
+  };
+  bf16x8 wcur[FB], wnext[FB];
+  load_wt(depth, 8 * kg, wcur);
+  for (int l = depth; l >= 1; --l) {
+    const int K = (l == depth) ? 32 : W;
+    floatx4 acc[FB][NB];
+#pragma unroll
+    for (int i = 0; i < FB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kk = k0 + 8 * kg;
+      if (k0 + 32 < K) load_wt(l, kk + 32, wnext);
+      bf16x8 af[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) af[j] = *reinterpret_cast<const bf16x8*>(&grad[(j * 16 + li) * P + kk]);
+#pragma unroll
+      for (int i = 0; i < FB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], af[j], acc[i][j], 0, 0, 0);
+      if (k0 + 32 < K) {
+#pragma unroll
+        for (int i = 0; i < FB; ++i) wcur[i] = wnext[i];
+      }
+    }
+    if (l > 1) load_wt(l - 1, 8 * kg, wcur);   // in flight during the epilogue
+    // dZ[l - 1] = dA * GELU'(z[l - 1]), rounded to BF16
+    const float* zl = keep.z[l - 1];
+    bf16x4 outv[FB][NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int64_t row = row0 + j * 16 + li;
+#pragma unroll
+      for (int i = 0; i < FB; ++i) {
+        const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
+        const floatx4 zv = row < n ? *reinterpret_cast<const floatx4*>(&zl[row * W + f0]) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) outv[i][j][c] = (__bf16)(acc[i][j][c] * gelu_grad(zv[c]));
+      }
+    }
+    __syncthreads();   // every wave has read this layer's gradient
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int64_t row = row0 + j * 16 + li;
+#pragma unroll
+      for (int i = 0; i < FB; ++i) {
+        const int f0 = wave * (W / NW) + i * 16 + 4 * kg;
+        *reinterpret_cast<bf16x4*>(&grad[(j * 16 + li) * P + f0]) = outv[i][j];
+        if (row < n) *reinterpret_cast<bf16x4*>(&keep.dz[l - 1][row * W + f0]) = outv[i][j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                     const float* master, const int64_t* d_offs, float* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -1006,17 +1106,35 @@ hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf1
   return hipGetLastError();
 }
 
-// Training batches are 10^3-10^5 pairs: 64-pair tiles at every width, so that a batch of 16384
-// still spreads over 256 workgroups (one per CU).
+// Training batches are 10^3-10^5 pairs, so the tiles are small: at width 256, 8 waves of 32
+// features over 64 pairs from 16384 pairs on (256 workgroups and more), 32 pairs below (batch
+// 16384: 125 TFLOP/s for the whole step against 115 with 4 waves of 64 features; batch 8192:
+// 91 against 80 with 64-pair tiles).
 hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                           const float* master, const int64_t* d_offs, const FwdKeep& keep,
                                           float* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (depth < 1 || depth >= kMaxLayers) return hipErrorInvalidValue;
-  const unsigned grid = (unsigned)((n + 63) / 64);
-  if (width == 256) k_mlp_fused_forward<256, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  const unsigned grid = (unsigned)((n + 63) / 64), grid32 = (unsigned)((n + 31) / 32);
+  if (width == 256 && n >= 16384)
+    k_mlp_fused_forward<256, 4, 8, true><<<grid, 512, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  else if (width == 256) k_mlp_fused_forward<256, 2, 8, true><<<grid32, 512, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else if (width == 128) k_mlp_fused_forward<128, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else if (width == 64) k_mlp_fused_forward<64, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_fused_train_backward(int width, int depth, int64_t n, const __bf16* dout, const __bf16* wbf_t,
+                                           const int64_t* d_offs, const BwdKeep& keep, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (depth < 1 || depth >= kMaxLayers) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((n + 63) / 64), grid32 = (unsigned)((n + 31) / 32);
+  if (width == 256 && n >= 16384)   // the tiles of the forward above
+    k_mlp_fused_train_backward<256, 4, 8><<<grid, 512, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
+  else if (width == 256) k_mlp_fused_train_backward<256, 2, 8><<<grid32, 512, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
+  else if (width == 128) k_mlp_fused_train_backward<128, 4, 4><<<grid, 256, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
+  else if (width == 64) k_mlp_fused_train_backward<64, 4, 4><<<grid, 256, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
