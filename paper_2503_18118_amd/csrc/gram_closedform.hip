@@ -70,13 +70,17 @@ __device__ double solid_angle_rect(double x, double u1, double u2, double v1, do
 
 // ULA user i: perpendicular distance x, position y along the array, closed-form
 // diagonal G~_ii and (PNUSW) the aperture factor S of eq. (4).  ok is false for
-// a user on the array line or with non-finite coordinates.
+// a user on the array line or with non-finite coordinates.  The pair kernel needs
+// the free-space diagonal only to know that it is finite: with diag_value false it
+// takes diag = c_fs / (d x), finite exactly when the diagonal is (the arctangent sum
+// is bounded and nonzero), and skips the two FP64 arctangents.
 struct UlaUser {
   double x, y, diag, sfac;
   bool ok;
 };
 
-__device__ __forceinline__ UlaUser ula_user(const ArrayK& arr, const double* __restrict__ p, double Ly, double c_fs) {
+__device__ __forceinline__ UlaUser ula_user(const ArrayK& arr, const double* __restrict__ p, double Ly, double c_fs,
+                                            bool diag_value = true) {
   UlaUser u;
   const double px = p[0], py = p[1], pz = p[2];
   u.x = sqrt(fma(px, px, pz * pz));
@@ -90,8 +94,10 @@ __device__ __forceinline__ UlaUser ula_user(const ArrayK& arr, const double* __r
     const double a = Ly - py, b = Ly + py;
     u.sfac = a / sqrt(fma(a, a, u.x * u.x)) + b / sqrt(fma(b, b, u.x * u.x));
     u.diag = arr.beta0 / (d * u.x) * u.sfac;
-  } else {
+  } else if (diag_value) {
     u.diag = c_fs / (d * u.x) * (atan((Ly - py) / u.x) + atan((Ly + py) / u.x));
+  } else {
+    u.diag = c_fs / (d * u.x);
   }
   return u;
 }
@@ -172,8 +178,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const double d = arr.spacing, lam = arr.lambda;
     const double c_fs = (lam / (4.0 * kPi)) * (lam / (4.0 * kPi));
     const double Ly = 0.5 * (double)dp.n_elems * d;
-    const UlaUser up = ula_user(arr, pos + (dp.user_off + p) * 3, Ly, c_fs);
-    const UlaUser uq = ula_user(arr, pos + (dp.user_off + q) * 3, Ly, c_fs);
+    // no closed-form diagonal is read here (k_closedform writes it): only its finiteness
+    const UlaUser up = ula_user(arr, pos + (dp.user_off + p) * 3, Ly, c_fs, false);
+    const UlaUser uq = ula_user(arr, pos + (dp.user_off + q) * 3, Ly, c_fs, false);
     out = gram + 2 * dp.gram_off;
     write = true;
     if (!(up.ok && uq.ok && isfinite(up.diag) && isfinite(uq.diag))) {

@@ -408,20 +408,27 @@ __device__ __forceinline__ void split_pair(const float* a, const float* c, const
 // relative for free space and 4.3e-7 for the projected aperture (it peaks at the
 // run's ends, where |m'| = 7.5).  The FP32 evaluation leaves |phase error| <=
 // 5e-7 turns at d = 1/2 (9e-7 at d = 1: the phase is carried to |theta| < 4.3
-// turns, so its rounding dominates) and 3e-7 relative in the amplitude.  Items
-// whose users come closer take the per-element FP64 path.
+// turns, so its rounding dominates) and 3e-7 relative in the amplitude.
+// A second tier (TIER = 2) serves users between kExpandXmin2 = 184 and 368 spacings:
+// the phase to t^6 (C_5 = mu (1 - mu^2)(7 mu^2 - 3) / 8, C_6 = (1 - mu^2)(21 mu^4
+// - 14 mu^2 + 1) / 16) and the amplitude to t^4 (P_4, C_4^(3/4)); at x >= 184 d the
+// first dropped phase term is below 5e-9 turns and the first dropped amplitude term
+// at most C_5(1) (7.5 / 184)^5: 1.1e-7 (free space), 3.0e-7 (projected aperture).
+// Three FMAs more per two elements.  Items whose users come closer still take the
+// per-element FP64 path.
 constexpr double kExpandXmin = 368.0;
+constexpr double kExpandXmin2 = 184.0;
 constexpr int kExpandRun = 16;
 
-template <int AMP>
+template <int AMP, int TIER = 1>
 struct Expansion {
-  float th[5];   // minus the phase in turns: -c0, then the coefficients of m', ..., m'^4 (all negated)
-  float am[4];   // amplitude (times the user scale): coefficients of 1, m', m'^2, m'^3
+  float th[TIER == 2 ? 7 : 5];   // minus the phase in turns: -c0, then the coefficients of m', m'^2, ... (all negated)
+  float am[TIER == 2 ? 5 : 4];   // amplitude (times the user scale): coefficients of 1, m', m'^2, ...
 };
 
-template <int AMP>
-__device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double ds, float us) {
-  Expansion<AMP> x;
+template <int AMP, int TIER = 1>
+__device__ __forceinline__ Expansion<AMP, TIER> expand(double dyc, double xp2, double ds, float us) {
+  Expansion<AMP, TIER> x;
   const double r2 = fma(dyc, dyc, xp2);
   const float yf = __builtin_amdgcn_rsqf((float)r2);
   const double y0 = (double)yf;
@@ -455,19 +462,36 @@ __device__ __forceinline__ Expansion<AMP> expand(double dyc, double xp2, double 
     x.am[2] = bq2 * __builtin_fmaf(2.625f, mu2, -0.75f);
     x.am[3] = bq2 * (qmu * __builtin_fmaf(4.8125f, mu2, -2.625f));
   }
+  if constexpr (TIER == 2) {
+    x.th[5] = (x.th[3] * q2) * __builtin_fmaf(1.75f, mu2, -0.75f);   // -mu (1 - mu^2)(7 mu^2 - 3) d^5 / (8 r_c^4)
+    x.th[6] = (x.th[2] * (q2 * q2)) *
+              __builtin_fmaf(__builtin_fmaf(2.625f, mu2, -1.75f), mu2, 0.125f);   // -C_6 d^6 / r_c^5
+    if constexpr (AMP == XLMIMO_AMP_FREESPACE)
+      x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(4.375f, mu2, -3.75f), mu2, 0.375f);
+    else
+      x.am[4] = (bq2 * q2) * __builtin_fmaf(__builtin_fmaf(9.0234375f, mu2, -7.21875f), mu2, 0.65625f);
+  }
   return x;
 }
 
 // The two elements at m' = -p and +p from the even and odd parts of both series,
 // with the phase carried negated (so that sn = sin(-theta) needs no sign flip):
-// -theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (9 FMAs per pair).
-template <int AMP>
-__device__ __forceinline__ void expansion_pair(const Expansion<AMP>& x, float p, float (&a)[2], float (&c)[2],
+// -theta(+-p) = E(p^2) +- p O(p^2), A(+-p) = Ae(p^2) +- p Ao(p^2) (9 FMAs per pair, 12 for
+// the second tier).
+template <int AMP, int TIER>
+__device__ __forceinline__ void expansion_pair(const Expansion<AMP, TIER>& x, float p, float (&a)[2], float (&c)[2],
                                                float (&sn)[2]) {
   const float p2 = p * p;
-  const float ev = __builtin_fmaf(__builtin_fmaf(x.th[4], p2, x.th[2]), p2, x.th[0]);
-  const float od = __builtin_fmaf(x.th[3], p2, x.th[1]);
-  const float ae = __builtin_fmaf(x.am[2], p2, x.am[0]);
+  float ev, od, ae;
+  if constexpr (TIER == 2) {
+    ev = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(x.th[6], p2, x.th[4]), p2, x.th[2]), p2, x.th[0]);
+    od = __builtin_fmaf(__builtin_fmaf(x.th[5], p2, x.th[3]), p2, x.th[1]);
+    ae = __builtin_fmaf(__builtin_fmaf(x.am[4], p2, x.am[2]), p2, x.am[0]);
+  } else {
+    ev = __builtin_fmaf(__builtin_fmaf(x.th[4], p2, x.th[2]), p2, x.th[0]);
+    od = __builtin_fmaf(x.th[3], p2, x.th[1]);
+    ae = __builtin_fmaf(x.am[2], p2, x.am[0]);
+  }
   const float ao = __builtin_fmaf(x.am[3], p2, x.am[1]);
   const float th0 = __builtin_fmaf(-p, od, ev), th1 = __builtin_fmaf(p, od, ev);
   a[0] = __builtin_fmaf(-p, ao, ae);
@@ -478,11 +502,15 @@ __device__ __forceinline__ void expansion_pair(const Expansion<AMP>& x, float p,
   sn[1] = __builtin_amdgcn_sinf(th1);
 }
 
-template <int NB, int GEOM, int AMP, bool EXPAND>
+// EXPAND: 0 the per-element FP64 path, 1 or 2 the expansion tier.
+template <int NB, int GEOM, int AMP, int EXPAND>
 __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, const UserLane (&u)[NB],
                            const float (&us)[NB], double* __restrict__ part_out, double* s_red);
 
-template <int NB, int GEOM, int AMP>
+// TIER2: whether users between 184 and 368 spacings take the second expansion tier (the kernels
+// for batches of at most 32 users) or the per-element path (the kernels that also hold the larger
+// drops' paths, whose register budget the second tier's code would strain).
+template <int NB, int GEOM, int AMP, bool TIER2 = true>
 __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const ItemK& it,
                                    const double* __restrict__ pos, double* __restrict__ part_out, double* s_red) {
   const int lane = threadIdx.x & 63;
@@ -491,8 +519,8 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
   UserLane u[NB];
   float us[NB];
   const double ds = arr.spacing * sc;
-  const double xmin = kExpandXmin * ds;
-  bool near = false;
+  const double xmin = kExpandXmin * ds, xmin2 = kExpandXmin2 * ds;
+  bool near = false, near2 = false;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int k = 16 * b + (lane & 15);
@@ -508,14 +536,20 @@ __device__ void process_item_split(const ArrayK& arr, const DropK& dp, const Ite
     u[b].uz = z;
     us[b] = k < dp.k ? __builtin_ldexpf(1.0f, split_exp(u[b].xp2, AMP)) : 1.0f;
     near |= !(u[b].xp2 >= xmin * xmin);
+    near2 |= !(u[b].xp2 >= xmin2 * xmin2);
   }
   // every wave of the workgroup holds the same users, so they all take the same path
-  const bool expand = (GEOM == XLMIMO_ULA || arr.n_z % kExpandRun == 0) && !__any(near);
-  if (expand) split_body<NB, GEOM, AMP, true>(arr, dp, it, u, us, part_out, s_red);
-  else split_body<NB, GEOM, AMP, false>(arr, dp, it, u, us, part_out, s_red);
+  const bool runs = GEOM == XLMIMO_ULA || arr.n_z % kExpandRun == 0;
+  if (runs && !__any(near)) {
+    split_body<NB, GEOM, AMP, 1>(arr, dp, it, u, us, part_out, s_red);
+  } else if (TIER2 && runs && !__any(near2)) {
+    if constexpr (TIER2) split_body<NB, GEOM, AMP, 2>(arr, dp, it, u, us, part_out, s_red);
+  } else {
+    split_body<NB, GEOM, AMP, 0>(arr, dp, it, u, us, part_out, s_red);
+  }
 }
 
-template <int NB, int GEOM, int AMP, bool EXPAND>
+template <int NB, int GEOM, int AMP, int EXPAND>
 __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, const UserLane (&u)[NB],
                            const float (&us)[NB], double* __restrict__ part_out, double* s_red) {
   constexpr int NRE = NB * (NB + 1) / 2;
@@ -599,11 +633,11 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
     constexpr bool TAIL = decltype(tail_tag)::value;
     if constexpr (EXPAND) {
       // the run's centre, element e + 7.5, and the expansion of each user about it
-      Expansion<AMP> x[NB];
+      Expansion<AMP, EXPAND> x[NB];
       if constexpr (GEOM == XLMIMO_ULA) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          x[b] = expand<AMP>(dyc[b], u[b].xp2, ds, us[b]);
+          x[b] = expand<AMP, EXPAND>(dyc[b], u[b].xp2, ds, us[b]);
           dyc[b] -= ROUND * ds;
         }
       } else {
@@ -612,7 +646,7 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const double dy = u[b].uy - ey;
-          x[b] = expand<AMP>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
+          x[b] = expand<AMP, EXPAND>(u[b].uz - ez, fma(dy, dy, u[b].xp2), ds, us[b]);
         }
         ca += qa;
         cb += qb;
@@ -632,7 +666,7 @@ __device__ void split_body(const ArrayK& arr, const DropK& dp, const ItemK& it, 
           for (int j = 0; j < 4; ++j) {
             const int k = 4 * s + j;
             float a[2], c[2], sn[2];
-            expansion_pair<AMP>(x[b], 0.5f + (float)k, a, c, sn);
+            expansion_pair(x[b], 0.5f + (float)k, a, c, sn);
             if constexpr (TAIL) {
               a[0] = e + 7 - k < it.e_end ? a[0] : 0.0f;
               a[1] = e + 8 + k < it.e_end ? a[1] : 0.0f;
@@ -1015,8 +1049,8 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(SP
     double* out = partials + dp.part_off + it.chunk * (int64_t)(partial_values(dp.nb) * 64);
     if constexpr (SPLIT) {
       switch (dp.nb) {
-        case 1: process_item_split<1, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
-        case 2: if constexpr (NBM >= 2) process_item_split<2, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
+        case 1: process_item_split<1, GEOM, AMP, (NBM <= 2)>(arr, dp, it, pos, out, s_red); break;
+        case 2: if constexpr (NBM >= 2) process_item_split<2, GEOM, AMP, (NBM <= 2)>(arr, dp, it, pos, out, s_red); break;
         // 33-48 users, and the cross blocks of virtual drops (more than 64 users): FP32C products
         case 3: if constexpr (NBM >= 3 && !WIDE_ONLY) process_item<3, float, GEOM, AMP>(arr, dp, it, pos, out, s_red); break;
         case 4:

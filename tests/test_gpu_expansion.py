@@ -1,13 +1,16 @@
-"""The FP32H exact Gram's two channel paths against the FP64 oracle.
+"""The FP32H exact Gram's channel paths against the FP64 oracle.
 
 Items whose users are all at least 368 element spacings from the array line
-(plane) evaluate each lane's run of 8 consecutive elements from an FP64 distance
+(plane) evaluate each lane's run of 16 consecutive elements from an FP64 distance
 and phase at the run's centre plus FP32 expansions of the phase and amplitude
-along the run; other items evaluate every element in FP64.  Each case below is
-built so that one path or the other must run (users all far, or one user near),
-for the ULA and the UPA, both amplitude models and three spacings, and each is
-held to the exact form's tolerance (1e-5 normwise) against the oracle, with
-ragged element counts so that the last run of an item is partial."""
+along the run; in batches of at most 32 users, items whose users are all at least
+184 spacings away take a second tier of the expansion (two more phase terms, one
+more amplitude term); other items evaluate every element in FP64.  Each case below
+is built so that one path must run (users all far, one user between 184 and 368
+spacings, or one user nearer), for the ULA and the UPA, both amplitude models and
+three spacings, and each is held to the exact form's tolerance (1e-5 normwise)
+against the oracle, with ragged element counts so that the last run of an item is
+partial."""
 import numpy as np
 import pytest
 import torch
@@ -19,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 XMIN = 368.0   # element spacings
+XMIN2 = 184.0  # the second expansion tier
 
 
 @pytest.fixture(scope="module")
@@ -69,13 +73,31 @@ def test_ula_far_and_near_users(X, ctx, amp, spacing_lam):
     ns = [1000, 4099, 70001, 129, 16384]
     ks = [16, 9, 16, 32, 5]
     far = [_users(rng, k, x_far, x_far + 40.0, 30.0) for k in ks]          # expansion path
+    mid = [u.copy() for u in far]
+    for u in mid:
+        u[-1, 0] = XMIN2 * d * 1.001                                         # one user at 184 d: second tier
     near = [u.copy() for u in far]
     for u in near:
-        u[-1, 0] = x_far * 0.5                                               # one user near: FP64 path
+        u[-1, 0] = XMIN2 * d * 0.8                                           # one user nearer: FP64 path
     arr = W.ula(1, lam, amp, spacing=d)
     w_far = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(far)), "far users")
+    w_mid = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(mid)), "one user at 184 spacings")
     w_near = _check(X, ctx, arr, W._pack(ns, ks, np.concatenate(near)), "one near user")
-    print(f"worst normwise error: far {w_far:.2e}, near {w_near:.2e}", flush=True)
+    print(f"worst normwise error: far {w_far:.2e}, 184 d {w_mid:.2e}, near {w_near:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("amp", [W.AMP_FREESPACE, W.AMP_PNUSW])
+def test_upa_second_tier(X, ctx, amp):
+    # users between 184 and 368 spacings of a panel whose columns hold whole runs: the second tier
+    lam = W.LAMBDA_100GHZ_UPA
+    d = lam / 2
+    rng = np.random.default_rng(184 + amp)
+    k = 16
+    users = [_users(rng, k, XMIN2 * d * 1.001, XMIN * d * 0.99, 0.3, 0.3) for _ in range(3)]
+    arr = W.ArraySpec(W.GEOM_UPA, 48, 32, d, lam, amp)
+    drops = W._pack([48 * 32] * 3, [k] * 3, np.concatenate(users))
+    w = _check(X, ctx, arr, drops, "UPA 48x32, users at 184-368 spacings")
+    print(f"worst normwise error {w:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("ny,nz", [(40, 64), (33, 24), (16, 21)])
