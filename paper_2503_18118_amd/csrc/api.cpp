@@ -184,7 +184,8 @@ int check_array(xlmimo_ctx* c, const xlmimo_array* a) {
   if (a->amp_model == XLMIMO_AMP_PNUSW && !finite_pos(a->beta0)) return set_err(c, XLMIMO_EINVAL, "beta0 must be finite and > 0");
   if (a->n_y < 1 || a->n_z < 1) return set_err(c, XLMIMO_EINVAL, "array sizes must be >= 1");
   if (a->geometry == XLMIMO_ULA && a->n_z != 1) return set_err(c, XLMIMO_EINVAL, "a ULA has n_z == 1");
-  if (a->n_y * a->n_z > 2147483647LL) return set_err(c, XLMIMO_EINVAL, "at most 2^31-1 elements");
+  if (a->n_y > 2147483647LL || a->n_z > 2147483647LL || a->n_y * a->n_z > 2147483647LL)
+    return set_err(c, XLMIMO_EINVAL, "at most 2^31-1 elements");
   return XLMIMO_OK;
 }
 
@@ -298,55 +299,52 @@ int get_plan(xlmimo_ctx* c, const xlmimo_array* a, const xlmimo_batch* b, const 
   return XLMIMO_OK;
 }
 
-int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of, const int32_t* kk, uint64_t h,
-               Plan& p, const int32_t* cross) {
-  p.n_drops = n;
-  std::vector<DropK> drops(n);
-  int64_t uoff = 0, goff = 0, total_elems = 0, pairs = 0;
-  bool has3_or_cross = false;
+// Host layout of a batch: each drop's descriptor (its users', Gram entries', user pairs' and
+// partial images' offsets) and the work items, chunk-long element ranges of every drop in
+// longest-first order (stable for equal costs) for the persistent queue.  No device call.
+struct HostLayout {
+  std::vector<DropK> drops;
+  std::vector<ItemK> items;
+  int nb_max = 1, k_max = 1;
+  bool has3_or_cross = false;   // a 3-block drop or a cross-only virtual drop
+  int64_t total_users = 0, gram_elems = 0, n_pairs = 0, total_elems = 0, partial_doubles = 0;
+};
+
+void layout_drops(int n, const int64_t* ne_of, const int32_t* kk, const int32_t* cross, HostLayout& L) {
+  L.drops.assign(n, DropK{});
   for (int d = 0; d < n; ++d) {
-    DropK& dk = drops[d];
+    DropK& dk = L.drops[d];
     const int64_t ne = ne_of[d];
     dk.n_elems = (int32_t)ne;
     dk.k = kk[d];
     dk.cross = cross ? cross[d] : 0;
     dk.nb = (dk.k + 15) / 16;
-    dk.user_off = uoff;
-    dk.gram_off = goff;
-    dk.pair_off = pairs;
-    pairs += (int64_t)dk.k * (dk.k - 1) / 2;
-    uoff += dk.k;
-    goff += (int64_t)dk.k * dk.k;
-    total_elems += ne;
-    p.nb_max = std::max(p.nb_max, dk.nb);
-    p.k_max = std::max(p.k_max, dk.k);
-    has3_or_cross = has3_or_cross || dk.nb == 3 || dk.cross;
+    dk.user_off = L.total_users;
+    dk.gram_off = L.gram_elems;
+    dk.pair_off = L.n_pairs;
+    L.n_pairs += (int64_t)dk.k * (dk.k - 1) / 2;
+    L.total_users += dk.k;
+    L.gram_elems += (int64_t)dk.k * dk.k;
+    L.total_elems += ne;
+    L.nb_max = std::max(L.nb_max, dk.nb);
+    L.k_max = std::max(L.k_max, dk.k);
+    L.has3_or_cross = L.has3_or_cross || dk.nb == 3 || dk.cross;
   }
-  if (p.nb_max == 4 && !has3_or_cross) p.nb_max = kNbWide;
-  p.total_users = uoff;
-  p.gram_elems = goff;
-  p.n_pairs = pairs;
-  p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
-  p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
-  p.grid_fp32h = gram_exact_grid(XLMIMO_FP32H, p.nb_max, a->geometry, a->amp_model);
-  auto tc = c->tuned_chunk.find(h);
-  const int64_t ch = tc != c->tuned_chunk.end()
-                         ? tc->second
-                         : chunk_length(total_elems, std::min(std::min(p.grid_fp32, p.grid_fp64), p.grid_fp32h));
-  p.chunk = ch;
-  p.key = h;
+}
+
+void layout_items(int64_t ch, HostLayout& L) {
   std::vector<ItemK> items;
   std::vector<int64_t> cost;
   int64_t poff = 0;
-  for (int d = 0; d < n; ++d) {
-    DropK& dk = drops[d];
+  for (size_t d = 0; d < L.drops.size(); ++d) {
+    DropK& dk = L.drops[d];
     const int64_t ni = (dk.n_elems + ch - 1) / ch;
     dk.n_items = (int32_t)ni;
     dk.part_off = poff;
     poff += ni * (int64_t)partial_values(dk.nb) * 64;
     for (int64_t i = 0; i < ni; ++i) {
       ItemK itm;
-      itm.drop = d;
+      itm.drop = (int32_t)d;
       itm.chunk = (int32_t)i;
       itm.e_begin = (int32_t)(i * ch);
       itm.e_end = (int32_t)std::min<int64_t>((i + 1) * ch, dk.n_elems);
@@ -355,18 +353,42 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
       cost.push_back((int64_t)(itm.e_end - itm.e_begin) * (nb * 8 + 3 * (nb * (nb + 1) / 2 + nb * nb)));
     }
   }
-  // longest-first order for the persistent queue (stable for equal costs)
   std::vector<int> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  std::vector<ItemK> sorted(items.size());
-  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
-  p.n_items = (int)sorted.size();
-  p.partial_doubles = poff;
+  L.items.resize(items.size());
+  for (size_t i = 0; i < order.size(); ++i) L.items[i] = items[order[i]];
+  L.partial_doubles = poff;
+}
+
+int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of, const int32_t* kk, uint64_t h,
+               Plan& p, const int32_t* cross) {
+  p.n_drops = n;
+  HostLayout L;
+  layout_drops(n, ne_of, kk, cross, L);
+  p.nb_max = L.nb_max;
+  p.k_max = L.k_max;
+  if (p.nb_max == 4 && !L.has3_or_cross) p.nb_max = kNbWide;
+  p.total_users = L.total_users;
+  p.gram_elems = L.gram_elems;
+  p.n_pairs = L.n_pairs;
+  p.grid_fp32 = gram_exact_grid(XLMIMO_FP32C, p.nb_max, a->geometry, a->amp_model);
+  p.grid_fp64 = gram_exact_grid(XLMIMO_FP64, p.nb_max, a->geometry, a->amp_model);
+  p.grid_fp32h = gram_exact_grid(XLMIMO_FP32H, p.nb_max, a->geometry, a->amp_model);
+  auto tc = c->tuned_chunk.find(h);
+  const int64_t ch = tc != c->tuned_chunk.end()
+                         ? tc->second
+                         : chunk_length(L.total_elems, std::min(std::min(p.grid_fp32, p.grid_fp64), p.grid_fp32h));
+  p.chunk = ch;
+  p.key = h;
+  layout_items(ch, L);
+  p.n_items = (int)L.items.size();
+  p.partial_doubles = L.partial_doubles;
   HIP_TRY(c, hipMalloc(&p.d_drops, sizeof(DropK) * std::max(n, 1)));
-  HIP_TRY(c, hipMalloc(&p.d_items, sizeof(ItemK) * std::max<size_t>(sorted.size(), 1)));
-  HIP_TRY(c, hipMemcpy(p.d_drops, drops.data(), sizeof(DropK) * n, hipMemcpyHostToDevice));
-  if (!sorted.empty()) HIP_TRY(c, hipMemcpy(p.d_items, sorted.data(), sizeof(ItemK) * sorted.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMalloc(&p.d_items, sizeof(ItemK) * std::max<size_t>(L.items.size(), 1)));
+  HIP_TRY(c, hipMemcpy(p.d_drops, L.drops.data(), sizeof(DropK) * n, hipMemcpyHostToDevice));
+  if (!L.items.empty())
+    HIP_TRY(c, hipMemcpy(p.d_items, L.items.data(), sizeof(ItemK) * L.items.size(), hipMemcpyHostToDevice));
   return XLMIMO_OK;
 }
 
