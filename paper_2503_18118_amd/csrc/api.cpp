@@ -392,13 +392,35 @@ int build_plan(xlmimo_ctx* c, const xlmimo_array* a, int n, const int64_t* ne_of
   return XLMIMO_OK;
 }
 
-// Virtual drops of a batch with K > XLMIMO_MAX_USERS.  A drop with K <=
-// XLMIMO_MAX_USERS is one virtual drop of its own; a larger one has
-// g = ceil(K / kGroupUsers) groups (group i holds users [32 i, min(32 i + 32, K)),
-// so only the last is short and it is never group a) and one virtual drop per
-// group pair a < b.  The pairs (a, a + 1) compute their whole Gram and give
-// group a's own block (the last group's from (g - 2, g - 1)); every other pair
-// computes only the products between its two groups.
+// The virtual drops of one drop of K users.  K <= XLMIMO_MAX_USERS: one of its own (block a
+// only).  A larger drop has g = ceil(K / kGroupUsers) groups (group i holds users
+// [32 i, min(32 i + 32, K)), so only the last is short and it is never group a) and one
+// virtual drop per group pair a < b, whose a-b block is always copied out.  The pairs
+// (a, a + 1) compute their whole Gram and also give group a's own block (kVCopyA), the last
+// pair also the last group's (kVCopyB); every other pair computes only the products between
+// its two groups (cross).
+struct GroupPair {
+  int a0, ka, b0, kb, flags, cross;
+};
+std::vector<GroupPair> group_pairs(int K) {
+  std::vector<GroupPair> out;
+  if (K <= XLMIMO_MAX_USERS) {
+    out.push_back({0, K, 0, 0, kVCopyA, 0});
+    return out;
+  }
+  const int g = (K + kGroupUsers - 1) / kGroupUsers;
+  auto first = [&](int i) { return std::min(K, i * kGroupUsers); };
+  for (int ga = 0; ga < g; ++ga)
+    for (int gb = ga + 1; gb < g; ++gb) {
+      int flags = 0;
+      if (gb == ga + 1) flags |= kVCopyA;
+      if (ga == g - 2 && gb == g - 1) flags |= kVCopyB;
+      out.push_back({first(ga), first(ga + 1) - first(ga), first(gb), first(gb + 1) - first(gb), flags, flags ? 0 : 1});
+    }
+  return out;
+}
+
+// Virtual drops of a batch with K > XLMIMO_MAX_USERS (every drop as group_pairs lays it out).
 int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
   if (c->capturing)
     return set_err(c, XLMIMO_EINVAL, "a new batch shape needs a launch plan during graph capture: "
@@ -428,19 +450,7 @@ int build_groups(xlmimo_ctx* c, const xlmimo_array* a, Plan& p) {
       vcross.push_back(cross);
       vgoff += (int64_t)(ka + kb) * (ka + kb);
     };
-    if (K <= XLMIMO_MAX_USERS) {
-      add(0, K, 0, 0, kVCopyA, 0);
-    } else {
-      const int g = (K + kGroupUsers - 1) / kGroupUsers;
-      auto first = [&](int i) { return std::min(K, i * kGroupUsers); };
-      for (int ga = 0; ga < g; ++ga)
-        for (int gb = ga + 1; gb < g; ++gb) {
-          int flags = 0;
-          if (gb == ga + 1) flags |= kVCopyA;
-          if (ga == g - 2 && gb == g - 1) flags |= kVCopyB;
-          add(first(ga), first(ga + 1) - first(ga), first(gb), first(gb + 1) - first(gb), flags, flags ? 0 : 1);
-        }
-    }
+    for (const GroupPair& gp : group_pairs(K)) add(gp.a0, gp.ka, gp.b0, gp.kb, gp.flags, gp.cross);
     uoff += K;
     goff += (int64_t)K * K;
   }

@@ -1,6 +1,6 @@
 // Host-side checks of the C-ABI library: argument validation of every entry point, the launch
-// plan's layout of a batch into drop descriptors and work items, the virtual-drop plan of drops
-// with more than 64 users, and the Gauss-Legendre table the context uploads.  Built with
+// plan's layout of a batch into drop descriptors and work items, the user-group virtual drops of
+// drops with more than 64 users, and the Gauss-Legendre table the context uploads.  Built with
 // AddressSanitizer and UndefinedBehaviorSanitizer on the host code; no kernel runs.  The library
 // source is included so that its internal helpers are callable; the kernels it refers to come
 // from the built library.  A context object is constructed directly, so without a GPU every call
@@ -259,6 +259,38 @@ void test_entry_points() {
   c.cap_failed = false;
 }
 
+// The user-group plan of one drop: every user pair (i < j) computed by exactly one virtual drop
+// that copies it out (its cross block, or the own block of its group), every group's own block
+// copied exactly once, cross-only drops exactly the pairs that copy no own block, and at most 64
+// users per virtual drop.
+void test_group_pairs() {
+  for (int K : {1, 2, 31, 63, 64, 65, 96, 97, 128, 200, 511, 1000, 1024}) {
+    const std::vector<GroupPair> gps = group_pairs(K);
+    std::vector<int> seen((size_t)K * K, 0);
+    for (const GroupPair& gp : gps) {
+      CHECK(gp.ka >= 1 && gp.kb >= 0 && gp.ka + gp.kb <= XLMIMO_MAX_USERS);
+      CHECK(gp.a0 >= 0 && gp.a0 + gp.ka <= K && gp.b0 >= 0 && gp.b0 + gp.kb <= K);
+      CHECK(gp.cross == ((gp.flags & (kVCopyA | kVCopyB)) == 0 ? 1 : 0) || K <= XLMIMO_MAX_USERS);
+      if (gp.kb > 0) CHECK(gp.a0 + gp.ka <= gp.b0);   // disjoint groups, a before b
+      for (int i = 0; i < gp.ka; ++i)
+        for (int j = 0; j < gp.kb; ++j) ++seen[(size_t)(gp.a0 + i) * K + (gp.b0 + j)];
+      auto own = [&](int o, int k) {
+        for (int i = 0; i < k; ++i)
+          for (int j = i + 1; j < k; ++j) ++seen[(size_t)(o + i) * K + (o + j)];
+      };
+      if (gp.flags & kVCopyA) own(gp.a0, gp.ka);
+      if (gp.flags & kVCopyB) own(gp.b0, gp.kb);
+    }
+    int bad = 0;
+    for (int i = 0; i < K; ++i)
+      for (int j = i + 1; j < K; ++j) bad += seen[(size_t)i * K + j] != 1;
+    if (bad) std::fprintf(stderr, "K = %d: %d user pairs not covered exactly once\n", K, bad);
+    CHECK(bad == 0);
+    const int g = (K + kGroupUsers - 1) / kGroupUsers;
+    CHECK((int)gps.size() == (K <= XLMIMO_MAX_USERS ? 1 : g * (g - 1) / 2));
+  }
+}
+
 // Launch plans built against a constructed context: the host layout runs in full (the drops,
 // the items and, above 64 users, the user-group virtual drops) and the build stops cleanly at
 // the first device allocation when no GPU is present.
@@ -313,6 +345,7 @@ int main() {
   test_check_batch();
   test_chunk_length();
   test_layout();
+  test_group_pairs();
   test_entry_points();
   test_plan_builds();
   test_gauss_legendre();
