@@ -93,7 +93,7 @@ __device__ __forceinline__ void channel_parts(double dy, double dz, double xp2, 
   sn = __builtin_amdgcn_sinf(-t);
 }
 
-template <int GEOM, int AMP>
+template <int GEOM, int AMP, bool SC = true>
 __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, float& re, float& im) {
   float a, c, sn;
   channel_parts<GEOM, AMP>(dy, dz, xp2, 1.0f, a, c, sn);
@@ -102,8 +102,9 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
 }
 
 // FP64: distances in units of lambda / 2 (r counts half turns),
-// h = a (-1)^q (cos(pi t) - j sin(pi t)), q = rint(r), t = r - q, Taylor sin/cos.
-template <int GEOM, int AMP>
+// h = a (-1)^q (cos(pi t) - j sin(pi t)), q = rint(r), t = r - q, Taylor sin/cos
+// (SC: the series' coefficients in scalar registers).
+template <int GEOM, int AMP, bool SC = true>
 __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, double& re, double& im) {
   double r2 = fma(dy, dy, xp2);
   if constexpr (GEOM == XLMIMO_UPA) r2 = fma(dz, dz, r2);
@@ -112,7 +113,7 @@ __device__ __forceinline__ void channel_entry(double dy, double dz, double xp2, 
   r = fma(0.5 * y, fma(-r, r, r2), r);
   const double qd = __builtin_rint(r);
   double ns, c;
-  sincos_half(r - qd, ns, c);
+  sincos_half<SC>(r - qd, ns, c);
   double a = y;
   if constexpr (AMP == XLMIMO_AMP_PNUSW) a = a * sqrt(a);
   if (((int)qd) & 1) a = -a;
@@ -198,7 +199,7 @@ __device__ void process_item(const ArrayK& arr, const DropK& dp, const ItemK& it
   auto round = [&](const double* dy, double ez) {
     T hre[NB], him[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP>(dy[b], u[b].uz - ez, u[b].xp2, hre[b], him[b]);
+    for (int b = 0; b < NB; ++b) channel_entry<GEOM, AMP, (NB <= 2)>(dy[b], u[b].uz - ez, u[b].xp2, hre[b], him[b]);
     if constexpr (CROSS) {
       {
 #pragma unroll
