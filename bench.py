@@ -58,9 +58,9 @@ FLOP_PER_ENTRY_EVAL = 11
 FLOP_PER_PAIR_MAC = 8
 GATE = 1e-3          # sum-rate accuracy gate (relative)
 # The learned correction's network: 6 inputs, MLP_DEPTH hidden layers of MLP_WIDTH (GELU), 7 outputs.
-# Width 128 holds the same gate, the same errors and the same gain over its base as width 256 on
-# the sweep (the network's capacity is not what limits the correction), at under half the forward.
-MLP_WIDTH, MLP_DEPTH = 128, 4
+# Widths 64, 128 and 256 hold the same gate, the same errors and the same gain over the network's
+# base on the sweep (its capacity is not what limits the correction); the narrowest is the fastest.
+MLP_WIDTH, MLP_DEPTH = 64, 4
 GATE_GRAM = 1e-5     # exact-form Gram accuracy (normwise)
 COUNTER_RECORD = os.path.join(ROOT, "profiles", "gram_exact_fp32h_sweep_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_18118_amd", "csrc", f) for f in ("gram_exact.hip", "device_math.h")]
@@ -183,14 +183,26 @@ def train_mlp(ctx, X, Lr, W, snr, args):
     batch = args.mlp_batch
     hist, secs = Lr.train(mlp, data, args.mlp_train_steps, batch=batch, lr_max=args.mlp_lr, lr_min=1e-5,
                           log_every=max(args.mlp_train_steps // 6, 1))
-    del data
     fl = 3 * mlp_flops_per_pair() * batch  # forward + two backward GEMMs per layer
-    info = {"train_pairs": int(tdrops.n_drops * 120), "train_drops": args.mlp_train_drops,
+    # the same training kernels on a 256-wide network of the same depth, for their throughput at
+    # a size where the products, not the per-step fixed costs, dominate (a short run, not used)
+    wide = X.MLP(ctx, 256, MLP_DEPTH)
+    wide.set_params(Lr.init_params(256, MLP_DEPTH, np.random.default_rng(0), math.log(var0)))
+    wide_steps = 1000
+    Lr.train(wide, data, 50, batch=batch, lr_max=args.mlp_lr, lr_min=1e-5, log_every=50)   # workspaces
+    _, wsecs = Lr.train(wide, data, wide_steps, batch=batch, lr_max=args.mlp_lr, lr_min=1e-5, log_every=wide_steps)
+    wide.close()
+    del data
+    wfl = 3 * mlp_flops_per_pair(256, MLP_DEPTH) * batch * wide_steps / wsecs / 1e12
+    info = {"width": MLP_WIDTH, "depth": MLP_DEPTH, "train_pairs": int(tdrops.n_drops * 120),
+            "train_drops": args.mlp_train_drops,
             "steps": args.mlp_train_steps, "batch": batch, "lr_max": args.mlp_lr, "data_seconds": prep,
             "train_seconds": secs, "steps_per_s": args.mlp_train_steps / secs,
             "train_tflops": fl * args.mlp_train_steps / secs / 1e12,
             "train_frac_of_bf16_peak": fl * args.mlp_train_steps / secs / 1e12 / PEAK_BF16_MFMA_TFLOPS,
-            "loss_history": hist}
+            "loss_history": hist,
+            "train_kernels_at_width_256": {"steps": wide_steps, "batch": batch, "steps_per_s": wide_steps / wsecs,
+                                           "tflops": wfl, "frac_of_bf16_peak": wfl / PEAK_BF16_MFMA_TFLOPS}}
     carr, cdrops, cmeta = W.learned_calibration(args.mlp_calibration_drops)
     rho_c = snr.rho_for_snr(carr, cmeta["snr_db"], cmeta["ref_distance"], int(cdrops.user_off[-1]))
     t0 = time.perf_counter()

@@ -830,7 +830,8 @@ hipError_t launch_mlp_apply(int64_t n, const float* out, const float* aux, const
 // MFMA operand registers (W[o][k] is k-contiguous), and each fragment feeds NB
 // MFMAs: the weight traffic per pair falls as the tile grows (W = 256 and W = 128 run
 // 128-pair tiles: 0.86 against 0.99 ms per 10^6 pairs with 64-pair tiles at W = 256, depth 4;
-// 0.30 against 0.32 ms at W = 128, depth 4).  Wave w
+// 0.30 against 0.32 ms at W = 128, depth 4; W = 64 keeps 64-pair tiles, 0.11 ms against 0.12
+// and 0.14 with 128 and 256 pairs).  Wave w
 // owns output columns [w W/NW, (w+1) W/NW) of the hidden layers and row blocks
 // w, w + NW, ... of the output layer.
 // TRAIN: also store each hidden layer's pre-activation (FP32) and GELU output (BF16) for the
@@ -1111,7 +1112,8 @@ hipError_t launch_mlp_fused_forward(int width, int depth, int64_t n, const __bf1
 // features over 64 pairs from 16384 pairs on (256 workgroups and more), 32 pairs below (batch
 // 16384: 125 TFLOP/s for the whole step against 115 with 4 waves of 64 features; batch 8192:
 // 91 against 80 with 64-pair tiles); at width 128, 8 waves of 16 features over 32 pairs (batch
-// 16384, depth 4: 64 TFLOP/s against 58 with 4 waves over 64 pairs).
+// 16384, depth 4: 64 TFLOP/s against 58 with 4 waves over 64 pairs); at width 64, 4 waves of 16
+// features over 32 pairs (16500 against 15400 steps/s over 64 pairs).
 hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const __bf16* feat, const __bf16* wbf,
                                           const float* master, const int64_t* d_offs, const FwdKeep& keep,
                                           float* out, hipStream_t s) {
@@ -1122,7 +1124,7 @@ hipError_t launch_mlp_fused_train_forward(int width, int depth, int64_t n, const
     k_mlp_fused_forward<256, 4, 8, true><<<grid, 512, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else if (width == 256) k_mlp_fused_forward<256, 2, 8, true><<<grid32, 512, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else if (width == 128) k_mlp_fused_forward<128, 2, 8, true><<<grid32, 512, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
-  else if (width == 64) k_mlp_fused_forward<64, 4, 4, true><<<grid, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
+  else if (width == 64) k_mlp_fused_forward<64, 2, 4, true><<<grid32, 256, 0, s>>>(n, depth, feat, wbf, master, d_offs, out, keep);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1136,7 +1138,7 @@ hipError_t launch_mlp_fused_train_backward(int width, int depth, int64_t n, cons
     k_mlp_fused_train_backward<256, 4, 8><<<grid, 512, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
   else if (width == 256) k_mlp_fused_train_backward<256, 2, 8><<<grid32, 512, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
   else if (width == 128) k_mlp_fused_train_backward<128, 2, 8><<<grid32, 512, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
-  else if (width == 64) k_mlp_fused_train_backward<64, 4, 4><<<grid, 256, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
+  else if (width == 64) k_mlp_fused_train_backward<64, 2, 4><<<grid32, 256, 0, s>>>(n, depth, dout, wbf_t, d_offs, keep);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

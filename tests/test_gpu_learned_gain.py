@@ -41,16 +41,16 @@ def env():
     from paper_2503_18118_amd import snr
     from paper_2503_18118_amd import xlmimo as X
     ctx = X.Context(0)
-    mlp = X.MLP(ctx, 128, 4)
+    mlp = X.MLP(ctx, 64, 4)
     tarr, tdrops = W.learned_drops(83334, stream=1)
     print("training the network (12000 steps)", flush=True)
     data, *_ = Lr.pair_set(ctx, mlp, tarr, tdrops)
     var0 = float((data.target[:, 0] ** 2 + data.target[:, 1] ** 2).mean())
-    mlp.set_params(Lr.init_params(128, 4, np.random.default_rng(0), math.log(var0)))
+    mlp.set_params(Lr.init_params(64, 4, np.random.default_rng(0), math.log(var0)))
     Lr.train(mlp, data, 12000, batch=8192, lr_max=3e-3, lr_min=1e-5, log_every=2000)
     del data
-    base = Lr.constant_network(ctx, 128, 4, [-1, 0, -1, 0, 0, 0])
-    ends = Lr.constant_network(ctx, 128, 4, [0, 0, 0, 0, 0, 0])
+    base = Lr.constant_network(ctx, 64, 4, [-1, 0, -1, 0, 0, 0])
+    ends = Lr.constant_network(ctx, 64, 4, [0, 0, 0, 0, 0, 0])
     yield X, Lr, snr, ctx, {"base": base, "ends": ends, "net": mlp}
     ctx.close()
 

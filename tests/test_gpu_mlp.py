@@ -168,13 +168,13 @@ def test_multi_step_training_equals_single_steps(X, ctx):
     assert np.array_equal(np.array(la), lb.cpu().numpy())
 
 
-@pytest.mark.parametrize("width,depth", [(512, 9), (256, 4), (128, 4)])
+@pytest.mark.parametrize("width,depth", [(512, 9), (256, 4), (128, 4), (64, 4)])
 def test_gradient_paths_agree(X, ctx, width, depth):
     # Two implementations of each training pass, on one batch of 16384 pairs and on its 32
     # sub-batches of 512.  Width 512 runs the layer GEMMs: a network whose split-K weight-gradient
     # slices fit the library's budget runs the grouped weight-gradient launch on a transposed weight
     # copy (every sub-batch here); one whose slices do not (2.1 M parameters x 32 slices at 16384
-    # pairs) reduces each layer right after its GEMM.  Widths 256 and 128 run the fused forward and
+    # pairs) reduces each layer right after its GEMM.  Widths 256, 128 and 64 run the fused forward and
     # input-gradient passes (at width 256 with 64-pair tiles at 16384 pairs and 32-pair tiles below).  The
     # gradient of the mean loss over 16384 pairs is the mean of the 32 sub-batch gradients: the 1/n
     # scalings are powers of two, so every BF16 rounding scales exactly and only the FP32 summation
