@@ -741,7 +741,26 @@ __device__ void inv_diag_global(cplx* M, int K, cplx* s_rows, double* s_inv) {
         for (int r = 0; r < kPanel; ++r)
           if (r < nr) acc[r] = {s_rows[r * K + k].x * wkk, s_rows[r * K + k].y * wkk};
         const int t0 = (k & ~63) + 1;
-        for (int t = t0; t < i0; ++t) {
+        // four loads of W in flight per step (the sums keep their order over t)
+        int t = t0;
+        for (; t + 4 <= i0; t += 4) {
+          cplx m[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) m[u] = M[(int64_t)(t + u) * K + k];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const cplx w = t + u > k ? m[u] : cplx{0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < kPanel; ++r) {
+              if (r < nr) {
+                const cplx p = cmul(s_rows[r * K + t + u], w);
+                acc[r].x += p.x;
+                acc[r].y += p.y;
+              }
+            }
+          }
+        }
+        for (; t < i0; ++t) {
           const cplx m = M[(int64_t)t * K + k];
           const cplx w = t > k ? m : cplx{0.0, 0.0};
 #pragma unroll
