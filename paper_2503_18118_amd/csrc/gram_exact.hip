@@ -1085,40 +1085,25 @@ __global__ void k_reset_counter(int* counter) {
   if (threadIdx.x == 0) *counter = 0;
 }
 
-// The work items of the selected drops, in their original order (one workgroup:
-// per 1024 items, a ballot prefix within each wave, then the waves in order).
-__global__ __launch_bounds__(1024) void k_compact_items(const ItemK* __restrict__ items, int n_items,
-                                                        const int32_t* __restrict__ mask, ItemK* __restrict__ out,
-                                                        int* __restrict__ count) {
-  __shared__ int s_wave[16], s_off[16], s_base;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_base = 0;
-  __syncthreads();
-  for (int i0 = 0; i0 < n_items; i0 += 1024) {
-    const int i = i0 + tid;
-    ItemK it{};
-    bool keep = false;
-    if (i < n_items) {
-      it = items[i];
-      keep = mask[it.drop] != 0;
-    }
-    const unsigned long long bal = __ballot(keep);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) s_wave[wave] = __popcll(bal);
-    __syncthreads();
-    if (tid == 0) {
-      int acc = s_base;
-      for (int w = 0; w < 16; ++w) {
-        s_off[w] = acc;
-        acc += s_wave[w];
-      }
-      s_base = acc;
-    }
-    __syncthreads();
-    if (keep) out[s_off[wave] + before] = it;
-    __syncthreads();
+// The work items of the selected drops: one thread per item and one slot range per wave (an
+// atomic on the count, which k_reset_counter zeroes first).  The list's order follows the waves'
+// atomics; it decides only which workgroup takes which item, since every item writes its own
+// partial image and the finalize pass sums a drop's images in chunk order.
+__global__ __launch_bounds__(256) void k_compact_items(const ItemK* __restrict__ items, int n_items,
+                                                       const int32_t* __restrict__ mask, ItemK* __restrict__ out,
+                                                       int* __restrict__ count) {
+  const int i = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x & 63;
+  ItemK it{};
+  bool keep = false;
+  if (i < n_items) {
+    it = items[i];
+    keep = mask[it.drop] != 0;
   }
-  if (tid == 0) *count = s_base;
+  const unsigned long long bal = __ballot(keep);
+  int base = 0;
+  if (lane == 0 && bal != 0ull) base = atomicAdd(count, __popcll(bal));
+  base = __shfl(base, 0, 64);
+  if (keep) out[base + __popcll(bal & ((1ull << lane) - 1ull))] = it;
 }
 
 // Position of C[row][col] of a 16x16 MFMA accumulator in the (value, lane) image.
@@ -1274,7 +1259,8 @@ hipError_t launch_gram_exact(int precision, int nb_max, const ArrayK& arr, const
   MainArgs a{arr, d_drops, d_pos, d_items, n_items, d_counter, d_partials, d_mask, nullptr};
   if (d_mask != nullptr && d_items_sel != nullptr && d_n_sel != nullptr) {
     // a few selected drops: pop only their items
-    k_compact_items<<<1, 1024, 0, s>>>(d_items, n_items, d_mask, d_items_sel, d_n_sel);
+    k_reset_counter<<<1, 64, 0, s>>>(d_n_sel);
+    if (n_items > 0) k_compact_items<<<(n_items + 255) / 256, 256, 0, s>>>(d_items, n_items, d_mask, d_items_sel, d_n_sel);
     a.items = d_items_sel;
     a.n_items_dev = d_n_sel;
   }
