@@ -522,6 +522,29 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
   const int K = dp.k;
   const int np = K * (K - 1) / 2;
   const double lam = arr.lambda;
+  const double ytop = 0.5 * (double)(dp.n_elems - 1) * arr.spacing;
+  // per user, once per drop: perpendicular distance and position, the two user features, and
+  // at each array end (top, bottom) the distance r_e, (y_e - y) / r_e and x^2 / r_e^3
+  constexpr int kU = 10;
+  __shared__ double s_user[XLMIMO_MAX_USERS * kU];
+  for (int u = threadIdx.x; u < K; u += blockDim.x) {
+    const double* pu = pos + (dp.user_off + u) * 3;
+    const double x = sqrt(fma(pu[0], pu[0], pu[2] * pu[2])), y = pu[1];
+    double* su = s_user + u * kU;
+    su[0] = x;
+    su[1] = y;
+    su[2] = sqrt(x * x + y * y) / 50.0;
+    su[3] = atan2(y, x) / (kPiD / 3.0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const double d = (e == 0 ? ytop : -ytop) - y;
+      const double r = sqrt(fma(d, d, x * x));
+      su[4 + 3 * e] = r;
+      su[5 + 3 * e] = d / r;
+      su[6 + 3 * e] = x * x / (r * r * r);
+    }
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < np; t += blockDim.x) {
     int i = 0, rem = t;
     while (rem >= K - 1 - i) {
@@ -530,12 +553,11 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
     }
     const int j = i + 1 + rem;
     const int64_t p = dp.pair_off + t;
-    const double* ui = pos + (dp.user_off + i) * 3;
-    const double* uj = pos + (dp.user_off + j) * 3;
-    const double xi = sqrt(fma(ui[0], ui[0], ui[2] * ui[2])), yi = ui[1];
-    const double xj = sqrt(fma(uj[0], uj[0], uj[2] * uj[2])), yj = uj[1];
-    const double f[8] = {sqrt(xi * xi + yi * yi) / 50.0, atan2(yi, xi) / (kPiD / 3.0),
-                         sqrt(xj * xj + yj * yj) / 50.0, atan2(yj, xj) / (kPiD / 3.0),
+    const double* si = s_user + i * kU;
+    const double* sj = s_user + j * kU;
+    const double xi = si[0], yi = si[1];
+    const double xj = sj[0], yj = sj[1];
+    const double f[8] = {si[2], si[3], sj[2], sj[3],
                          log((double)dp.n_elems) / log(4.0) - 6.0, arr.spacing / lam - 0.5, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 8; ++q) feat[p * 8 + q] = (__bf16)(float)f[q];
@@ -548,30 +570,29 @@ __global__ __launch_bounds__(256) void k_pair_inputs(ArrayK arr, const DropK* __
     const double kw = 2.0 * kPiD * arr.inv_lambda;
     const double c_fs = (lam / (4.0 * kPiD)) * (lam / (4.0 * kPiD));
     // End-element term of the discrete sum: f e^{j phi} conj(D) / (|D|^2 + eps^2),
-    // D = 1 - e^{-j sign phi' d}, eps^2 = d^2 |phi''| / (2 pi), in correlation units.
-    auto end_term = [&](double y, double sign, float& br, float& bi) {
-      const double di = y - yi, dj = y - yj;
-      const double ra = sqrt(fma(di, di, xi * xi)), rb = sqrt(fma(dj, dj, xj * xj));
-      const double d1 = kw * (di / ra - dj / rb);
-      const double d2 = kw * (xi * xi / (ra * ra * ra) - xj * xj / (rb * rb * rb));
+    // D = 1 - e^{-j sign phi' d}, eps^2 = d^2 |phi''| / (2 pi), in correlation units
+    // (end e: 0 top, 1 bottom, from the per-user values above).
+    auto end_term = [&](int e, double sign, float& br, float& bi) {
+      const double ra = si[4 + 3 * e], rb = sj[4 + 3 * e];
+      const double d1 = kw * (si[5 + 3 * e] - sj[5 + 3 * e]);
+      const double d2 = kw * (si[6 + 3 * e] - sj[6 + 3 * e]);
       const double ang = sign * d1 * arr.spacing;
       const double dre = 1.0 - cos(ang), dim = sin(ang);
       const double den = dre * dre + dim * dim + arr.spacing * arr.spacing * fabs(d2) / (2.0 * kPiD);
       const double amp = (arr.amp == XLMIMO_AMP_FREESPACE) ? c_fs / (ra * rb)
                                                            : arr.beta0 * sqrt(xi * xj) / ((ra * rb) * sqrt(ra * rb));
       float pr, pi;
-      phasor_turns(dphase(y), pr, pi);
+      phasor_turns((ra - rb) * arr.inv_lambda, pr, pi);
       const double g = amp / (den * scale);
       // (pr + j pi)(dre - j dim)
       br = (float)(g * ((double)pr * dre + (double)pi * dim));
       bi = (float)(g * ((double)pi * dre - (double)pr * dim));
     };
-    const double ytop = 0.5 * (double)(dp.n_elems - 1) * arr.spacing;
     float pr, pi;
-    end_term(ytop, 1.0, pr, pi);
+    end_term(0, 1.0, pr, pi);
     aux[p * 8 + 0] = pr;
     aux[p * 8 + 1] = pi;
-    end_term(-ytop, -1.0, pr, pi);
+    end_term(1, -1.0, pr, pi);
     aux[p * 8 + 2] = pr;
     aux[p * 8 + 3] = pi;
     if (xi != xj) {
